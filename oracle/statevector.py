@@ -1,0 +1,26 @@
+"""Brute-force statevector simulation (no truncation): the exact result the
+MPS contraction must reproduce when nothing is discarded.  Big-endian: qubit 0
+is the most significant bit of the amplitude index."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gates as G
+
+
+def apply_gate(psi: np.ndarray, n: int, u: np.ndarray, qubits) -> np.ndarray:
+    g = len(qubits)
+    T = psi.reshape((2,) * n)
+    T = np.tensordot(u.reshape((2,) * (2 * g)), T, axes=(list(range(g, 2 * g)), list(qubits)))
+    T = np.moveaxis(T, list(range(g)), list(qubits))
+    return T.reshape(-1)
+
+
+def simulate(circuit) -> np.ndarray:
+    n = circuit.n
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1.0
+    for layer in circuit.layers:
+        for g in layer:
+            psi = apply_gate(psi, n, G.matrix(g.name), g.qubits)
+    return psi

@@ -1,0 +1,192 @@
+/*
+ * cluster_tebd.h -- C ABI of the MI355X cluster-TEBD library (libctebd.so).
+ *
+ * The library simulates an n-qubit circuit on a matrix-product state (MPS) with
+ * the cluster-TEBD iteration of De Girolamo et al., arXiv:2502.19289, Sec. III.A:
+ * qubits joined by entangling gates are grouped into entanglement clusters, the
+ * gates of each cluster over several layers are merged into one exact
+ * 2^k x 2^k unitary, the unitary is applied to the MPS block the cluster covers,
+ * and the block is split back into k sites by a sweep of truncated SVDs with
+ * cutoff eta and cap chi_max (Sec. II.B), whose discarded weights give the
+ * fidelity estimate F = prod_i f_i (Eqs. f_i and approxF).
+ *
+ * Conventions shared by every call
+ *   - Sites are 0..n-1, bond b joins sites b and b+1 (0 <= b < n-1).
+ *   - Gate matrices are row-major complex128 stored as interleaved (re, im)
+ *     doubles.  A matrix acting on qubits q[0..k-1] is big-endian in that list:
+ *     q[0] is the most significant bit of its row/column index.
+ *   - Statevector amplitudes use the same order (qubit 0 most significant).
+ *   - Ownership: the caller owns every array it passes; the library copies what
+ *     it needs before returning.  All device memory belongs to the handle and is
+ *     released by mps_destroy.
+ *   - Errors: every call returns an mps_status; nothing is thrown across the
+ *     ABI.  mps_last_error(h) gives a message for the last failed call on h.
+ *   - Concurrency: one handle must not be used from two host threads at once.
+ *     Work is queued on the handle's HIP stream; the calls documented as
+ *     "synchronises" wait for it.
+ */
+#ifndef CLUSTER_TEBD_H
+#define CLUSTER_TEBD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_ctx* mps_handle;
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_EINVAL = -1,       /* bad argument (size, index, null pointer)            */
+  MPS_ENOMEM = -2,       /* device or host allocation failed                     */
+  MPS_ESPAN = -3,        /* cluster wider than k_max or qubits not ascending     */
+  MPS_ENOTUNITARY = -4,  /* ||U^dagger U - 1||_max > 1e-10                       */
+  MPS_EDEVICE = -5,      /* a HIP call failed or no GPU is present               */
+  MPS_ESTATE = -6,       /* call not valid in the handle's current state         */
+  MPS_EIO = -7           /* file could not be read or written                    */
+} mps_status;
+
+/* Arithmetic of the contractions (merge, unitary application, projection).
+ * The Gram matrices, the eigen-solver and every singular value stay FP64. */
+enum {
+  MPS_PREC_FP64 = 0,    /* complex128 site tensors, FP64 MFMA contractions      */
+  MPS_PREC_FP32 = 1,    /* complex64 site tensors, FP32 MFMA contractions       */
+  MPS_PREC_BF16X6 = 2   /* complex64 tensors, contractions as six BF16 MFMA
+                           products of a three-way hi/mid/lo split, FP32 sums   */
+};
+
+/* How the truncated SVD of each split is obtained. */
+enum {
+  MPS_SVD_EXACT = 0,    /* FP64 Gram matrix + FP64 block-Jacobi eigen-solver    */
+  MPS_SVD_LEARNED = 1   /* randomized range finder with a sketch size chosen by
+                           the kept-rank network; exact SVD when its residual
+                           check fails                                          */
+};
+
+/* How the independent clusters of one step are launched. */
+enum {
+  MPS_BATCH_NONE = 0,   /* one cluster per launch sequence                      */
+  MPS_BATCH_STEP = 1    /* every cluster of a step in the same launches         */
+};
+
+typedef struct {
+  int k_max;        /* most qubits per cluster; wider gates are SWAP-routed    */
+  int q_max;        /* Eq. cond_cTEBD: 2^k chi_l chi_r <= 2^q_max; <= 0 gives
+                       k_max + 2 ceil(log2 chi_max), which never binds         */
+  int l_max;        /* Eq. cond2_cTEBD: sub-layers per step; <= 0: unlimited  */
+  int precision;    /* MPS_PREC_*                                              */
+  int svd_mode;     /* MPS_SVD_*                                               */
+  int batch;        /* MPS_BATCH_*                                             */
+  double floor_c;   /* the kept-value threshold is max(eps, floor_c * u) with
+                       u = 2^-24 for FP32/BF16X6 and 2^-26.5 for FP64; the
+                       Gram route cannot resolve singular values below it    */
+  void* hip_stream; /* hipStream_t to queue work on; NULL: a stream of its own */
+} mps_options;
+
+/* A one- or two-qubit gate: nq in {1,2}, q[0..nq-1] the qubits, u the
+ * 2^nq x 2^nq matrix (row-major, interleaved re/im, big-endian in q). */
+typedef struct {
+  int nq;
+  int q[2];
+  double u[32];
+} mps_gate;
+
+/* Counters of the work done so far (all cumulative). */
+typedef struct {
+  int64_t steps;            /* cluster-TEBD iterations executed                  */
+  int64_t cluster_updates;  /* clusters with k >= 2 contracted and split         */
+  int64_t svds;             /* truncated SVDs (k-1 per cluster)                  */
+  int64_t site_updates;     /* sites updated by one-qubit gates alone            */
+  int64_t sketch_accepted;  /* learned-sketch SVDs that passed the residual test */
+  int64_t sketch_fallback;  /* learned-sketch SVDs redone exactly                */
+  int64_t jacobi_sweeps;    /* block-Jacobi sweeps launched                      */
+  double discarded_weight;  /* sum over SVDs of (1 - f_i)                        */
+} mps_stats;
+
+/* Fills *opt with the defaults: k_max 4, q_max 0, l_max 0, FP32, exact SVD,
+ * step batching, floor_c 4, library stream. */
+mps_status mps_default_options(mps_options* opt);
+
+/* Sec. II.B / IV.A: creates the product state |0...0> on n >= 2 qubits (every
+ * bond of dimension one, F = 1) with bond cap chi_max >= 1 and cutoff eps >= 0
+ * (singular values below eps, on the normalised spectrum, are dropped).
+ * opt may be NULL (defaults).  Allocates the site tensors at their largest
+ * possible size min(chi_max, 2^min(b+1, n-b-1)) per bond. */
+mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt,
+                      mps_handle* out);
+mps_status mps_destroy(mps_handle h);
+
+/* Sec. III.A steps "contract" and "decompose" for one cluster: applies the
+ * 2^k x 2^k unitary U (interleaved complex128, row-major, big-endian in
+ * qubits[]) to the sites qubits[0]..qubits[k-1], which must be strictly
+ * ascending with qubits[k-1]-qubits[0]+1 <= k_max (else MPS_ESPAN); idle qubits
+ * inside the span are padded with the identity.  The block is then split back
+ * by k'-1 truncated SVDs (k' = span), adding log f_i of each to the fidelity
+ * estimate.  Pending layers are flushed first.  2 <= k <= 12. */
+mps_status mps_apply_cluster(mps_handle h, const int* qubits, int k, const double* U);
+
+/* Sec. III.A iteration driver: buffers one circuit layer (gates on disjoint
+ * qubits, Sec. II.A).  Gates wider than k_max are routed by adjacent SWAPs.
+ * When the buffered layers no longer fit the caps (k_max, Eq. cond_cTEBD,
+ * Eq. cond2_cTEBD) the step made of the layers that do fit is contracted. */
+mps_status mps_run_layer(mps_handle h, const mps_gate* gates, int ngates);
+
+/* Contracts every buffered layer (as many steps as the caps need). */
+mps_status mps_flush(mps_handle h);
+
+/* Eq. approxF: flushes, synchronises, returns F_est = exp(sum log f_i) and
+ * sum log f_i (either pointer may be NULL). */
+mps_status mps_fidelity(mps_handle h, double* F_est, double* log_f);
+
+/* Synchronises; writes the n-1 current bond dimensions into chi. */
+mps_status mps_bond_dims(mps_handle h, int* chi);
+
+/* Synchronises; copies the normalised Schmidt values of bond b (descending,
+ * FP64) into sigma[0..cap-1] and their count into *len. */
+mps_status mps_schmidt(mps_handle h, int bond, double* sigma, int cap, int* len);
+
+/* Synchronises; copies site tensor B_j, shape (chi_{j-1}, 2, chi_j) row-major,
+ * as interleaved complex128 into B[0..2*cap-1] (cap counts complex entries)
+ * and its shape into dims[0..2].  Sites 1..n-1 are right-canonical; the
+ * state is the contraction B_0 B_1 ... B_{n-1}. */
+mps_status mps_export_site(mps_handle h, int site, double* B, int64_t cap, int* dims);
+
+/* Replaces the whole state: sites[j] points at chi_{j-1}*2*chi_j interleaved
+ * complex128 values (right-canonical for j >= 1), lams[b] at chi[b] Schmidt
+ * values.  Bond dimensions must not exceed the handle's capacities. */
+mps_status mps_import(mps_handle h, const int* chi, const double* const* sites,
+                      const double* const* lams, double log_f);
+
+/* Synchronises; writes the 2^n amplitudes (interleaved complex128) of the
+ * state; n <= 24 and cap >= 2^n. */
+mps_status mps_amplitudes(mps_handle h, double* psi, int64_t cap);
+
+mps_status mps_get_stats(mps_handle h, mps_stats* st);
+
+/* Device time (ms) spent in each kernel class since creation, measured with
+ * HIP events on the handle's stream around every launch of that class when
+ * timing is on (mps_set_timing).  names receives a comma-separated list. */
+mps_status mps_set_timing(mps_handle h, int on);
+mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, int cap,
+                            char* names, int names_cap, int* count);
+
+const char* mps_last_error(mps_handle h);
+
+/* Host-side planner of Sec. III.A, exposed for testing: legalises the layers
+ * (SWAP routing, sub-layers of disjoint spans) and plans the first step from
+ * sub-layer `start` with bond dimensions chi[0..n-2].
+ *   layers: nl layers; layer_len[i] gates each; gates flattened in order.
+ *   out_end: index (exclusive) of the last sub-layer of the step.
+ *   out_clusters: pairs (first site, k) of the step's clusters, at most cap.
+ *   n_sub: number of sub-layers after legalisation. */
+mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi,
+                    const mps_gate* gates, const int* layer_len, int nl, int start,
+                    int* out_end, int* out_clusters, int cap, int* out_count,
+                    int* n_sub);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLUSTER_TEBD_H */

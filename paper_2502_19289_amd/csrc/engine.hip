@@ -1,0 +1,1252 @@
+// Host side of the cluster-TEBD library: handle state, the step executor that
+// queues the kernels of one iteration (arXiv:2502.19289, Sec. III.A), and the
+// C ABI declared in include/cluster_tebd.h.
+//
+// One step = the clusters chosen by the planner plus the one-qubit gates of the
+// sites outside them.  Every cluster goes through
+//   unitary build -> merge chain -> unitary application -> (k-1) x split,
+//   split = Gram (FP64) -> block-Jacobi eigen (FP64) -> select -> gather -> project,
+//   finalize (B_a = X / sqrt(prod f)).
+// With MPS_BATCH_STEP all clusters of the step share each launch (the kernels
+// are grouped: one workgroup per output tile of any cluster); with
+// MPS_BATCH_NONE every cluster gets its own launches.  Ranks chosen by a
+// truncation are written to device memory and read there by the later kernels
+// of the same step, so a step needs one host synchronisation at its end (plus
+// one per Jacobi sweep to stop converged solves).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+
+#include "engine.hpp"
+
+using namespace ctebd;
+
+namespace ctebd {
+
+hipError_t DeviceArena::reserve(size_t bytes) {
+  if (bytes <= cap) return hipSuccess;
+  const size_t want = std::max(bytes, cap * 3 / 2);
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = 0;
+  hipError_t e = hipMalloc(&base, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    base = nullptr;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void DeviceArena::release() {
+  if (base) (void)hipFree(base);
+  base = nullptr;
+  cap = used = 0;
+}
+
+hipError_t DescBlob::prepare() {
+  const size_t bytes = std::max<size_t>(host.size(), 16);
+  if (bytes > pinned_cap) {
+    if (pinned) (void)hipHostFree(pinned);
+    pinned_cap = std::max(bytes, pinned_cap * 2);
+    hipError_t e = hipHostMalloc(&pinned, pinned_cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      pinned = nullptr;
+      pinned_cap = 0;
+      return e;
+    }
+  }
+  if (bytes > dev_cap) {
+    if (dev) (void)hipFree(dev);
+    dev_cap = std::max(bytes, dev_cap * 2);
+    hipError_t e = hipMalloc(&dev, dev_cap);
+    if (e != hipSuccess) {
+      dev = nullptr;
+      dev_cap = 0;
+      return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t DescBlob::upload(hipStream_t s) {
+  const size_t bytes = host.size();
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = prepare();
+  if (e != hipSuccess) return e;
+  memcpy(pinned, host.data(), bytes);
+  return hipMemcpyAsync(dev, pinned, bytes, hipMemcpyHostToDevice, s);
+}
+
+void DescBlob::release() {
+  if (pinned) (void)hipHostFree(pinned);
+  if (dev) (void)hipFree(dev);
+  pinned = dev = nullptr;
+  pinned_cap = dev_cap = 0;
+  host.clear();
+}
+
+int KernelTimer::cls_of(const char* name) {
+  for (size_t i = 0; i < names.size(); ++i)
+    if (names[i] == name) return (int)i;
+  names.push_back(name);
+  ms.push_back(0.0);
+  launches.push_back(0);
+  return (int)names.size() - 1;
+}
+
+}  // namespace ctebd
+
+namespace {
+
+struct Fail {
+  mps_status st;
+};
+
+#define HIP_OK(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+      throw Fail{e_ == hipErrorOutOfMemory ? MPS_ENOMEM : MPS_EDEVICE};          \
+    }                                                                            \
+  } while (0)
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// --------------------------------------------------------------- timing --
+struct Timed {
+  mps_ctx* ctx;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(mps_ctx* c, const char* name) : ctx(c), cls(-1) {
+    if (!ctx->timing) return;
+    cls = ctx->timer.cls_of(name);
+    auto take = [&]() {
+      hipEvent_t e;
+      if (!ctx->timer.pool.empty()) {
+        e = ctx->timer.pool.back();
+        ctx->timer.pool.pop_back();
+      } else {
+        (void)hipEventCreate(&e);
+      }
+      return e;
+    };
+    a = take();
+    b = take();
+    (void)hipEventRecord(a, ctx->stream);
+  }
+  ~Timed() {
+    if (cls < 0) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->timer.pending.push_back({cls, a, b});
+  }
+};
+
+void collect_timing(mps_ctx* ctx) {
+  for (auto& p : ctx->timer.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->timer.ms[p.cls] += ms;
+      ctx->timer.launches[p.cls] += 1;
+    }
+    ctx->timer.pool.push_back(p.a);
+    ctx->timer.pool.push_back(p.b);
+  }
+  ctx->timer.pending.clear();
+}
+
+// ------------------------------------------------------ job bookkeeping --
+struct Level {
+  int m;        // split index: site a+m is split off
+  int rows;     // chi_l 2^m
+  int c_bound;  // bound of c (bond right of site a+m)
+  int r_bound;  // bound of the kept rank
+  int ksplit;
+};
+
+struct JobRun {
+  const Job* job;
+  int a, k, chi_l, chi_r;
+  std::vector<int> mid;  // bonds a..a+k-2 before the step
+  int64_t theta;
+  std::vector<Level> lv;
+  int ld;
+  void* U64 = nullptr;
+  void* Uw = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  void* Vr = nullptr;
+  double2 *G = nullptr, *V = nullptr, *J = nullptr, *part = nullptr;
+  int *pair_rot = nullptr, *flags = nullptr, *perm = nullptr;
+  double *scale = nullptr, *logf = nullptr, *rec = nullptr;
+  int cur = 0;
+  int flag_index = 0;
+};
+
+int bond_dim(const mps_ctx* ctx, int b) { return (b < 0 || b >= ctx->n - 1) ? 1 : ctx->chi[b]; }
+
+Dim fixed(int v) { return Dim{v, nullptr}; }
+
+// Dim of c (the bond right of site a+m) at level t
+Dim c_dim(mps_ctx* ctx, const JobRun& j, int t, int mult) {
+  if (t == 0) return fixed(mult * j.chi_r);
+  return Dim{mult, ctx->d_chi + (j.a + j.lv[t].m)};
+}
+
+void plan_job(mps_ctx* ctx, const Job& job, JobRun& j) {
+  j.job = &job;
+  j.a = job.a;
+  j.k = job.k;
+  j.chi_l = bond_dim(ctx, job.a - 1);
+  j.chi_r = bond_dim(ctx, job.a + job.k - 1);
+  j.mid.clear();
+  for (int b = job.a; b < job.a + job.k - 1; ++b) j.mid.push_back(ctx->chi[b]);
+  j.theta = (int64_t)j.chi_l * ((int64_t)1 << job.k) * j.chi_r;
+  j.lv.clear();
+  int c = j.chi_r, cmax = c;
+  for (int m = job.k - 1; m >= 1; --m) {
+    Level L;
+    L.m = m;
+    L.rows = j.chi_l << m;
+    L.c_bound = c;
+    L.r_bound = std::min(ctx->chi_max, std::min(L.rows, 2 * c));
+    L.r_bound = std::min(L.r_bound, ctx->cap[job.a + m - 1]);
+    const int T = ceil_div(2 * c, 64);
+    const int tiles = T * (T + 1) / 2;
+    int ks = std::max(1, 256 / std::max(1, tiles));
+    ks = std::min(ks, std::max(1, L.rows / 256));
+    ks = std::min(ks, 16);
+    L.ksplit = ks;
+    cmax = std::max(cmax, c);
+    c = L.r_bound;
+    j.lv.push_back(L);
+  }
+  j.ld = ((2 * cmax + 63) / 64) * 64;
+}
+
+size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
+  const size_t dimU = (size_t)1 << (2 * j.k);
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
+  add(dimU * sizeof(double2));
+  if (ctx->prec != Prec::FP64) add(dimU * ctx->esz);
+  add(j.theta * ctx->esz);
+  add(j.theta * ctx->esz);
+  const size_t ld = j.ld;
+  add(ld * ld * sizeof(double2));  // G
+  add(ld * ld * sizeof(double2));  // V
+  add(ld * 64 * sizeof(double2));  // J
+  int ks = 1;
+  size_t vr = 0;
+  for (const auto& L : j.lv) {
+    ks = std::max(ks, L.ksplit);
+    vr = std::max(vr, (size_t)2 * L.c_bound * L.r_bound);
+  }
+  if (ks > 1) add((size_t)ks * ld * ld * sizeof(double2));
+  add(vr * ctx->esz);
+  add(ld / 64 * sizeof(int));
+  add(ld * sizeof(int));
+  add(sizeof(double));
+  add(4 * j.k * sizeof(double));
+  return b;
+}
+
+void assign_job(mps_ctx* ctx, JobRun& j) {
+  DeviceArena& A = ctx->arena;
+  const size_t dimU = (size_t)1 << (2 * j.k);
+  j.U64 = A.take(dimU * sizeof(double2));
+  j.Uw = (ctx->prec == Prec::FP64) ? j.U64 : A.take(dimU * ctx->esz);
+  j.buf[0] = A.take(j.theta * ctx->esz);
+  j.buf[1] = A.take(j.theta * ctx->esz);
+  const size_t ld = j.ld;
+  j.G = (double2*)A.take(ld * ld * sizeof(double2));
+  j.V = (double2*)A.take(ld * ld * sizeof(double2));
+  j.J = (double2*)A.take(ld * 64 * sizeof(double2));
+  int ks = 1;
+  size_t vr = 0;
+  for (const auto& L : j.lv) {
+    ks = std::max(ks, L.ksplit);
+    vr = std::max(vr, (size_t)2 * L.c_bound * L.r_bound);
+  }
+  j.part = ks > 1 ? (double2*)A.take((size_t)ks * ld * ld * sizeof(double2)) : nullptr;
+  j.Vr = A.take(vr * ctx->esz);
+  j.pair_rot = (int*)A.take(ld / 64 * sizeof(int));
+  j.perm = (int*)A.take(ld * sizeof(int));
+  j.scale = (double*)A.take(sizeof(double));
+  j.rec = (double*)A.take(4 * j.k * sizeof(double));
+}
+
+// ------------------------------------------------------------ executor --
+// Runs the given clusters (all in the same launches) plus the one-qubit site
+// updates; ends with the host synchronisation of the step.
+void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q) {
+  hipStream_t s = ctx->stream;
+  const Prec P = ctx->prec;
+  std::vector<JobRun> runs(jobs.size());
+  size_t bytes = 0;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    plan_job(ctx, jobs[i], runs[i]);
+    bytes += job_bytes(ctx, runs[i]);
+  }
+  const int nj = (int)jobs.size();
+  bytes += (size_t)nj * (sizeof(double) + 4 * sizeof(int)) + 4096;
+  ctx->arena.reset();
+  HIP_OK(ctx->arena.reserve(bytes));
+  double* logf_all = (double*)ctx->arena.take(std::max(1, nj) * sizeof(double));
+  int* flags_all = (int*)ctx->arena.take(std::max(1, nj) * 4 * sizeof(int));
+  for (int i = 0; i < nj; ++i) {
+    assign_job(ctx, runs[i]);
+    runs[i].logf = logf_all + i;
+    runs[i].flags = flags_all + 4 * i;
+    runs[i].flag_index = i;
+  }
+  if (nj) HIP_OK(hipMemsetAsync(logf_all, 0, nj * sizeof(double), s));
+
+  DescBlob& B = ctx->blob;
+  B.host.clear();
+  int kmax = 0;
+  for (auto& r : runs) kmax = std::max(kmax, r.k);
+
+  // ---- unitaries
+  std::vector<UnitaryDesc> ud;
+  std::vector<int> ubase{0};
+  size_t ulds = 0;
+  std::vector<size_t> gate_off(nj, 0);
+  for (int i = 0; i < nj; ++i) {
+    const Job& jb = jobs[i];
+    if (!jb.U.empty()) continue;
+    std::vector<UGate> ug;
+    for (const auto& g : jb.gates) {
+      UGate u{};
+      u.nq = g.nq;
+      u.q0 = g.q[0] - jb.a;
+      u.q1 = g.nq > 1 ? g.q[1] - jb.a : 0;
+      const int dd = 1 << (2 * g.nq);
+      for (int e = 0; e < dd; ++e) {
+        u.u[2 * e] = g.u[e].real();
+        u.u[2 * e + 1] = g.u[e].imag();
+      }
+      ug.push_back(u);
+    }
+    gate_off[i] = ug.empty() ? 0 : B.add_vec(ug);
+    UnitaryDesc d{};
+    d.ngates = (int)ug.size();
+    d.k = jb.k;
+    d.U64 = (double2*)runs[i].U64;
+    d.U32 = (P == Prec::FP64) ? nullptr : (float2*)runs[i].Uw;
+    const int dim = 1 << jb.k;
+    d.cols = std::max(1, std::min(16, 4096 / dim));
+    d.blocks = ceil_div(dim, d.cols);
+    ulds = std::max(ulds, (size_t)d.cols * dim * sizeof(double2));
+    ud.push_back(d);
+    ubase.push_back(ubase.back() + d.blocks);
+  }
+  std::vector<int> ud_job;
+  for (int i = 0; i < nj; ++i)
+    if (jobs[i].U.empty()) ud_job.push_back(i);
+
+  // ---- merges (j = 1..kmax-1), unitary application
+  std::vector<std::vector<GemmDesc>> mg(kmax);
+  for (auto& r : runs) {
+    for (int j = 1; j < r.k; ++j) {
+      GemmDesc d{};
+      const int M = r.chi_l << j;
+      const int K = r.mid[j - 1];
+      const int N = 2 * ((j == r.k - 1) ? r.chi_r : r.mid[j]);
+      d.A = (j == 1) ? ctx->site[r.a] : r.buf[(j - 1) & 1];
+      d.B = ctx->site[r.a + j];
+      d.C = r.buf[j & 1];
+      d.M = fixed(M);
+      d.N = fixed(N);
+      d.K = fixed(K);
+      d.lda = fixed(K);
+      d.ldb = fixed(N);
+      d.ldc = fixed(N);
+      d.batch = 1;
+      d.tm = ceil_div(M, 64);
+      d.tn = ceil_div(N, 64);
+      d.ksplit = 1;
+      d.alpha = 1.0;
+      mg[j].push_back(d);
+    }
+    r.cur = (r.k - 1) & 1;
+  }
+  std::vector<GemmDesc> ap;
+  for (auto& r : runs) {
+    GemmDesc d{};
+    const int D = 1 << r.k;
+    d.A = r.Uw;
+    d.B = r.buf[r.cur];
+    d.C = r.buf[r.cur ^ 1];
+    d.M = fixed(D);
+    d.N = fixed(r.chi_r);
+    d.K = fixed(D);
+    d.lda = fixed(D);
+    d.ldb = fixed(r.chi_r);
+    d.ldc = fixed(r.chi_r);
+    d.sA = 0;
+    d.sB = d.sC = (int64_t)D * r.chi_r;
+    d.batch = r.chi_l;
+    d.tm = ceil_div(D, 64);
+    d.tn = ceil_div(r.chi_r, 64);
+    d.ksplit = 1;
+    d.alpha = 1.0;
+    ap.push_back(d);
+    r.cur ^= 1;
+  }
+
+  auto upload_gemm = [&](const std::vector<GemmDesc>& v, size_t& off, size_t& boff) {
+    std::vector<int> base{0};
+    for (const auto& d : v) base.push_back(base.back() + gemm_tiles(d));
+    off = B.add_vec(v);
+    boff = B.add_vec(base);
+    return base.back();
+  };
+
+  // Split levels: descriptors are built for every level up front.
+  const int tmax = kmax - 1;
+  struct LevelDescs {
+    std::vector<int> jobs;
+    std::vector<GemmDesc> gram, proj;
+    std::vector<GramReduceDesc> red;
+    std::vector<EigDesc> eig;
+    std::vector<SelectDesc> sel;
+    std::vector<GatherDesc> gat;
+    size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_eig, b_pair, b_upd, o_sel, o_gat, b_gat;
+    int n_gram, n_proj, n_red, n_pair, n_upd, n_gat;
+    int nb_max_all;
+  };
+  std::vector<LevelDescs> LD(std::max(0, tmax));
+  for (int t = 0; t < tmax; ++t) {
+    LevelDescs& L = LD[t];
+    L.nb_max_all = 0;
+    for (int i = 0; i < nj; ++i) {
+      JobRun& r = runs[i];
+      if (t >= r.k - 1) continue;
+      L.jobs.push_back(i);
+      const Level& lv = r.lv[t];
+      const int m = lv.m;
+      const Dim n2c = c_dim(ctx, r, t, 2);
+      void* X = r.buf[r.cur];
+      void* Y = r.buf[r.cur ^ 1];
+      {
+        GemmDesc d{};
+        d.A = X;
+        d.B = X;
+        d.C = lv.ksplit > 1 ? (void*)r.part : (void*)r.G;
+        d.M = n2c;
+        d.N = n2c;
+        d.K = fixed(lv.rows);
+        d.lda = n2c;
+        d.ldb = n2c;
+        d.ldc = fixed(r.ld);
+        d.batch = 1;
+        d.tm = d.tn = ceil_div(2 * lv.c_bound, 64);
+        d.ksplit = lv.ksplit;
+        d.part = (int64_t)r.ld * r.ld;
+        d.w = r.a > 0 ? ctx->lam[r.a - 1] : ctx->d_ones;
+        d.wshift = m;
+        d.alpha = 1.0;
+        L.gram.push_back(d);
+        if (lv.ksplit > 1) {
+          GramReduceDesc g{};
+          g.part = r.part;
+          g.G = r.G;
+          g.n = n2c;
+          g.ld = fixed(r.ld);
+          g.ksplit = lv.ksplit;
+          g.stride = (int64_t)r.ld * r.ld;
+          const int T = ceil_div(2 * lv.c_bound, 64);
+          g.tiles = T * T;
+          L.red.push_back(g);
+        }
+      }
+      {
+        EigDesc e{};
+        e.G = r.G;
+        e.V = r.V;
+        e.J = r.J;
+        e.pair_rot = r.pair_rot;
+        e.flags = r.flags;
+        e.scale = r.scale;
+        e.n = n2c;
+        e.ld = r.ld;
+        int nb = ceil_div(2 * lv.c_bound, JB);
+        nb = std::max(nb, 2);
+        nb += nb & 1;
+        e.nb_max = nb;
+        e.tol = 1e-13;
+        L.nb_max_all = std::max(L.nb_max_all, nb);
+        L.eig.push_back(e);
+      }
+      int* r_out = ctx->d_chi + (r.a + m - 1);
+      {
+        SelectDesc sd{};
+        sd.G = r.G;
+        sd.ldg = r.ld;
+        sd.n = n2c;
+        sd.rows = lv.rows;
+        sd.chi_max = ctx->chi_max;
+        sd.eps_eff = ctx->eps_eff;
+        sd.perm = r.perm;
+        sd.r_out = r_out;
+        sd.lam_out = ctx->lam[r.a + m - 1];
+        sd.logf_acc = r.logf;
+        sd.rec = r.rec + 4 * t;
+        L.sel.push_back(sd);
+      }
+      {
+        GatherDesc g{};
+        g.V = r.V;
+        g.ldv = r.ld;
+        g.perm = r.perm;
+        g.r = r_out;
+        g.n = n2c;
+        g.B = ctx->site[r.a + m];
+        g.Vr = r.Vr;
+        g.tiles = ceil_div(lv.r_bound, 64) * ceil_div(2 * lv.c_bound, 64);
+        L.gat.push_back(g);
+      }
+      {
+        GemmDesc d{};
+        d.A = X;
+        d.B = r.Vr;
+        d.C = Y;
+        d.M = fixed(lv.rows);
+        d.K = n2c;
+        d.N = Dim{1, r_out};
+        d.lda = n2c;
+        d.ldb = Dim{1, r_out};
+        d.ldc = Dim{1, r_out};
+        d.batch = 1;
+        d.tm = ceil_div(lv.rows, 64);
+        d.tn = ceil_div(lv.r_bound, 64);
+        d.ksplit = 1;
+        d.alpha = 1.0;
+        L.proj.push_back(d);
+      }
+      r.cur ^= 1;
+    }
+  }
+  std::vector<ScaleDesc> fin;
+  std::vector<int> fbase{0};
+  for (auto& r : runs) {
+    ScaleDesc d{};
+    d.X = r.buf[r.cur];
+    d.B = ctx->site[r.a];
+    d.count = Dim{2 * r.chi_l, ctx->d_chi + r.a};
+    d.logf = r.logf;
+    const int64_t bound = (int64_t)2 * r.chi_l * std::min(ctx->chi_max, 2 * r.chi_l);
+    d.blocks = std::max(1, std::min(1024, ceil_div(bound, 256)));
+    fin.push_back(d);
+    fbase.push_back(fbase.back() + d.blocks);
+  }
+  std::vector<int> sbase{0};
+  for (const auto& d : sites1q) sbase.push_back(sbase.back() + d.blocks);
+
+  // ---- serialise descriptors
+  size_t o_ud = 0, b_ud = 0;
+  if (!ud.empty()) {
+    o_ud = B.add_vec(ud);
+    b_ud = B.add_vec(ubase);
+  }
+  std::vector<size_t> o_mg(kmax, 0), b_mg(kmax, 0);
+  std::vector<int> n_mg(kmax, 0);
+  for (int j = 1; j < kmax; ++j) n_mg[j] = upload_gemm(mg[j], o_mg[j], b_mg[j]);
+  size_t o_ap = 0, b_ap = 0;
+  const int n_ap = nj ? upload_gemm(ap, o_ap, b_ap) : 0;
+  for (auto& L : LD) {
+    L.n_gram = upload_gemm(L.gram, L.o_gram, L.b_gram);
+    L.n_proj = upload_gemm(L.proj, L.o_proj, L.b_proj);
+    L.n_red = 0;
+    if (!L.red.empty()) {
+      std::vector<int> base{0};
+      for (const auto& g : L.red) base.push_back(base.back() + g.tiles);
+      L.o_red = B.add_vec(L.red);
+      L.b_red = B.add_vec(base);
+      L.n_red = base.back();
+    }
+    std::vector<int> pb{0}, ub{0};
+    for (const auto& e : L.eig) {
+      pb.push_back(pb.back() + e.nb_max / 2);
+      ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+    }
+    L.o_eig = B.add_vec(L.eig);
+    L.b_pair = B.add_vec(pb);
+    L.b_upd = B.add_vec(ub);
+    L.n_pair = pb.back();
+    L.n_upd = ub.back();
+    L.o_sel = B.add_vec(L.sel);
+    std::vector<int> gb{0};
+    for (const auto& g : L.gat) gb.push_back(gb.back() + g.tiles);
+    L.o_gat = B.add_vec(L.gat);
+    L.b_gat = B.add_vec(gb);
+    L.n_gat = gb.back();
+  }
+  size_t o_fin = 0, b_fin = 0;
+  if (nj) {
+    o_fin = B.add_vec(fin);
+    b_fin = B.add_vec(fbase);
+  }
+  size_t o_s1 = 0, b_s1 = 0;
+  if (!sites1q.empty()) {
+    o_s1 = B.add_vec(sites1q);
+    b_s1 = B.add_vec(sbase);
+  }
+  HIP_OK(B.prepare());
+  // gate pointers of the unitary descriptors, now that the blob has a device address
+  for (size_t q = 0; q < ud.size(); ++q) {
+    UnitaryDesc* d = B.host_at<UnitaryDesc>(o_ud) + q;
+    d->gates = d->ngates ? B.at<UGate>(gate_off[ud_job[q]]) : nullptr;
+  }
+  HIP_OK(B.upload(s));
+
+  // ---- launches
+  if (!ud.empty()) {
+    Timed tm(ctx, "unitary");
+    HIP_OK(launch_build_unitary(B.at<UnitaryDesc>(o_ud), B.at<int>(b_ud), (int)ud.size(), ubase.back(), ulds, s));
+  }
+  for (int i = 0; i < nj; ++i) {
+    if (jobs[i].U.empty()) continue;
+    const size_t dimU = (size_t)1 << (2 * jobs[i].k);
+    HIP_OK(hipMemcpyAsync(runs[i].U64, jobs[i].U.data(), dimU * sizeof(double2), hipMemcpyHostToDevice, s));
+    if (P != Prec::FP64) HIP_OK(launch_convert_d2f((const double2*)runs[i].U64, (float2*)runs[i].Uw, dimU, s));
+  }
+  for (int j = 1; j < kmax; ++j) {
+    Timed tm(ctx, "merge");
+    HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(o_mg[j]), B.at<int>(b_mg[j]), (int)mg[j].size(), n_mg[j], s));
+  }
+  if (nj) {
+    Timed tm(ctx, "apply");
+    HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(o_ap), B.at<int>(b_ap), nj, n_ap, s));
+  }
+  for (int t = 0; t < tmax; ++t) {
+    LevelDescs& L = LD[t];
+    const int np = (int)L.jobs.size();
+    {
+      Timed tm(ctx, "gram");
+      HIP_OK(launch_gram(P == Prec::FP64 ? Prec::FP64 : Prec::FP32, B.at<GemmDesc>(L.o_gram),
+                         B.at<int>(L.b_gram), np, L.n_gram, s));
+    }
+    if (L.n_red) {
+      Timed tm(ctx, "gram_reduce");
+      HIP_OK(launch_gram_reduce(B.at<GramReduceDesc>(L.o_red), B.at<int>(L.b_red), (int)L.red.size(), L.n_red, s));
+    }
+    EigDesc* de = B.at<EigDesc>(L.o_eig);
+    int ldmax = 0;
+    for (const auto& e : L.eig) ldmax = std::max(ldmax, e.ld);
+    {
+      Timed tm(ctx, "eig_init");
+      HIP_OK(launch_eig_init(de, np, ldmax, s));
+    }
+    const int max_sweeps = 30;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      for (int round = 0; round < L.nb_max_all - 1; ++round) {
+        {
+          Timed tm(ctx, "eig_pairs");
+          HIP_OK(launch_eig_pairs(de, B.at<int>(L.b_pair), np, L.n_pair, round, s));
+        }
+        {
+          Timed tm(ctx, "eig_update");
+          HIP_OK(launch_eig_update(de, B.at<int>(L.b_upd), np, L.n_upd, round, s));
+        }
+      }
+      HIP_OK(launch_eig_sweep_end(de, np, s));
+      ctx->stats.jacobi_sweeps += 1;
+      HIP_OK(hipMemcpyAsync(ctx->h_flags, flags_all, (size_t)nj * 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      bool all = true;
+      for (int q : L.jobs)
+        if (!ctx->h_flags[4 * q]) all = false;
+      if (all) break;
+    }
+    {
+      Timed tm(ctx, "select");
+      HIP_OK(launch_select(B.at<SelectDesc>(L.o_sel), np, s));
+    }
+    {
+      Timed tm(ctx, "gather");
+      HIP_OK(launch_gather(P, B.at<GatherDesc>(L.o_gat), B.at<int>(L.b_gat), np, L.n_gat, s));
+    }
+    {
+      Timed tm(ctx, "project");
+      HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(L.o_proj), B.at<int>(L.b_proj), np, L.n_proj, s));
+    }
+  }
+  if (nj) {
+    Timed tm(ctx, "finalize");
+    HIP_OK(launch_finalize(P, B.at<ScaleDesc>(o_fin), B.at<int>(b_fin), nj, fbase.back(), s));
+    HIP_OK(launch_accumulate(logf_all, nj, ctx->d_logf, s));
+  }
+  if (!sites1q.empty()) {
+    Timed tm(ctx, "one_qubit");
+    HIP_OK(launch_apply_1q(P, B.at<Site1QDesc>(o_s1), B.at<int>(b_s1), (int)sites1q.size(), sbase.back(), s));
+  }
+  // ---- end of step: bond dimensions and per-SVD records back to the host
+  std::vector<double> rec;
+  size_t nrec = 0;
+  for (auto& r : runs) nrec += 4 * (r.k - 1);
+  rec.resize(nrec);
+  HIP_OK(hipMemcpyAsync(ctx->chi.data(), ctx->d_chi, (ctx->n - 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  {
+    size_t off = 0;
+    for (auto& r : runs) {
+      HIP_OK(hipMemcpyAsync(rec.data() + off, r.rec, 4 * (r.k - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      off += 4 * (r.k - 1);
+    }
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  if (ctx->timing) collect_timing(ctx);
+  for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
+  ctx->stats.cluster_updates += nj;
+  for (auto& r : runs) ctx->stats.svds += r.k - 1;
+  ctx->stats.site_updates += (int64_t)sites1q.size();
+}
+
+void run_jobs(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q) {
+  if (ctx->opt.batch == MPS_BATCH_NONE && jobs.size() > 1) {
+    for (size_t i = 0; i < jobs.size(); ++i) {
+      std::vector<Job> one{jobs[i]};
+      run_group(ctx, one, i + 1 == jobs.size() ? sites1q : std::vector<Site1QDesc>{});
+    }
+  } else {
+    run_group(ctx, jobs, sites1q);
+  }
+  ctx->stats.steps += 1;
+}
+
+// Executes one planned step from the pending sub-layers; returns the number
+// of sub-layers consumed.
+int execute_step(mps_ctx* ctx, int end_hint) {
+  std::vector<Cluster> cl;
+  const int end = plan_step(ctx->pending, 0, ctx->n, ctx->chi, ctx->opt.k_max, ctx->q_max_eff,
+                            ctx->l_max_eff, cl);
+  (void)end_hint;
+  std::vector<int> owner(ctx->n, -1);
+  for (size_t c = 0; c < cl.size(); ++c)
+    for (int q = cl[c].a; q < cl[c].a + cl[c].k; ++q) owner[q] = (int)c;
+  std::vector<Job> jobs(cl.size());
+  for (size_t c = 0; c < cl.size(); ++c) {
+    jobs[c].a = cl[c].a;
+    jobs[c].k = cl[c].k;
+  }
+  std::vector<std::array<cplx, 4>> u1(ctx->n);
+  std::vector<char> has1(ctx->n, 0);
+  for (int sl = 0; sl < end; ++sl) {
+    for (const auto& g : ctx->pending[sl]) {
+      const int o = owner[g.q[0]];
+      if (o >= 0) {
+        jobs[o].gates.push_back(g);
+      } else {
+        const int q = g.q[0];
+        if (!has1[q]) {
+          u1[q] = {cplx(1), cplx(0), cplx(0), cplx(1)};
+          has1[q] = 1;
+        }
+        const auto& m = u1[q];
+        std::array<cplx, 4> r;
+        r[0] = g.u[0] * m[0] + g.u[1] * m[2];
+        r[1] = g.u[0] * m[1] + g.u[1] * m[3];
+        r[2] = g.u[2] * m[0] + g.u[3] * m[2];
+        r[3] = g.u[2] * m[1] + g.u[3] * m[3];
+        u1[q] = r;
+      }
+    }
+  }
+  std::vector<Site1QDesc> s1;
+  for (int q = 0; q < ctx->n; ++q) {
+    if (!has1[q]) continue;
+    Site1QDesc d{};
+    d.B = ctx->site[q];
+    d.chi_l = bond_dim(ctx, q - 1);
+    d.chi_r = bond_dim(ctx, q);
+    for (int e = 0; e < 4; ++e) {
+      d.u[2 * e] = u1[q][e].real();
+      d.u[2 * e + 1] = u1[q][e].imag();
+    }
+    d.blocks = std::max(1, std::min(256, ceil_div((int64_t)d.chi_l * d.chi_r, 256)));
+    s1.push_back(d);
+  }
+  run_jobs(ctx, jobs, s1);
+  ctx->pending.erase(ctx->pending.begin(), ctx->pending.begin() + end);
+  return end;
+}
+
+void flush_all(mps_ctx* ctx) {
+  while (!ctx->pending.empty()) execute_step(ctx, 0);
+}
+
+HostGate to_host_gate(const mps_gate& g) {
+  HostGate h;
+  h.nq = g.nq;
+  h.q[0] = g.q[0];
+  h.q[1] = g.nq > 1 ? g.q[1] : g.q[0];
+  const int dd = 1 << (2 * g.nq);
+  for (int e = 0; e < 16; ++e) h.u[e] = e < dd ? cplx(g.u[2 * e], g.u[2 * e + 1]) : cplx(0);
+  return h;
+}
+
+mps_status check_gates(mps_ctx* ctx, const mps_gate* gates, int ngates, int n) {
+  std::vector<char> used(n, 0);
+  for (int i = 0; i < ngates; ++i) {
+    const mps_gate& g = gates[i];
+    if (g.nq < 1 || g.nq > 2) {
+      ctx->err = "gate with nq outside {1,2}";
+      return MPS_EINVAL;
+    }
+    for (int j = 0; j < g.nq; ++j) {
+      if (g.q[j] < 0 || g.q[j] >= n) {
+        ctx->err = "gate qubit out of range";
+        return MPS_EINVAL;
+      }
+      if (used[g.q[j]]) {
+        ctx->err = "gates of one layer must act on disjoint qubits";
+        return MPS_EINVAL;
+      }
+      used[g.q[j]] = 1;
+    }
+  }
+  return MPS_OK;
+}
+
+bool is_unitary(const std::vector<cplx>& U, int dim) {
+  for (int i = 0; i < dim; ++i)
+    for (int j = 0; j < dim; ++j) {
+      cplx s = 0;
+      for (int k = 0; k < dim; ++k) s += std::conj(U[(size_t)k * dim + i]) * U[(size_t)k * dim + j];
+      if (std::abs(s - (i == j ? cplx(1) : cplx(0))) > 1e-10) return false;
+    }
+  return true;
+}
+
+template <typename F>
+mps_status guarded(mps_ctx* ctx, F&& f) {
+  try {
+    return f();
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return MPS_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return MPS_EINVAL;
+  }
+}
+
+void destroy_ctx(mps_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->arena.release();
+  ctx->blob.release();
+  if (ctx->state_mem) (void)hipFree(ctx->state_mem);
+  if (ctx->d_chi) (void)hipFree(ctx->d_chi);
+  if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+  for (auto e : ctx->timer.pool) (void)hipEventDestroy(e);
+  for (auto& p : ctx->timer.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+mps_status mps_default_options(mps_options* opt) {
+  if (!opt) return MPS_EINVAL;
+  opt->k_max = 4;
+  opt->q_max = 0;
+  opt->l_max = 0;
+  opt->precision = MPS_PREC_FP32;
+  opt->svd_mode = MPS_SVD_EXACT;
+  opt->batch = MPS_BATCH_STEP;
+  opt->floor_c = 4.0;
+  opt->hip_stream = nullptr;
+  return MPS_OK;
+}
+
+mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mps_handle* out) {
+  if (!out || n < 2 || chi_max < 1 || chi_max > 2048 || !(eps >= 0.0)) return MPS_EINVAL;
+  *out = nullptr;
+  mps_ctx* ctx = new (std::nothrow) mps_ctx();
+  if (!ctx) return MPS_ENOMEM;
+  mps_status st = guarded(ctx, [&]() -> mps_status {
+    if (opt)
+      ctx->opt = *opt;
+    else
+      mps_default_options(&ctx->opt);
+    const mps_options& o = ctx->opt;
+    if (o.k_max < 2 || o.k_max > 12 || o.precision < 0 || o.precision > 2 || o.svd_mode < 0 ||
+        o.svd_mode > 1 || o.batch < 0 || o.batch > 1 || !(o.floor_c >= 0.0)) {
+      ctx->err = "invalid options";
+      return MPS_EINVAL;
+    }
+    if (o.precision == MPS_PREC_BF16X6) {
+      ctx->err = "BF16X6 contractions are not built in this library version";
+      return MPS_EINVAL;
+    }
+    if (o.svd_mode == MPS_SVD_LEARNED) {
+      ctx->err = "learned-sketch SVD is not built in this library version";
+      return MPS_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      (void)hipGetLastError();
+      ctx->err = "no HIP device";
+      return MPS_EDEVICE;
+    }
+    ctx->n = n;
+    ctx->chi_max = chi_max;
+    ctx->eps = eps;
+    ctx->prec = (Prec)o.precision;
+    ctx->esz = ctx->prec == Prec::FP64 ? 16 : 8;
+    const double u = ctx->prec == Prec::FP64 ? std::pow(2.0, -26.5) : std::pow(2.0, -24.0);
+    ctx->eps_eff = std::max(eps, o.floor_c * u);
+    ctx->q_max_eff = o.q_max > 0 ? o.q_max : default_q_max(o.k_max, chi_max);
+    ctx->l_max_eff = o.l_max > 0 ? o.l_max : (1 << 30);
+    if (o.hip_stream) {
+      ctx->stream = (hipStream_t)o.hip_stream;
+    } else {
+      HIP_OK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+      ctx->own_stream = true;
+    }
+    ctx->cap.resize(n - 1);
+    ctx->chi.assign(n - 1, 1);
+    for (int b = 0; b < n - 1; ++b) {
+      const int e = std::min(b + 1, n - b - 1);
+      ctx->cap[b] = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
+    }
+    std::vector<size_t> soff(n), loff(n - 1);
+    size_t total = 0;
+    auto al = [&](size_t x) {
+      const size_t o2 = (total + 255) & ~size_t(255);
+      total = o2 + x;
+      return o2;
+    };
+    for (int j = 0; j < n; ++j) {
+      const size_t cl = j > 0 ? ctx->cap[j - 1] : 1, cr = j < n - 1 ? ctx->cap[j] : 1;
+      soff[j] = al(cl * 2 * cr * ctx->esz);
+    }
+    for (int b = 0; b < n - 1; ++b) loff[b] = al(ctx->cap[b] * sizeof(double));
+    const size_t ones_off = al(2048 * sizeof(double));
+    const size_t logf_off = al(sizeof(double));
+    HIP_OK(hipMalloc(&ctx->state_mem, total));
+    HIP_OK(hipMemsetAsync(ctx->state_mem, 0, total, ctx->stream));
+    ctx->site.resize(n);
+    ctx->lam.resize(n - 1);
+    for (int j = 0; j < n; ++j) ctx->site[j] = ctx->state_mem + soff[j];
+    for (int b = 0; b < n - 1; ++b) ctx->lam[b] = (double*)(ctx->state_mem + loff[b]);
+    ctx->d_ones = (double*)(ctx->state_mem + ones_off);
+    ctx->d_logf = (double*)(ctx->state_mem + logf_off);
+    HIP_OK(hipMalloc(&ctx->d_chi, (n - 1) * sizeof(int)));
+    HIP_OK(hipHostMalloc(&ctx->h_flags, 4096 * 4 * sizeof(int), hipHostMallocDefault));
+    // |0...0>: B_j = e_0 of shape (1, 2, 1); Lambda_b = [1]; ones for edge weights
+    std::vector<double> one(2048, 1.0);
+    HIP_OK(hipMemcpyAsync(ctx->d_ones, one.data(), 2048 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const double c64[2] = {1.0, 0.0};
+    const float c32[2] = {1.f, 0.f};
+    for (int j = 0; j < n; ++j)
+      HIP_OK(hipMemcpyAsync(ctx->site[j], ctx->prec == Prec::FP64 ? (const void*)c64 : (const void*)c32,
+                            ctx->esz, hipMemcpyHostToDevice, ctx->stream));
+    for (int b = 0; b < n - 1; ++b)
+      HIP_OK(hipMemcpyAsync(ctx->lam[b], one.data(), sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ctx->d_chi, ctx->chi.data(), (n - 1) * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return MPS_OK;
+  });
+  if (st != MPS_OK) {
+    std::fprintf(stderr, "mps_create: %s\n", ctx->err.c_str());
+    destroy_ctx(ctx);
+    return st;
+  }
+  *out = ctx;
+  return MPS_OK;
+}
+
+mps_status mps_destroy(mps_handle h) {
+  destroy_ctx(h);
+  return MPS_OK;
+}
+
+mps_status mps_apply_cluster(mps_handle ctx, const int* qubits, int k, const double* U) {
+  if (!ctx || !qubits || !U || k < 1 || k > 12) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    for (int i = 0; i < k; ++i)
+      if (qubits[i] < 0 || qubits[i] >= ctx->n || (i > 0 && qubits[i] <= qubits[i - 1])) {
+        ctx->err = "qubits must be strictly ascending and in range";
+        return MPS_ESPAN;
+      }
+    const int a = qubits[0], span = qubits[k - 1] - qubits[0] + 1;
+    if (span > ctx->opt.k_max || span < 2) {
+      ctx->err = "cluster span must be in [2, k_max]";
+      return MPS_ESPAN;
+    }
+    const int dk = 1 << k;
+    std::vector<cplx> Uk((size_t)dk * dk);
+    for (size_t e = 0; e < Uk.size(); ++e) Uk[e] = cplx(U[2 * e], U[2 * e + 1]);
+    if (!is_unitary(Uk, dk)) {
+      ctx->err = "U is not unitary to 1e-10";
+      return MPS_ENOTUNITARY;
+    }
+    flush_all(ctx);
+    // embed U on the span: identity on the idle qubits (big-endian positions)
+    const int ds = 1 << span;
+    std::vector<int> pos(k);
+    for (int i = 0; i < k; ++i) pos[i] = span - 1 - (qubits[i] - a);  // bit of qubit i
+    int idle_mask = ds - 1;
+    for (int i = 0; i < k; ++i) idle_mask &= ~(1 << pos[i]);
+    auto sub = [&](int x) {
+      int r = 0;
+      for (int i = 0; i < k; ++i) r = (r << 1) | ((x >> pos[i]) & 1);
+      return r;
+    };
+    Job job;
+    job.a = a;
+    job.k = span;
+    job.U.assign((size_t)ds * ds, cplx(0));
+    for (int i = 0; i < ds; ++i)
+      for (int j = 0; j < ds; ++j)
+        if ((i & idle_mask) == (j & idle_mask)) job.U[(size_t)i * ds + j] = Uk[(size_t)sub(i) * dk + sub(j)];
+    std::vector<Job> jobs{job};
+    run_jobs(ctx, jobs, {});
+    return MPS_OK;
+  });
+}
+
+mps_status mps_run_layer(mps_handle ctx, const mps_gate* gates, int ngates) {
+  if (!ctx || ngates < 0 || (ngates > 0 && !gates)) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    const mps_status st = check_gates(ctx, gates, ngates, ctx->n);
+    if (st != MPS_OK) return st;
+    std::vector<HostGate> layer;
+    for (int i = 0; i < ngates; ++i) layer.push_back(to_host_gate(gates[i]));
+    legalize_layer(layer, ctx->opt.k_max, ctx->pending);
+    // execute every step that can no longer grow
+    while (!ctx->pending.empty()) {
+      std::vector<Cluster> cl;
+      const int end = plan_step(ctx->pending, 0, ctx->n, ctx->chi, ctx->opt.k_max, ctx->q_max_eff,
+                                ctx->l_max_eff, cl);
+      if (end >= (int)ctx->pending.size()) break;
+      execute_step(ctx, end);
+    }
+    return MPS_OK;
+  });
+}
+
+mps_status mps_flush(mps_handle ctx) {
+  if (!ctx) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    flush_all(ctx);
+    return MPS_OK;
+  });
+}
+
+mps_status mps_fidelity(mps_handle ctx, double* F_est, double* log_f) {
+  if (!ctx) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    flush_all(ctx);
+    double lf = 0;
+    HIP_OK(hipMemcpyAsync(&lf, ctx->d_logf, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    if (F_est) *F_est = std::exp(lf);
+    if (log_f) *log_f = lf;
+    return MPS_OK;
+  });
+}
+
+mps_status mps_bond_dims(mps_handle ctx, int* chi) {
+  if (!ctx || !chi) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    std::memcpy(chi, ctx->chi.data(), (ctx->n - 1) * sizeof(int));
+    return MPS_OK;
+  });
+}
+
+mps_status mps_schmidt(mps_handle ctx, int bond, double* sigma, int cap, int* len) {
+  if (!ctx || bond < 0 || bond >= ctx->n - 1 || !len) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    const int c = ctx->chi[bond];
+    *len = c;
+    if (sigma && cap > 0)
+      HIP_OK(hipMemcpy(sigma, ctx->lam[bond], std::min(c, cap) * sizeof(double), hipMemcpyDeviceToHost));
+    return MPS_OK;
+  });
+}
+
+mps_status mps_export_site(mps_handle ctx, int site, double* Bout, int64_t cap, int* dims) {
+  if (!ctx || site < 0 || site >= ctx->n || !dims) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    const int cl = bond_dim(ctx, site - 1), cr = bond_dim(ctx, site);
+    dims[0] = cl;
+    dims[1] = 2;
+    dims[2] = cr;
+    const int64_t cnt = (int64_t)cl * 2 * cr;
+    if (!Bout) return MPS_OK;
+    if (cap < cnt) {
+      ctx->err = "export buffer too small";
+      return MPS_EINVAL;
+    }
+    if (ctx->prec == Prec::FP64) {
+      HIP_OK(hipMemcpy(Bout, ctx->site[site], cnt * 16, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(2 * cnt);
+      HIP_OK(hipMemcpy(tmp.data(), ctx->site[site], cnt * 8, hipMemcpyDeviceToHost));
+      for (int64_t e = 0; e < 2 * cnt; ++e) Bout[e] = tmp[e];
+    }
+    return MPS_OK;
+  });
+}
+
+mps_status mps_import(mps_handle ctx, const int* chi, const double* const* sites, const double* const* lams,
+                      double log_f) {
+  if (!ctx || !chi || !sites || !lams) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    for (int b = 0; b < ctx->n - 1; ++b)
+      if (chi[b] < 1 || chi[b] > ctx->cap[b]) {
+        ctx->err = "bond dimension exceeds capacity";
+        return MPS_EINVAL;
+      }
+    flush_all(ctx);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    for (int b = 0; b < ctx->n - 1; ++b) ctx->chi[b] = chi[b];
+    for (int j = 0; j < ctx->n; ++j) {
+      const int64_t cnt = (int64_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j);
+      if (ctx->prec == Prec::FP64) {
+        HIP_OK(hipMemcpy(ctx->site[j], sites[j], cnt * 16, hipMemcpyHostToDevice));
+      } else {
+        std::vector<float> tmp(2 * cnt);
+        for (int64_t e = 0; e < 2 * cnt; ++e) tmp[e] = (float)sites[j][e];
+        HIP_OK(hipMemcpy(ctx->site[j], tmp.data(), cnt * 8, hipMemcpyHostToDevice));
+      }
+    }
+    for (int b = 0; b < ctx->n - 1; ++b)
+      HIP_OK(hipMemcpy(ctx->lam[b], lams[b], chi[b] * sizeof(double), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(ctx->d_chi, ctx->chi.data(), (ctx->n - 1) * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice));
+    return MPS_OK;
+  });
+}
+
+mps_status mps_amplitudes(mps_handle ctx, double* psi, int64_t cap) {
+  if (!ctx || !psi || ctx->n > 24 || cap < ((int64_t)1 << ctx->n)) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    flush_all(ctx);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    // host contraction B_0 B_1 ... B_{n-1} in FP64 (a read-out for tests)
+    std::vector<cplx> cur(2), nxt;
+    int cols = 1;
+    int64_t rows = 1;
+    std::vector<double> buf;
+    for (int j = 0; j < ctx->n; ++j) {
+      int dims[3];
+      const int cl = bond_dim(ctx, j - 1), cr = bond_dim(ctx, j);
+      buf.assign((size_t)2 * cl * 2 * cr, 0.0);
+      mps_status st = mps_export_site(ctx, j, buf.data(), (int64_t)cl * 2 * cr, dims);
+      if (st != MPS_OK) return st;
+      if (j == 0) {
+        cur.assign((size_t)2 * cr, cplx(0));
+        for (int e = 0; e < 2 * cr; ++e) cur[e] = cplx(buf[2 * e], buf[2 * e + 1]);
+        rows = 2;
+        cols = cr;
+        continue;
+      }
+      nxt.assign((size_t)rows * 2 * cr, cplx(0));
+      for (int64_t r = 0; r < rows; ++r)
+        for (int l = 0; l < cl; ++l) {
+          const cplx x = cur[(size_t)r * cols + l];
+          if (x == cplx(0)) continue;
+          for (int e = 0; e < 2 * cr; ++e)
+            nxt[(size_t)r * 2 * cr + e] += x * cplx(buf[2 * ((size_t)l * 2 * cr + e)], buf[2 * ((size_t)l * 2 * cr + e) + 1]);
+        }
+      rows *= 2;
+      cols = cr;
+      cur.swap(nxt);
+    }
+    for (int64_t i = 0; i < rows; ++i) {
+      psi[2 * i] = cur[i].real();
+      psi[2 * i + 1] = cur[i].imag();
+    }
+    return MPS_OK;
+  });
+}
+
+mps_status mps_get_stats(mps_handle ctx, mps_stats* st) {
+  if (!ctx || !st) return MPS_EINVAL;
+  *st = ctx->stats;
+  return MPS_OK;
+}
+
+mps_status mps_set_timing(mps_handle ctx, int on) {
+  if (!ctx) return MPS_EINVAL;
+  ctx->timing = on != 0;
+  return MPS_OK;
+}
+
+mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, int cap, char* names, int names_cap,
+                            int* count) {
+  if (!ctx || !count) return MPS_EINVAL;
+  const int c = (int)ctx->timer.names.size();
+  *count = c;
+  std::string all;
+  for (int i = 0; i < c; ++i) {
+    if (i < cap) {
+      if (ms) ms[i] = ctx->timer.ms[i];
+      if (launches) launches[i] = ctx->timer.launches[i];
+    }
+    all += (i ? "," : "") + ctx->timer.names[i];
+  }
+  if (names && names_cap > 0) {
+    std::strncpy(names, all.c_str(), names_cap - 1);
+    names[names_cap - 1] = 0;
+  }
+  return MPS_OK;
+}
+
+const char* mps_last_error(mps_handle ctx) { return ctx ? ctx->err.c_str() : "null handle"; }
+
+mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi, const mps_gate* gates,
+                    const int* layer_len, int nl, int start, int* out_end, int* out_clusters, int cap,
+                    int* out_count, int* n_sub) {
+  if (n < 2 || k_max < 2 || !chi || !layer_len || nl < 0 || !out_end || !out_count) return MPS_EINVAL;
+  try {
+    std::vector<SubLayer> subs;
+    int off = 0;
+    for (int l = 0; l < nl; ++l) {
+      std::vector<HostGate> layer;
+      for (int i = 0; i < layer_len[l]; ++i) layer.push_back(to_host_gate(gates[off + i]));
+      off += layer_len[l];
+      legalize_layer(layer, k_max, subs);
+    }
+    if (n_sub) *n_sub = (int)subs.size();
+    if (start < 0 || start >= (int)subs.size()) {
+      *out_end = start;
+      *out_count = 0;
+      return subs.empty() ? MPS_OK : MPS_EINVAL;
+    }
+    std::vector<int> ch(chi, chi + n - 1);
+    std::vector<Cluster> cl;
+    const int qm = q_max > 0 ? q_max : 62;
+    const int lm = l_max > 0 ? l_max : (1 << 30);
+    *out_end = plan_step(subs, start, n, ch, k_max, qm, lm, cl);
+    *out_count = (int)cl.size();
+    for (int i = 0; i < (int)cl.size() && i < cap; ++i) {
+      out_clusters[2 * i] = cl[i].a;
+      out_clusters[2 * i + 1] = cl[i].k;
+    }
+    return MPS_OK;
+  } catch (...) {
+    return MPS_EINVAL;
+  }
+}
+
+}  // extern "C"

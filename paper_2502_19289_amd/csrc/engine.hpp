@@ -1,0 +1,113 @@
+// Handle state and step executor of the cluster-TEBD library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <complex>
+#include <cstring>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cluster_tebd.h"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+namespace ctebd {
+
+// Bump allocator over one device allocation; reset at every step.  Grows (by
+// reallocation, only between steps) when a step needs more than it holds.
+struct DeviceArena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  hipError_t reserve(size_t bytes);
+  void reset() { used = 0; }
+  void* take(size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    return base + off;
+  }
+  void release();
+};
+
+// Host-side blob of descriptors uploaded once per step (pinned host staging).
+struct DescBlob {
+  std::vector<char> host;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  size_t add(const void* p, size_t bytes) {
+    const size_t off = (host.size() + 15) & ~size_t(15);
+    host.resize(off + bytes);
+    memcpy(host.data() + off, p, bytes);
+    return off;
+  }
+  template <typename T>
+  size_t add_vec(const std::vector<T>& v) {
+    return add(v.data(), v.size() * sizeof(T));
+  }
+  hipError_t prepare();  // sizes the pinned and device buffers to the blob
+  hipError_t upload(hipStream_t s);
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(dev + off);
+  }
+  template <typename T>
+  T* host_at(size_t off) {
+    return reinterpret_cast<T*>(host.data() + off);
+  }
+  void release();
+};
+
+// A cluster to contract and split: sites a..a+k-1 and either the gates that
+// make its unitary or an explicit unitary.
+struct Job {
+  int a = 0, k = 0;
+  std::vector<HostGate> gates;
+  std::vector<std::complex<double>> U;  // explicit 2^k x 2^k, row-major (if non-empty)
+};
+
+struct KernelTimer {
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<int64_t> launches;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  int cls_of(const char* name);
+};
+
+}  // namespace ctebd
+
+struct mps_ctx {
+  int n = 0, chi_max = 1;
+  double eps = 0.0;
+  mps_options opt{};
+  ctebd::Prec prec = ctebd::Prec::FP32;
+  size_t esz = 8;  // bytes per complex entry of the site tensors
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<int> cap;             // bond capacity (n-1)
+  std::vector<int> chi;             // host mirror of bond dimensions (n-1)
+  std::vector<void*> site;          // per-site device tensors
+  std::vector<double*> lam;         // per-bond Schmidt values (device)
+  char* state_mem = nullptr;        // one allocation holding sites and lambdas
+  int* d_chi = nullptr;             // device bond dimensions (n-1)
+  double* d_logf = nullptr;         // device sum log f
+  double* d_ones = nullptr;         // weights of a left edge (all ones)
+  int ones_len = 0;
+  ctebd::DeviceArena arena;
+  ctebd::DescBlob blob;
+  int* h_flags = nullptr;           // pinned: eigen convergence flags
+  std::vector<ctebd::SubLayer> pending;
+  mps_stats stats{};
+  std::string err;
+  bool timing = false;
+  ctebd::KernelTimer timer;
+  int q_max_eff = 0, l_max_eff = 0;
+  double eps_eff = 0.0;
+};

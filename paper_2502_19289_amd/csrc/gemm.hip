@@ -1,0 +1,213 @@
+// Grouped complex GEMMs on the matrix cores (FP32 and FP64 MFMA 16x16x4).
+//
+// Used for the block merge Theta_j = Theta_{j-1} B_j, the application of the
+// cluster unitary Theta'_l = U Theta_l (batched over the left bond index l),
+// the projection X <- X V_r of the split sweep, and the FP64 Gram matrix
+// G = X^H D^2 X of every truncated SVD (arXiv:2502.19289, Secs. II.B, III.A).
+//
+// Tiling: a 256-thread workgroup computes a 64x64 complex output tile; its four
+// wavefronts own 32x32 quadrants made of 2x2 MFMA blocks.  K advances in slices
+// of 16 staged in LDS k-major (As[k][m], Bs[k][n]) so that the sixteen lanes
+// that share a k read consecutive addresses.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+namespace ctebd {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+enum { MODE_NN = 0, MODE_GRAM = 1 };
+
+template <typename CI, typename TM>
+__device__ __forceinline__ typename cpx_of<TM>::type load_c(const CI* p) {
+  const CI v = *p;
+  typename cpx_of<TM>::type r;
+  r.x = (TM)v.x;
+  r.y = (TM)v.y;
+  return r;
+}
+
+template <typename CI, typename CO, typename TM, int MODE>
+__global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ descs,
+                                                   const int* __restrict__ base, int nprob) {
+  using CM = typename cpx_of<TM>::type;
+  __shared__ CM As[BK][BM];
+  __shared__ CM Bs[BK][BN];
+
+  const int p = find_problem(base, nprob, blockIdx.x);
+  const GemmDesc& d = descs[p];
+  int t = blockIdx.x - base[p];
+  const int M = dim_value(d.M), N = dim_value(d.N), K = dim_value(d.K);
+  const int lda = dim_value(d.lda), ldb = dim_value(d.ldb), ldc = dim_value(d.ldc);
+  const int tj = t % d.tn;
+  t /= d.tn;
+  const int ti = t % d.tm;
+  t /= d.tm;
+  const int split = t % d.ksplit;
+  const int b = t / d.ksplit;
+  const int m0 = ti * BM, n0 = tj * BN;
+  if (b >= d.batch || m0 >= M || n0 >= N) return;
+  if (MODE == MODE_GRAM && ti > tj) return;
+
+  const CI* A = (const CI*)d.A + (int64_t)b * d.sA;
+  const CI* Bm = (const CI*)d.B + (int64_t)b * d.sB;
+  CO* C = (CO*)d.C + (int64_t)b * d.sC + (int64_t)split * d.part;
+
+  int kbeg = 0, kend = K;
+  if (d.ksplit > 1) {
+    const int kc = ((K + d.ksplit - 1) / d.ksplit + BK - 1) / BK * BK;
+    kbeg = split * kc;
+    kend = min(K, kbeg + kc);
+  }
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  CAcc<TM> acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j].clear();
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // ---- stage A (BM x BK) k-major and B (BK x BN)
+    if (MODE == MODE_NN) {
+      const int r = tid >> 2, c4 = (tid & 3) * 4;
+      const int gm = m0 + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gk = k0 + c4 + i;
+        CM v;
+        v.x = 0;
+        v.y = 0;
+        if (gm < M && gk < kend) v = load_c<CI, TM>(A + (int64_t)gm * lda + gk);
+        As[c4 + i][r] = v;
+      }
+      const int kk = tid >> 4, n4 = (tid & 15) * 4;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gn = n0 + n4 + i;
+        CM v;
+        v.x = 0;
+        v.y = 0;
+        if (gk < kend && gn < N) v = load_c<CI, TM>(Bm + (int64_t)gk * ldb + gn);
+        Bs[kk][n4 + i] = v;
+      }
+    } else {
+      const int kk = tid >> 4, c4 = (tid & 15) * 4;
+      const int gk = k0 + kk;
+      const TM wk = (gk < kend) ? (TM)d.w[gk >> d.wshift] : (TM)0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + c4 + i, gn = n0 + c4 + i;
+        CM va, vb;
+        va.x = va.y = vb.x = vb.y = 0;
+        if (gk < kend && gm < M) {
+          va = load_c<CI, TM>(A + (int64_t)gk * lda + gm);
+          va.x *= wk;
+          va.y = -va.y * wk;
+        }
+        if (gk < kend && gn < N) {
+          vb = load_c<CI, TM>(A + (int64_t)gk * lda + gn);
+          vb.x *= wk;
+          vb.y *= wk;
+        }
+        As[kk][c4 + i] = va;
+        Bs[kk][c4 + i] = vb;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      CM a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
+      CM b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
+      acc[0][0].mac(a0.x, a0.y, b0.x, b0.y);
+      acc[0][1].mac(a0.x, a0.y, b1.x, b1.y);
+      acc[1][0].mac(a1.x, a1.y, b0.x, b0.y);
+      acc[1][1].mac(a1.x, a1.y, b1.x, b1.y);
+    }
+    __syncthreads();
+  }
+
+  const TM alpha = (TM)d.alpha;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + bi * 16 + Mfma<TM>::row(lane, r);
+        const int gn = n0 + wn * 32 + bj * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          CO v;
+          v.x = acc[bi][bj].re[r] * alpha;
+          v.y = acc[bi][bj].im[r] * alpha;
+          C[(int64_t)gm * ldc + gn] = v;
+          // a Gram matrix without split-K is complete here: mirror it
+          if (MODE == MODE_GRAM && d.ksplit == 1 && ti < tj) {
+            v.y = -v.y;
+            C[(int64_t)gn * ldc + gm] = v;
+          }
+        }
+      }
+}
+
+// Sums the split-K partial Gram matrices and fills the lower triangle from
+// the upper one (G is Hermitian).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const GramReduceDesc* __restrict__ descs,
+                                                          const int* __restrict__ base, int nprob) {
+  const int p = find_problem(base, nprob, blockIdx.x);
+  const GramReduceDesc& d = descs[p];
+  const int n = dim_value(d.n), ld = dim_value(d.ld);
+  const int t = blockIdx.x - base[p];
+  const int nt = (n + 63) / 64;
+  const int ti = t / nt, tj = t % nt;
+  if (ti >= nt || ti > tj) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int i = ti * 64 + (e >> 6), j = tj * 64 + (e & 63);
+    if (i >= n || j >= n) continue;
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = 0; q < d.ksplit; ++q) s = cadd(s, d.part[(int64_t)q * d.stride + (int64_t)i * ld + j]);
+    d.G[(int64_t)i * ld + j] = s;
+    if (ti < tj) d.G[(int64_t)j * ld + i] = make_double2(s.x, -s.y);
+  }
+}
+
+}  // namespace
+
+int gemm_tiles(const GemmDesc& d) { return d.tm * d.tn * d.ksplit * d.batch; }
+
+hipError_t launch_gemm_nn(Prec p, const GemmDesc* d_desc, const int* d_base, int nprob, int blocks,
+                          hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (p == Prec::FP64)
+    cgemm_kernel<double2, double2, double, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  else
+    cgemm_kernel<float2, float2, float, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, int nprob, int blocks,
+                       hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (in_prec == Prec::FP64)
+    cgemm_kernel<double2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  else
+    cgemm_kernel<float2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const GramReduceDesc* d_desc, const int* d_base, int nprob, int blocks,
+                              hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  gram_reduce_kernel<<<blocks, 256, 0, s>>>(d_desc, d_base, nprob);
+  return hipGetLastError();
+}
+
+}  // namespace ctebd

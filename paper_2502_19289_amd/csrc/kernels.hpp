@@ -1,0 +1,156 @@
+// Descriptors and launchers of the device kernels (all grouped: one launch
+// serves a list of independent problems, one workgroup per output tile).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace ctebd {
+
+// ---------------------------------------------------------------- GEMM ----
+// C = alpha * A * B                         (mode NN)
+// C = (W X)^H (W X), W = diag(w[row>>wshift])  (mode GRAM: A = B = X, FP64 out,
+//                                            tiles with ti <= tj only, mirrored)
+// Row-major complex matrices; batch b offsets A, B, C by b*sA, b*sB, b*sC.
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  Dim M, N, K, lda, ldb, ldc;
+  int64_t sA, sB, sC;
+  int batch;
+  int tm, tn;       // tile counts the grid reserves (upper bounds)
+  int ksplit;       // GRAM: K is cut into ksplit slices written to C + s*part
+  int64_t part;     // element stride between the partial results of slices
+  const double* w;  // GRAM row weights
+  int wshift;
+  double alpha;
+};
+
+struct GramReduceDesc {
+  const double2* part;  // ksplit partial results, stride `part` elements
+  double2* G;
+  Dim n, ld;
+  int ksplit;
+  int64_t stride;
+  int tiles;            // element tiles of 64x64 reserved by the grid
+};
+
+enum class Prec : int { FP64 = 0, FP32 = 1, BF16X6 = 2 };
+
+int gemm_tiles(const GemmDesc& d);  // blocks one problem needs
+
+// Launches over `nprob` descriptors already in device memory (d_desc) with
+// per-problem block offsets d_base (exclusive prefix, nprob+1 entries).
+hipError_t launch_gemm_nn(Prec p, const GemmDesc* d_desc, const int* d_base, int nprob, int blocks,
+                          hipStream_t s);
+hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, int nprob,
+                       int blocks, hipStream_t s);
+hipError_t launch_gram_reduce(const GramReduceDesc* d_desc, const int* d_base, int nprob, int blocks,
+                              hipStream_t s);
+
+// ------------------------------------------------------ eigen (Jacobi) ----
+constexpr int JB = 32;        // Jacobi block size: subproblems are 2*JB square
+constexpr int JP = 2 * JB;    // subproblem / update-tile size
+
+struct EigDesc {
+  double2* G;       // Hermitian matrix, ld x ld, overwritten (-> diagonal)
+  double2* V;       // eigenvectors (columns), ld x ld
+  double2* J;       // workspace: npair_max subproblem rotations of JP x JP
+  int* pair_rot;    // per pair slot: rotation applied this round
+  int* flags;       // [0] converged, [1] rotated during the current sweep
+  double* scale;    // trace of G (set by eig_init)
+  Dim n;            // matrix size
+  int ld;
+  int nb_max;       // block count the grids reserve (even)
+  double tol;       // relative off-diagonal threshold
+};
+
+hipError_t launch_eig_init(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
+hipError_t launch_eig_pairs(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+                            hipStream_t s);
+hipError_t launch_eig_update(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+                             hipStream_t s);
+hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s);
+
+// ------------------------------------------------------- site kernels ----
+// Truncation selection for one split (one workgroup per problem).
+struct SelectDesc {
+  const double2* G;     // diagonalised Gram matrix (eigenvalues on the diagonal)
+  int ldg;
+  Dim n;                // 2c
+  int rows;             // chi_l 2^m: rank bound of X
+  int chi_max;
+  double eps_eff;       // threshold on normalised singular values
+  int* perm;            // out: eigenvalue order, descending (n entries)
+  int* r_out;           // out: kept rank (also the new bond dimension)
+  double* lam_out;      // out: normalised kept singular values (Lambda)
+  double* logf_acc;     // in/out: this cluster's sum of log f
+  double* rec;          // out: [f, sigma_r/sigma_1, discarded weight, degenerate]
+};
+hipError_t launch_select(const SelectDesc* d, int nprob, hipStream_t s);
+
+// B_site[i][col] = conj(V[col][perm[i]]) and Vr[col][i] = V[col][perm[i]]
+struct GatherDesc {
+  const double2* V;
+  int ldv;
+  const int* perm;
+  const int* r;
+  Dim n;            // rows of V used (2c)
+  void* B;          // site tensor (r x n) in working precision
+  void* Vr;         // projection matrix (n x r) in working precision
+  int tiles;        // 64 x 64 element tiles reserved
+};
+hipError_t launch_gather(Prec p, const GatherDesc* d, const int* d_base, int nprob, int blocks,
+                         hipStream_t s);
+
+// B_a = X / sqrt(exp(logf)) over `count` complex entries (count may be dynamic)
+struct ScaleDesc {
+  const void* X;
+  void* B;
+  Dim count;
+  const double* logf;
+  int blocks;
+};
+hipError_t launch_finalize(Prec p, const ScaleDesc* d, const int* d_base, int nprob, int blocks,
+                           hipStream_t s);
+
+// One-qubit gate products on sites outside every cluster.
+struct Site1QDesc {
+  void* B;
+  int chi_l, chi_r;
+  double u[8];  // 2x2 complex
+  int blocks;
+};
+hipError_t launch_apply_1q(Prec p, const Site1QDesc* d, const int* d_base, int nprob, int blocks,
+                           hipStream_t s);
+
+// Cluster unitaries from gate lists: U = G_last ... G_first on k local qubits.
+struct UGate {
+  int nq;
+  int q0, q1;     // local positions (q0 is the most significant of the gate)
+  int pad;
+  double u[32];   // 2^nq x 2^nq complex, row-major
+};
+struct UnitaryDesc {
+  const UGate* gates;
+  int ngates;
+  int k;
+  double2* U64;  // out: 2^k x 2^k FP64
+  float2* U32;   // out (optional): the same in FP32
+  int cols;      // columns per workgroup (cols * 2^k * 16 bytes of LDS)
+  int blocks;    // column blocks
+};
+// lds_bytes: largest cols * 2^k * sizeof(double2) over the problems (<= 64 KiB)
+hipError_t launch_build_unitary(const UnitaryDesc* d, const int* d_base, int nprob, int blocks,
+                                size_t lds_bytes, hipStream_t s);
+
+// Merge-kernel helper: copy with conversion (FP64 user unitary -> work precision)
+hipError_t launch_convert_d2f(const double2* src, float2* dst, int64_t n, hipStream_t s);
+
+// Log-f accumulation in a fixed order (deterministic): total += sum_i v[i]
+hipError_t launch_accumulate(const double* v, int n, double* total, hipStream_t s);
+
+}  // namespace ctebd

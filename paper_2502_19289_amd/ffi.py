@@ -1,0 +1,242 @@
+"""ctypes binding of libctebd.so (argument marshalling only).
+
+Every function of include/cluster_tebd.h is exposed with the same name; the
+``MPS`` class wraps a handle.  The library is loaded from this package's
+directory; importing fails loudly when it has not been built (there is no
+fallback implementation).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctebd.so")
+
+MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ESPAN, MPS_ENOTUNITARY, MPS_EDEVICE, MPS_ESTATE, MPS_EIO = \
+    0, -1, -2, -3, -4, -5, -6, -7
+PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2}
+SVD = {"exact": 0, "learned": 1}
+BATCH = {"none": 0, "step": 1}
+
+
+class Options(C.Structure):
+    _fields_ = [("k_max", C.c_int), ("q_max", C.c_int), ("l_max", C.c_int),
+                ("precision", C.c_int), ("svd_mode", C.c_int), ("batch", C.c_int),
+                ("floor_c", C.c_double), ("hip_stream", C.c_void_p)]
+
+
+class GateC(C.Structure):
+    _fields_ = [("nq", C.c_int), ("q", C.c_int * 2), ("u", C.c_double * 32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("cluster_updates", C.c_int64), ("svds", C.c_int64),
+                ("site_updates", C.c_int64), ("sketch_accepted", C.c_int64),
+                ("sketch_fallback", C.c_int64), ("jacobi_sweeps", C.c_int64),
+                ("discarded_weight", C.c_double)]
+
+
+class CtebdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster",
+           "mps_run_layer", "mps_flush", "mps_fidelity", "mps_bond_dims", "mps_schmidt",
+           "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
+           "mps_set_timing", "mps_kernel_times", "mps_last_error", "mps_plan"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2502_19289_amd.build`")
+    lib = C.CDLL(path)
+    P, I, D = C.c_void_p, C.c_int, C.c_double
+    lib.mps_default_options.argtypes = [C.POINTER(Options)]
+    lib.mps_create.argtypes = [I, I, D, C.POINTER(Options), C.POINTER(P)]
+    lib.mps_destroy.argtypes = [P]
+    lib.mps_apply_cluster.argtypes = [P, C.POINTER(I), I, C.POINTER(D)]
+    lib.mps_run_layer.argtypes = [P, C.POINTER(GateC), I]
+    lib.mps_flush.argtypes = [P]
+    lib.mps_fidelity.argtypes = [P, C.POINTER(D), C.POINTER(D)]
+    lib.mps_bond_dims.argtypes = [P, C.POINTER(I)]
+    lib.mps_schmidt.argtypes = [P, I, C.POINTER(D), I, C.POINTER(I)]
+    lib.mps_export_site.argtypes = [P, I, C.POINTER(D), C.c_int64, C.POINTER(I)]
+    lib.mps_import.argtypes = [P, C.POINTER(I), C.POINTER(C.POINTER(D)), C.POINTER(C.POINTER(D)), D]
+    lib.mps_amplitudes.argtypes = [P, C.POINTER(D), C.c_int64]
+    lib.mps_get_stats.argtypes = [P, C.POINTER(Stats)]
+    lib.mps_set_timing.argtypes = [P, I]
+    lib.mps_kernel_times.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int64), I, C.c_char_p, I, C.POINTER(I)]
+    lib.mps_last_error.argtypes = [P]
+    lib.mps_last_error.restype = C.c_char_p
+    lib.mps_plan.argtypes = [I, I, I, I, C.POINTER(I), C.POINTER(GateC), C.POINTER(I), I, I,
+                             C.POINTER(I), C.POINTER(I), I, C.POINTER(I), C.POINTER(I)]
+    for name in EXPORTS:
+        if name != "mps_last_error":
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def make_gates(gates: Iterable[Tuple[Sequence[int], np.ndarray]]):
+    """[(qubits, matrix)] -> ctypes array of GateC."""
+    gl = list(gates)
+    arr = (GateC * max(1, len(gl)))()
+    for i, (q, u) in enumerate(gl):
+        u = np.asarray(u, dtype=np.complex128)
+        arr[i].nq = len(q)
+        for j, qq in enumerate(q):
+            arr[i].q[j] = int(qq)
+        flat = np.zeros(32)
+        v = u.reshape(-1)
+        flat[0:2 * v.size:2] = v.real
+        flat[1:2 * v.size:2] = v.imag
+        arr[i].u[:] = flat.tolist()
+    return arr, len(gl)
+
+
+def default_options() -> Options:
+    o = Options()
+    load().mps_default_options(C.byref(o))
+    return o
+
+
+class MPS:
+    """An n-qubit MPS living on the GPU (handle of libctebd.so)."""
+
+    def __init__(self, n: int, chi_max: int, eps: float, k_max: int = 4, precision: str = "fp32",
+                 batch: str = "step", svd: str = "exact", q_max: int = 0, l_max: int = 0,
+                 floor_c: float = 4.0, hip_stream: Optional[int] = None):
+        self.lib = load()
+        o = default_options()
+        o.k_max, o.q_max, o.l_max = k_max, q_max, l_max
+        o.precision, o.batch, o.svd_mode = PREC[precision], BATCH[batch], SVD[svd]
+        o.floor_c = floor_c
+        o.hip_stream = hip_stream
+        h = C.c_void_p()
+        st = self.lib.mps_create(n, chi_max, eps, C.byref(o), C.byref(h))
+        if st != MPS_OK:
+            raise CtebdError(st, "mps_create failed")
+        self.h = h
+        self.n = n
+
+    def _check(self, st: int):
+        if st != MPS_OK:
+            raise CtebdError(st, self.lib.mps_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_cluster(self, qubits: Sequence[int], U: np.ndarray):
+        q = np.ascontiguousarray(qubits, dtype=np.int32)
+        u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128)).view(np.float64)
+        self._check(self.lib.mps_apply_cluster(self.h, _iptr(q), len(q), _dptr(u)))
+
+    def run_layer(self, gates: Iterable[Tuple[Sequence[int], np.ndarray]]):
+        arr, ng = make_gates(gates)
+        self._check(self.lib.mps_run_layer(self.h, arr, ng))
+
+    def flush(self):
+        self._check(self.lib.mps_flush(self.h))
+
+    def fidelity(self) -> Tuple[float, float]:
+        f, lf = C.c_double(), C.c_double()
+        self._check(self.lib.mps_fidelity(self.h, C.byref(f), C.byref(lf)))
+        return f.value, lf.value
+
+    def bond_dims(self) -> List[int]:
+        a = np.zeros(self.n - 1, dtype=np.int32)
+        self._check(self.lib.mps_bond_dims(self.h, _iptr(a)))
+        return a.tolist()
+
+    def schmidt(self, bond: int) -> np.ndarray:
+        ln = C.c_int()
+        self._check(self.lib.mps_schmidt(self.h, bond, None, 0, C.byref(ln)))
+        a = np.zeros(max(1, ln.value))
+        self._check(self.lib.mps_schmidt(self.h, bond, _dptr(a), a.size, C.byref(ln)))
+        return a[: ln.value]
+
+    def site(self, j: int) -> np.ndarray:
+        dims = np.zeros(3, dtype=np.int32)
+        self._check(self.lib.mps_export_site(self.h, j, None, 0, _iptr(dims)))
+        cnt = int(dims[0]) * 2 * int(dims[2])
+        buf = np.zeros(2 * cnt)
+        self._check(self.lib.mps_export_site(self.h, j, _dptr(buf), cnt, _iptr(dims)))
+        return buf.view(np.complex128).reshape(int(dims[0]), 2, int(dims[2]))
+
+    def sites(self) -> List[np.ndarray]:
+        return [self.site(j) for j in range(self.n)]
+
+    def import_state(self, B: Sequence[np.ndarray], lam: Sequence[np.ndarray], log_f: float = 0.0):
+        chi = np.array([b.shape[2] for b in B[:-1]], dtype=np.int32)
+        sb = [np.ascontiguousarray(np.asarray(b, dtype=np.complex128)).view(np.float64) for b in B]
+        lb = [np.ascontiguousarray(np.asarray(l, dtype=np.float64)) for l in lam]
+        sp = (C.POINTER(C.c_double) * len(sb))(*[_dptr(x) for x in sb])
+        lp = (C.POINTER(C.c_double) * len(lb))(*[_dptr(x) for x in lb])
+        self._check(self.lib.mps_import(self.h, _iptr(chi), sp, lp, log_f))
+
+    def amplitudes(self) -> np.ndarray:
+        buf = np.zeros(2 << self.n)
+        self._check(self.lib.mps_amplitudes(self.h, _dptr(buf), 1 << self.n))
+        return buf.view(np.complex128)
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.mps_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def set_timing(self, on: bool = True):
+        self._check(self.lib.mps_set_timing(self.h, int(on)))
+
+    def kernel_times(self) -> dict:
+        cnt = C.c_int()
+        ms = np.zeros(64)
+        la = np.zeros(64, dtype=np.int64)
+        names = C.create_string_buffer(4096)
+        self._check(self.lib.mps_kernel_times(self.h, _dptr(ms), la.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              64, names, 4096, C.byref(cnt)))
+        nm = names.value.decode().split(",") if cnt.value else []
+        return {n: (float(ms[i]), int(la[i])) for i, n in enumerate(nm)}
+
+
+def plan(n: int, k_max: int, layers, chi: Sequence[int], start: int = 0, q_max: int = 0, l_max: int = 0):
+    """Host planner (mps_plan): returns (end, clusters, n_sub)."""
+    lib = load()
+    flat = [g for l in layers for g in l]
+    arr, ng = make_gates(flat)
+    ll = np.array([len(l) for l in layers], dtype=np.int32)
+    ch = np.ascontiguousarray(chi, dtype=np.int32)
+    end, cnt, nsub = C.c_int(), C.c_int(), C.c_int()
+    out = np.zeros(2 * n, dtype=np.int32)
+    st = lib.mps_plan(n, k_max, q_max, l_max, _iptr(ch), arr, _iptr(ll), len(layers), start,
+                      C.byref(end), _iptr(out), n, C.byref(cnt), C.byref(nsub))
+    if st != MPS_OK:
+        raise CtebdError(st, "mps_plan failed")
+    cl = [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(cnt.value)]
+    return end.value, cl, nsub.value

@@ -135,6 +135,26 @@ mps_status mps_run_layer(mps_handle h, const mps_gate* gates, int ngates);
 /* Contracts every buffered layer (as many steps as the caps need). */
 mps_status mps_flush(mps_handle h);
 
+/* Buffers one layer like mps_run_layer but never executes a step. */
+mps_status mps_queue_layer(mps_handle h, const mps_gate* gates, int ngates);
+
+/* Sec. III.A, one iteration: plans the clusters of the buffered sub-layers
+ * and contracts exactly one step.  *clusters receives the number of clusters
+ * (k >= 2) of that step (0 when nothing is buffered) and *remaining the
+ * sub-layers still buffered; either pointer may be NULL.  Synchronises. */
+mps_status mps_step(mps_handle h, int* clusters, int* remaining);
+
+/* Copies the state (sites, Schmidt values, bond dimensions, fidelity sum and
+ * buffered sub-layers) into a new handle whose options come from opt (the
+ * precision may differ: tensors are converted on the device).  n, chi_max and
+ * eps are those of h.  Synchronises. */
+mps_status mps_clone(mps_handle h, const mps_options* opt, mps_handle* out);
+
+/* <a|b> of the states of two handles with the same n, by a transfer-matrix
+ * sweep in FP64 on the device (E <- sum_s A_s^dagger E B_s).  Flushes both and
+ * synchronises. */
+mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im);
+
 /* Eq. approxF: flushes, synchronises, returns F_est = exp(sum log f_i) and
  * sum log f_i (either pointer may be NULL). */
 mps_status mps_fidelity(mps_handle h, double* F_est, double* log_f);

@@ -204,7 +204,10 @@ void plan_job(mps_ctx* ctx, const Job& job, JobRun& j) {
   j.chi_r = bond_dim(ctx, job.a + job.k - 1);
   j.mid.clear();
   for (int b = job.a; b < job.a + job.k - 1; ++b) j.mid.push_back(ctx->chi[b]);
+  // largest tensor of the merge chain: Theta_j = (chi_l 2^{j+1}) x chi_{a+j}
   j.theta = (int64_t)j.chi_l * ((int64_t)1 << job.k) * j.chi_r;
+  for (int q = 1; q < job.k - 1; ++q)
+    j.theta = std::max(j.theta, (int64_t)j.chi_l * ((int64_t)2 << q) * j.mid[q]);
   j.lv.clear();
   int c = j.chi_r, cmax = c;
   for (int m = job.k - 1; m >= 1; --m) {
@@ -1044,6 +1047,152 @@ mps_status mps_flush(mps_handle ctx) {
   if (!ctx) return MPS_EINVAL;
   return guarded(ctx, [&]() -> mps_status {
     flush_all(ctx);
+    return MPS_OK;
+  });
+}
+
+mps_status mps_queue_layer(mps_handle ctx, const mps_gate* gates, int ngates) {
+  if (!ctx || ngates < 0 || (ngates > 0 && !gates)) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    const mps_status st = check_gates(ctx, gates, ngates, ctx->n);
+    if (st != MPS_OK) return st;
+    std::vector<HostGate> layer;
+    for (int i = 0; i < ngates; ++i) layer.push_back(to_host_gate(gates[i]));
+    legalize_layer(layer, ctx->opt.k_max, ctx->pending);
+    return MPS_OK;
+  });
+}
+
+mps_status mps_step(mps_handle ctx, int* clusters, int* remaining) {
+  if (!ctx) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    const int64_t before = ctx->stats.cluster_updates;
+    if (!ctx->pending.empty()) execute_step(ctx, 0);
+    if (clusters) *clusters = (int)(ctx->stats.cluster_updates - before);
+    if (remaining) *remaining = (int)ctx->pending.size();
+    return MPS_OK;
+  });
+}
+
+mps_status mps_clone(mps_handle src, const mps_options* opt, mps_handle* out) {
+  if (!src || !opt || !out) return MPS_EINVAL;
+  *out = nullptr;
+  mps_handle dst = nullptr;
+  mps_status st = mps_create(src->n, src->chi_max, src->eps, opt, &dst);
+  if (st != MPS_OK) return st;
+  mps_ctx* ctx = dst;
+  st = guarded(ctx, [&]() -> mps_status {
+    HIP_OK(hipStreamSynchronize(src->stream));
+    hipStream_t s = dst->stream;
+    const int n = src->n;
+    for (int j = 0; j < n; ++j) {
+      const int64_t cnt = (int64_t)bond_dim(src, j - 1) * 2 * bond_dim(src, j);
+      if (src->prec == dst->prec || (src->prec != Prec::FP64 && dst->prec != Prec::FP64))
+        HIP_OK(hipMemcpyAsync(dst->site[j], src->site[j], cnt * src->esz, hipMemcpyDeviceToDevice, s));
+      else if (src->prec == Prec::FP64)
+        HIP_OK(launch_convert_d2f((const double2*)src->site[j], (float2*)dst->site[j], cnt, s));
+      else
+        HIP_OK(launch_convert_f2d((const float2*)src->site[j], (double2*)dst->site[j], cnt, s));
+    }
+    for (int b = 0; b < n - 1; ++b)
+      HIP_OK(hipMemcpyAsync(dst->lam[b], src->lam[b], src->chi[b] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(dst->d_chi, src->d_chi, (n - 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(dst->d_logf, src->d_logf, sizeof(double), hipMemcpyDeviceToDevice, s));
+    dst->chi = src->chi;
+    if (dst->opt.k_max == src->opt.k_max) dst->pending = src->pending;
+    HIP_OK(hipStreamSynchronize(s));
+    return MPS_OK;
+  });
+  if (st != MPS_OK) {
+    mps_destroy(dst);
+    return st;
+  }
+  *out = dst;
+  return MPS_OK;
+}
+
+mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im) {
+  if (!a || !b || a->n != b->n) return MPS_EINVAL;
+  mps_ctx* ctx = a;
+  return guarded(ctx, [&]() -> mps_status {
+    flush_all(a);
+    flush_all(b);
+    HIP_OK(hipStreamSynchronize(b->stream));
+    HIP_OK(hipStreamSynchronize(a->stream));
+    hipStream_t s = a->stream;
+    const int n = a->n;
+    int ca = 1, cb = 1;
+    for (int j = 0; j < n - 1; ++j) {
+      ca = std::max(ca, a->chi[j]);
+      cb = std::max(cb, b->chi[j]);
+    }
+    const size_t cmax = std::max(ca, cb);
+    ctx->arena.reset();
+    HIP_OK(ctx->arena.reserve(8 * cmax * cmax * sizeof(double2) + 4096));
+    double2* E[2] = {(double2*)ctx->arena.take(cmax * cmax * sizeof(double2)),
+                     (double2*)ctx->arena.take(cmax * cmax * sizeof(double2))};
+    double2* T = (double2*)ctx->arena.take(2 * cmax * cmax * sizeof(double2));
+    double2* A64 = (double2*)ctx->arena.take(2 * cmax * cmax * sizeof(double2));
+    double2* B64 = (double2*)ctx->arena.take(2 * cmax * cmax * sizeof(double2));
+    const double2 one = make_double2(1.0, 0.0);
+    HIP_OK(hipMemcpyAsync(E[0], &one, sizeof(one), hipMemcpyHostToDevice, s));
+    DescBlob& Bl = ctx->blob;
+    Bl.host.clear();
+    std::vector<size_t> off(2 * n);
+    std::vector<int> base{0, 0};
+    for (int j = 0; j < n; ++j) {
+      const int la = bond_dim(a, j - 1), ra = bond_dim(a, j), lb = bond_dim(b, j - 1), rb = bond_dim(b, j);
+      GemmDesc t{};
+      t.A = E[j & 1];
+      t.B = (b->prec == Prec::FP64) ? b->site[j] : (void*)B64;
+      t.C = T;
+      t.M = fixed(la);
+      t.K = fixed(lb);
+      t.N = fixed(2 * rb);
+      t.lda = fixed(lb);
+      t.ldb = fixed(2 * rb);
+      t.ldc = fixed(2 * rb);
+      t.batch = 1;
+      t.tm = ceil_div(la, 64);
+      t.tn = ceil_div(2 * rb, 64);
+      t.ksplit = 1;
+      t.alpha = 1.0;
+      GemmDesc e{};
+      e.A = (a->prec == Prec::FP64) ? a->site[j] : (void*)A64;
+      e.B = T;
+      e.C = E[(j + 1) & 1];
+      e.M = fixed(ra);
+      e.N = fixed(rb);
+      e.K = fixed(2 * la);
+      e.lda = fixed(ra);
+      e.ldb = fixed(rb);
+      e.ldc = fixed(rb);
+      e.batch = 1;
+      e.tm = ceil_div(ra, 64);
+      e.tn = ceil_div(rb, 64);
+      e.ksplit = 1;
+      e.alpha = 1.0;
+      off[2 * j] = Bl.add(&t, sizeof(t));
+      off[2 * j + 1] = Bl.add(&e, sizeof(e));
+    }
+    const size_t boff = Bl.add_vec(base);
+    HIP_OK(Bl.upload(s));
+    for (int j = 0; j < n; ++j) {
+      const int la = bond_dim(a, j - 1), ra = bond_dim(a, j), lb = bond_dim(b, j - 1), rb = bond_dim(b, j);
+      if (a->prec != Prec::FP64)
+        HIP_OK(launch_convert_f2d((const float2*)a->site[j], A64, (int64_t)la * 2 * ra, s));
+      if (b->prec != Prec::FP64)
+        HIP_OK(launch_convert_f2d((const float2*)b->site[j], B64, (int64_t)lb * 2 * rb, s));
+      HIP_OK(launch_gemm_nn(Prec::FP64, Bl.at<GemmDesc>(off[2 * j]), Bl.at<int>(boff), 1,
+                            ceil_div(la, 64) * ceil_div(2 * rb, 64), s));
+      HIP_OK(launch_gemm_cn(Bl.at<GemmDesc>(off[2 * j + 1]), Bl.at<int>(boff), 1,
+                            ceil_div(ra, 64) * ceil_div(rb, 64), s));
+    }
+    double2 r;
+    HIP_OK(hipMemcpyAsync(&r, E[n & 1], sizeof(r), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (re) *re = r.x;
+    if (im) *im = r.y;
     return MPS_OK;
   });
 }

@@ -19,7 +19,7 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
-enum { MODE_NN = 0, MODE_GRAM = 1 };
+enum { MODE_NN = 0, MODE_GRAM = 1, MODE_CN = 2 };
 
 template <typename CI, typename TM>
 __device__ __forceinline__ typename cpx_of<TM>::type load_c(const CI* p) {
@@ -97,6 +97,23 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
         v.y = 0;
         if (gk < kend && gn < N) v = load_c<CI, TM>(Bm + (int64_t)gk * ldb + gn);
         Bs[kk][n4 + i] = v;
+      }
+    } else if (MODE == MODE_CN) {
+      // A^H B with A (K x M) and B (K x N) row-major
+      const int kk = tid >> 4, c4 = (tid & 15) * 4;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + c4 + i, gn = n0 + c4 + i;
+        CM va, vb;
+        va.x = va.y = vb.x = vb.y = 0;
+        if (gk < kend && gm < M) {
+          va = load_c<CI, TM>(A + (int64_t)gk * lda + gm);
+          va.y = -va.y;
+        }
+        if (gk < kend && gn < N) vb = load_c<CI, TM>(Bm + (int64_t)gk * ldb + gn);
+        As[kk][c4 + i] = va;
+        Bs[kk][c4 + i] = vb;
       }
     } else {
       const int kk = tid >> 4, c4 = (tid & 15) * 4;
@@ -200,6 +217,12 @@ hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, 
     cgemm_kernel<double2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
   else
     cgemm_kernel<float2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_cn(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  cgemm_kernel<double2, double2, double, MODE_CN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
   return hipGetLastError();
 }
 

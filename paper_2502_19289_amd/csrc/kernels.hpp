@@ -50,6 +50,8 @@ hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, 
                        int blocks, hipStream_t s);
 hipError_t launch_gram_reduce(const GramReduceDesc* d_desc, const int* d_base, int nprob, int blocks,
                               hipStream_t s);
+// C = A^H B in FP64 (A: K x M, B: K x N, row-major) -- overlaps of two states
+hipError_t launch_gemm_cn(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s);
 
 // ------------------------------------------------------ eigen (Jacobi) ----
 constexpr int JB = 32;        // Jacobi block size: subproblems are 2*JB square
@@ -149,6 +151,7 @@ hipError_t launch_build_unitary(const UnitaryDesc* d, const int* d_base, int npr
 
 // Merge-kernel helper: copy with conversion (FP64 user unitary -> work precision)
 hipError_t launch_convert_d2f(const double2* src, float2* dst, int64_t n, hipStream_t s);
+hipError_t launch_convert_f2d(const float2* src, double2* dst, int64_t n, hipStream_t s);
 
 // Log-f accumulation in a fixed order (deterministic): total += sum_i v[i]
 hipError_t launch_accumulate(const double* v, int n, double* total, hipStream_t s);

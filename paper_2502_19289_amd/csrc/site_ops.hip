@@ -269,6 +269,11 @@ __global__ void convert_kernel(const double2* __restrict__ src, float2* __restri
     dst[i] = make_float2((float)src[i].x, (float)src[i].y);
 }
 
+__global__ void convert_f2d_kernel(const float2* __restrict__ src, double2* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = make_double2(src[i].x, src[i].y);
+}
+
 __global__ void accumulate_kernel(const double* __restrict__ v, int n, double* total) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = *total;
@@ -327,6 +332,13 @@ hipError_t launch_convert_d2f(const double2* src, float2* dst, int64_t n, hipStr
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
   convert_kernel<<<blocks, 256, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f2d(const float2* src, double2* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  convert_f2d_kernel<<<blocks, 256, 0, s>>>(src, dst, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,243 @@
+"""Benchmark of the cluster-TEBD hot path on one MI355X.
+
+A step is one cluster-TEBD iteration (arXiv:2502.19289, Sec. III.A) of the
+chi_max = 1024 workload (200 qubits, 50 random-structured layers, T density 0.2,
+clusters of at most 6 qubits, eps = 1e-10): plan the clusters, build each
+cluster unitary, merge its MPS block, apply the unitary, split it back with
+truncated SVDs and record the discarded weight.  The state evolves from
+|0...0>; untimed warm-up steps bring a quarter of the bonds up to chi_max
+(the state lives in HBM from then on), then K steps are timed with the
+batched mixed-precision path and, from the same state, with the plain FP64
+path (FP64 contractions and eigen-solver, one cluster per launch).
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+``--copy-calibration BYTES`` instead runs one device copy of that size (the
+reference kernel for scaling HBM counters).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "cluster updates/s + MFMA % at chi=1024 vs plain FP64 GPU path; final infidelity"
+WORKLOAD = "chi1024_n200_l50"
+
+# MI355X published peaks (TFLOP/s, GB/s)
+PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_VALU_TF = {"fp64": 78.6, "fp32": 157.3}
+PEAK_HBM = 8000.0
+
+MFMA_CLASSES = ("merge", "apply", "gram", "project", "eig_update", "eig_rayleigh")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=-1,
+                    help="untimed steps first; -1: until a quarter of the bonds reach chi_max")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0: skip)")
+    ap.add_argument("--warmup-budget", type=float, default=240.0, help="seconds cap of the auto warm-up")
+    ap.add_argument("--copy-calibration", type=int, default=0)
+    return ap.parse_args()
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}))
+
+
+def timed_steps(m, k):
+    import torch
+    torch.cuda.synchronize()
+    c0 = m.stats()["cluster_updates"]
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(k):
+        _, rem = m.step()
+        done += 1
+        if rem == 0:
+            break
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return done, m.stats()["cluster_updates"] - c0, dt
+
+
+def roofline(kt: dict, dtype: str) -> dict:
+    """Dominant kernel class of the timed region against its peak."""
+    name, (ms, launches, flop) = max(kt.items(), key=lambda kv: kv[1][0])
+    avg_ms = ms / max(1, launches)
+    per_launch = flop / max(1, launches)
+    if name in MFMA_CLASSES:
+        prec = "fp64" if (dtype == "fp64" or name in ("gram", "eig_rayleigh")) else "fp32"
+        peak, bound = PEAK_TF[prec], "mfma"
+    else:
+        prec = "fp64" if dtype == "fp64" else "fp32"
+        peak, bound = PEAK_VALU_TF[prec], "alu"
+    achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    return {"bound": bound, "kernel": name, "precision": prec, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "avg_launch_ms": avg_ms, "launches": launches, "flop_per_launch": per_launch}
+
+
+def mfma_share(kt: dict, dtype: str) -> dict:
+    """Achieved fraction of the matrix-core peak of each contraction class."""
+    out = {}
+    for k, (ms, launches, flop) in kt.items():
+        if k not in MFMA_CLASSES or ms <= 0:
+            continue
+        prec = "fp64" if (dtype == "fp64" or k in ("gram", "eig_rayleigh")) else "fp32"
+        out[k] = round(flop / (ms * 1e-3) / 1e12 / PEAK_TF[prec], 4)
+    return out
+
+
+def cpu_baseline(m, circ, p, remaining: int, budget: float) -> dict:
+    """The FP64 oracle on the clusters of the next step of the same workload
+    (their site tensors exported from the GPU state), until `budget` seconds.
+    `remaining` is the number of sub-layers the library still holds."""
+    from oracle import ctebd as CT
+    from oracle import planner as PL
+    subs = PL.legalize(circ.layers, p["k_max"])
+    start = len(subs) - remaining
+    chi = m.bond_dims()
+    end, clusters = PL.plan_step(subs, start, circ.n, chi, p["k_max"], PL.default_q_max(p["k_max"], p["chi_max"]),
+                                 1 << 30)
+    per_cluster, _ = PL.step_gates(subs, start, end, clusters, circ.n)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    done, t_used, shapes = 0, 0.0, []
+    order = sorted(range(len(clusters)), key=lambda i: clusters[i][1])
+    for ci in order:
+        a, k = clusters[ci]
+        B = [m.site(j) for j in range(a, a + k)]
+        lam_l = m.schmidt(a - 1) if a > 0 else np.ones(1)
+        U = CT.cluster_unitary(a, k, per_cluster[ci])
+        psi = CT.MPS([np.ones((1, 2, B[0].shape[0]))] + B, [lam_l] + [np.ones(b.shape[2]) for b in B[:-1]])
+        t0 = time.perf_counter()
+        CT.apply_cluster(psi, 1, k, U, p["chi_max"], p["eps"])
+        t_used += time.perf_counter() - t0
+        done += 1
+        shapes.append([k, int(B[0].shape[0]), int(B[-1].shape[2])])
+        if t_used > budget:
+            break
+    return {"value": done / t_used if t_used > 0 else None, "unit": "cluster updates/s", "cores": threads,
+            "kind": "oracle", "sample": f"{done} of the {len(clusters)} clusters of the first timed step, "
+            f"smallest k first ([k, chi_l, chi_r] = {shapes}), FP64 NumPy/LAPACK on the host, "
+            f"{t_used:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    import torch  # noqa: F401  (device plumbing only)
+
+    import paper_2502_19289_amd as P
+    from workloads import make_workload
+
+    circ, p = make_workload(args.workload, seed=args.seed)
+    m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=args.precision, batch="step")
+    for layer in circ.layers:
+        m.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
+
+    # ---- warm-up (untimed): evolve until the bonds saturate
+    t0 = time.time()
+    wsteps = 0
+    rem = None
+    while True:
+        if args.warmup >= 0 and wsteps >= args.warmup:
+            break
+        if args.warmup < 0:
+            d = np.array(m.bond_dims())
+            if (d >= p["chi_max"]).mean() >= 0.25 or time.time() - t0 > args.warmup_budget:
+                break
+        _, rem = m.step()
+        wsteps += 1
+        if rem == 0:
+            break
+        if wsteps % 50 == 0:
+            print(f"# warm-up step {wsteps}, {time.time() - t0:.0f} s", file=sys.stderr, flush=True)
+    warm_s = time.time() - t0
+    dims0 = np.array(m.bond_dims())
+
+    cpu = None
+    if args.cpu_seconds > 0 and rem:
+        cpu = cpu_baseline(m, circ, p, rem, args.cpu_seconds)
+
+    ref = None
+    if not args.no_fp64:
+        ref = m.clone(precision="fp64", batch="none")
+        ref.set_timing(True)
+
+    # ---- timed: batched mixed-precision path
+    m.set_timing(True)
+    steps, updates, dt = timed_steps(m, args.steps)
+    print(f"# timed {steps} steps, {updates} cluster updates, {dt:.1f} s", file=sys.stderr, flush=True)
+    kt = m.kernel_times()
+    value = updates / dt
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cluster updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": wsteps,
+        "ms_per_step": 1e3 * dt / max(1, steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": circ.n, "layers": len(circ.layers),
+                   "chi_max": p["chi_max"], "k_max": p["k_max"], "eps": p["eps"],
+                   "batch": "step", "seed": args.seed,
+                   "bonds_at_chi_max_at_start": int((dims0 >= p["chi_max"]).sum()),
+                   "max_chi_at_start": int(dims0.max())},
+        "roofline": roofline(kt, args.precision),
+        "cpu_baseline": cpu,
+        "mfma_frac": mfma_share(kt, args.precision),
+        "kernel_ms": {k: round(v[0], 3) for k, v in kt.items()},
+        "kernel_launches": {k: v[1] for k, v in kt.items()},
+        "warmup_s": round(warm_s, 1),
+    }
+    if ref is not None:
+        s64, u64, dt64 = timed_steps(ref, steps)
+        print(f"# fp64 leg {s64} steps, {dt64:.1f} s", file=sys.stderr, flush=True)
+        kt64 = ref.kernel_times()
+        out["fp64_path"] = {"value": u64 / dt64, "ms_per_step": 1e3 * dt64 / max(1, s64),
+                            "mfma_frac": mfma_share(kt64, "fp64"),
+                            "kernel_ms": {k: round(v[0], 3) for k, v in kt64.items()}}
+        out["speedup_vs_fp64"] = value / (u64 / dt64)
+        out["infidelity_vs_fp64_path"] = m.infidelity(ref)
+        out["F_est"] = m.fidelity()[0]
+        out["F_est_fp64_path"] = ref.fidelity()[0]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

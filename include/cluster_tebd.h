@@ -184,14 +184,58 @@ mps_status mps_amplitudes(mps_handle h, double* psi, int64_t cap);
 
 mps_status mps_get_stats(mps_handle h, mps_stats* st);
 
-/* Device time (ms) spent in each kernel class since creation, measured with
- * HIP events on the handle's stream around every launch of that class when
- * timing is on (mps_set_timing).  names receives a comma-separated list. */
+/* Device time (ms) spent in each kernel class since timing was switched on,
+ * measured with HIP events on the handle's stream around every launch of that
+ * class (mps_set_timing), the number of launches, and the algorithmic real
+ * flops the class performed (8 per complex multiply-add; merges, unitary
+ * products, Hermitian half of the Gram matrices, projections, Rayleigh
+ * products, and the rotation tiles eig_update applied).  Arrays hold cap
+ * entries; names receives the class names, comma-separated; *count the
+ * number of classes. */
 mps_status mps_set_timing(mps_handle h, int on);
-mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, int cap,
+mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, double* flop, int cap,
                             char* names, int names_cap, int* count);
 
 const char* mps_last_error(mps_handle h);
+
+/* ---- learned sketch -------------------------------------------------------
+ * The paper does not sketch its SVDs; these calls serve the build's learned
+ * sketch (svd_mode MPS_SVD_LEARNED): a network 12 -> 64 -> 64 -> 1 with GELU
+ * (tanh form), FP32 on the device, predicts log2 of the rank a truncated SVD
+ * keeps; the prediction sizes a randomized range finder on the split's Gram
+ * matrix (Halko, Martinsson, Tropp, SIAM Rev. 53 (2011), Algs. 4.1/4.3/5.1),
+ * accepted only when its 8-probe residual estimate shows that every
+ * eigenvalue it missed lies below the truncation threshold, and otherwise
+ * redone by the exact solve.  Features of a split (12 FP32): k, log2 chi_l,
+ * log2 chi_r, m/k, log2 rows, log2 (2c bound), 2q gates crossing the bond,
+ * 2q gates of the cluster, non-Clifford phase gates of the cluster,
+ * sub-layers of the step, log2 of the bond's dimension before the step,
+ * log2 chi_max.  Parameters are a flat FP32 vector: W1 (64x12), b1, W2
+ * (64x64), b2, w3 (64), b3. */
+typedef struct mlp_ctx* mlp_handle;
+
+int mlp_num_params(void);
+/* He-initialised weights (seeded), zero biases; MPS_EDEVICE without a GPU. */
+mps_status mlp_create(int seed, mlp_handle* out);
+mps_status mlp_destroy(mlp_handle h);
+mps_status mlp_get_params(mlp_handle h, float* p);
+mps_status mlp_set_params(mlp_handle h, const float* p);
+/* y[i] = network(X[i, 0..11]) for n samples (host arrays). */
+mps_status mlp_forward(mlp_handle h, const float* X, int n, float* y);
+/* Gradient of the mean pinball loss (quantile tau in (0,1)) at targets t,
+ * and the loss; grad may be NULL. */
+mps_status mlp_grad(mlp_handle h, const float* X, const float* t, int n, float tau, float* grad,
+                    float* loss);
+/* Adam (lr, beta 0.9/0.999) on shuffled minibatches (seeded) for `epochs`;
+ * *final_loss is the mean pinball loss over all n samples afterwards. */
+mps_status mlp_train(mlp_handle h, const float* X, const float* t, int n, int epochs, int batch,
+                     float lr, float tau, uint64_t seed, float* final_loss);
+/* Attaches a network to a handle (NULL detaches); it must outlive that use. */
+mps_status mps_set_sketch_model(mps_handle h, mlp_handle model);
+/* Moves up to cap logged (features, log2 kept rank) pairs of the handle's
+ * truncated SVDs into X (cap x 12) and t; *count = pairs held before the
+ * call.  With X or t NULL only *count is set. */
+mps_status mps_svd_log(mps_handle h, float* X, float* t, int cap, int* count);
 
 /* Host-side planner of Sec. III.A, exposed for testing: legalises the layers
  * (SWAP routing, sub-layers of disjoint spans) and plans the first step from

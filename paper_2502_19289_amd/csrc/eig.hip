@@ -1,15 +1,22 @@
-// FP64 Hermitian eigen-solver for the Gram matrices of the split sweep
+// Hermitian eigen-solver for the Gram matrices of the split sweep
 // (G = X^H D^2 X, whose eigenpairs give the singular values and right singular
 // vectors of D X used by every truncated SVD of arXiv:2502.19289, Sec. II.B).
 //
 // Method: two-sided cyclic block Jacobi.  The padded matrix is cut into nb
 // blocks of JB = 32 rows/columns; a round pairs the blocks (circle method, nb-1
-// rounds per sweep) and every pair (P, Q) diagonalises its 64x64 subproblem
-// G[P u Q, P u Q] with scalar cyclic Jacobi in LDS (eig_pairs, one workgroup per
-// pair), producing a unitary J_PQ.  The round's rotations are then applied to
-// the whole matrix, G <- J^H G J and V <- V J, as 64x64 tile products on the
-// FP64 matrix cores (eig_update).  A sweep in which no subproblem needed a
-// rotation ends the iteration for that matrix.
+// rounds per sweep) and every pair (P, Q) runs one cyclic sweep of scalar
+// Jacobi rotations on its 64x64 subproblem G[P u Q, P u Q] in LDS (eig_pairs,
+// one workgroup per pair; a matrix of at most 64 rows is solved completely),
+// giving a unitary J_PQ.  The round's rotations are then applied to the whole
+// matrix, G <- J^H G J and V <- V J, as 64x64 tile products on the matrix cores
+// (eig_update).  A sweep in which no subproblem needed a rotation ends the
+// iteration for that matrix.
+//
+// Two instantiations: T = double (the FP64 path) and T = float (the mixed
+// path).  The float solve works on an FP32 copy of the FP64 Gram matrix; its
+// eigenvalues are then taken as FP64 Rayleigh quotients v_i^H G v_i of the
+// FP32 eigenvectors (eig_to64 + an FP64 GEMM W = G V + eig_rayleigh), so the
+// values that decide the truncation and f_i stay FP64.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -18,8 +25,18 @@ namespace ctebd {
 
 namespace {
 
-constexpr double kTolIn = 1e-15;   // inner rotation threshold (relative)
-constexpr double kAbsFloor = 8.7e-19;  // 2^-60 times the trace of G
+template <typename T>
+struct JacobiTol;
+template <>
+struct JacobiTol<double> {
+  static constexpr double inner = 1e-14;     // inner rotation threshold (relative)
+  static constexpr double floor = 8.9e-16;   // 2^-50: absolute floor, times trace(G)
+};
+template <>
+struct JacobiTol<float> {
+  static constexpr float inner = 1e-6f;
+  static constexpr float floor = 4.8e-7f;    // 2^-21
+};
 
 __device__ __forceinline__ int nblocks_of(int n) {
   int nb = (n + JB - 1) / JB;
@@ -48,18 +65,48 @@ __device__ __forceinline__ void pair64(int t, int s, int& p, int& q) {
   }
 }
 
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+template <typename C>
+__device__ __forceinline__ C mkc(typename real_of<C>::type x, typename real_of<C>::type y) {
+  C r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C tmul(C a, C b) {
+  return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C>
+__device__ __forceinline__ C tmulc(C a, C b) {  // conj(a) * b
+  return mkc<C>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename C>
+__device__ __forceinline__ C tadd(C a, C b) {
+  return mkc<C>(a.x + b.x, a.y + b.y);
+}
+template <typename C>
+__device__ __forceinline__ typename real_of<C>::type tabs2(C a) {
+  return a.x * a.x + a.y * a.y;
+}
 
 // ------------------------------------------------------------------ init --
+template <typename T>
 __global__ __launch_bounds__(256) void eig_init_kernel(const EigDesc* __restrict__ descs) {
+  using C = typename cpx_of<T>::type;
   const EigDesc& d = descs[blockIdx.y];
   const int n = dim_value(d.n);
   const int npad = nblocks_of(n) * JB;
   const int ld = d.ld;
+  C* Gw = (C*)d.Gw;
+  C* Vw = (C*)d.Vw;
   for (int row = blockIdx.x; row < npad; row += gridDim.x) {
     for (int c = threadIdx.x; c < npad; c += blockDim.x) {
-      d.V[(int64_t)row * ld + c] = make_double2(row == c ? 1.0 : 0.0, 0.0);
-      if (row >= n || c >= n) d.G[(int64_t)row * ld + c] = make_double2(0.0, 0.0);
+      const int64_t e = (int64_t)row * ld + c;
+      Vw[e] = mkc<C>(row == c ? (T)1 : (T)0, (T)0);
+      if (row >= n || c >= n)
+        Gw[e] = mkc<C>((T)0, (T)0);
+      else if (sizeof(T) == 4)
+        Gw[e] = mkc<C>((T)d.G[e].x, (T)d.G[e].y);
     }
   }
   if (blockIdx.x == 0) {
@@ -81,12 +128,16 @@ __global__ __launch_bounds__(256) void eig_init_kernel(const EigDesc* __restrict
 }
 
 // ------------------------------------------------- subproblem rotations --
-__global__ __launch_bounds__(256) void eig_pairs_kernel(const EigDesc* __restrict__ descs,
-                                                        const int* __restrict__ base, int nprob,
-                                                        int round) {
-  __shared__ double2 S[JP][JP + 1];
-  __shared__ double2 Jm[JP][JP + 1];
-  __shared__ double2 rot[JP / 2][4];
+constexpr int EP_THREADS = 512;
+
+template <typename T>
+__global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __restrict__ descs,
+                                                               const int* __restrict__ base, int nprob,
+                                                               int round) {
+  using C = typename cpx_of<T>::type;
+  __shared__ C S[JP][JP + 1];
+  __shared__ C Jm[JP][JP + 1];
+  __shared__ C rot[JP / 2][4];
   __shared__ int rp[JP / 2], rq[JP / 2];
   __shared__ int need;
 
@@ -103,75 +154,65 @@ __global__ __launch_bounds__(256) void eig_pairs_kernel(const EigDesc* __restric
   int P, Q;
   pair_of(nb, round, slot, P, Q);
   const int ld = d.ld;
-  const double floor_abs = kAbsFloor * (*d.scale);
-  const double tol_out = d.tol;
+  const C* Gw = (const C*)d.Gw;
+  // off-diagonal entries below the floor are rounding noise of the Gram matrix
+  // itself (its eigenvalues are only accurate to that absolute level)
+  const T floor_abs = (T)(JacobiTol<T>::floor * (*d.scale));
+  const T tol_out = (T)d.tol;
+  const T tol_in = JacobiTol<T>::inner;
+  // a single pair covers the whole matrix: solve it completely here
+  const int max_inner = (nb == 2) ? 30 : 1;
 
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += EP_THREADS) {
     const int i = e / JP, j = e % JP;
     const int gi = i < JB ? P * JB + i : Q * JB + (i - JB);
     const int gj = j < JB ? P * JB + j : Q * JB + (j - JB);
-    S[i][j] = d.G[(int64_t)gi * ld + gj];
-    Jm[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    S[i][j] = Gw[(int64_t)gi * ld + gj];
+    Jm[i][j] = mkc<C>(i == j ? (T)1 : (T)0, (T)0);
   }
-  if (tid == 0) need = 0;
-  __syncthreads();
-  {
-    int mine = 0;
-    for (int e = tid; e < JP * JP; e += 256) {
-      const int i = e / JP, j = e % JP;
-      if (i < j) {
-        const double a2 = cabs2(S[i][j]);
-        const double dd = fabs(S[i][i].x * S[j][j].x);
-        if (a2 > tol_out * tol_out * dd && a2 > floor_abs * floor_abs) mine = 1;
-      }
-    }
-    if (mine) need = 1;
-  }
-  __syncthreads();
-  if (!need) {
-    if (tid == 0) d.pair_rot[slot] = 0;
-    return;
-  }
-
-  for (int sweep = 0; sweep < 12; ++sweep) {
-    if (sweep > 0) {
-      __syncthreads();
-      if (tid == 0) need = 0;
-      __syncthreads();
+  int rotated = 0;
+  for (int sweep = 0; sweep < max_inner; ++sweep) {
+    if (tid == 0) need = 0;
+    __syncthreads();
+    {
+      const T tl = sweep == 0 ? tol_out : tol_in;
       int mine = 0;
-      for (int e = tid; e < JP * JP; e += 256) {
+      for (int e = tid; e < JP * JP; e += EP_THREADS) {
         const int i = e / JP, j = e % JP;
         if (i < j) {
-          const double a2 = cabs2(S[i][j]);
-          const double dd = fabs(S[i][i].x * S[j][j].x);
-          if (a2 > kTolIn * kTolIn * dd && a2 > floor_abs * floor_abs) mine = 1;
+          const T a2 = tabs2(S[i][j]);
+          const T dd = fabs(S[i][i].x * S[j][j].x);
+          if (a2 > tl * tl * dd && a2 > floor_abs * floor_abs) mine = 1;
         }
       }
       if (mine) need = 1;
-      __syncthreads();
-      if (!need) break;
     }
+    __syncthreads();
+    if (!need) break;
+    rotated = 1;
+    // real flops of one inner sweep: 63 rounds of 1024 two-sided 2x2 updates
+    // (112 flops each) and 2048 column-pair updates of Jm (28 flops each)
+    if (tid == 0 && d.work) atomicAdd(d.work + 1, (unsigned long long)(JP - 1) * (1024 * 112 + 2048 * 28));
     for (int r = 0; r < JP - 1; ++r) {
       if (tid < JP / 2) {
         int a, b;
         pair64(r, tid, a, b);
         rp[tid] = a;
         rq[tid] = b;
-        const double sa = S[a][a].x, sd = S[b][b].x;
-        const double2 c = S[a][b];
-        const double g = sqrt(cabs2(c));
-        double2 j00 = make_double2(1, 0), j01 = make_double2(0, 0), j10 = make_double2(0, 0),
-                j11 = make_double2(1, 0);
-        if (g > floor_abs && g * g > kTolIn * kTolIn * fabs(sa * sd)) {
+        const T sa = S[a][a].x, sd = S[b][b].x;
+        const C c = S[a][b];
+        const T g = sqrt(tabs2(c));
+        C j00 = mkc<C>(1, 0), j01 = mkc<C>(0, 0), j10 = mkc<C>(0, 0), j11 = mkc<C>(1, 0);
+        if (g > floor_abs && g * g > tol_in * tol_in * fabs(sa * sd)) {
           // J2 = diag(e, 1) [[cs, sn], [-sn, cs]] with e = c/|c| zeroes S_ab
-          const double ex = c.x / g, ey = c.y / g;
-          const double zeta = (sd - sa) / (2.0 * g);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-          j00 = make_double2(ex * cs, ey * cs);
-          j01 = make_double2(ex * sn, ey * sn);
-          j10 = make_double2(-sn, 0.0);
-          j11 = make_double2(cs, 0.0);
+          const T ex = c.x / g, ey = c.y / g;
+          const T zeta = (sd - sa) / ((T)2 * g);
+          const T t = (zeta >= 0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+          const T cs = (T)1 / sqrt((T)1 + t * t), sn = t * cs;
+          j00 = mkc<C>(ex * cs, ey * cs);
+          j01 = mkc<C>(ex * sn, ey * sn);
+          j10 = mkc<C>(-sn, 0);
+          j11 = mkc<C>(cs, 0);
         }
         rot[tid][0] = j00;
         rot[tid][1] = j01;
@@ -180,27 +221,25 @@ __global__ __launch_bounds__(256) void eig_pairs_kernel(const EigDesc* __restric
       }
       __syncthreads();
       // S <- J^H S J on 2x2 blocks (row slot ra, column slot cb), one owner each
-      for (int blk = tid; blk < (JP / 2) * (JP / 2); blk += 256) {
+      for (int blk = tid; blk < (JP / 2) * (JP / 2); blk += EP_THREADS) {
         const int ra = blk / (JP / 2), cb = blk % (JP / 2);
         const int pa = rp[ra], qa = rq[ra], pb = rp[cb], qb = rq[cb];
-        const double2 m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
-        const double2 c00 = rot[cb][0], c01 = rot[cb][1], c10 = rot[cb][2], c11 = rot[cb][3];
-        // T = M * Jc
-        const double2 t00 = cadd(cmul(m00, c00), cmul(m01, c10));
-        const double2 t01 = cadd(cmul(m00, c01), cmul(m01, c11));
-        const double2 t10 = cadd(cmul(m10, c00), cmul(m11, c10));
-        const double2 t11 = cadd(cmul(m10, c01), cmul(m11, c11));
-        const double2 r00 = rot[ra][0], r01 = rot[ra][1], r10 = rot[ra][2], r11 = rot[ra][3];
-        // M' = Jr^H T
-        double2 n00 = cadd(cmulc(r00, t00), cmulc(r10, t10));
-        double2 n01 = cadd(cmulc(r00, t01), cmulc(r10, t11));
-        double2 n10 = cadd(cmulc(r01, t00), cmulc(r11, t10));
-        double2 n11 = cadd(cmulc(r01, t01), cmulc(r11, t11));
+        const C m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
+        const C c00 = rot[cb][0], c01 = rot[cb][1], c10 = rot[cb][2], c11 = rot[cb][3];
+        const C t00 = tadd(tmul(m00, c00), tmul(m01, c10));
+        const C t01 = tadd(tmul(m00, c01), tmul(m01, c11));
+        const C t10 = tadd(tmul(m10, c00), tmul(m11, c10));
+        const C t11 = tadd(tmul(m10, c01), tmul(m11, c11));
+        const C r00 = rot[ra][0], r01 = rot[ra][1], r10 = rot[ra][2], r11 = rot[ra][3];
+        C n00 = tadd(tmulc(r00, t00), tmulc(r10, t10));
+        C n01 = tadd(tmulc(r00, t01), tmulc(r10, t11));
+        C n10 = tadd(tmulc(r01, t00), tmulc(r11, t10));
+        C n11 = tadd(tmulc(r01, t01), tmulc(r11, t11));
         if (ra == cb) {
-          n00.y = 0.0;
-          n11.y = 0.0;
-          n01 = make_double2(0.0, 0.0);
-          n10 = make_double2(0.0, 0.0);
+          n00.y = 0;
+          n11.y = 0;
+          n01 = mkc<C>(0, 0);
+          n10 = mkc<C>(0, 0);
         }
         S[pa][pb] = n00;
         S[pa][qb] = n01;
@@ -208,18 +247,22 @@ __global__ __launch_bounds__(256) void eig_pairs_kernel(const EigDesc* __restric
         S[qa][qb] = n11;
       }
       // Jm <- Jm * J (columns pb, qb of every row)
-      for (int e = tid; e < JP * (JP / 2); e += 256) {
+      for (int e = tid; e < JP * (JP / 2); e += EP_THREADS) {
         const int row = e / (JP / 2), cb = e % (JP / 2);
         const int pb = rp[cb], qb = rq[cb];
-        const double2 x = Jm[row][pb], y = Jm[row][qb];
-        Jm[row][pb] = cadd(cmul(x, rot[cb][0]), cmul(y, rot[cb][2]));
-        Jm[row][qb] = cadd(cmul(x, rot[cb][1]), cmul(y, rot[cb][3]));
+        const C x = Jm[row][pb], y = Jm[row][qb];
+        Jm[row][pb] = tadd(tmul(x, rot[cb][0]), tmul(y, rot[cb][2]));
+        Jm[row][qb] = tadd(tmul(x, rot[cb][1]), tmul(y, rot[cb][3]));
       }
       __syncthreads();
     }
   }
-  double2* Jout = d.J + (int64_t)slot * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) Jout[e] = Jm[e / JP][e % JP];
+  if (!rotated) {
+    if (tid == 0) d.pair_rot[slot] = 0;
+    return;
+  }
+  C* Jout = (C*)d.J + (int64_t)slot * JP * JP;
+  for (int e = tid; e < JP * JP; e += EP_THREADS) Jout[e] = Jm[e / JP][e % JP];
   if (tid == 0) {
     d.pair_rot[slot] = 1;
     d.flags[1] = 1;
@@ -227,10 +270,13 @@ __global__ __launch_bounds__(256) void eig_pairs_kernel(const EigDesc* __restric
 }
 
 // ------------------------------------------------------ apply rotations --
-// Tile products on the FP64 matrix cores: each of the four wavefronts owns a
-// 32x32 quadrant of the 64x64 output (2x2 MFMA blocks of 16x16).
+// Tile products on the matrix cores: each of the four wavefronts owns a 32x32
+// quadrant of the 64x64 output (2x2 MFMA blocks of 16x16).  K = 64 advances in
+// slices of 16; the next slice is fetched into registers while the current
+// one is multiplied.
+template <typename T>
 struct TileAcc {
-  CAcc<double> a[2][2];
+  CAcc<T> a[2][2];
   __device__ __forceinline__ void clear() {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -239,14 +285,14 @@ struct TileAcc {
   }
 };
 
-// acc += As * Bs over a k-slice of 16 (As[k][m], Bs[k][n] in LDS)
-__device__ __forceinline__ void tile_mma16(TileAcc& acc, double2 (*As)[JP], double2 (*Bs)[JP],
-                                           int lane, int wm, int wn) {
+template <typename T, typename C>
+__device__ __forceinline__ void tile_mma16(TileAcc<T>& acc, C (*As)[JP], C (*Bs)[JP], int lane, int wm,
+                                           int wn) {
 #pragma unroll
   for (int ks = 0; ks < 16; ks += 4) {
     const int kr = ks + (lane >> 4), cl = lane & 15;
-    const double2 a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
-    const double2 b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
+    const C a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
+    const C b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
     acc.a[0][0].mac(a0.x, a0.y, b0.x, b0.y);
     acc.a[0][1].mac(a0.x, a0.y, b1.x, b1.y);
     acc.a[1][0].mac(a1.x, a1.y, b0.x, b0.y);
@@ -254,12 +300,28 @@ __device__ __forceinline__ void tile_mma16(TileAcc& acc, double2 (*As)[JP], doub
   }
 }
 
+template <typename T, typename C>
+__device__ __forceinline__ void acc_to_lds(const TileAcc<T>& acc, C (*Tt)[JP + 1], int lane, int wm, int wn) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wm * 32 + bi * 16 + Mfma<T>::row(lane, r);
+        const int c = wn * 32 + bj * 16 + (lane & 15);
+        Tt[m][c] = mkc<C>(acc.a[bi][bj].re[r], acc.a[bi][bj].im[r]);
+      }
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restrict__ descs,
                                                          const int* __restrict__ base, int nprob,
                                                          int round) {
-  __shared__ double2 As[16][JP];
-  __shared__ double2 Bs[16][JP];
-  __shared__ double2 Tt[JP][JP + 1];
+  using C = typename cpx_of<T>::type;
+  __shared__ C As[16][JP];
+  __shared__ C Bs[16][JP];
+  __shared__ C Tt[JP][JP + 1];
 
   const int p = find_problem(base, nprob, blockIdx.x);
   const EigDesc& d = descs[p];
@@ -289,56 +351,61 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   const bool roti = is_g && d.pair_rot[ti];
   const bool rotj = d.pair_rot[tj];
   if (!roti && !rotj) return;
+  if (tid == 0 && d.work)  // executed complex MACs of this tile, for the roofline
+    atomicAdd(d.work, (unsigned long long)((is_g ? (int)roti + (int)rotj : 1) * JP * JP * JP));
 
   int Pi = 0, Qi = 0, Pj, Qj;
   pair_of(nb, round, tj, Pj, Qj);
   if (is_g) pair_of(nb, round, ti, Pi, Qi);
   auto gidx = [](int P, int Q, int i) { return i < JB ? P * JB + i : Q * JB + (i - JB); };
-  const double2* Ji = d.J + (int64_t)ti * JP * JP;
-  const double2* Jj = d.J + (int64_t)tj * JP * JP;
-  double2* Mat = is_g ? d.G : d.V;
+  const C* Ji = (const C*)d.J + (int64_t)ti * JP * JP;
+  const C* Jj = (const C*)d.J + (int64_t)tj * JP * JP;
+  C* Mat = is_g ? (C*)d.Gw : (C*)d.Vw;
 
   // ---- step 1: T = M_tile * Jj  (or M_tile when Jj = I)
-  TileAcc acc;
+  TileAcc<T> acc;
   acc.clear();
   if (rotj) {
+    const int m = tid >> 2, k4 = (tid & 3) * 4;
+    const int kk = tid >> 4, n4 = (tid & 15) * 4;
+    const int64_t grow = (int64_t)(is_g ? gidx(Pi, Qi, m) : rb * JP + m) * ld;
+    C ra[4], rbv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ra[i] = Mat[grow + gidx(Pj, Qj, k4 + i)];
+      rbv[i] = Jj[kk * JP + n4 + i];
+    }
     for (int k0 = 0; k0 < JP; k0 += 16) {
-      {
-        const int m = tid >> 2, k4 = (tid & 3) * 4;
-        const int grow = is_g ? gidx(Pi, Qi, m) : rb * JP + m;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) As[k4 + i][m] = Mat[(int64_t)grow * ld + gidx(Pj, Qj, k0 + k4 + i)];
-        const int kk = tid >> 4, n4 = (tid & 15) * 4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) Bs[kk][n4 + i] = Jj[(k0 + kk) * JP + n4 + i];
+      for (int i = 0; i < 4; ++i) {
+        As[k4 + i][m] = ra[i];
+        Bs[kk][n4 + i] = rbv[i];
       }
       __syncthreads();
-      tile_mma16(acc, As, Bs, lane, wm, wn);
+      if (k0 + 16 < JP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ra[i] = Mat[grow + gidx(Pj, Qj, k0 + 16 + k4 + i)];
+          rbv[i] = Jj[(k0 + 16 + kk) * JP + n4 + i];
+        }
+      }
+      tile_mma16<T, C>(acc, As, Bs, lane, wm, wn);
       __syncthreads();
     }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = wm * 32 + bi * 16 + Mfma<double>::row(lane, r);
-          const int c = wn * 32 + bj * 16 + (lane & 15);
-          Tt[m][c] = make_double2(acc.a[bi][bj].re[r], acc.a[bi][bj].im[r]);
-        }
+    acc_to_lds<T, C>(acc, Tt, lane, wm, wn);
   } else {
     for (int e = tid; e < JP * JP; e += 256) {
-      const int m = e / JP, c = e % JP;
-      const int grow = is_g ? gidx(Pi, Qi, m) : rb * JP + m;
-      Tt[m][c] = Mat[(int64_t)grow * ld + gidx(Pj, Qj, c)];
+      const int mm = e / JP, c = e % JP;
+      const int grow = is_g ? gidx(Pi, Qi, mm) : rb * JP + mm;
+      Tt[mm][c] = Mat[(int64_t)grow * ld + gidx(Pj, Qj, c)];
     }
   }
   __syncthreads();
 
   if (!is_g) {
     for (int e = tid; e < JP * JP; e += 256) {
-      const int m = e / JP, c = e % JP;
-      d.V[(int64_t)(rb * JP + m) * ld + gidx(Pj, Qj, c)] = Tt[m][c];
+      const int mm = e / JP, c = e % JP;
+      Mat[(int64_t)(rb * JP + mm) * ld + gidx(Pj, Qj, c)] = Tt[mm][c];
     }
     return;
   }
@@ -346,38 +413,33 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   // ---- step 2: out = Ji^H * T
   if (roti) {
     acc.clear();
-    for (int k0 = 0; k0 < JP; k0 += 16) {
-      {
-        const int kk = tid >> 4, m4 = (tid & 15) * 4;
+    const int kk = tid >> 4, m4 = (tid & 15) * 4;
+    C rj[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double2 v = Ji[(k0 + kk) * JP + m4 + i];  // (Ji^H)[m][k] = conj(Ji[k][m])
-          As[kk][m4 + i] = make_double2(v.x, -v.y);
-          Bs[kk][m4 + i] = Tt[k0 + kk][m4 + i];
-        }
+    for (int i = 0; i < 4; ++i) rj[i] = Ji[kk * JP + m4 + i];
+    for (int k0 = 0; k0 < JP; k0 += 16) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        As[kk][m4 + i] = mkc<C>(rj[i].x, -rj[i].y);  // (Ji^H)[m][k] = conj(Ji[k][m])
+        Bs[kk][m4 + i] = Tt[k0 + kk][m4 + i];
       }
       __syncthreads();
-      tile_mma16(acc, As, Bs, lane, wm, wn);
+      if (k0 + 16 < JP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rj[i] = Ji[(k0 + 16 + kk) * JP + m4 + i];
+      }
+      tile_mma16<T, C>(acc, As, Bs, lane, wm, wn);
       __syncthreads();
     }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = wm * 32 + bi * 16 + Mfma<double>::row(lane, r);
-          const int c = wn * 32 + bj * 16 + (lane & 15);
-          Tt[m][c] = make_double2(acc.a[bi][bj].re[r], acc.a[bi][bj].im[r]);
-        }
+    acc_to_lds<T, C>(acc, Tt, lane, wm, wn);
     __syncthreads();
   }
   for (int e = tid; e < JP * JP; e += 256) {
-    const int m = e / JP, c = e % JP;
-    const int gr = gidx(Pi, Qi, m), gc = gidx(Pj, Qj, c);
-    const double2 v = Tt[m][c];
-    d.G[(int64_t)gr * ld + gc] = v;
-    if (ti != tj) d.G[(int64_t)gc * ld + gr] = make_double2(v.x, -v.y);
+    const int mm = e / JP, c = e % JP;
+    const int gr = gidx(Pi, Qi, mm), gc = gidx(Pj, Qj, c);
+    const C v = Tt[mm][c];
+    Mat[(int64_t)gr * ld + gc] = v;
+    if (ti != tj) Mat[(int64_t)gc * ld + gr] = mkc<C>(v.x, -v.y);
   }
 }
 
@@ -391,32 +453,82 @@ __global__ void eig_sweep_end_kernel(const EigDesc* __restrict__ descs, int npro
   }
 }
 
+// V (FP64) <- Vw (FP32) over the padded square
+__global__ __launch_bounds__(256) void eig_to64_kernel(const EigDesc* __restrict__ descs) {
+  const EigDesc& d = descs[blockIdx.y];
+  const int n = dim_value(d.n);
+  const int npad = nblocks_of(n) * JB;
+  const float2* Vw = (const float2*)d.Vw;
+  for (int row = blockIdx.x; row < npad; row += gridDim.x)
+    for (int c = threadIdx.x; c < npad; c += blockDim.x) {
+      const int64_t e = (int64_t)row * d.ld + c;
+      d.V[e] = make_double2(Vw[e].x, Vw[e].y);
+    }
+}
+
+// lam[i] = Re sum_k conj(V[k][i]) W[k][i], W = G V (FP64 Rayleigh quotients)
+__global__ __launch_bounds__(256) void eig_rayleigh_kernel(const EigDesc* __restrict__ descs) {
+  const EigDesc& d = descs[blockIdx.y];
+  const int n = dim_value(d.n);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double2 v = d.V[(int64_t)k * d.ld + i], w = d.W[(int64_t)k * d.ld + i];
+    s += v.x * w.x + v.y * w.y;
+  }
+  d.lam[i] = s;
+}
+
 }  // namespace
 
-hipError_t launch_eig_init(const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
+hipError_t launch_eig_init(bool fp32, const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   dim3 grid(min(ld_max, 256), nprob);
-  eig_init_kernel<<<grid, 256, 0, s>>>(d);
+  if (fp32)
+    eig_init_kernel<float><<<grid, 256, 0, s>>>(d);
+  else
+    eig_init_kernel<double><<<grid, 256, 0, s>>>(d);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_pairs(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+hipError_t launch_eig_pairs(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
                             hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  eig_pairs_kernel<<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
+  if (fp32)
+    eig_pairs_kernel<float><<<blocks, EP_THREADS, 0, s>>>(d, d_base, nprob, round);
+  else
+    eig_pairs_kernel<double><<<blocks, EP_THREADS, 0, s>>>(d, d_base, nprob, round);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_update(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
                              hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  eig_update_kernel<<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
+  if (fp32)
+    eig_update_kernel<float><<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
+  else
+    eig_update_kernel<double><<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   eig_sweep_end_kernel<<<(nprob + 63) / 64, 64, 0, s>>>(d, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  dim3 grid(min(ld_max, 256), nprob);
+  eig_to64_kernel<<<grid, 256, 0, s>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  dim3 grid((n_max + 255) / 256, nprob);
+  eig_rayleigh_kernel<<<grid, 256, 0, s>>>(d);
   return hipGetLastError();
 }
 

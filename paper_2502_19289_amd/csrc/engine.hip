@@ -95,6 +95,7 @@ int KernelTimer::cls_of(const char* name) {
   names.push_back(name);
   ms.push_back(0.0);
   launches.push_back(0);
+  flop.push_back(0.0);
   return (int)names.size() - 1;
 }
 
@@ -179,7 +180,9 @@ struct JobRun {
   void* Uw = nullptr;
   void* buf[2] = {nullptr, nullptr};
   void* Vr = nullptr;
-  double2 *G = nullptr, *V = nullptr, *J = nullptr, *part = nullptr;
+  double2 *G = nullptr, *V = nullptr, *part = nullptr, *W = nullptr;
+  void *J = nullptr, *Gw = nullptr, *Vw = nullptr;
+  double* lamR = nullptr;
   int *pair_rot = nullptr, *flags = nullptr, *perm = nullptr;
   double *scale = nullptr, *logf = nullptr, *rec = nullptr;
   int cur = 0;
@@ -242,6 +245,12 @@ size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
   add(ld * ld * sizeof(double2));  // G
   add(ld * ld * sizeof(double2));  // V
   add(ld * 64 * sizeof(double2));  // J
+  if (ctx->prec != Prec::FP64) {     // FP32 solve: Gw, Vw, W = G V, Rayleigh quotients
+    add(ld * ld * sizeof(float2));
+    add(ld * ld * sizeof(float2));
+    add(ld * ld * sizeof(double2));
+    add(ld * sizeof(double));
+  }
   int ks = 1;
   size_t vr = 0;
   for (const auto& L : j.lv) {
@@ -267,7 +276,16 @@ void assign_job(mps_ctx* ctx, JobRun& j) {
   const size_t ld = j.ld;
   j.G = (double2*)A.take(ld * ld * sizeof(double2));
   j.V = (double2*)A.take(ld * ld * sizeof(double2));
-  j.J = (double2*)A.take(ld * 64 * sizeof(double2));
+  j.J = A.take(ld * 64 * sizeof(double2));
+  if (ctx->prec != Prec::FP64) {
+    j.Gw = A.take(ld * ld * sizeof(float2));
+    j.Vw = A.take(ld * ld * sizeof(float2));
+    j.W = (double2*)A.take(ld * ld * sizeof(double2));
+    j.lamR = (double*)A.take(ld * sizeof(double));
+  } else {
+    j.Gw = j.G;
+    j.Vw = j.V;
+  }
   int ks = 1;
   size_t vr = 0;
   for (const auto& L : j.lv) {
@@ -282,12 +300,174 @@ void assign_job(mps_ctx* ctx, JobRun& j) {
   j.rec = (double*)A.take(4 * j.k * sizeof(double));
 }
 
+// Algorithmic flops of a finished step per kernel class (sizes are final on
+// the host once the step's bond dimensions are back): merge and unitary
+// products as written, the Hermitian half of each Gram matrix, the projection,
+// the FP64 Rayleigh product, and the tiles eig_update counted on the device.
+void account_flops(mps_ctx* ctx, const std::vector<JobRun>& runs, bool mixed, double eig_cmac,
+                   double pair_flops) {
+  double merge = 0, apply = 0, gram = 0, proj = 0, ray = 0;
+  for (const auto& r : runs) {
+    for (int j = 1; j < r.k; ++j) {
+      const double M = (double)r.chi_l * (1 << j), K = r.mid[j - 1];
+      const double N = 2.0 * ((j == r.k - 1) ? r.chi_r : r.mid[j]);
+      merge += M * N * K;
+    }
+    apply += (double)(1 << r.k) * (1 << r.k) * r.chi_l * r.chi_r;
+    for (size_t t = 0; t < r.lv.size(); ++t) {
+      const int m = r.lv[t].m;
+      const double c = (t == 0) ? r.chi_r : ctx->chi[r.a + m];
+      const double rr = ctx->chi[r.a + m - 1];
+      const double n2 = 2.0 * c, rows = r.lv[t].rows;
+      gram += n2 * (n2 + 1) / 2 * rows;
+      proj += rows * n2 * rr;
+      if (mixed) ray += n2 * n2 * n2;
+    }
+  }
+  auto add = [&](const char* name, double cmac) { ctx->timer.flop[ctx->timer.cls_of(name)] += 8.0 * cmac; };
+  add("merge", merge);
+  add("apply", apply);
+  add("gram", gram);
+  add("project", proj);
+  if (mixed) add("eig_rayleigh", ray);
+  add("eig_update", eig_cmac);
+  ctx->timer.flop[ctx->timer.cls_of("eig_pairs")] += pair_flops;
+}
+
 // ------------------------------------------------------------ executor --
 // Runs the given clusters (all in the same launches) plus the one-qubit site
 // updates; ends with the host synchronisation of the step.
-void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q) {
+// ------------------------------------------------------- learned sketch --
+// Features of every split of a job (12 per level, see mps_svd_log).
+bool non_clifford_phase(const HostGate& g) {
+  if (g.nq != 1 || std::abs(g.u[1]) > 1e-12 || std::abs(g.u[2]) > 1e-12) return false;
+  const cplx ph = g.u[3] / g.u[0];
+  const double a = std::arg(ph) / (M_PI / 2);
+  return std::abs(a - std::round(a)) > 1e-9;
+}
+
+void job_features(const mps_ctx* ctx, const JobRun& r, const Job& job, int nsub, std::vector<float>& out) {
+  int n2q = 0, nt = 0;
+  for (const auto& g : job.gates) {
+    if (g.nq == 2) ++n2q;
+    if (non_clifford_phase(g)) ++nt;
+  }
+  for (const auto& L : r.lv) {
+    const int b = r.a + L.m - 1;
+    int cross = 0;
+    for (const auto& g : job.gates)
+      if (g.nq == 2 && g.lo() <= b && b < g.hi()) ++cross;
+    const float f[N_FEAT] = {(float)r.k, std::log2((float)r.chi_l), std::log2((float)r.chi_r),
+                             (float)L.m / (float)r.k, std::log2((float)L.rows), std::log2(2.f * L.c_bound),
+                             (float)cross, (float)n2q, (float)nt, (float)nsub,
+                             std::log2((float)ctx->chi[b]), std::log2((float)ctx->chi_max)};
+    out.insert(out.end(), f, f + N_FEAT);
+  }
+}
+
+// Workspace of one sketched split (n = 2c bound, s = sketch size).
+struct SkRun {
+  int job = 0, t = 0, s = 0, ld_s = 0, ld_y = 0, nb = 2;
+  double2 *Omega, *Probe, *Y, *Q, *Vs, *R1, *R2, *C8, *Bq, *Gy, *Uy, *Hw, *Wh;
+  void *Ja, *Jb;
+  int *pr_a, *pr_b, *flags_a, *flags_b, *use;
+  double *scale_a, *scale_b, *lam, *est;
+};
+
+size_t sk_bytes(int n, const SkRun& k) {
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
+  const size_t pan = (size_t)n * k.ld_s * sizeof(double2);
+  for (int i = 0; i < 7; ++i) add(pan);  // Omega, Probe, Y, Q, Vs, R1, R2
+  add((size_t)k.ld_y * k.ld_s * sizeof(double2) * 2);  // C8, Bq
+  for (int i = 0; i < 4; ++i) add((size_t)k.ld_y * k.ld_y * sizeof(double2));
+  add((size_t)k.ld_y * 64 * sizeof(double2) * 2);
+  add((size_t)k.ld_y / 64 * sizeof(int) * 2 + 16);
+  add(k.ld_y * sizeof(double) + 64);
+  return b;
+}
+
+void sk_assign(DeviceArena& A, SkRun& k, int n, int* flags, double* scales) {
+  const size_t pan = (size_t)n * k.ld_s * sizeof(double2);
+  double2** pans[7] = {&k.Omega, &k.Probe, &k.Y, &k.Q, &k.Vs, &k.R1, &k.R2};
+  for (auto p : pans) *p = (double2*)A.take(pan);
+  k.C8 = (double2*)A.take((size_t)k.ld_y * k.ld_s * sizeof(double2));
+  k.Bq = (double2*)A.take((size_t)k.ld_y * k.ld_s * sizeof(double2));
+  double2** sq[4] = {&k.Gy, &k.Uy, &k.Hw, &k.Wh};
+  for (auto p : sq) *p = (double2*)A.take((size_t)k.ld_y * k.ld_y * sizeof(double2));
+  k.Ja = A.take((size_t)k.ld_y * 64 * sizeof(double2));
+  k.Jb = A.take((size_t)k.ld_y * 64 * sizeof(double2));
+  k.pr_a = (int*)A.take((size_t)k.ld_y / 64 * sizeof(int) + 4);
+  k.pr_b = (int*)A.take((size_t)k.ld_y / 64 * sizeof(int) + 4);
+  k.lam = (double*)A.take(k.ld_y * sizeof(double));
+  k.est = (double*)A.take(2 * sizeof(double));
+  k.flags_a = flags;
+  k.flags_b = flags + 4;
+  k.use = flags + 8;
+  k.scale_a = scales;
+  k.scale_b = scales + 1;
+}
+
+GemmDesc gemm64(const void* A, const void* B, void* C, Dim M, Dim N, Dim K, Dim lda, Dim ldb, Dim ldc, int mb,
+                int nbnd) {
+  GemmDesc d{};
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.M = M;
+  d.N = N;
+  d.K = K;
+  d.lda = lda;
+  d.ldb = ldb;
+  d.ldc = ldc;
+  d.batch = 1;
+  d.tm = ceil_div(mb, 64);
+  d.tn = ceil_div(nbnd, 64);
+  d.ksplit = 1;
+  d.alpha = 1.0;
+  return d;
+}
+
+// Runs a group of FP64/FP32 block-Jacobi solves to convergence (host checks
+// the convergence flags after every sweep).  flags_dev/h_flags hold `stride`
+// ints per problem at the indices given.
+void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>& host, const int* b_pair,
+               const int* b_upd, int n_pair, int n_upd, const int* flags_dev, int nflag_ints,
+               const std::vector<int>& flag_at) {
+  hipStream_t s = ctx->stream;
+  const int np = (int)host.size();
+  if (!np) return;
+  int nb_all = 0, ldmax = 0;
+  for (const auto& e : host) {
+    nb_all = std::max(nb_all, e.nb_max);
+    ldmax = std::max(ldmax, e.ld);
+  }
+  for (int sw = 0; sw < 30; ++sw) {
+    for (int round = 0; round < nb_all - 1; ++round) {
+      {
+        Timed tm(ctx, "eig_pairs");
+        HIP_OK(launch_eig_pairs(fp32, de, b_pair, np, n_pair, round, s));
+      }
+      {
+        Timed tm(ctx, "eig_update");
+        HIP_OK(launch_eig_update(fp32, de, b_upd, np, n_upd, round, s));
+      }
+    }
+    HIP_OK(launch_eig_sweep_end(de, np, s));
+    ctx->stats.jacobi_sweeps += 1;
+    HIP_OK(hipMemcpyAsync(ctx->h_flags, flags_dev, (size_t)nflag_ints * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int q : flag_at)
+      if (!ctx->h_flags[q]) all = false;
+    if (all) break;
+  }
+}
+
+void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q, int nsub) {
   hipStream_t s = ctx->stream;
   const Prec P = ctx->prec;
+  const bool mixed = P != Prec::FP64;  // FP32 Jacobi + FP64 Rayleigh quotients
   std::vector<JobRun> runs(jobs.size());
   size_t bytes = 0;
   for (size_t i = 0; i < jobs.size(); ++i) {
@@ -295,9 +475,67 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     bytes += job_bytes(ctx, runs[i]);
   }
   const int nj = (int)jobs.size();
-  bytes += (size_t)nj * (sizeof(double) + 4 * sizeof(int)) + 4096;
+
+  // ---- learned sketch: features of every split, predicted kept ranks
+  std::vector<float> feats;
+  std::vector<int> lv_job, lv_t;
+  for (int i = 0; i < nj; ++i) {
+    job_features(ctx, runs[i], jobs[i], nsub, feats);
+    for (size_t t = 0; t < runs[i].lv.size(); ++t) {
+      lv_job.push_back(i);
+      lv_t.push_back((int)t);
+    }
+  }
+  const int nlev = (int)lv_job.size();
+  std::vector<SkRun> sk;
+  std::vector<std::vector<int>> sk_of(nj);  // per job: sketch index per level or -1
+  for (int i = 0; i < nj; ++i) sk_of[i].assign(runs[i].lv.size(), -1);
+  if (ctx->opt.svd_mode == MPS_SVD_LEARNED && ctx->mlp_params && nlev > 0) {
+    std::vector<float> pred(nlev);
+    float *dX = nullptr, *dy = nullptr;
+    HIP_OK(hipMalloc(&dX, feats.size() * sizeof(float)));
+    HIP_OK(hipMalloc(&dy, nlev * sizeof(float)));
+    HIP_OK(hipMemcpyAsync(dX, feats.data(), feats.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    {
+      Timed tm(ctx, "mlp_forward");
+      HIP_OK(launch_mlp_forward(ctx->mlp_params, dX, dy, nlev, s));
+    }
+    HIP_OK(hipMemcpyAsync(pred.data(), dy, nlev * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    (void)hipFree(dX);
+    (void)hipFree(dy);
+    for (int q = 0; q < nlev; ++q) {
+      const Level& L = runs[lv_job[q]].lv[lv_t[q]];
+      const int n = 2 * L.c_bound;
+      const double rhat = std::exp2((double)std::min(pred[q], 30.f));
+      int ssz = (int)std::ceil(rhat) + 8;  // oversampling p = 8
+      if (n < 128 || ssz > n / 2 || rhat + 8 >= ctx->chi_max) continue;  // exact is cheaper or cap binds
+      ssz = std::max(ssz, 16);
+      SkRun k;
+      k.job = lv_job[q];
+      k.t = lv_t[q];
+      k.s = ssz;
+      k.ld_s = ((std::max(ssz, SK_PROBES) + 7) / 8) * 8;
+      k.ld_y = ((ssz + 63) / 64) * 64;
+      int nb = ceil_div(ssz, JB);
+      nb = std::max(nb, 2);
+      k.nb = nb + (nb & 1);
+      sk_of[k.job][k.t] = (int)sk.size();
+      sk.push_back(k);
+      bytes += sk_bytes(n, k);
+    }
+  }
+  const int nsk = (int)sk.size();
+
+  bytes += (size_t)nj * (sizeof(double) + 4 * sizeof(int)) + (size_t)nsk * (12 * sizeof(int) + 2 * sizeof(double)) +
+           8192;
   ctx->arena.reset();
   HIP_OK(ctx->arena.reserve(bytes));
+  int* skflags_all = (int*)ctx->arena.take(std::max(1, nsk) * 12 * sizeof(int));
+  double* skscale_all = (double*)ctx->arena.take(std::max(1, nsk) * 2 * sizeof(double));
+  for (int q = 0; q < nsk; ++q)
+    sk_assign(ctx->arena, sk[q], 2 * runs[sk[q].job].lv[sk[q].t].c_bound, skflags_all + 12 * q,
+              skscale_all + 2 * q);
   double* logf_all = (double*)ctx->arena.take(std::max(1, nj) * sizeof(double));
   int* flags_all = (int*)ctx->arena.take(std::max(1, nj) * 4 * sizeof(int));
   for (int i = 0; i < nj; ++i) {
@@ -307,6 +545,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     runs[i].flag_index = i;
   }
   if (nj) HIP_OK(hipMemsetAsync(logf_all, 0, nj * sizeof(double), s));
+  if (ctx->timing) HIP_OK(hipMemsetAsync(ctx->d_work, 0, 2 * sizeof(unsigned long long), s));
 
   DescBlob& B = ctx->blob;
   B.host.clear();
@@ -415,11 +654,17 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     std::vector<int> jobs;
     std::vector<GemmDesc> gram, proj;
     std::vector<GramReduceDesc> red;
-    std::vector<EigDesc> eig;
+    // exact solves: group 0 in FP64, group 1 in FP32 (+ FP64 Rayleigh quotients)
+    std::vector<EigDesc> eig[2];
+    std::vector<int> eig_jobs[2];
     std::vector<SelectDesc> sel;
+    std::vector<GemmDesc> ray;  // FP32 solve: W = G V in FP64
     std::vector<GatherDesc> gat;
-    size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_eig, b_pair, b_upd, o_sel, o_gat, b_gat;
-    int n_gram, n_proj, n_red, n_pair, n_upd, n_gat;
+    size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_sel, o_gat, b_gat;
+    size_t o_eig[2] = {0, 0}, b_pair[2] = {0, 0}, b_upd[2] = {0, 0};
+    int n_pair[2] = {0, 0}, n_upd[2] = {0, 0};
+    size_t o_ray = 0, b_ray = 0;
+    int n_gram, n_proj, n_red, n_gat, n_ray = 0;
     int nb_max_all;
   };
   std::vector<LevelDescs> LD(std::max(0, tmax));
@@ -468,27 +713,55 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         }
       }
       {
+        // The FP32 solve resolves eigenvalues of G only to ~1e-7 of its trace;
+        // it serves large splits whose rank bound exceeds chi_max, where the
+        // cut lies far above that level.  Other splits use the FP64 solve.
+        const bool e32 = mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
         EigDesc e{};
         e.G = r.G;
         e.V = r.V;
         e.J = r.J;
+        e.Gw = e32 ? r.Gw : (void*)r.G;
+        e.Vw = e32 ? r.Vw : (void*)r.V;
+        e.W = r.W;
+        e.lam = r.lamR;
         e.pair_rot = r.pair_rot;
         e.flags = r.flags;
         e.scale = r.scale;
+        e.work = ctx->timing ? ctx->d_work : nullptr;
         e.n = n2c;
         e.ld = r.ld;
         int nb = ceil_div(2 * lv.c_bound, JB);
         nb = std::max(nb, 2);
         nb += nb & 1;
         e.nb_max = nb;
-        e.tol = 1e-13;
+        e.tol = e32 ? 2e-6 : 1e-13;
         L.nb_max_all = std::max(L.nb_max_all, nb);
-        L.eig.push_back(e);
+        L.eig[e32].push_back(e);
+        L.eig_jobs[e32].push_back(i);
+        if (e32) {
+          GemmDesc g{};
+          g.A = r.G;
+          g.B = r.V;
+          g.C = r.W;
+          g.M = n2c;
+          g.N = n2c;
+          g.K = n2c;
+          g.lda = g.ldb = g.ldc = fixed(r.ld);
+          g.batch = 1;
+          g.tm = g.tn = ceil_div(2 * lv.c_bound, 64);
+          g.ksplit = 1;
+          g.alpha = 1.0;
+          if (sk_of[i][t] >= 0) g.skip = sk[sk_of[i][t]].use;
+          L.ray.push_back(g);
+        }
       }
       int* r_out = ctx->d_chi + (r.a + m - 1);
       {
+        const bool e32 = mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
         SelectDesc sd{};
         sd.G = r.G;
+        sd.lam_in = e32 ? r.lamR : nullptr;
         sd.ldg = r.ld;
         sd.n = n2c;
         sd.rows = lv.rows;
@@ -499,6 +772,13 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         sd.lam_out = ctx->lam[r.a + m - 1];
         sd.logf_acc = r.logf;
         sd.rec = r.rec + 4 * t;
+        if (sk_of[i][t] >= 0) {
+          const SkRun& k = sk[sk_of[i][t]];
+          sd.use_sk = k.use;
+          sd.lam_sk = k.lam;
+          sd.tot_sk = r.scale;
+          sd.s_sk = k.s;
+        }
         L.sel.push_back(sd);
       }
       {
@@ -511,6 +791,12 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         g.B = ctx->site[r.a + m];
         g.Vr = r.Vr;
         g.tiles = ceil_div(lv.r_bound, 64) * ceil_div(2 * lv.c_bound, 64);
+        if (sk_of[i][t] >= 0) {
+          const SkRun& k = sk[sk_of[i][t]];
+          g.use_sk = k.use;
+          g.Vs = k.Vs;
+          g.ld_sk = k.ld_s;
+        }
         L.gat.push_back(g);
       }
       {
@@ -534,6 +820,94 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       r.cur ^= 1;
     }
   }
+  // Learned-sketch descriptors per level: range finder on G, two s x s solves,
+  // residual probes, acceptance (see sketch.hip).
+  struct SkLevel {
+    std::vector<int> ids;
+    std::vector<SketchDesc> sd;
+    std::vector<EigDesc> ea, eb;
+    std::vector<GemmDesc> g[9];  // Y, Y^H Y, Q, G Q, H, Vs, C8, R1, R2
+    size_t o_sd = 0, o_ea = 0, o_eb = 0, bp_a = 0, bu_a = 0, bp_b = 0, bu_b = 0;
+    size_t o[9] = {0}, b[9] = {0};
+    int n[9] = {0};
+    int np_a = 0, nu_a = 0, np_b = 0, nu_b = 0;
+    std::vector<int> flag_a, flag_b;
+  };
+  std::vector<SkLevel> SL(std::max(0, tmax));
+  for (int q = 0; q < nsk; ++q) {
+    SkRun& k = sk[q];
+    JobRun& r = runs[k.job];
+    const Level& lv = r.lv[k.t];
+    SkLevel& S = SL[k.t];
+    S.ids.push_back(q);
+    const Dim n2c = c_dim(ctx, r, k.t, 2);
+    const int nb = 2 * lv.c_bound;
+    const Dim fs = fixed(k.s), fls = fixed(k.ld_s), fly = fixed(k.ld_y), fld = fixed(r.ld), f8 = fixed(SK_PROBES);
+    SketchDesc d{};
+    d.n = n2c;
+    d.s = k.s;
+    d.ld_s = k.ld_s;
+    d.ld_y = k.ld_y;
+    d.seed = ctx->sketch_seed;
+    d.stream = ctx->sketch_stream++;
+    d.Omega = k.Omega;
+    d.Probe = k.Probe;
+    d.Bq = k.Bq;
+    d.R1 = k.R1;
+    d.R2 = k.R2;
+    d.Gy = k.Gy;
+    d.Uy = k.Uy;
+    d.Hw = k.Hw;
+    d.lam = k.lam;
+    d.trace = r.scale;
+    d.eps_eff = ctx->eps_eff;
+    d.use = k.use;
+    d.est = k.est;
+    d.exact_flags = r.flags;
+    S.sd.push_back(d);
+    S.g[0].push_back(gemm64(r.G, k.Omega, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));  // Y = G Omega
+    {
+      GemmDesc g = gemm64(k.Y, k.Y, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);     // Y^H Y
+      g.w = ctx->d_ones;
+      g.wshift = 0;
+      S.g[1].push_back(g);
+    }
+    S.g[2].push_back(gemm64(k.Y, k.Bq, k.Q, n2c, fs, fs, fls, fls, fls, nb, k.s));      // Q = Y Bq
+    S.g[3].push_back(gemm64(r.G, k.Q, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));      // G Q (into Y)
+    S.g[4].push_back(gemm64(k.Q, k.Y, k.Hw, fs, fs, n2c, fls, fls, fly, k.s, k.s));     // H = Q^H G Q
+    S.g[5].push_back(gemm64(k.Q, k.Wh, k.Vs, n2c, fs, fs, fls, fly, fls, nb, k.s));     // Vs = Q W
+    S.g[6].push_back(gemm64(k.Q, k.Probe, k.C8, fs, f8, n2c, fls, fls, fls, k.s, SK_PROBES));  // Q^H g
+    S.g[7].push_back(gemm64(r.G, k.Probe, k.R1, n2c, f8, n2c, fld, fls, fls, nb, SK_PROBES));  // G g
+    S.g[8].push_back(gemm64(k.Y, k.C8, k.R2, n2c, f8, fs, fls, fls, fls, nb, SK_PROBES));      // G Q Q^H g
+    EigDesc ea{};
+    ea.G = k.Gy;
+    ea.V = k.Uy;
+    ea.Gw = k.Gy;
+    ea.Vw = k.Uy;
+    ea.J = k.Ja;
+    ea.pair_rot = k.pr_a;
+    ea.flags = k.flags_a;
+    ea.scale = k.scale_a;
+    ea.work = ctx->timing ? ctx->d_work : nullptr;
+    ea.n = fs;
+    ea.ld = k.ld_y;
+    ea.nb_max = k.nb;
+    ea.tol = 1e-13;
+    EigDesc eb = ea;
+    eb.G = k.Hw;
+    eb.V = k.Wh;
+    eb.Gw = k.Hw;
+    eb.Vw = k.Wh;
+    eb.J = k.Jb;
+    eb.pair_rot = k.pr_b;
+    eb.flags = k.flags_b;
+    eb.scale = k.scale_b;
+    S.ea.push_back(ea);
+    S.eb.push_back(eb);
+    S.flag_a.push_back(12 * q);
+    S.flag_b.push_back(12 * q + 4);
+  }
+
   std::vector<ScaleDesc> fin;
   std::vector<int> fbase{0};
   for (auto& r : runs) {
@@ -572,22 +946,42 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       L.b_red = B.add_vec(base);
       L.n_red = base.back();
     }
-    std::vector<int> pb{0}, ub{0};
-    for (const auto& e : L.eig) {
-      pb.push_back(pb.back() + e.nb_max / 2);
-      ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+    for (int g = 0; g < 2; ++g) {
+      if (L.eig[g].empty()) continue;
+      std::vector<int> pb{0}, ub{0};
+      for (const auto& e : L.eig[g]) {
+        pb.push_back(pb.back() + e.nb_max / 2);
+        ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+      }
+      L.o_eig[g] = B.add_vec(L.eig[g]);
+      L.b_pair[g] = B.add_vec(pb);
+      L.b_upd[g] = B.add_vec(ub);
+      L.n_pair[g] = pb.back();
+      L.n_upd[g] = ub.back();
     }
-    L.o_eig = B.add_vec(L.eig);
-    L.b_pair = B.add_vec(pb);
-    L.b_upd = B.add_vec(ub);
-    L.n_pair = pb.back();
-    L.n_upd = ub.back();
     L.o_sel = B.add_vec(L.sel);
+    if (!L.ray.empty()) L.n_ray = upload_gemm(L.ray, L.o_ray, L.b_ray);
     std::vector<int> gb{0};
     for (const auto& g : L.gat) gb.push_back(gb.back() + g.tiles);
     L.o_gat = B.add_vec(L.gat);
     L.b_gat = B.add_vec(gb);
     L.n_gat = gb.back();
+  }
+  for (auto& S : SL) {
+    if (S.ids.empty()) continue;
+    S.o_sd = B.add_vec(S.sd);
+    for (int g = 0; g < 9; ++g) S.n[g] = upload_gemm(S.g[g], S.o[g], S.b[g]);
+    std::vector<int> pa{0}, ua{0};
+    for (const auto& e : S.ea) {
+      pa.push_back(pa.back() + e.nb_max / 2);
+      ua.push_back(ua.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+    }
+    S.o_ea = B.add_vec(S.ea);
+    S.o_eb = B.add_vec(S.eb);
+    S.bp_a = B.add_vec(pa);
+    S.bu_a = B.add_vec(ua);
+    S.np_a = pa.back();
+    S.nu_a = ua.back();
   }
   size_t o_fin = 0, b_fin = 0;
   if (nj) {
@@ -638,33 +1032,66 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       Timed tm(ctx, "gram_reduce");
       HIP_OK(launch_gram_reduce(B.at<GramReduceDesc>(L.o_red), B.at<int>(L.b_red), (int)L.red.size(), L.n_red, s));
     }
-    EigDesc* de = B.at<EigDesc>(L.o_eig);
     int ldmax = 0;
-    for (const auto& e : L.eig) ldmax = std::max(ldmax, e.ld);
-    {
+    for (int g = 0; g < 2; ++g)
+      for (const auto& e : L.eig[g]) ldmax = std::max(ldmax, e.ld);
+    for (int g = 0; g < 2; ++g) {
+      if (L.eig[g].empty()) continue;
       Timed tm(ctx, "eig_init");
-      HIP_OK(launch_eig_init(de, np, ldmax, s));
+      HIP_OK(launch_eig_init(g == 1, B.at<EigDesc>(L.o_eig[g]), (int)L.eig[g].size(), ldmax, s));
     }
-    const int max_sweeps = 30;
-    for (int sw = 0; sw < max_sweeps; ++sw) {
-      for (int round = 0; round < L.nb_max_all - 1; ++round) {
-        {
-          Timed tm(ctx, "eig_pairs");
-          HIP_OK(launch_eig_pairs(de, B.at<int>(L.b_pair), np, L.n_pair, round, s));
-        }
-        {
-          Timed tm(ctx, "eig_update");
-          HIP_OK(launch_eig_update(de, B.at<int>(L.b_upd), np, L.n_upd, round, s));
-        }
+    SkLevel& S = SL[t];
+    if (!S.ids.empty()) {
+      // learned sketch of this level's predicted-low-rank splits
+      const int ns = (int)S.ids.size();
+      SketchDesc* dsk = B.at<SketchDesc>(S.o_sd);
+      auto nn = [&](int g) { HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+      auto cn = [&](int g) { HIP_OK(launch_gemm_cn(B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+      int ldy = 0;
+      for (int q : S.ids) ldy = std::max(ldy, sk[q].ld_y);
+      {
+        Timed tm(ctx, "sketch");
+        HIP_OK(launch_gauss_fill(dsk, ns, 0, s));
+        HIP_OK(launch_gauss_fill(dsk, ns, 1, s));
+        nn(0);
+        HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
+        HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
       }
-      HIP_OK(launch_eig_sweep_end(de, np, s));
-      ctx->stats.jacobi_sweeps += 1;
-      HIP_OK(hipMemcpyAsync(ctx->h_flags, flags_all, (size_t)nj * 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
-      bool all = true;
-      for (int q : L.jobs)
-        if (!ctx->h_flags[4 * q]) all = false;
-      if (all) break;
+      solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+                skflags_all, 12 * nsk, S.flag_a);
+      {
+        Timed tm(ctx, "sketch");
+        HIP_OK(launch_orth_scale(dsk, ns, s));
+        nn(2);
+        nn(3);
+        cn(4);
+        HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
+      }
+      solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+                skflags_all, 12 * nsk, S.flag_b);
+      {
+        Timed tm(ctx, "sketch");
+        nn(5);
+        cn(6);
+        nn(7);
+        nn(8);
+        HIP_OK(launch_sketch_accept(dsk, ns, s));
+      }
+    }
+    for (int g = 0; g < 2; ++g) {
+      if (L.eig[g].empty()) continue;
+      std::vector<int> at;
+      for (int q : L.eig_jobs[g]) at.push_back(4 * q);
+      solve_eig(ctx, g == 1, B.at<EigDesc>(L.o_eig[g]), L.eig[g], B.at<int>(L.b_pair[g]), B.at<int>(L.b_upd[g]),
+                L.n_pair[g], L.n_upd[g], flags_all, 4 * nj, at);
+    }
+    if (!L.eig[1].empty()) {
+      Timed tm(ctx, "eig_rayleigh");
+      EigDesc* de32 = B.at<EigDesc>(L.o_eig[1]);
+      const int n32 = (int)L.eig[1].size();
+      HIP_OK(launch_eig_to64(de32, n32, ldmax, s));
+      HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(L.o_ray), B.at<int>(L.b_ray), n32, L.n_ray, s));
+      HIP_OK(launch_eig_rayleigh(de32, n32, ldmax, s));
     }
     {
       Timed tm(ctx, "select");
@@ -701,22 +1128,47 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       off += 4 * (r.k - 1);
     }
   }
+  unsigned long long eig_work[2] = {0, 0};
+  if (ctx->timing)
+    HIP_OK(hipMemcpyAsync(eig_work, ctx->d_work, sizeof(eig_work), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  if (ctx->timing) collect_timing(ctx);
+  if (ctx->timing) {
+    collect_timing(ctx);
+    account_flops(ctx, runs, mixed, (double)eig_work[0], (double)eig_work[1]);
+  }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
+  if (nsk) {
+    std::vector<int> skf(12 * nsk);
+    HIP_OK(hipMemcpy(skf.data(), skflags_all, skf.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (int q = 0; q < nsk; ++q) {
+      if (skf[12 * q + 8])
+        ctx->stats.sketch_accepted += 1;
+      else
+        ctx->stats.sketch_fallback += 1;
+    }
+  }
+  // (features, log2 kept rank) of every split, for training the network
+  if (ctx->log_t.size() < (size_t)4000000) {
+    for (int q = 0; q < nlev; ++q) {
+      const JobRun& r = runs[lv_job[q]];
+      const int rk = ctx->chi[r.a + r.lv[lv_t[q]].m - 1];
+      ctx->log_x.insert(ctx->log_x.end(), feats.begin() + (size_t)q * N_FEAT, feats.begin() + (size_t)(q + 1) * N_FEAT);
+      ctx->log_t.push_back(std::log2((float)rk));
+    }
+  }
   ctx->stats.cluster_updates += nj;
   for (auto& r : runs) ctx->stats.svds += r.k - 1;
   ctx->stats.site_updates += (int64_t)sites1q.size();
 }
 
-void run_jobs(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q) {
+void run_jobs(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q, int nsub) {
   if (ctx->opt.batch == MPS_BATCH_NONE && jobs.size() > 1) {
     for (size_t i = 0; i < jobs.size(); ++i) {
       std::vector<Job> one{jobs[i]};
-      run_group(ctx, one, i + 1 == jobs.size() ? sites1q : std::vector<Site1QDesc>{});
+      run_group(ctx, one, i + 1 == jobs.size() ? sites1q : std::vector<Site1QDesc>{}, nsub);
     }
   } else {
-    run_group(ctx, jobs, sites1q);
+    run_group(ctx, jobs, sites1q, nsub);
   }
   ctx->stats.steps += 1;
 }
@@ -773,7 +1225,7 @@ int execute_step(mps_ctx* ctx, int end_hint) {
     d.blocks = std::max(1, std::min(256, ceil_div((int64_t)d.chi_l * d.chi_r, 256)));
     s1.push_back(d);
   }
-  run_jobs(ctx, jobs, s1);
+  run_jobs(ctx, jobs, s1, end);
   ctx->pending.erase(ctx->pending.begin(), ctx->pending.begin() + end);
   return end;
 }
@@ -847,6 +1299,7 @@ void destroy_ctx(mps_ctx* ctx) {
   ctx->blob.release();
   if (ctx->state_mem) (void)hipFree(ctx->state_mem);
   if (ctx->d_chi) (void)hipFree(ctx->d_chi);
+  if (ctx->d_work) (void)hipFree(ctx->d_work);
   if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
   for (auto e : ctx->timer.pool) (void)hipEventDestroy(e);
   for (auto& p : ctx->timer.pending) {
@@ -895,10 +1348,6 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
       ctx->err = "BF16X6 contractions are not built in this library version";
       return MPS_EINVAL;
     }
-    if (o.svd_mode == MPS_SVD_LEARNED) {
-      ctx->err = "learned-sketch SVD is not built in this library version";
-      return MPS_EINVAL;
-    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
       (void)hipGetLastError();
@@ -938,7 +1387,7 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
       soff[j] = al(cl * 2 * cr * ctx->esz);
     }
     for (int b = 0; b < n - 1; ++b) loff[b] = al(ctx->cap[b] * sizeof(double));
-    const size_t ones_off = al(2048 * sizeof(double));
+    const size_t ones_off = al(4096 * sizeof(double));
     const size_t logf_off = al(sizeof(double));
     HIP_OK(hipMalloc(&ctx->state_mem, total));
     HIP_OK(hipMemsetAsync(ctx->state_mem, 0, total, ctx->stream));
@@ -949,10 +1398,11 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
     ctx->d_ones = (double*)(ctx->state_mem + ones_off);
     ctx->d_logf = (double*)(ctx->state_mem + logf_off);
     HIP_OK(hipMalloc(&ctx->d_chi, (n - 1) * sizeof(int)));
+    HIP_OK(hipMalloc(&ctx->d_work, 2 * sizeof(unsigned long long)));
     HIP_OK(hipHostMalloc(&ctx->h_flags, 4096 * 4 * sizeof(int), hipHostMallocDefault));
     // |0...0>: B_j = e_0 of shape (1, 2, 1); Lambda_b = [1]; ones for edge weights
-    std::vector<double> one(2048, 1.0);
-    HIP_OK(hipMemcpyAsync(ctx->d_ones, one.data(), 2048 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    std::vector<double> one(4096, 1.0);
+    HIP_OK(hipMemcpyAsync(ctx->d_ones, one.data(), 4096 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     const double c64[2] = {1.0, 0.0};
     const float c32[2] = {1.f, 0.f};
     for (int j = 0; j < n; ++j)
@@ -1018,7 +1468,7 @@ mps_status mps_apply_cluster(mps_handle ctx, const int* qubits, int k, const dou
       for (int j = 0; j < ds; ++j)
         if ((i & idle_mask) == (j & idle_mask)) job.U[(size_t)i * ds + j] = Uk[(size_t)sub(i) * dk + sub(j)];
     std::vector<Job> jobs{job};
-    run_jobs(ctx, jobs, {});
+    run_jobs(ctx, jobs, {}, 0);
     return MPS_OK;
   });
 }
@@ -1341,8 +1791,8 @@ mps_status mps_set_timing(mps_handle ctx, int on) {
   return MPS_OK;
 }
 
-mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, int cap, char* names, int names_cap,
-                            int* count) {
+mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, double* flop, int cap, char* names,
+                            int names_cap, int* count) {
   if (!ctx || !count) return MPS_EINVAL;
   const int c = (int)ctx->timer.names.size();
   *count = c;
@@ -1351,6 +1801,7 @@ mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, int c
     if (i < cap) {
       if (ms) ms[i] = ctx->timer.ms[i];
       if (launches) launches[i] = ctx->timer.launches[i];
+      if (flop) flop[i] = ctx->timer.flop[i];
     }
     all += (i ? "," : "") + ctx->timer.names[i];
   }

@@ -72,6 +72,7 @@ struct KernelTimer {
   std::vector<std::string> names;
   std::vector<double> ms;
   std::vector<int64_t> launches;
+  std::vector<double> flop;  // algorithmic real flops per class (8 per complex MAC)
   struct Pending {
     int cls;
     hipEvent_t a, b;
@@ -97,6 +98,7 @@ struct mps_ctx {
   std::vector<double*> lam;         // per-bond Schmidt values (device)
   char* state_mem = nullptr;        // one allocation holding sites and lambdas
   int* d_chi = nullptr;             // device bond dimensions (n-1)
+  unsigned long long* d_work = nullptr;  // eig_update complex-MAC counter
   double* d_logf = nullptr;         // device sum log f
   double* d_ones = nullptr;         // weights of a left edge (all ones)
   int ones_len = 0;
@@ -110,4 +112,24 @@ struct mps_ctx {
   ctebd::KernelTimer timer;
   int q_max_eff = 0, l_max_eff = 0;
   double eps_eff = 0.0;
+  // learned sketch: attached network (device parameters) and the log of
+  // (features, log2 kept rank) of every truncated SVD since the last read
+  const float* mlp_params = nullptr;
+  std::vector<float> log_x, log_t;
+  uint64_t sketch_seed = 0x9E3779B97F4A7C15ull;
+  uint32_t sketch_stream = 0;
 };
+
+struct mlp_ctx {
+  float* P = nullptr;      // parameters (device)
+  float* m = nullptr;      // Adam moments
+  float* v = nullptr;
+  float* g = nullptr;      // gradient
+  int t = 0;               // Adam step count
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+namespace ctebd {
+constexpr int N_FEAT = 12;
+}

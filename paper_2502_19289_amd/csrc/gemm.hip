@@ -50,6 +50,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
   const int b = t / d.ksplit;
   const int m0 = ti * BM, n0 = tj * BN;
   if (b >= d.batch || m0 >= M || n0 >= N) return;
+  if (d.skip && *d.skip) return;
   if (MODE == MODE_GRAM && ti > tj) return;
 
   const CI* A = (const CI*)d.A + (int64_t)b * d.sA;

@@ -27,6 +27,7 @@ struct GemmDesc {
   const double* w;  // GRAM row weights
   int wshift;
   double alpha;
+  const int* skip;  // when non-null and *skip != 0 the problem is skipped
 };
 
 struct GramReduceDesc {
@@ -58,29 +59,79 @@ constexpr int JB = 32;        // Jacobi block size: subproblems are 2*JB square
 constexpr int JP = 2 * JB;    // subproblem / update-tile size
 
 struct EigDesc {
-  double2* G;       // Hermitian matrix, ld x ld, overwritten (-> diagonal)
-  double2* V;       // eigenvectors (columns), ld x ld
-  double2* J;       // workspace: npair_max subproblem rotations of JP x JP
+  double2* G;       // Hermitian Gram matrix (FP64), ld x ld
+  double2* V;       // eigenvectors (columns, FP64), ld x ld
+  void* Gw;         // working copy rotated to diagonal form (== G for FP64)
+  void* Vw;         // working eigenvectors (== V for FP64)
+  void* J;          // workspace: npair_max subproblem rotations of JP x JP
+  double2* W;       // FP32 solve: G V for the Rayleigh quotients
+  double* lam;      // FP32 solve: FP64 Rayleigh quotients (n entries)
   int* pair_rot;    // per pair slot: rotation applied this round
   int* flags;       // [0] converged, [1] rotated during the current sweep
   double* scale;    // trace of G (set by eig_init)
+  unsigned long long* work;  // complex MACs executed by eig_update (or null)
   Dim n;            // matrix size
   int ld;
   int nb_max;       // block count the grids reserve (even)
   double tol;       // relative off-diagonal threshold
 };
 
-hipError_t launch_eig_init(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
-hipError_t launch_eig_pairs(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+// fp32: the solve runs in FP32 on Gw/Vw (then eig_to64 + W = G V + rayleigh)
+hipError_t launch_eig_init(bool fp32, const EigDesc* d, int nprob, int ld_max, hipStream_t s);
+hipError_t launch_eig_pairs(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
                             hipStream_t s);
-hipError_t launch_eig_update(const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
+hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
                              hipStream_t s);
 hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s);
+hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
+hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s);
+
+// ------------------------------------------------------ learned sketch ----
+constexpr int SK_PROBES = 8;
+
+// One randomized range finder on the Gram matrix G of a split (2c x 2c).
+struct SketchDesc {
+  Dim n;               // 2c
+  int s;               // sketch size
+  int ld_s;            // leading dim of the n x s (and n x SK_PROBES) panels
+  int ld_y;            // leading dim of the s x s matrices
+  uint64_t seed;
+  uint32_t stream;
+  double2* Omega;      // n x s Gaussian test matrix
+  double2* Probe;      // n x SK_PROBES Gaussian probes
+  double2* Bq;         // s x s: U Lambda^{-1/2}
+  const double2* R1;   // n x SK_PROBES: G probes
+  const double2* R2;   // n x SK_PROBES: (G Q)(Q^H probes); R1 - R2 = G (I - Q Q^H) probes
+  const double2* Gy;   // diagonalised Y^H Y (eigenvalues on the diagonal)
+  const double2* Uy;   // its eigenvectors
+  const double2* Hw;   // diagonalised Q^H G Q
+  double* lam;         // out: eigenvalues of Q^H G Q (s)
+  const double* trace; // trace of G
+  double eps_eff;
+  int* use;            // out: 1 when the sketch is accepted
+  double* est;         // out: [residual estimate, trace]
+  int* exact_flags;    // the exact solve's flags (converged := 1 when accepted)
+};
+hipError_t launch_gauss_fill(const SketchDesc* d, int nprob, int which, hipStream_t s);
+hipError_t launch_orth_scale(const SketchDesc* d, int nprob, hipStream_t s);
+hipError_t launch_sketch_accept(const SketchDesc* d, int nprob, hipStream_t s);
+
+int mlp_param_count();
+int mlp_chunk();
+hipError_t launch_mlp_forward(const float* P, const float* X, float* y, int B, hipStream_t s);
+hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const int* idx, int B, float tau,
+                           float* part, float* loss_part, float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* P, const float* g, float* m, float* v, float lr, int t, hipStream_t s);
 
 // ------------------------------------------------------- site kernels ----
 // Truncation selection for one split (one workgroup per problem).
 struct SelectDesc {
   const double2* G;     // diagonalised Gram matrix (eigenvalues on the diagonal)
+  const double* lam_in; // eigenvalues given explicitly instead (or null)
+  const int* use_sk;    // when *use_sk: take lam_sk (s_sk values) and total *tot_sk
+  const double* lam_sk;
+  const double* tot_sk;
+  int s_sk;
   int ldg;
   Dim n;                // 2c
   int rows;             // chi_l 2^m: rank bound of X
@@ -98,6 +149,9 @@ hipError_t launch_select(const SelectDesc* d, int nprob, hipStream_t s);
 struct GatherDesc {
   const double2* V;
   int ldv;
+  const int* use_sk;    // when *use_sk: V := Vs with leading dim ld_sk
+  const double2* Vs;
+  int ld_sk;
   const int* perm;
   const int* r;
   Dim n;            // rows of V used (2c)

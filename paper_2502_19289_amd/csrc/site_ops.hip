@@ -127,13 +127,14 @@ __global__ __launch_bounds__(1024) void select_kernel(const SelectDesc* __restri
   __shared__ double red[1024];
   __shared__ int ired[1024];
   const SelectDesc& d = descs[blockIdx.x];
-  const int n = dim_value(d.n);
+  const bool sk = d.use_sk && *d.use_sk;  // accepted learned sketch: its s eigenvalues
+  const int n = sk ? d.s_sk : dim_value(d.n);
   int np2 = 1;
   while (np2 < n) np2 <<= 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < np2; i += 1024) {
     if (i < n) {
-      const double v = d.G[(int64_t)i * d.ldg + i].x;
+      const double v = sk ? d.lam_sk[i] : d.lam_in ? d.lam_in[i] : d.G[(int64_t)i * d.ldg + i].x;
       val[i] = v > 0.0 ? v : 0.0;
     } else {
       val[i] = -1.0;
@@ -172,7 +173,8 @@ __global__ __launch_bounds__(1024) void select_kernel(const SelectDesc* __restri
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
-  const double tot = red[0];
+  // the sketch misses eigenvalues below the threshold: the total is trace(G)
+  const double tot = sk ? *d.tot_sk : red[0];
   __syncthreads();
   // count of normalised singular values >= eps_eff
   int c = 0;
@@ -227,11 +229,14 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restric
   const int tr = t / tcols, tc = t % tcols;  // tr: block of kept columns i, tc: block of V rows
   const int i0 = tr * 64, v0 = tc * 64;
   if (i0 >= r || v0 >= n) return;
+  const bool sk = d.use_sk && *d.use_sk;  // accepted learned sketch: V = Q W
+  const double2* V = sk ? d.Vs : d.V;
+  const int ldv = sk ? d.ld_sk : d.ldv;
   // read V[v0 + a][perm[i0 + b]] -> tile[a][b]
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int a = e >> 6, b = e & 63;
     double2 v = make_double2(0.0, 0.0);
-    if (v0 + a < n && i0 + b < r) v = d.V[(int64_t)(v0 + a) * d.ldv + d.perm[i0 + b]];
+    if (v0 + a < n && i0 + b < r) v = V[(int64_t)(v0 + a) * ldv + d.perm[i0 + b]];
     tile[a][b] = v;
   }
   __syncthreads();

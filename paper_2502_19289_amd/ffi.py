@@ -47,9 +47,13 @@ class CtebdError(RuntimeError):
 
 
 EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster",
-           "mps_run_layer", "mps_flush", "mps_fidelity", "mps_bond_dims", "mps_schmidt",
+           "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_clone", "mps_overlap",
+           "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
-           "mps_set_timing", "mps_kernel_times", "mps_last_error", "mps_plan"]
+           "mps_set_timing", "mps_kernel_times", "mps_last_error", "mps_plan",
+           "mlp_num_params", "mlp_create", "mlp_destroy", "mlp_get_params", "mlp_set_params",
+           "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log"]
+N_FEAT = 12
 
 _lib = None
 
@@ -68,6 +72,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_apply_cluster.argtypes = [P, C.POINTER(I), I, C.POINTER(D)]
     lib.mps_run_layer.argtypes = [P, C.POINTER(GateC), I]
     lib.mps_flush.argtypes = [P]
+    lib.mps_queue_layer.argtypes = [P, C.POINTER(GateC), I]
+    lib.mps_step.argtypes = [P, C.POINTER(I), C.POINTER(I)]
+    lib.mps_clone.argtypes = [P, C.POINTER(Options), C.POINTER(P)]
+    lib.mps_overlap.argtypes = [P, P, C.POINTER(D), C.POINTER(D)]
     lib.mps_fidelity.argtypes = [P, C.POINTER(D), C.POINTER(D)]
     lib.mps_bond_dims.argtypes = [P, C.POINTER(I)]
     lib.mps_schmidt.argtypes = [P, I, C.POINTER(D), I, C.POINTER(I)]
@@ -76,11 +84,23 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_amplitudes.argtypes = [P, C.POINTER(D), C.c_int64]
     lib.mps_get_stats.argtypes = [P, C.POINTER(Stats)]
     lib.mps_set_timing.argtypes = [P, I]
-    lib.mps_kernel_times.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int64), I, C.c_char_p, I, C.POINTER(I)]
+    lib.mps_kernel_times.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), I, C.c_char_p, I,
+                                     C.POINTER(I)]
     lib.mps_last_error.argtypes = [P]
     lib.mps_last_error.restype = C.c_char_p
     lib.mps_plan.argtypes = [I, I, I, I, C.POINTER(I), C.POINTER(GateC), C.POINTER(I), I, I,
                              C.POINTER(I), C.POINTER(I), I, C.POINTER(I), C.POINTER(I)]
+    F = C.POINTER(C.c_float)
+    lib.mlp_num_params.argtypes = []
+    lib.mlp_create.argtypes = [I, C.POINTER(P)]
+    lib.mlp_destroy.argtypes = [P]
+    lib.mlp_get_params.argtypes = [P, F]
+    lib.mlp_set_params.argtypes = [P, F]
+    lib.mlp_forward.argtypes = [P, F, I, F]
+    lib.mlp_grad.argtypes = [P, F, F, I, C.c_float, F, F]
+    lib.mlp_train.argtypes = [P, F, F, I, I, I, C.c_float, C.c_float, C.c_uint64, F]
+    lib.mps_set_sketch_model.argtypes = [P, P]
+    lib.mps_svd_log.argtypes = [P, F, F, I, C.POINTER(I)]
     for name in EXPORTS:
         if name != "mps_last_error":
             getattr(lib, name).restype = C.c_int
@@ -135,6 +155,7 @@ class MPS:
         st = self.lib.mps_create(n, chi_max, eps, C.byref(o), C.byref(h))
         if st != MPS_OK:
             raise CtebdError(st, "mps_create failed")
+        self._opt = o
         self.h = h
         self.n = n
 
@@ -164,6 +185,38 @@ class MPS:
 
     def flush(self):
         self._check(self.lib.mps_flush(self.h))
+
+    def queue_layer(self, gates: Iterable[Tuple[Sequence[int], np.ndarray]]):
+        arr, ng = make_gates(gates)
+        self._check(self.lib.mps_queue_layer(self.h, arr, ng))
+
+    def step(self) -> Tuple[int, int]:
+        """Executes one cluster-TEBD step; returns (clusters, sub-layers left)."""
+        c, r = C.c_int(), C.c_int()
+        self._check(self.lib.mps_step(self.h, C.byref(c), C.byref(r)))
+        return c.value, r.value
+
+    def clone(self, precision: Optional[str] = None, batch: Optional[str] = None) -> "MPS":
+        o = Options()
+        o.k_max, o.q_max, o.l_max = self._opt.k_max, self._opt.q_max, self._opt.l_max
+        o.precision = PREC[precision] if precision else self._opt.precision
+        o.batch = BATCH[batch] if batch else self._opt.batch
+        o.svd_mode, o.floor_c, o.hip_stream = self._opt.svd_mode, self._opt.floor_c, None
+        h = C.c_void_p()
+        self._check(self.lib.mps_clone(self.h, C.byref(o), C.byref(h)))
+        m = MPS.__new__(MPS)
+        m.lib, m.h, m.n, m._opt = self.lib, h, self.n, o
+        return m
+
+    def overlap(self, other: "MPS") -> complex:
+        re, im = C.c_double(), C.c_double()
+        self._check(self.lib.mps_overlap(self.h, other.h, C.byref(re), C.byref(im)))
+        return complex(re.value, im.value)
+
+    def infidelity(self, other: "MPS") -> float:
+        """1 - |<a|b>|^2 / (<a|a><b|b>), computed on the device in FP64."""
+        ab = abs(self.overlap(other)) ** 2
+        return 1.0 - ab / (self.overlap(self).real * other.overlap(other).real)
 
     def fidelity(self) -> Tuple[float, float]:
         f, lf = C.c_double(), C.c_double()
@@ -215,14 +268,97 @@ class MPS:
         self._check(self.lib.mps_set_timing(self.h, int(on)))
 
     def kernel_times(self) -> dict:
+        """{class: (ms, launches, algorithmic flops)} since timing was switched on."""
         cnt = C.c_int()
         ms = np.zeros(64)
+        fl = np.zeros(64)
         la = np.zeros(64, dtype=np.int64)
         names = C.create_string_buffer(4096)
         self._check(self.lib.mps_kernel_times(self.h, _dptr(ms), la.ctypes.data_as(C.POINTER(C.c_int64)),
-                                              64, names, 4096, C.byref(cnt)))
+                                              _dptr(fl), 64, names, 4096, C.byref(cnt)))
         nm = names.value.decode().split(",") if cnt.value else []
-        return {n: (float(ms[i]), int(la[i])) for i, n in enumerate(nm)}
+        return {n: (float(ms[i]), int(la[i]), float(fl[i])) for i, n in enumerate(nm)}
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class KeptRankNet:
+    """The kept-rank network of the learned sketch (device-resident, FP32)."""
+
+    def __init__(self, seed: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.mlp_create(seed, C.byref(h))
+        if st != MPS_OK:
+            raise CtebdError(st, "mlp_create failed")
+        self.h = h
+        self.n_params = self.lib.mlp_num_params()
+
+    def _check(self, st):
+        if st != MPS_OK:
+            raise CtebdError(st, "network call failed")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.lib.mlp_get_params(self.h, _fptr(p)))
+        return p
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self.lib.mlp_set_params(self.h, _fptr(p)))
+
+    def forward(self, X: np.ndarray) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        y = np.zeros(X.shape[0], dtype=np.float32)
+        self._check(self.lib.mlp_forward(self.h, _fptr(X), X.shape[0], _fptr(y)))
+        return y
+
+    def grad(self, X: np.ndarray, t: np.ndarray, tau: float):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_float()
+        self._check(self.lib.mlp_grad(self.h, _fptr(X), _fptr(t), X.shape[0], tau, _fptr(g), C.byref(loss)))
+        return g, loss.value
+
+    def train(self, X, t, epochs=50, batch=256, lr=3e-3, tau=0.9, seed=0) -> float:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        loss = C.c_float()
+        self._check(self.lib.mlp_train(self.h, _fptr(X), _fptr(t), X.shape[0], epochs, batch, lr, tau, seed,
+                                       C.byref(loss)))
+        return loss.value
+
+
+def attach_model(mps: "MPS", net: Optional[KeptRankNet]):
+    st = load().mps_set_sketch_model(mps.h, net.h if net is not None else None)
+    if st != MPS_OK:
+        raise CtebdError(st, "mps_set_sketch_model failed")
+
+
+def svd_log(mps: "MPS"):
+    """Moves the (features, log2 kept rank) pairs logged by `mps` out of it."""
+    lib = load()
+    cnt = C.c_int()
+    lib.mps_svd_log(mps.h, None, None, 0, C.byref(cnt))
+    n = cnt.value
+    X = np.zeros((max(n, 1), N_FEAT), dtype=np.float32)
+    t = np.zeros(max(n, 1), dtype=np.float32)
+    lib.mps_svd_log(mps.h, _fptr(X), _fptr(t), n, C.byref(cnt))
+    return X[:n], t[:n]
 
 
 def plan(n: int, k_max: int, layers, chi: Sequence[int], start: int = 0, q_max: int = 0, l_max: int = 0):

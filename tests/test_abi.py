@@ -22,7 +22,7 @@ def test_exports_every_declared_symbol():
     ffi = _lib()
     lib = ffi.load()
     header = open(os.path.join(ROOT, "include", "cluster_tebd.h")).read()
-    declared = set(re.findall(r"^\s*(?:const char\*|mps_status)\s+(mps_\w+)\s*\(", header, re.M))
+    declared = set(re.findall(r"^\s*(?:const char\*|mps_status|int)\s+((?:mps|mlp)_\w+)\s*\(", header, re.M))
     assert declared, "no declarations parsed"
     for name in declared:
         assert hasattr(lib, name), name

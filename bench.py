@@ -36,7 +36,21 @@ PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 PEAK_VALU_TF = {"fp64": 78.6, "fp32": 157.3}
 PEAK_HBM = 8000.0
 
-MFMA_CLASSES = ("merge", "apply", "gram", "project", "eig_update", "eig_rayleigh")
+MFMA_CLASSES = ("merge", "apply", "gram", "project", "eig_update", "eig_update32", "eig_rayleigh", "sketch")
+CONTRACTIONS = ("merge", "apply", "project")
+
+
+def class_peak(name: str, dtype: str):
+    """(bound, precision, peak TFLOP/s) of a kernel class in a run of `dtype`."""
+    if name in MFMA_CLASSES:
+        if dtype == "fp64" or name in ("gram", "eig_rayleigh", "eig_update", "sketch"):
+            return "mfma", "fp64", PEAK_TF["fp64"]
+        if dtype == "bf16x6" and name in CONTRACTIONS:
+            # six BF16 products per real product: algorithmic flops against peak/6
+            return "mfma", "bf16x6", PEAK_TF["bf16"] / 6.0
+        return "mfma", "fp32", PEAK_TF["fp32"]
+    prec = "fp32" if name.endswith("32") else ("fp64" if dtype == "fp64" or name == "eig_pairs" else "fp32")
+    return "alu", prec, PEAK_VALU_TF[prec]
 
 
 def parse():
@@ -86,12 +100,7 @@ def roofline(kt: dict, dtype: str) -> dict:
     name, (ms, launches, flop) = max(kt.items(), key=lambda kv: kv[1][0])
     avg_ms = ms / max(1, launches)
     per_launch = flop / max(1, launches)
-    if name in MFMA_CLASSES:
-        prec = "fp64" if (dtype == "fp64" or name in ("gram", "eig_rayleigh")) else "fp32"
-        peak, bound = PEAK_TF[prec], "mfma"
-    else:
-        prec = "fp64" if dtype == "fp64" else "fp32"
-        peak, bound = PEAK_VALU_TF[prec], "alu"
+    bound, prec, peak = class_peak(name, dtype)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     return {"bound": bound, "kernel": name, "precision": prec, "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
@@ -102,10 +111,10 @@ def mfma_share(kt: dict, dtype: str) -> dict:
     """Achieved fraction of the matrix-core peak of each contraction class."""
     out = {}
     for k, (ms, launches, flop) in kt.items():
-        if k not in MFMA_CLASSES or ms <= 0:
+        if k not in MFMA_CLASSES or ms <= 0 or flop <= 0:
             continue
-        prec = "fp64" if (dtype == "fp64" or k in ("gram", "eig_rayleigh")) else "fp32"
-        out[k] = round(flop / (ms * 1e-3) / 1e12 / PEAK_TF[prec], 4)
+        _, _, peak = class_peak(k, dtype)
+        out[k] = round(flop / (ms * 1e-3) / 1e12 / peak, 4)
     return out
 
 

@@ -150,13 +150,14 @@ mps_status mps_step(mps_handle h, int* clusters, int* remaining);
  * eps are those of h.  Synchronises. */
 mps_status mps_clone(mps_handle h, const mps_options* opt, mps_handle* out);
 
-/* <a|b> of the states of two handles with the same n, by a transfer-matrix
- * sweep in FP64 on the device (E <- sum_s A_s^dagger E B_s).  Flushes both and
- * synchronises. */
+/* <a|b> of the current states of two handles with the same n (buffered
+ * layers are not applied), by a transfer-matrix sweep in FP64 on the device
+ * (E <- sum_s A_s^dagger E B_s).  Synchronises. */
 mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im);
 
-/* Eq. approxF: flushes, synchronises, returns F_est = exp(sum log f_i) and
- * sum log f_i (either pointer may be NULL). */
+/* Eq. approxF: synchronises and returns F_est = exp(sum log f_i) and
+ * sum log f_i (either pointer may be NULL) of the steps executed so far;
+ * buffered layers are not flushed (call mps_flush first for those). */
 mps_status mps_fidelity(mps_handle h, double* F_est, double* log_f);
 
 /* Synchronises; writes the n-1 current bond dimensions into chi. */

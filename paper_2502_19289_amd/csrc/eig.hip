@@ -140,6 +140,8 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
   __shared__ C rot[JP / 2][4];
   __shared__ int rp[JP / 2], rq[JP / 2];
   __shared__ int need;
+  __shared__ int act[JP / 2];
+  __shared__ int nact[2];
 
   const int p = find_problem(base, nprob, blockIdx.x);
   const EigDesc& d = descs[p];
@@ -147,6 +149,7 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
   const int tid = threadIdx.x;
   const int n = dim_value(d.n);
   const int nb = nblocks_of(n);
+  if (tid == 0) nact[0] = 0;
   if (d.flags[0] || 2 * slot >= nb || round >= nb - 1) {
     if (tid == 0) d.pair_rot[slot] = 0;
     return;
@@ -192,8 +195,9 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
     rotated = 1;
     // real flops of one inner sweep: 63 rounds of 1024 two-sided 2x2 updates
     // (112 flops each) and 2048 column-pair updates of Jm (28 flops each)
-    if (tid == 0 && d.work) atomicAdd(d.work + 1, (unsigned long long)(JP - 1) * (1024 * 112 + 2048 * 28));
+    int rounds_done = 0;
     for (int r = 0; r < JP - 1; ++r) {
+      if (tid == 0) nact[(r + 1) & 1] = 0;
       if (tid < JP / 2) {
         int a, b;
         pair64(r, tid, a, b);
@@ -203,7 +207,10 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
         const C c = S[a][b];
         const T g = sqrt(tabs2(c));
         C j00 = mkc<C>(1, 0), j01 = mkc<C>(0, 0), j10 = mkc<C>(0, 0), j11 = mkc<C>(1, 0);
-        if (g > floor_abs && g * g > tol_in * tol_in * fabs(sa * sd)) {
+        const bool on = g > floor_abs && g * g > tol_in * tol_in * fabs(sa * sd);
+        act[tid] = on ? 1 : 0;
+        if (on) atomicAdd(&nact[r & 1], 1);
+        if (on) {
           // J2 = diag(e, 1) [[cs, sn], [-sn, cs]] with e = c/|c| zeroes S_ab
           const T ex = c.x / g, ey = c.y / g;
           const T zeta = (sd - sa) / ((T)2 * g);
@@ -220,9 +227,12 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
         rot[tid][3] = j11;
       }
       __syncthreads();
+      if (nact[r & 1] == 0) continue;  // every rotation of this round is the identity
+      ++rounds_done;
       // S <- J^H S J on 2x2 blocks (row slot ra, column slot cb), one owner each
       for (int blk = tid; blk < (JP / 2) * (JP / 2); blk += EP_THREADS) {
         const int ra = blk / (JP / 2), cb = blk % (JP / 2);
+        if (!act[ra] && !act[cb]) continue;
         const int pa = rp[ra], qa = rq[ra], pb = rp[cb], qb = rq[cb];
         const C m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
         const C c00 = rot[cb][0], c01 = rot[cb][1], c10 = rot[cb][2], c11 = rot[cb][3];
@@ -249,6 +259,7 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
       // Jm <- Jm * J (columns pb, qb of every row)
       for (int e = tid; e < JP * (JP / 2); e += EP_THREADS) {
         const int row = e / (JP / 2), cb = e % (JP / 2);
+        if (!act[cb]) continue;
         const int pb = rp[cb], qb = rq[cb];
         const C x = Jm[row][pb], y = Jm[row][qb];
         Jm[row][pb] = tadd(tmul(x, rot[cb][0]), tmul(y, rot[cb][2]));
@@ -256,6 +267,8 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
       }
       __syncthreads();
     }
+    if (tid == 0 && d.work)  // real flops: per executed round at most 1024 two-sided
+      atomicAdd(d.work + 1, (unsigned long long)rounds_done * (1024 * 112 + 2048 * 28));  // + 2048 J updates
   }
   if (!rotated) {
     if (tid == 0) d.pair_rot[slot] = 0;

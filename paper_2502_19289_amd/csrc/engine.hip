@@ -445,11 +445,11 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
   for (int sw = 0; sw < 30; ++sw) {
     for (int round = 0; round < nb_all - 1; ++round) {
       {
-        Timed tm(ctx, "eig_pairs");
+        Timed tm(ctx, fp32 ? "eig_pairs32" : "eig_pairs");
         HIP_OK(launch_eig_pairs(fp32, de, b_pair, np, n_pair, round, s));
       }
       {
-        Timed tm(ctx, "eig_update");
+        Timed tm(ctx, fp32 ? "eig_update32" : "eig_update");
         HIP_OK(launch_eig_update(fp32, de, b_upd, np, n_upd, round, s));
       }
     }
@@ -545,7 +545,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     runs[i].flag_index = i;
   }
   if (nj) HIP_OK(hipMemsetAsync(logf_all, 0, nj * sizeof(double), s));
-  if (ctx->timing) HIP_OK(hipMemsetAsync(ctx->d_work, 0, 2 * sizeof(unsigned long long), s));
+  if (ctx->timing) HIP_OK(hipMemsetAsync(ctx->d_work, 0, 4 * sizeof(unsigned long long), s));
 
   DescBlob& B = ctx->blob;
   B.host.clear();
@@ -728,7 +728,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         e.pair_rot = r.pair_rot;
         e.flags = r.flags;
         e.scale = r.scale;
-        e.work = ctx->timing ? ctx->d_work : nullptr;
+        e.work = ctx->timing ? ctx->d_work + (e32 ? 2 : 0) : nullptr;
         e.n = n2c;
         e.ld = r.ld;
         int nb = ceil_div(2 * lv.c_bound, JB);
@@ -826,10 +826,10 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     std::vector<int> ids;
     std::vector<SketchDesc> sd;
     std::vector<EigDesc> ea, eb;
-    std::vector<GemmDesc> g[9];  // Y, Y^H Y, Q, G Q, H, Vs, C8, R1, R2
+    std::vector<GemmDesc> g[13];  // Y, Y^H Y, Q, G Q, H, Vs, C8, R1, R2, two Newton-Schulz steps
     size_t o_sd = 0, o_ea = 0, o_eb = 0, bp_a = 0, bu_a = 0, bp_b = 0, bu_b = 0;
-    size_t o[9] = {0}, b[9] = {0};
-    int n[9] = {0};
+    size_t o[13] = {0}, b[13] = {0};
+    int n[13] = {0};
     int np_a = 0, nu_a = 0, np_b = 0, nu_b = 0;
     std::vector<int> flag_a, flag_b;
   };
@@ -879,6 +879,15 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     S.g[6].push_back(gemm64(k.Q, k.Probe, k.C8, fs, f8, n2c, fls, fls, fls, k.s, SK_PROBES));  // Q^H g
     S.g[7].push_back(gemm64(r.G, k.Probe, k.R1, n2c, f8, n2c, fld, fls, fls, nb, SK_PROBES));  // G g
     S.g[8].push_back(gemm64(k.Y, k.C8, k.R2, n2c, f8, fs, fls, fls, fls, nb, SK_PROBES));      // G Q Q^H g
+    for (int it = 0; it < 2; ++it) {  // Newton-Schulz: S = X^H X, X' = X (1.5 I - 0.5 S)
+      double2* from = it == 0 ? k.Q : k.Vs;
+      double2* to = it == 0 ? k.Vs : k.Q;
+      GemmDesc g = gemm64(from, from, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);
+      g.w = ctx->d_ones;
+      g.wshift = 0;
+      S.g[9 + 2 * it].push_back(g);
+      S.g[10 + 2 * it].push_back(gemm64(from, k.Bq, to, n2c, fs, fs, fls, fls, fls, nb, k.s));
+    }
     EigDesc ea{};
     ea.G = k.Gy;
     ea.V = k.Uy;
@@ -970,7 +979,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   for (auto& S : SL) {
     if (S.ids.empty()) continue;
     S.o_sd = B.add_vec(S.sd);
-    for (int g = 0; g < 9; ++g) S.n[g] = upload_gemm(S.g[g], S.o[g], S.b[g]);
+    for (int g = 0; g < 13; ++g) S.n[g] = upload_gemm(S.g[g], S.o[g], S.b[g]);
     std::vector<int> pa{0}, ua{0};
     for (const auto& e : S.ea) {
       pa.push_back(pa.back() + e.nb_max / 2);
@@ -1063,6 +1072,12 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         Timed tm(ctx, "sketch");
         HIP_OK(launch_orth_scale(dsk, ns, s));
         nn(2);
+        for (int it = 0; it < 2; ++it) {
+          HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[9 + 2 * it]), B.at<int>(S.b[9 + 2 * it]), ns,
+                             S.n[9 + 2 * it], s));
+          HIP_OK(launch_newton_schulz(dsk, ns, s));
+          nn(10 + 2 * it);
+        }
         nn(3);
         cn(4);
         HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
@@ -1128,13 +1143,15 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       off += 4 * (r.k - 1);
     }
   }
-  unsigned long long eig_work[2] = {0, 0};
+  unsigned long long eig_work[4] = {0, 0, 0, 0};
   if (ctx->timing)
     HIP_OK(hipMemcpyAsync(eig_work, ctx->d_work, sizeof(eig_work), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (ctx->timing) {
     collect_timing(ctx);
     account_flops(ctx, runs, mixed, (double)eig_work[0], (double)eig_work[1]);
+    ctx->timer.flop[ctx->timer.cls_of("eig_update32")] += 8.0 * (double)eig_work[2];
+    ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
   }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
   if (nsk) {
@@ -1145,6 +1162,16 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         ctx->stats.sketch_accepted += 1;
       else
         ctx->stats.sketch_fallback += 1;
+    }
+    if (std::getenv("CTEBD_SKETCH_TRACE")) {
+      for (int q = 0; q < nsk; ++q) {
+        double est[2];
+        HIP_OK(hipMemcpy(est, sk[q].est, sizeof(est), hipMemcpyDeviceToHost));
+        const JobRun& r = runs[sk[q].job];
+        const Level& L = r.lv[sk[q].t];
+        std::fprintf(stderr, "sketch n=%d s=%d kept=%d accepted=%d est/trace=%.3e\n", 2 * L.c_bound, sk[q].s,
+                     ctx->chi[r.a + L.m - 1], skf[12 * q + 8], est[1] > 0 ? est[0] / est[1] : -1.0);
+      }
     }
   }
   // (features, log2 kept rank) of every split, for training the network
@@ -1344,10 +1371,6 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
       ctx->err = "invalid options";
       return MPS_EINVAL;
     }
-    if (o.precision == MPS_PREC_BF16X6) {
-      ctx->err = "BF16X6 contractions are not built in this library version";
-      return MPS_EINVAL;
-    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
       (void)hipGetLastError();
@@ -1398,7 +1421,7 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
     ctx->d_ones = (double*)(ctx->state_mem + ones_off);
     ctx->d_logf = (double*)(ctx->state_mem + logf_off);
     HIP_OK(hipMalloc(&ctx->d_chi, (n - 1) * sizeof(int)));
-    HIP_OK(hipMalloc(&ctx->d_work, 2 * sizeof(unsigned long long)));
+    HIP_OK(hipMalloc(&ctx->d_work, 4 * sizeof(unsigned long long)));
     HIP_OK(hipHostMalloc(&ctx->h_flags, 4096 * 4 * sizeof(int), hipHostMallocDefault));
     // |0...0>: B_j = e_0 of shape (1, 2, 1); Lambda_b = [1]; ones for edge weights
     std::vector<double> one(4096, 1.0);
@@ -1565,8 +1588,6 @@ mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im) {
   if (!a || !b || a->n != b->n) return MPS_EINVAL;
   mps_ctx* ctx = a;
   return guarded(ctx, [&]() -> mps_status {
-    flush_all(a);
-    flush_all(b);
     HIP_OK(hipStreamSynchronize(b->stream));
     HIP_OK(hipStreamSynchronize(a->stream));
     hipStream_t s = a->stream;
@@ -1650,7 +1671,6 @@ mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im) {
 mps_status mps_fidelity(mps_handle ctx, double* F_est, double* log_f) {
   if (!ctx) return MPS_EINVAL;
   return guarded(ctx, [&]() -> mps_status {
-    flush_all(ctx);
     double lf = 0;
     HIP_OK(hipMemcpyAsync(&lf, ctx->d_logf, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));

@@ -197,15 +197,155 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramReduceDesc* 
   }
 }
 
+// ------------------------------------------------------------ BF16X6 ----
+// C = A B for complex64 A, B with the BF16 matrix cores: every FP32 component
+// x is split exactly into x = hi + mid + lo (three BF16 values, 24 mantissa
+// bits in all) and each real product keeps the six partial products of order
+// >= 2^-16 relative (hh, hm, mh, hl, lh, mm), accumulated in FP32.
+// Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br.  64x64 complex output per workgroup,
+// four wavefronts of 32x32 (2x2 blocks of v_mfma_f32_16x16x32_bf16), K slices
+// of 32 staged in LDS as three planes per real component.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r1 = x - (float)h;
+  m = (__bf16)r1;
+  const float r2 = r1 - (float)m;
+  l = (__bf16)r2;
+}
+
+constexpr int XK = 32, XPAD = 40;  // K slice and padded LDS row (bf16 elements)
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc += X * Y with the six-product split; X planes xa[3], Y planes yb[3]
+__device__ __forceinline__ f32x4 mac6(const bf16x8* xa, const bf16x8* yb, f32x4 acc) {
+  acc = mfma_bf16(xa[0], yb[0], acc);
+  acc = mfma_bf16(xa[0], yb[1], acc);
+  acc = mfma_bf16(xa[1], yb[0], acc);
+  acc = mfma_bf16(xa[0], yb[2], acc);
+  acc = mfma_bf16(xa[2], yb[0], acc);
+  acc = mfma_bf16(xa[1], yb[1], acc);
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __restrict__ descs,
+                                                           const int* __restrict__ base, int nprob) {
+  // planes [3 (hi,mid,lo)][2 (re,im)][64 rows][XPAD]; A as [m][k], B as [n][k]
+  __shared__ __attribute__((aligned(16))) __bf16 As[3][2][64][XPAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[3][2][64][XPAD];
+
+  const int p = find_problem(base, nprob, blockIdx.x);
+  const GemmDesc& d = descs[p];
+  int t = blockIdx.x - base[p];
+  const int M = dim_value(d.M), N = dim_value(d.N), K = dim_value(d.K);
+  const int lda = dim_value(d.lda), ldb = dim_value(d.ldb), ldc = dim_value(d.ldc);
+  const int tj = t % d.tn;
+  t /= d.tn;
+  const int ti = t % d.tm;
+  t /= d.tm;
+  const int b = t;
+  const int m0 = ti * 64, n0 = tj * 64;
+  if (b >= d.batch || m0 >= M || n0 >= N) return;
+  if (d.skip && *d.skip) return;
+  const float2* A = (const float2*)d.A + (int64_t)b * d.sA;
+  const float2* Bm = (const float2*)d.B + (int64_t)b * d.sB;
+  float2* C = (float2*)d.C + (int64_t)b * d.sC;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  f32x4 arr[2][2], ari[2][2], aim[2][2];  // Ar Br, Ai Bi, Ar Bi + Ai Br
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      arr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ari[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      aim[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  for (int k0 = 0; k0 < K; k0 += XK) {
+    {  // A: row r = tid/4, k = (tid%4)*8 .. +7
+      const int r = tid >> 2, k8 = (tid & 3) * 8;
+      const int gm = m0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + k8 + i;
+        float2 v = make_float2(0.f, 0.f);
+        if (gm < M && gk < K) v = A[(int64_t)gm * lda + gk];
+        split3(v.x, As[0][0][r][k8 + i], As[1][0][r][k8 + i], As[2][0][r][k8 + i]);
+        split3(v.y, As[0][1][r][k8 + i], As[1][1][r][k8 + i], As[2][1][r][k8 + i]);
+      }
+    }
+    {  // B: row k = tid/8, columns (tid%8)*8 .. +7, stored transposed
+      const int kk = tid >> 3, n8 = (tid & 7) * 8;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gn = n0 + n8 + i;
+        float2 v = make_float2(0.f, 0.f);
+        if (gk < K && gn < N) v = Bm[(int64_t)gk * ldb + gn];
+        split3(v.x, Bs[0][0][n8 + i][kk], Bs[1][0][n8 + i][kk], Bs[2][0][n8 + i][kk]);
+        split3(v.y, Bs[0][1][n8 + i][kk], Bs[1][1][n8 + i][kk], Bs[2][1][n8 + i][kk]);
+      }
+    }
+    __syncthreads();
+    const int kq = 8 * (lane >> 4), cl = lane & 15;
+    bf16x8 ar[2][3], ai[2][3], br[2][3], bi[2][3];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) {
+        ar[x][pl] = *(const bf16x8*)&As[pl][0][wm * 32 + x * 16 + cl][kq];
+        ai[x][pl] = *(const bf16x8*)&As[pl][1][wm * 32 + x * 16 + cl][kq];
+        br[x][pl] = *(const bf16x8*)&Bs[pl][0][wn * 32 + x * 16 + cl][kq];
+        bi[x][pl] = *(const bf16x8*)&Bs[pl][1][wn * 32 + x * 16 + cl][kq];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        arr[i][j] = mac6(ar[i], br[j], arr[i][j]);
+        ari[i][j] = mac6(ai[i], bi[j], ari[i][j]);
+        aim[i][j] = mac6(ar[i], bi[j], aim[i][j]);
+        aim[i][j] = mac6(ai[i], br[j], aim[i][j]);
+      }
+    __syncthreads();
+  }
+  const float alpha = (float)d.alpha;
+#pragma unroll
+  for (int bi2 = 0; bi2 < 2; ++bi2)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm * 32 + bi2 * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn * 32 + bj * 16 + (lane & 15);
+        if (gm < M && gn < N)
+          C[(int64_t)gm * ldc + gn] =
+              make_float2((arr[bi2][bj][r] - ari[bi2][bj][r]) * alpha, aim[bi2][bj][r] * alpha);
+      }
+}
+
 }  // namespace
 
 int gemm_tiles(const GemmDesc& d) { return d.tm * d.tn * d.ksplit * d.batch; }
+
+hipError_t launch_gemm_bf16x6(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  cgemm_bf16x6_kernel<<<blocks, 256, 0, s>>>(d_desc, d_base, nprob);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemm_nn(Prec p, const GemmDesc* d_desc, const int* d_base, int nprob, int blocks,
                           hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (p == Prec::FP64)
     cgemm_kernel<double2, double2, double, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  else if (p == Prec::BF16X6)
+    return launch_gemm_bf16x6(d_desc, d_base, nprob, blocks, s);
   else
     cgemm_kernel<float2, float2, float, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
   return hipGetLastError();

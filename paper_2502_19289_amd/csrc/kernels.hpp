@@ -51,6 +51,8 @@ hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, 
                        int blocks, hipStream_t s);
 hipError_t launch_gram_reduce(const GramReduceDesc* d_desc, const int* d_base, int nprob, int blocks,
                               hipStream_t s);
+// complex64 C = A B as six BF16 matrix-core products per real product
+hipError_t launch_gemm_bf16x6(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s);
 // C = A^H B in FP64 (A: K x M, B: K x N, row-major) -- overlaps of two states
 hipError_t launch_gemm_cn(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s);
 
@@ -114,6 +116,7 @@ struct SketchDesc {
 };
 hipError_t launch_gauss_fill(const SketchDesc* d, int nprob, int which, hipStream_t s);
 hipError_t launch_orth_scale(const SketchDesc* d, int nprob, hipStream_t s);
+hipError_t launch_newton_schulz(const SketchDesc* d, int nprob, hipStream_t s);
 hipError_t launch_sketch_accept(const SketchDesc* d, int nprob, hipStream_t s);
 
 int mlp_param_count();

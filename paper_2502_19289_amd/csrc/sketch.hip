@@ -89,6 +89,19 @@ __global__ __launch_bounds__(256) void orth_scale_kernel(const SketchDesc* __res
   }
 }
 
+// Newton-Schulz step towards an orthonormal Q: Bq = 1.5 I - 0.5 Q^H Q (the
+// Gram S of Q is in Gy); Q <- Q Bq squares the orthogonality error.  The
+// first basis comes from Y^H Y, whose conditioning is that of Y squared, so
+// its columns are orthonormal only to u kappa(Y)^2 until these steps.
+__global__ __launch_bounds__(256) void newton_schulz_kernel(const SketchDesc* __restrict__ descs) {
+  const SketchDesc& d = descs[blockIdx.x];
+  for (int e = threadIdx.x; e < d.s * d.s; e += 256) {
+    const int i = e / d.s, j = e % d.s;
+    const double2 g = d.Gy[(int64_t)i * d.ld_y + j];
+    d.Bq[(int64_t)i * d.ld_s + j] = make_double2((i == j ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+  }
+}
+
 // est^2 = mean over probes of ||R[:, p]||^2 (R = G (I - Q Q^H) g); accept when
 // est <= eps_eff^2 trace(G): every eigenvalue outside span(Q) is then below the
 // truncation threshold.  Also copies the H eigenvalues into lam (s entries).
@@ -259,6 +272,12 @@ hipError_t launch_gauss_fill(const SketchDesc* d, int nprob, int which, hipStrea
 hipError_t launch_orth_scale(const SketchDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   orth_scale_kernel<<<nprob, 256, 0, s>>>(d);
+  return hipGetLastError();
+}
+
+hipError_t launch_newton_schulz(const SketchDesc* d, int nprob, hipStream_t s) {
+  if (nprob <= 0) return hipSuccess;
+  newton_schulz_kernel<<<nprob, 256, 0, s>>>(d);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ P = pytest.importorskip("paper_2502_19289_amd")
 
 # infidelity bars: FP64 contractions are exact to rounding; FP32 must stay
 # below the 1e-6 target on the states it produces
-INF_TOL = {"fp64": 1e-11, "fp32": 1e-6}
+INF_TOL = {"fp64": 1e-11, "fp32": 1e-6, "bf16x6": 1e-6}
 
 
 def gpu_run(c, prec="fp32", batch="step", **p):
@@ -66,7 +66,7 @@ def test_exact_workload_vs_statevector(prec, seed):
     assert abs(F - 1) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 @pytest.mark.parametrize("seed,k_max", [(0, 2), (1, 3), (2, 4), (3, 6)])
 def test_dense_exact_vs_statevector(prec, seed, k_max):
     c = dense_circuit(10, 8, 4, seed)
@@ -89,7 +89,7 @@ def test_dense_exact_vs_statevector(prec, seed, k_max):
         assert np.abs(got[: ref.size] - ref).max() < (1e-10 if prec == "fp64" else 1e-5)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 def test_apply_cluster_haar_vs_statevector(prec):
     n = 9
     m = P.MPS(n, 512, 0.0, k_max=9, precision=prec)
@@ -136,7 +136,7 @@ def test_clifford_workload_entropies_and_oracle(prec):
     assert abs(F - 1) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 @pytest.mark.parametrize("n,chi,a,k,seed", [(12, 37, 4, 2, 0), (14, 64, 5, 4, 1), (16, 100, 6, 3, 2),
                                              (18, 130, 7, 3, 3), (14, 16, 0, 5, 4), (14, 16, 9, 5, 5)])
 def test_step_local_cluster_vs_oracle(prec, n, chi, a, k, seed):

@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0: skip)")
     ap.add_argument("--warmup-budget", type=float, default=240.0, help="seconds cap of the auto warm-up")
     ap.add_argument("--copy-calibration", type=int, default=0)
+    ap.add_argument("--profile-window", action="store_true",
+                    help="ask an attached rocprofv3 to collect only during the timed steps")
     return ap.parse_args()
 
 
@@ -77,6 +79,25 @@ def copy_calibration(nbytes: int):
     b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes}))
+
+
+class ProfilerWindow:
+    """ROCTx pause/resume requests to an attached profiler (no-ops without one)."""
+
+    def __init__(self, on: bool):
+        self.lib = None
+        if on:
+            import ctypes
+            rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+            self.lib = ctypes.CDLL(os.path.join(rocm, "lib", "librocprofiler-sdk-roctx.so"))
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
 
 
 def timed_steps(m, k):
@@ -95,6 +116,31 @@ def timed_steps(m, k):
     return done, m.stats()["cluster_updates"] - c0, dt
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (profiles/*.md, lines ``TRAFFIC kernel=... bytes_per_launch=...
+    sources=a,b sha256=...``); None when no summary covers the kernel or its
+    sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if not line.startswith("TRAFFIC "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") != kernel:
+                continue
+            h = hashlib.sha256()
+            try:
+                for src in kv["sources"].split(","):
+                    with open(os.path.join(ROOT, src), "rb") as fh:
+                        h.update(fh.read())
+            except OSError:
+                return None
+            return float(kv["bytes_per_launch"]) if h.hexdigest() == kv.get("sha256") else None
+    return None
+
+
 def roofline(kt: dict, dtype: str) -> dict:
     """Dominant kernel class of the timed region against its peak."""
     name, (ms, launches, flop) = max(kt.items(), key=lambda kv: kv[1][0])
@@ -103,7 +149,7 @@ def roofline(kt: dict, dtype: str) -> dict:
     bound, prec, peak = class_peak(name, dtype)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     return {"bound": bound, "kernel": name, "precision": prec, "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(name),
             "avg_launch_ms": avg_ms, "launches": launches, "flop_per_launch": per_launch}
 
 
@@ -164,6 +210,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    window = ProfilerWindow(args.profile_window)
+    window.pause()
     import torch  # noqa: F401  (device plumbing only)
 
     import paper_2502_19289_amd as P
@@ -205,7 +253,9 @@ def main():
 
     # ---- timed: batched mixed-precision path
     m.set_timing(True)
+    window.resume()
     steps, updates, dt = timed_steps(m, args.steps)
+    window.pause()
     print(f"# timed {steps} steps, {updates} cluster updates, {dt:.1f} s", file=sys.stderr, flush=True)
     kt = m.kernel_times()
     value = updates / dt

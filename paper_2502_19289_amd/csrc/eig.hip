@@ -54,14 +54,14 @@ __device__ __forceinline__ void pair_of(int nb, int t, int s, int& P, int& Q) {
   }
 }
 
-// slot s of round t among 64 indices (circle method)
-__device__ __forceinline__ void pair64(int t, int s, int& p, int& q) {
+// slot s of round t among the JP indices of a subproblem (circle method)
+__device__ __forceinline__ void pair_in(int t, int s, int& p, int& q) {
   if (s == 0) {
     p = t;
-    q = 63;
+    q = JP - 1;
   } else {
-    p = (t + s) % 63;
-    q = (t - s + 63) % 63;
+    p = (t + s) % (JP - 1);
+    q = (t - s + JP - 1) % (JP - 1);
   }
 }
 
@@ -128,7 +128,8 @@ __global__ __launch_bounds__(256) void eig_init_kernel(const EigDesc* __restrict
 }
 
 // ------------------------------------------------- subproblem rotations --
-constexpr int EP_THREADS = 512;
+// one wavefront per 32x32 subproblem (8 wavefronts for 64x64)
+constexpr int EP_THREADS = JP == 32 ? 64 : 512;
 
 template <typename T>
 __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __restrict__ descs,
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
       if (tid == 0) nact[(r + 1) & 1] = 0;
       if (tid < JP / 2) {
         int a, b;
-        pair64(r, tid, a, b);
+        pair_in(r, tid, a, b);
         rp[tid] = a;
         rq[tid] = b;
         const T sa = S[a][a].x, sd = S[b][b].x;
@@ -268,7 +269,8 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
       __syncthreads();
     }
     if (tid == 0 && d.work)  // real flops: per executed round at most 1024 two-sided
-      atomicAdd(d.work + 1, (unsigned long long)rounds_done * (1024 * 112 + 2048 * 28));  // + 2048 J updates
+      atomicAdd(d.work + 1, (unsigned long long)rounds_done *
+                                ((JP / 2) * (JP / 2) * 112 + JP * (JP / 2) * 28));  // + the Jm updates
   }
   if (!rotated) {
     if (tid == 0) d.pair_rot[slot] = 0;
@@ -283,10 +285,14 @@ __global__ __launch_bounds__(EP_THREADS) void eig_pairs_kernel(const EigDesc* __
 }
 
 // ------------------------------------------------------ apply rotations --
-// Tile products on the matrix cores: each of the four wavefronts owns a 32x32
-// quadrant of the 64x64 output (2x2 MFMA blocks of 16x16).  K = 64 advances in
-// slices of 16; the next slice is fetched into registers while the current
-// one is multiplied.
+// Tile products on the matrix cores: each wavefront owns a 32x32 quadrant of
+// the JP x JP output (2x2 MFMA blocks of 16x16), so a 32x32 tile is one
+// wavefront and a 64x64 tile four.  K = JP advances in slices of 16; the next
+// slice is fetched into registers while the current one is multiplied.
+constexpr int UP_WD = JP / 32;               // wavefronts per tile dimension
+constexpr int UP_THREADS = 64 * UP_WD * UP_WD;
+constexpr int UP_EPT = 16 * JP / UP_THREADS;  // staged elements per thread and slice
+static_assert(JP == 32 || JP == 64, "update tiles are built from 32x32 wavefront quadrants");
 template <typename T>
 struct TileAcc {
   CAcc<T> a[2][2];
@@ -328,7 +334,7 @@ __device__ __forceinline__ void acc_to_lds(const TileAcc<T>& acc, C (*Tt)[JP + 1
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restrict__ descs,
+__global__ __launch_bounds__(UP_THREADS) void eig_update_kernel(const EigDesc* __restrict__ descs,
                                                          const int* __restrict__ base, int nprob,
                                                          int round) {
   using C = typename cpx_of<T>::type;
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   const int npair = nb / 2, npair_max = d.nb_max / 2;
   int t = blockIdx.x - base[p];
   const int ld = d.ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave / UP_WD, wn = wave % UP_WD;
 
   bool is_g;
   int ti, tj, rb = 0;
@@ -379,25 +385,26 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   TileAcc<T> acc;
   acc.clear();
   if (rotj) {
-    const int m = tid >> 2, k4 = (tid & 3) * 4;
-    const int kk = tid >> 4, n4 = (tid & 15) * 4;
+    // A slice: row m of the tile, UP_EPT consecutive k; B slice: row kk of Jj
+    const int m = tid / (16 / UP_EPT), k4 = (tid % (16 / UP_EPT)) * UP_EPT;
+    const int kk = tid / (JP / UP_EPT), n4 = (tid % (JP / UP_EPT)) * UP_EPT;
     const int64_t grow = (int64_t)(is_g ? gidx(Pi, Qi, m) : rb * JP + m) * ld;
-    C ra[4], rbv[4];
+    C ra[UP_EPT], rbv[UP_EPT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < UP_EPT; ++i) {
       ra[i] = Mat[grow + gidx(Pj, Qj, k4 + i)];
       rbv[i] = Jj[kk * JP + n4 + i];
     }
     for (int k0 = 0; k0 < JP; k0 += 16) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < UP_EPT; ++i) {
         As[k4 + i][m] = ra[i];
         Bs[kk][n4 + i] = rbv[i];
       }
       __syncthreads();
       if (k0 + 16 < JP) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < UP_EPT; ++i) {
           ra[i] = Mat[grow + gidx(Pj, Qj, k0 + 16 + k4 + i)];
           rbv[i] = Jj[(k0 + 16 + kk) * JP + n4 + i];
         }
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
     }
     acc_to_lds<T, C>(acc, Tt, lane, wm, wn);
   } else {
-    for (int e = tid; e < JP * JP; e += 256) {
+    for (int e = tid; e < JP * JP; e += UP_THREADS) {
       const int mm = e / JP, c = e % JP;
       const int grow = is_g ? gidx(Pi, Qi, mm) : rb * JP + mm;
       Tt[mm][c] = Mat[(int64_t)grow * ld + gidx(Pj, Qj, c)];
@@ -416,7 +423,7 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   __syncthreads();
 
   if (!is_g) {
-    for (int e = tid; e < JP * JP; e += 256) {
+    for (int e = tid; e < JP * JP; e += UP_THREADS) {
       const int mm = e / JP, c = e % JP;
       Mat[(int64_t)(rb * JP + mm) * ld + gidx(Pj, Qj, c)] = Tt[mm][c];
     }
@@ -426,20 +433,20 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
   // ---- step 2: out = Ji^H * T
   if (roti) {
     acc.clear();
-    const int kk = tid >> 4, m4 = (tid & 15) * 4;
-    C rj[4];
+    const int kk = tid / (JP / UP_EPT), m4 = (tid % (JP / UP_EPT)) * UP_EPT;
+    C rj[UP_EPT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rj[i] = Ji[kk * JP + m4 + i];
+    for (int i = 0; i < UP_EPT; ++i) rj[i] = Ji[kk * JP + m4 + i];
     for (int k0 = 0; k0 < JP; k0 += 16) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < UP_EPT; ++i) {
         As[kk][m4 + i] = mkc<C>(rj[i].x, -rj[i].y);  // (Ji^H)[m][k] = conj(Ji[k][m])
         Bs[kk][m4 + i] = Tt[k0 + kk][m4 + i];
       }
       __syncthreads();
       if (k0 + 16 < JP) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) rj[i] = Ji[(k0 + 16 + kk) * JP + m4 + i];
+        for (int i = 0; i < UP_EPT; ++i) rj[i] = Ji[(k0 + 16 + kk) * JP + m4 + i];
       }
       tile_mma16<T, C>(acc, As, Bs, lane, wm, wn);
       __syncthreads();
@@ -447,7 +454,7 @@ __global__ __launch_bounds__(256) void eig_update_kernel(const EigDesc* __restri
     acc_to_lds<T, C>(acc, Tt, lane, wm, wn);
     __syncthreads();
   }
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += UP_THREADS) {
     const int mm = e / JP, c = e % JP;
     const int gr = gidx(Pi, Qi, mm), gc = gidx(Pj, Qj, c);
     const C v = Tt[mm][c];
@@ -519,9 +526,9 @@ hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int
                              hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (fp32)
-    eig_update_kernel<float><<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
+    eig_update_kernel<float><<<blocks, UP_THREADS, 0, s>>>(d, d_base, nprob, round);
   else
-    eig_update_kernel<double><<<blocks, 256, 0, s>>>(d, d_base, nprob, round);
+    eig_update_kernel<double><<<blocks, UP_THREADS, 0, s>>>(d, d_base, nprob, round);
   return hipGetLastError();
 }
 

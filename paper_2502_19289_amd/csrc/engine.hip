@@ -259,7 +259,7 @@ size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
   }
   if (ks > 1) add((size_t)ks * ld * ld * sizeof(double2));
   add(vr * ctx->esz);
-  add(ld / 64 * sizeof(int));
+  add(ld / JP * sizeof(int) + 16);
   add(ld * sizeof(int));
   add(sizeof(double));
   add(4 * j.k * sizeof(double));
@@ -294,7 +294,7 @@ void assign_job(mps_ctx* ctx, JobRun& j) {
   }
   j.part = ks > 1 ? (double2*)A.take((size_t)ks * ld * ld * sizeof(double2)) : nullptr;
   j.Vr = A.take(vr * ctx->esz);
-  j.pair_rot = (int*)A.take(ld / 64 * sizeof(int));
+  j.pair_rot = (int*)A.take(ld / JP * sizeof(int) + 16);
   j.perm = (int*)A.take(ld * sizeof(int));
   j.scale = (double*)A.take(sizeof(double));
   j.rec = (double*)A.take(4 * j.k * sizeof(double));
@@ -382,7 +382,7 @@ size_t sk_bytes(int n, const SkRun& k) {
   add((size_t)k.ld_y * k.ld_s * sizeof(double2) * 2);  // C8, Bq
   for (int i = 0; i < 4; ++i) add((size_t)k.ld_y * k.ld_y * sizeof(double2));
   add((size_t)k.ld_y * 64 * sizeof(double2) * 2);
-  add((size_t)k.ld_y / 64 * sizeof(int) * 2 + 16);
+  add((size_t)k.ld_y / JP * sizeof(int) * 2 + 32);
   add(k.ld_y * sizeof(double) + 64);
   return b;
 }
@@ -397,8 +397,8 @@ void sk_assign(DeviceArena& A, SkRun& k, int n, int* flags, double* scales) {
   for (auto p : sq) *p = (double2*)A.take((size_t)k.ld_y * k.ld_y * sizeof(double2));
   k.Ja = A.take((size_t)k.ld_y * 64 * sizeof(double2));
   k.Jb = A.take((size_t)k.ld_y * 64 * sizeof(double2));
-  k.pr_a = (int*)A.take((size_t)k.ld_y / 64 * sizeof(int) + 4);
-  k.pr_b = (int*)A.take((size_t)k.ld_y / 64 * sizeof(int) + 4);
+  k.pr_a = (int*)A.take((size_t)k.ld_y / JP * sizeof(int) + 16);
+  k.pr_b = (int*)A.take((size_t)k.ld_y / JP * sizeof(int) + 16);
   k.lam = (double*)A.take(k.ld_y * sizeof(double));
   k.est = (double*)A.take(2 * sizeof(double));
   k.flags_a = flags;

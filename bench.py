@@ -56,10 +56,12 @@ def class_peak(name: str, dtype: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=-1,
                     help="untimed steps first; -1: until a quarter of the bonds reach chi_max")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
+    ap.add_argument("--eig", default="auto", choices=["auto", "jacobi", "tridiag"],
+                    help="eigen-solver of the exact splits")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
@@ -142,9 +144,17 @@ def measured_traffic(kernel: str):
 
 
 def roofline(kt: dict, dtype: str) -> dict:
-    """Dominant kernel class of the timed region against its peak."""
-    name, (ms, launches, flop) = max(kt.items(), key=lambda kv: kv[1][0])
+    """Dominant kernel class of the timed region against its peak: HBM
+    bandwidth for the classes that report algorithmic bytes, else the flop
+    peak of its unit."""
+    name, (ms, launches, flop, nbytes) = max(kt.items(), key=lambda kv: kv[1][0])
     avg_ms = ms / max(1, launches)
+    if nbytes > 0:
+        per_launch = nbytes / max(1, launches)
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        return {"bound": "hbm", "kernel": name, "precision": "fp64", "achieved": achieved, "peak": PEAK_HBM,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM, "traffic": measured_traffic(name),
+                "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": per_launch}
     per_launch = flop / max(1, launches)
     bound, prec, peak = class_peak(name, dtype)
     achieved = per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
@@ -156,7 +166,7 @@ def roofline(kt: dict, dtype: str) -> dict:
 def mfma_share(kt: dict, dtype: str) -> dict:
     """Achieved fraction of the matrix-core peak of each contraction class."""
     out = {}
-    for k, (ms, launches, flop) in kt.items():
+    for k, (ms, launches, flop, _) in kt.items():
         if k not in MFMA_CLASSES or ms <= 0 or flop <= 0:
             continue
         _, _, peak = class_peak(k, dtype)
@@ -218,7 +228,8 @@ def main():
     from workloads import make_workload
 
     circ, p = make_workload(args.workload, seed=args.seed)
-    m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=args.precision, batch="step")
+    m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=args.precision, batch="step",
+              eig=args.eig)
     for layer in circ.layers:
         m.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
 
@@ -274,7 +285,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": circ.n, "layers": len(circ.layers),
                    "chi_max": p["chi_max"], "k_max": p["k_max"], "eps": p["eps"],
-                   "batch": "step", "seed": args.seed,
+                   "batch": "step", "eig": args.eig, "seed": args.seed,
                    "bonds_at_chi_max_at_start": int((dims0 >= p["chi_max"]).sum()),
                    "max_chi_at_start": int(dims0.max())},
         "roofline": roofline(kt, args.precision),

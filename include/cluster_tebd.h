@@ -58,10 +58,23 @@ enum {
 
 /* How the truncated SVD of each split is obtained. */
 enum {
-  MPS_SVD_EXACT = 0,    /* FP64 Gram matrix + FP64 block-Jacobi eigen-solver    */
+  MPS_SVD_EXACT = 0,    /* FP64 Gram matrix + FP64 eigen-solver (eig_method)   */
   MPS_SVD_LEARNED = 1   /* randomized range finder with a sketch size chosen by
                            the kept-rank network; exact SVD when its residual
                            check fails                                          */
+};
+
+/* Eigen-solver of the exact split (the Gram matrix G is 2c x 2c, FP64).
+ * Both reach FP64 accuracy; they differ in cost.  Block Jacobi needs about
+ * 2 * 2c dependent rotation rounds per sweep and several sweeps; the
+ * tridiagonal route (Householder reduction to a real tridiagonal, Cuppen
+ * divide and conquer, back-transformation) needs 2 launches per column and
+ * O(log 2c) merge levels. */
+enum {
+  MPS_EIG_AUTO = 0,     /* tridiagonal for 256 <= 2c <= 2048, Jacobi otherwise  */
+  MPS_EIG_JACOBI = 1,   /* FP64 block Jacobi (an FP32 solve with FP64 Rayleigh
+                           quotients for large cap-limited splits of FP32 runs) */
+  MPS_EIG_TRIDIAG = 2   /* tridiagonal divide and conquer whenever 2c <= 2048   */
 };
 
 /* How the independent clusters of one step are launched. */
@@ -78,6 +91,7 @@ typedef struct {
   int precision;    /* MPS_PREC_*                                              */
   int svd_mode;     /* MPS_SVD_*                                               */
   int batch;        /* MPS_BATCH_*                                             */
+  int eig_method;   /* MPS_EIG_*                                               */
   double floor_c;   /* the kept-value threshold is max(eps, floor_c * u) with
                        u = 2^-24 for FP32/BF16X6 and 2^-26.5 for FP64; the
                        Gram route cannot resolve singular values below it    */
@@ -105,7 +119,7 @@ typedef struct {
 } mps_stats;
 
 /* Fills *opt with the defaults: k_max 4, q_max 0, l_max 0, FP32, exact SVD,
- * step batching, floor_c 4, library stream. */
+ * step batching, automatic eigen-solver choice, floor_c 4, library stream. */
 mps_status mps_default_options(mps_options* opt);
 
 /* Sec. II.B / IV.A: creates the product state |0...0> on n >= 2 qubits (every
@@ -197,6 +211,25 @@ mps_status mps_set_timing(mps_handle h, int on);
 mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, double* flop, int cap,
                             char* names, int names_cap, int* count);
 
+/* Sec. III.A, the eigen-decomposition behind every exact split, on its own:
+ * A (n x n Hermitian, interleaved complex128, row-major, host memory) =
+ * V diag(w) V^H with w ascending and V[i*n + j] the i-th component of the
+ * j-th eigenvector (unit norm).  Runs the tridiagonal divide-and-conquer
+ * solver of the large splits on the current device; 1 <= n <= 2048.
+ * Synchronous; allocates and frees its own device memory.  Both triangles
+ * of A are read: A must be Hermitian.
+ * MPS_EINVAL for a bad size or a null pointer, MPS_EDEVICE / MPS_ENOMEM for
+ * HIP failures; mps_last_error(NULL) then describes the failure. */
+mps_status mps_heev(int n, const double* A, double* w, double* V);
+
+/* Algorithmic HBM bytes of each kernel class since timing was switched on,
+ * for the classes bound by memory bandwidth (the HEMV and HER2 launches of
+ * the tridiagonal reduction: the trailing Gram block read, and read and
+ * written); 0 for the others.  Classes in the order of mps_kernel_times. */
+mps_status mps_kernel_bytes(mps_handle h, double* bytes, int cap, int* count);
+
+/* Message of the last failure of h; with h = NULL, of the last failed call
+ * of this thread that takes no handle (mps_heev). */
 const char* mps_last_error(mps_handle h);
 
 /* ---- learned sketch -------------------------------------------------------

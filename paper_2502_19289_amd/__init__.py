@@ -4,7 +4,7 @@ The hot path (cluster unitaries, merges, truncated-SVD splits, fidelity
 bookkeeping) runs in the HIP kernels of the library; this package only
 marshals arguments.  Importing it requires the built library.
 """
-from .ffi import MPS, CtebdError, load, plan  # noqa: F401
+from .ffi import MPS, CtebdError, heev, load, plan  # noqa: F401
 from .gates import GATES  # noqa: F401
 
 

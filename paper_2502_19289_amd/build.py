@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libctebd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["planner.cpp", "gemm.hip", "eig.hip", "site_ops.hip", "sketch.hip", "learned.hip", "engine.hip"]
+SOURCES = ["planner.cpp", "gemm.hip", "eig.hip", "htd.hip", "site_ops.hip", "sketch.hip", "learned.hip", "engine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

@@ -14,6 +14,7 @@
 // of the same step, so a step needs one host synchronisation at its end (plus
 // one per Jacobi sweep to stop converged solves).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -96,6 +97,7 @@ int KernelTimer::cls_of(const char* name) {
   ms.push_back(0.0);
   launches.push_back(0);
   flop.push_back(0.0);
+  bytes.push_back(0.0);
   return (int)names.size() - 1;
 }
 
@@ -117,6 +119,11 @@ struct Fail {
   } while (0)
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+[[noreturn]] void fail(mps_ctx* ctx, mps_status st, const char* msg) {
+  ctx->err = msg;
+  throw Fail{st};
+}
 
 // --------------------------------------------------------------- timing --
 struct Timed {
@@ -187,6 +194,8 @@ struct JobRun {
   double *scale = nullptr, *logf = nullptr, *rec = nullptr;
   int cur = 0;
   int flag_index = 0;
+  bool htd = false;  // some level uses the tridiagonal solver: hw holds its buffers
+  HtdDesc hw{};
 };
 
 int bond_dim(const mps_ctx* ctx, int b) { return (b < 0 || b >= ctx->n - 1) ? 1 : ctx->chi[b]; }
@@ -197,6 +206,59 @@ Dim fixed(int v) { return Dim{v, nullptr}; }
 Dim c_dim(mps_ctx* ctx, const JobRun& j, int t, int mult) {
   if (t == 0) return fixed(mult * j.chi_r);
   return Dim{mult, ctx->d_chi + (j.a + j.lv[t].m)};
+}
+
+// Eigen-solver of a split level: the tridiagonal route where it applies.
+bool level_htd(const mps_ctx* ctx, const Level& lv) {
+  const int n = 2 * lv.c_bound;
+  if (n > HTD_MAX) return false;
+  if (ctx->opt.eig_method == MPS_EIG_JACOBI) return false;
+  if (ctx->opt.eig_method == MPS_EIG_TRIDIAG) return true;
+  return n >= 256;
+}
+
+bool job_htd(const mps_ctx* ctx, const JobRun& j) {
+  for (const auto& L : j.lv)
+    if (level_htd(ctx, L)) return true;
+  return false;
+}
+
+// Buffers of the tridiagonal solver for Gram matrices of leading dim ld;
+// take(bytes) returns device memory (or only counts it).
+template <typename F>
+void htd_layout(size_t ld, HtdDesc& h, F take) {
+  const size_t nd = ld * sizeof(double), ni = ld * sizeof(int), nc = ld * sizeof(double2);
+  h.d = (double*)take(nd);
+  h.e = (double*)take(nd);
+  h.lam = (double*)take(nd);
+  h.tau = (double2*)take(nc);
+  h.v = (double2*)take(nc);
+  h.y = (double2*)take(nc);
+  h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
+  for (int q = 0; q < 2; ++q) {
+    h.Q[q] = (double*)take(ld * nd);
+    h.D[q] = (double*)take(nd);
+  }
+  h.DeltaT = (double*)take(ld * nd);
+  h.U = (double*)take(ld * nd);
+  h.dl = (double*)take(nd);
+  h.w = (double*)take(nd);
+  h.ndcol = (int*)take(ni);
+  h.dval = (double*)take(nd);
+  h.dcol = (int*)take(ni);
+  h.rot_a = (int*)take(ni);
+  h.rot_b = (int*)take(ni);
+  h.rot_c = (double*)take(nd);
+  h.rot_s = (double*)take(nd);
+  h.origin = (int*)take(ni);
+  h.stau = (double*)take(nd);
+  h.zhat = (double*)take(nd);
+  h.pos_nd = (int*)take(ni);
+  h.cnt = (int*)take(4 * ni);
+  h.rho = (double*)take(nd);
+  h.T = (double2*)take((ld / HTD_NB + 1) * HTD_NB * HTD_NB * sizeof(double2));
+  h.Wp = (double2*)take(((ld + BT_CH - 1) / BT_CH) * HTD_NB * nc);
+  h.W = (double2*)take(HTD_NB * nc);
 }
 
 void plan_job(mps_ctx* ctx, const Job& job, JobRun& j) {
@@ -263,6 +325,13 @@ size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
   add(ld * sizeof(int));
   add(sizeof(double));
   add(4 * j.k * sizeof(double));
+  if (job_htd(ctx, j)) {
+    HtdDesc tmp{};
+    htd_layout(ld, tmp, [&](size_t x) -> void* {
+      add(x);
+      return nullptr;
+    });
+  }
   return b;
 }
 
@@ -298,6 +367,8 @@ void assign_job(mps_ctx* ctx, JobRun& j) {
   j.perm = (int*)A.take(ld * sizeof(int));
   j.scale = (double*)A.take(sizeof(double));
   j.rec = (double*)A.take(4 * j.k * sizeof(double));
+  j.htd = job_htd(ctx, j);
+  if (j.htd) htd_layout(ld, j.hw, [&](size_t x) { return A.take(x); });
 }
 
 // Algorithmic flops of a finished step per kernel class (sizes are final on
@@ -437,12 +508,25 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
   hipStream_t s = ctx->stream;
   const int np = (int)host.size();
   if (!np) return;
-  int nb_all = 0, ldmax = 0;
+  // Sizes set by earlier splits of this step live in d_chi: read them so that
+  // a sweep runs the rounds of the largest actual size, not of its bound.
+  std::vector<int> chi_now(ctx->n - 1);
+  HIP_OK(hipMemcpyAsync(chi_now.data(), ctx->d_chi, chi_now.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int nb_all = 2;
   for (const auto& e : host) {
-    nb_all = std::max(nb_all, e.nb_max);
-    ldmax = std::max(ldmax, e.ld);
+    const ptrdiff_t at = e.n.ptr ? e.n.ptr - ctx->d_chi : -1;
+    const bool in_chi = at >= 0 && at < (ptrdiff_t)chi_now.size();
+    const int n = !e.n.ptr ? e.n.mult : (in_chi ? e.n.mult * chi_now[at] : e.nb_max * JB);
+    int nb = std::max(2, ceil_div(n, JB));
+    nb += nb & 1;
+    nb_all = std::max(nb_all, std::min(nb, e.nb_max));
   }
+  const bool trace = std::getenv("CTEBD_EIG_TRACE") != nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
+  int sweeps = 0;
   for (int sw = 0; sw < 30; ++sw) {
+    ++sweeps;
     for (int round = 0; round < nb_all - 1; ++round) {
       {
         Timed tm(ctx, fp32 ? "eig_pairs32" : "eig_pairs");
@@ -461,6 +545,106 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
     for (int q : flag_at)
       if (!ctx->h_flags[q]) all = false;
     if (all) break;
+  }
+  if (trace) {
+    std::string sizes;
+    for (const auto& e : host) {
+      int v = 1;
+      if (e.n.ptr) HIP_OK(hipMemcpy(&v, e.n.ptr, sizeof(int), hipMemcpyDeviceToHost));
+      sizes += " " + std::to_string(e.n.mult * v) + "/" + std::to_string(e.nb_max * JB);
+    }
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "eig %s np=%d rounds=%d sweeps=%d ms=%.2f n/bound:%s\n", fp32 ? "fp32" : "fp64", np,
+                 nb_all - 1, sweeps, ms, sizes.c_str());
+  }
+}
+
+// Tridiagonal divide-and-conquer solves of one split level.  The sizes set
+// by earlier splits of the step are read back first: the host needs them for
+// the launch grids (2 launches per column, 7 per merge level, 3 per block of
+// reflectors).
+void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host) {
+  hipStream_t s = ctx->stream;
+  const int np = (int)host.size();
+  if (!np) return;
+  std::vector<int> chi_now(std::max(0, ctx->n - 1));
+  if (!chi_now.empty()) {
+    HIP_OK(hipMemcpyAsync(chi_now.data(), ctx->d_chi, chi_now.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  std::vector<int> nv(np);
+  int nmax = 0;
+  for (int p = 0; p < np; ++p) {
+    const Dim& dm = host[p].n;
+    const ptrdiff_t at = dm.ptr ? dm.ptr - ctx->d_chi : -1;
+    if (dm.ptr && (at < 0 || at >= (ptrdiff_t)chi_now.size())) fail(ctx, MPS_EINVAL, "tridiagonal solve: size pointer");
+    nv[p] = dm.ptr ? dm.mult * chi_now[at] : dm.mult;
+    if (nv[p] < 1 || nv[p] > HTD_MAX) fail(ctx, MPS_EINVAL, "tridiagonal solve: size out of range");
+    nmax = std::max(nmax, nv[p]);
+  }
+  auto total = [&](auto f) {
+    int t = 0;
+    for (int p = 0; p < np; ++p) t += f(nv[p]);
+    return t;
+  };
+  const bool timing = ctx->timing;
+  const int c_hemv = timing ? ctx->timer.cls_of("trd_hemv") : -1, c_her2 = timing ? ctx->timer.cls_of("trd_her2") : -1;
+  const int c_bt = timing ? ctx->timer.cls_of("bt") : -1;
+  for (int k = 0; k + 1 < nmax; ++k) {
+    {
+      Timed tm(ctx, "trd_hemv");
+      HIP_OK(launch_trd_hemv(dd, np, k, total([k](int n) { return htd_hemv_blocks(n, k); }), s));
+    }
+    {
+      Timed tm(ctx, "trd_her2");
+      HIP_OK(launch_trd_her2(dd, np, k, total([k](int n) { return htd_her2_blocks(n, k); }), s));
+    }
+    if (timing) {  // algorithmic traffic: G22 read (HEMV), read and written (HER2)
+      for (int p = 0; p < np; ++p) {
+        const double m = nv[p] - k - 1;
+        if (m <= 0) continue;
+        ctx->timer.bytes[c_hemv] += 16.0 * m * m;
+        ctx->timer.bytes[c_her2] += 32.0 * m * m;
+        ctx->timer.flop[c_hemv] += 8.0 * m * m;
+        ctx->timer.flop[c_her2] += 16.0 * m * m;
+      }
+    }
+  }
+  {
+    Timed tm(ctx, "dc");
+    HIP_OK(launch_trd_finish(dd, np, s));
+    HIP_OK(launch_dc_init(dd, np, total([](int n) { return n; }), s));
+  }
+  int Lmax = 0;
+  while ((1 << Lmax) < nmax) ++Lmax;
+  for (int L = 1; L <= Lmax; ++L) {
+    Timed tm(ctx, "dc");
+    const int nodes = total([L](int n) { return htd_nodes(n, L); });
+    const int rows = total([](int n) { return htd_rows(n); });
+    HIP_OK(launch_dc_prep(dd, np, L, nodes, s));
+    for (int stage = 0; stage < 4; ++stage) HIP_OK(launch_dc_rows(stage, dd, np, L, rows, s));
+    HIP_OK(launch_dc_place(dd, np, L, nodes, s));
+    HIP_OK(launch_dc_gemm(dd, np, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
+  }
+  {
+    Timed tm(ctx, "bt");
+    HIP_OK(launch_bt_init(dd, np, Lmax, total([](int n) { return n; }), s));
+    HIP_OK(launch_bt_larft(dd, np, total([](int n) { return htd_nblk(n); }), s));
+  }
+  int nbmax = 0;
+  for (int p = 0; p < np; ++p) nbmax = std::max(nbmax, htd_nblk(nv[p]));
+  for (int b = nbmax - 1; b >= 0; --b) {
+    Timed tm(ctx, "bt");
+    HIP_OK(launch_bt_wpart(dd, np, b, total([b](int n) { return htd_wpart_blocks(n, b); }), s));
+    HIP_OK(launch_bt_wred(dd, np, b, total([b](int n) { return htd_wred_blocks(n, b); }), s));
+    HIP_OK(launch_bt_update(dd, np, b, total([b](int n) { return htd_update_blocks(n, b); }), s));
+    if (timing)  // two products of (rows x HTD_NB) by (HTD_NB x n) complex
+      for (int p = 0; p < np; ++p)
+        if (b < htd_nblk(nv[p])) {
+          const double rows = htd_bt_rows(nv[p], b), nb = std::min(HTD_NB, nv[p] - 1 - HTD_NB * b);
+          ctx->timer.flop[c_bt] += 2.0 * 8.0 * rows * nb * nv[p];
+        }
   }
 }
 
@@ -657,6 +841,9 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     // exact solves: group 0 in FP64, group 1 in FP32 (+ FP64 Rayleigh quotients)
     std::vector<EigDesc> eig[2];
     std::vector<int> eig_jobs[2];
+    std::vector<HtdDesc> htd;   // tridiagonal solves
+    std::vector<EigDesc> eig_h;  // their trace / flag initialisation
+    size_t o_htd = 0, o_eig_h = 0;
     std::vector<SelectDesc> sel;
     std::vector<GemmDesc> ray;  // FP32 solve: W = G V in FP64
     std::vector<GatherDesc> gat;
@@ -716,7 +903,9 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         // The FP32 solve resolves eigenvalues of G only to ~1e-7 of its trace;
         // it serves large splits whose rank bound exceeds chi_max, where the
         // cut lies far above that level.  Other splits use the FP64 solve.
-        const bool e32 = mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
+        const bool uh = level_htd(ctx, lv);
+        const bool e32 =
+            !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
         EigDesc e{};
         e.G = r.G;
         e.V = r.V;
@@ -736,9 +925,20 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
         nb += nb & 1;
         e.nb_max = nb;
         e.tol = e32 ? 2e-6 : 1e-13;
-        L.nb_max_all = std::max(L.nb_max_all, nb);
-        L.eig[e32].push_back(e);
-        L.eig_jobs[e32].push_back(i);
+        if (uh) {
+          L.eig_h.push_back(e);
+          HtdDesc h = r.hw;
+          h.A = r.G;
+          h.V = r.V;
+          h.n = n2c;
+          h.ld = r.ld;
+          h.skip = r.flags;
+          L.htd.push_back(h);
+        } else {
+          L.nb_max_all = std::max(L.nb_max_all, nb);
+          L.eig[e32].push_back(e);
+          L.eig_jobs[e32].push_back(i);
+        }
         if (e32) {
           GemmDesc g{};
           g.A = r.G;
@@ -758,10 +958,12 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       }
       int* r_out = ctx->d_chi + (r.a + m - 1);
       {
-        const bool e32 = mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
+        const bool uh = level_htd(ctx, lv);
+        const bool e32 =
+            !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
         SelectDesc sd{};
         sd.G = r.G;
-        sd.lam_in = e32 ? r.lamR : nullptr;
+        sd.lam_in = uh ? r.hw.lam : e32 ? r.lamR : nullptr;
         sd.ldg = r.ld;
         sd.n = n2c;
         sd.rows = lv.rows;
@@ -968,6 +1170,10 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       L.n_pair[g] = pb.back();
       L.n_upd[g] = ub.back();
     }
+    if (!L.htd.empty()) {
+      L.o_htd = B.add_vec(L.htd);
+      L.o_eig_h = B.add_vec(L.eig_h);
+    }
     L.o_sel = B.add_vec(L.sel);
     if (!L.ray.empty()) L.n_ray = upload_gemm(L.ray, L.o_ray, L.b_ray);
     std::vector<int> gb{0};
@@ -1044,6 +1250,11 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     int ldmax = 0;
     for (int g = 0; g < 2; ++g)
       for (const auto& e : L.eig[g]) ldmax = std::max(ldmax, e.ld);
+    for (const auto& e : L.eig_h) ldmax = std::max(ldmax, e.ld);
+    if (!L.eig_h.empty()) {
+      Timed tm(ctx, "eig_init");
+      HIP_OK(launch_eig_init(false, B.at<EigDesc>(L.o_eig_h), (int)L.eig_h.size(), ldmax, s));
+    }
     for (int g = 0; g < 2; ++g) {
       if (L.eig[g].empty()) continue;
       Timed tm(ctx, "eig_init");
@@ -1100,6 +1311,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       solve_eig(ctx, g == 1, B.at<EigDesc>(L.o_eig[g]), L.eig[g], B.at<int>(L.b_pair[g]), B.at<int>(L.b_upd[g]),
                 L.n_pair[g], L.n_upd[g], flags_all, 4 * nj, at);
     }
+    if (!L.htd.empty()) solve_htd(ctx, B.at<HtdDesc>(L.o_htd), L.htd);
     if (!L.eig[1].empty()) {
       Timed tm(ctx, "eig_rayleigh");
       EigDesc* de32 = B.at<EigDesc>(L.o_eig[1]);
@@ -1350,6 +1562,7 @@ mps_status mps_default_options(mps_options* opt) {
   opt->precision = MPS_PREC_FP32;
   opt->svd_mode = MPS_SVD_EXACT;
   opt->batch = MPS_BATCH_STEP;
+  opt->eig_method = MPS_EIG_AUTO;
   opt->floor_c = 4.0;
   opt->hip_stream = nullptr;
   return MPS_OK;
@@ -1367,7 +1580,8 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
       mps_default_options(&ctx->opt);
     const mps_options& o = ctx->opt;
     if (o.k_max < 2 || o.k_max > 12 || o.precision < 0 || o.precision > 2 || o.svd_mode < 0 ||
-        o.svd_mode > 1 || o.batch < 0 || o.batch > 1 || !(o.floor_c >= 0.0)) {
+        o.svd_mode > 1 || o.batch < 0 || o.batch > 1 || o.eig_method < 0 || o.eig_method > 2 ||
+        !(o.floor_c >= 0.0)) {
       ctx->err = "invalid options";
       return MPS_EINVAL;
     }
@@ -1832,7 +2046,79 @@ mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, doubl
   return MPS_OK;
 }
 
-const char* mps_last_error(mps_handle ctx) { return ctx ? ctx->err.c_str() : "null handle"; }
+namespace {
+thread_local std::string g_err;  // message of the last failed call without a handle
+}
+
+mps_status mps_heev(int n, const double* A, double* w, double* V) {
+  if (n < 1 || n > HTD_MAX || !A || !w || !V) {
+    g_err = "mps_heev: need 1 <= n <= 2048 and non-null pointers";
+    return MPS_EINVAL;
+  }
+  mps_ctx tmp;
+  tmp.n = 1;
+  char* mem = nullptr;
+  mps_status st = guarded(&tmp, [&]() -> mps_status {
+    mps_ctx* ctx = &tmp;
+    HIP_OK(hipStreamCreateWithFlags(&tmp.stream, hipStreamNonBlocking));
+    const size_t ld = (size_t)ceil_div(n, 64) * 64;
+    HtdDesc h{};
+    size_t bytes = 0;
+    auto count = [&](size_t x) -> void* {
+      bytes = ((bytes + 255) & ~size_t(255)) + x;
+      return nullptr;
+    };
+    count(ld * ld * sizeof(double2));
+    count(ld * ld * sizeof(double2));
+    htd_layout(ld, h, count);
+    count(sizeof(HtdDesc));
+    HIP_OK(hipMalloc(&mem, bytes));
+    size_t used = 0;
+    auto take = [&](size_t x) -> void* {
+      const size_t off = (used + 255) & ~size_t(255);
+      used = off + x;
+      return mem + off;
+    };
+    h.A = (double2*)take(ld * ld * sizeof(double2));
+    h.V = (double2*)take(ld * ld * sizeof(double2));
+    htd_layout(ld, h, take);
+    h.n = Dim{n, nullptr};
+    h.ld = (int)ld;
+    h.skip = nullptr;
+    hipStream_t s = tmp.stream;
+    HIP_OK(hipMemcpy2DAsync(h.A, ld * sizeof(double2), A, n * sizeof(double2), n * sizeof(double2), n,
+                            hipMemcpyHostToDevice, s));
+    HtdDesc* dd = (HtdDesc*)take(sizeof(HtdDesc));
+    HIP_OK(hipMemcpyAsync(dd, &h, sizeof(HtdDesc), hipMemcpyHostToDevice, s));
+    solve_htd(ctx, dd, std::vector<HtdDesc>{h});
+    HIP_OK(hipMemcpyAsync(w, h.lam, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpy2DAsync(V, n * sizeof(double2), h.V, ld * sizeof(double2), n * sizeof(double2), n,
+                            hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return MPS_OK;
+  });
+  if (tmp.stream) {
+    (void)hipStreamSynchronize(tmp.stream);
+    (void)hipStreamDestroy(tmp.stream);
+  }
+  if (mem) (void)hipFree(mem);
+  if (st != MPS_OK) g_err = "mps_heev: " + tmp.err;
+  return st;
+}
+
+mps_status mps_kernel_bytes(mps_handle ctx, double* bytes, int cap, int* count) {
+  if (!ctx || !count) return MPS_EINVAL;
+  const int c = (int)ctx->timer.names.size();
+  *count = c;
+  for (int i = 0; i < c && i < cap; ++i)
+    if (bytes) bytes[i] = ctx->timer.bytes[i];
+  return MPS_OK;
+}
+
+const char* mps_last_error(mps_handle ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_err.empty() ? "null handle" : g_err.c_str();
+}
 
 mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi, const mps_gate* gates,
                     const int* layer_len, int nl, int start, int* out_end, int* out_clusters, int cap,

@@ -73,6 +73,7 @@ struct KernelTimer {
   std::vector<double> ms;
   std::vector<int64_t> launches;
   std::vector<double> flop;  // algorithmic real flops per class (8 per complex MAC)
+  std::vector<double> bytes; // algorithmic HBM bytes per class (bandwidth-bound classes)
   struct Pending {
     int cls;
     hipEvent_t a, b;

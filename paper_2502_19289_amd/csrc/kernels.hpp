@@ -88,6 +88,96 @@ hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s);
 hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
 hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s);
 
+// ------------------------------- tridiagonal divide-and-conquer eigen ----
+// Hermitian G = Q T Q^H (Householder, T real tridiagonal), T = Z diag(w) Z^T
+// (Cuppen divide and conquer), eigenvectors Q Z (blocked back-transformation).
+constexpr int HTD_MAX = 2048;  // largest n: per-node lists are staged in LDS
+constexpr int HTD_NB = 32;     // reflectors per back-transformation block
+constexpr int HV_ROWS = 8;     // trailing-matrix rows per HEMV workgroup
+constexpr int BT_CH = 256;     // rows per split-K chunk of the back-transformation
+
+struct HtdDesc {
+  double2* A;       // n x n Hermitian (ld); row k keeps reflector v_k (cols > k)
+  double2* V;       // out: eigenvectors as columns (ld)
+  double* lam;      // out: eigenvalues, ascending (n)
+  Dim n;
+  int ld;
+  const int* skip;  // nonzero: the problem is solved elsewhere (accepted sketch)
+  // reduction to tridiagonal form
+  double* d;        // diagonal of T (n)
+  double* e;        // off-diagonal of T (n - 1)
+  double2* tau;     // reflector scalars (n - 1)
+  double2* v;       // current reflector (n)
+  double2* y;       // tau G v of the current step (n)
+  double2* part;    // per HEMV workgroup: sum of conj(y_i) v_i
+  // divide and conquer (node lists are indexed by the node's first row)
+  double* Q[2];     // n x n (ld) block-diagonal eigenvector matrices, by level parity
+  double* D[2];     // eigenvalues of the nodes, ascending within a node
+  double* DeltaT;   // ld x ld: DeltaT[lo+j][lo+k] = dl_j - lambda_k
+  double* U;        // ld x ld: eigenvectors of the rank-one updated diagonal
+  double* dl;       // non-deflated poles (ascending)
+  double* w;        // their z components
+  int* ndcol;       // their columns
+  double* dval;     // deflated eigenvalues (sorted)
+  int* dcol;        // their columns
+  int* rot_a;       // deflation rotations: column pair, cosine, sine
+  int* rot_b;
+  double* rot_c;
+  double* rot_s;
+  int* origin;      // secular roots: lambda_k = dl[origin_k] + stau_k
+  double* stau;
+  double* zhat;     // recomputed z (Loewner)
+  int* pos_nd;      // output position of root k within its node
+  int* cnt;         // 4 ints per node: non-deflated, deflated, rotations, merged
+  double* rho;      // per node: rank-one weight
+  // back-transformation
+  double2* T;       // per block of HTD_NB reflectors: HTD_NB x HTD_NB upper triangle
+  double2* Wp;      // split-K partials: ceil(ld / BT_CH) x HTD_NB x ld
+  double2* W;       // T (V_b^H Z): HTD_NB x ld
+};
+
+// Per-problem workgroup counts of the launches (identical on host and device).
+__host__ __device__ inline int htd_hemv_blocks(int n, int k) {
+  const int m = n - k - 1;
+  return m > 0 ? (m + HV_ROWS - 1) / HV_ROWS : 0;
+}
+__host__ __device__ inline int htd_her2_blocks(int n, int k) {
+  const int m = n - k - 1, t = (m + 63) / 64;
+  return m > 0 ? t * t : 0;
+}
+__host__ __device__ inline int htd_rows(int n) { return (n + 255) / 256; }
+__host__ __device__ inline int htd_nodes(int n, int L) { return (n + (1 << L) - 1) >> L; }
+__host__ __device__ inline int htd_gemm_tiles(int n, int L) {
+  const int t = ((1 << L) + 63) / 64;
+  return htd_nodes(n, L) * t * t;
+}
+__host__ __device__ inline int htd_nblk(int n) { return n >= 2 ? (n - 2) / HTD_NB + 1 : 0; }
+__host__ __device__ inline int htd_bt_rows(int n, int b) { return n - HTD_NB * b - 1; }
+__host__ __device__ inline int htd_wpart_blocks(int n, int b) {
+  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((n + 63) / 64) : 0;
+}
+__host__ __device__ inline int htd_wred_blocks(int n, int b) { return b < htd_nblk(n) ? (n + 63) / 64 : 0; }
+__host__ __device__ inline int htd_update_blocks(int n, int b) {
+  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + 63) / 64) * ((n + 63) / 64) : 0;
+}
+
+// launches over np descriptors in device memory; `blocks` is the sum of the
+// per-problem counts above for the given step / level / block
+hipError_t launch_trd_hemv(const HtdDesc* d, int np, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_her2(const HtdDesc* d, int np, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_finish(const HtdDesc* d, int np, hipStream_t s);
+hipError_t launch_dc_init(const HtdDesc* d, int np, int blocks, hipStream_t s);
+hipError_t launch_dc_prep(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
+// stage 0: deflation rotations, 1: secular roots, 2: Loewner z, 3: eigenvectors
+hipError_t launch_dc_rows(int stage, const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
+hipError_t launch_dc_place(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
+hipError_t launch_dc_gemm(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
+hipError_t launch_bt_init(const HtdDesc* d, int np, int Lmax, int blocks, hipStream_t s);
+hipError_t launch_bt_larft(const HtdDesc* d, int np, int blocks, hipStream_t s);
+hipError_t launch_bt_wpart(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
+hipError_t launch_bt_wred(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
+hipError_t launch_bt_update(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
+
 // ------------------------------------------------------ learned sketch ----
 constexpr int SK_PROBES = 8;
 

@@ -21,12 +21,13 @@ MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ESPAN, MPS_ENOTUNITARY, MPS_EDEVICE, MPS_EST
 PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2}
 SVD = {"exact": 0, "learned": 1}
 BATCH = {"none": 0, "step": 1}
+EIG = {"auto": 0, "jacobi": 1, "tridiag": 2}
 
 
 class Options(C.Structure):
     _fields_ = [("k_max", C.c_int), ("q_max", C.c_int), ("l_max", C.c_int),
                 ("precision", C.c_int), ("svd_mode", C.c_int), ("batch", C.c_int),
-                ("floor_c", C.c_double), ("hip_stream", C.c_void_p)]
+                ("eig_method", C.c_int), ("floor_c", C.c_double), ("hip_stream", C.c_void_p)]
 
 
 class GateC(C.Structure):
@@ -50,7 +51,7 @@ EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluste
            "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
-           "mps_set_timing", "mps_kernel_times", "mps_last_error", "mps_plan",
+           "mps_set_timing", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_last_error", "mps_plan",
            "mlp_num_params", "mlp_create", "mlp_destroy", "mlp_get_params", "mlp_set_params",
            "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log"]
 N_FEAT = 12
@@ -86,6 +87,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_set_timing.argtypes = [P, I]
     lib.mps_kernel_times.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), I, C.c_char_p, I,
                                      C.POINTER(I)]
+    lib.mps_kernel_bytes.argtypes = [P, C.POINTER(D), I, C.POINTER(I)]
+    lib.mps_heev.argtypes = [I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
     lib.mps_last_error.argtypes = [P]
     lib.mps_last_error.restype = C.c_char_p
     lib.mps_plan.argtypes = [I, I, I, I, C.POINTER(I), C.POINTER(GateC), C.POINTER(I), I, I,
@@ -144,11 +147,12 @@ class MPS:
 
     def __init__(self, n: int, chi_max: int, eps: float, k_max: int = 4, precision: str = "fp32",
                  batch: str = "step", svd: str = "exact", q_max: int = 0, l_max: int = 0,
-                 floor_c: float = 4.0, hip_stream: Optional[int] = None):
+                 floor_c: float = 4.0, hip_stream: Optional[int] = None, eig: str = "auto"):
         self.lib = load()
         o = default_options()
         o.k_max, o.q_max, o.l_max = k_max, q_max, l_max
         o.precision, o.batch, o.svd_mode = PREC[precision], BATCH[batch], SVD[svd]
+        o.eig_method = EIG[eig]
         o.floor_c = floor_c
         o.hip_stream = hip_stream
         h = C.c_void_p()
@@ -196,11 +200,13 @@ class MPS:
         self._check(self.lib.mps_step(self.h, C.byref(c), C.byref(r)))
         return c.value, r.value
 
-    def clone(self, precision: Optional[str] = None, batch: Optional[str] = None) -> "MPS":
+    def clone(self, precision: Optional[str] = None, batch: Optional[str] = None,
+              eig: Optional[str] = None) -> "MPS":
         o = Options()
         o.k_max, o.q_max, o.l_max = self._opt.k_max, self._opt.q_max, self._opt.l_max
         o.precision = PREC[precision] if precision else self._opt.precision
         o.batch = BATCH[batch] if batch else self._opt.batch
+        o.eig_method = EIG[eig] if eig else self._opt.eig_method
         o.svd_mode, o.floor_c, o.hip_stream = self._opt.svd_mode, self._opt.floor_c, None
         h = C.c_void_p()
         self._check(self.lib.mps_clone(self.h, C.byref(o), C.byref(h)))
@@ -268,16 +274,19 @@ class MPS:
         self._check(self.lib.mps_set_timing(self.h, int(on)))
 
     def kernel_times(self) -> dict:
-        """{class: (ms, launches, algorithmic flops)} since timing was switched on."""
+        """{class: (ms, launches, algorithmic flops, algorithmic HBM bytes)} since
+        timing was switched on."""
         cnt = C.c_int()
         ms = np.zeros(64)
         fl = np.zeros(64)
+        by = np.zeros(64)
         la = np.zeros(64, dtype=np.int64)
         names = C.create_string_buffer(4096)
         self._check(self.lib.mps_kernel_times(self.h, _dptr(ms), la.ctypes.data_as(C.POINTER(C.c_int64)),
                                               _dptr(fl), 64, names, 4096, C.byref(cnt)))
+        self._check(self.lib.mps_kernel_bytes(self.h, _dptr(by), 64, C.byref(cnt)))
         nm = names.value.decode().split(",") if cnt.value else []
-        return {n: (float(ms[i]), int(la[i]), float(fl[i])) for i, n in enumerate(nm)}
+        return {n: (float(ms[i]), int(la[i]), float(fl[i]), float(by[i])) for i, n in enumerate(nm)}
 
 
 def _fptr(a: np.ndarray):
@@ -376,3 +385,19 @@ def plan(n: int, k_max: int, layers, chi: Sequence[int], start: int = 0, q_max: 
         raise CtebdError(st, "mps_plan failed")
     cl = [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(cnt.value)]
     return end.value, cl, nsub.value
+
+
+def heev(A: np.ndarray):
+    """Eigen-decomposition of a Hermitian matrix on the GPU by the tridiagonal
+    divide-and-conquer solver of the large splits: (w ascending, V columns)."""
+    lib = load()
+    a = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("square matrix expected")
+    w = np.zeros(n)
+    V = np.zeros((n, n), dtype=np.complex128)
+    st = lib.mps_heev(n, _dptr(a.view(np.float64)), _dptr(w), _dptr(V.view(np.float64)))
+    if st != MPS_OK:
+        raise CtebdError(st, lib.mps_last_error(None).decode())
+    return w, V

@@ -21,9 +21,9 @@ P = pytest.importorskip("paper_2502_19289_amd")
 INF_TOL = {"fp64": 1e-11, "fp32": 1e-6, "bf16x6": 1e-6}
 
 
-def gpu_run(c, prec="fp32", batch="step", **p):
+def gpu_run(c, prec="fp32", batch="step", eig="auto", **p):
     m = P.MPS(c.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=prec, batch=batch,
-              q_max=p.get("q_max", 0), l_max=p.get("l_max", 0))
+              q_max=p.get("q_max", 0), l_max=p.get("l_max", 0), eig=eig)
     P.run_circuit(m, c.layers)
     return m
 
@@ -53,11 +53,17 @@ def infid(A, B):
     return MT.infidelity(A, B)
 
 
+# eigen-solvers: "auto" (Jacobi below 2c = 256, tridiagonal above) and the
+# tridiagonal divide and conquer forced for every split
+EIGS = ["auto", "tridiag"]
+
+
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("seed", range(5))
-def test_exact_workload_vs_statevector(prec, seed):
+def test_exact_workload_vs_statevector(prec, seed, eig):
     c, p = make_workload("exact_n12_l10", seed=seed)
-    m = gpu_run(c, prec, **p)
+    m = gpu_run(c, prec, eig=eig, **p)
     sv = SV.simulate(c)
     amp = m.amplitudes()
     tol = 1e-12 if prec == "fp64" else 2e-6
@@ -66,11 +72,12 @@ def test_exact_workload_vs_statevector(prec, seed):
     assert abs(F - 1) < 1e-9
 
 
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 @pytest.mark.parametrize("seed,k_max", [(0, 2), (1, 3), (2, 4), (3, 6)])
-def test_dense_exact_vs_statevector(prec, seed, k_max):
+def test_dense_exact_vs_statevector(prec, seed, k_max, eig):
     c = dense_circuit(10, 8, 4, seed)
-    m = gpu_run(c, prec, chi_max=1024, eps=0.0, k_max=k_max)
+    m = gpu_run(c, prec, eig=eig, chi_max=1024, eps=0.0, k_max=k_max)
     sv = SV.simulate(c)
     amp = m.amplitudes()
     # FP32 contractions and an FP32 Jacobi solve, which resolves eigenvalues of
@@ -89,10 +96,11 @@ def test_dense_exact_vs_statevector(prec, seed, k_max):
         assert np.abs(got[: ref.size] - ref).max() < (1e-10 if prec == "fp64" else 1e-5)
 
 
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
-def test_apply_cluster_haar_vs_statevector(prec):
+def test_apply_cluster_haar_vs_statevector(prec, eig):
     n = 9
-    m = P.MPS(n, 512, 0.0, k_max=9, precision=prec)
+    m = P.MPS(n, 512, 0.0, k_max=9, precision=prec, eig=eig)
     sv = np.zeros(2 ** n, complex)
     sv[0] = 1
     for i, (qs) in enumerate([(0, 1, 2), (2, 3, 4, 5), (5, 6, 7, 8), (1, 2, 3, 4, 5, 6), (3, 4),
@@ -107,12 +115,13 @@ def test_apply_cluster_haar_vs_statevector(prec):
     assert inf < (1e-14 if prec == "fp64" else 1e-7)
 
 
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("chi", [2, 4])
-def test_truncating_run_vs_oracle(prec, chi):
+def test_truncating_run_vs_oracle(prec, chi, eig):
     c = dense_circuit(12, 10, 3, seed=4)
     p = dict(chi_max=chi, eps=1e-12, k_max=4)
-    m = gpu_run(c, prec, **p)
+    m = gpu_run(c, prec, eig=eig, **p)
     ref = CT.run(c, **p)
     F, _ = m.fidelity()
     assert abs(F - ref.fidelity) < (1e-10 if prec == "fp64" else 1e-5)
@@ -120,10 +129,11 @@ def test_truncating_run_vs_oracle(prec, chi):
     assert infid(m.sites(), ref.psi.B) < INF_TOL[prec]
 
 
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_clifford_workload_entropies_and_oracle(prec):
+def test_clifford_workload_entropies_and_oracle(prec, eig):
     c, p = make_workload("clifford_n100_l20", seed=0)
-    m = gpu_run(c, prec, **p)
+    m = gpu_run(c, prec, eig=eig, **p)
     S_tab = ST.circuit_entropies(c)
     dims = m.bond_dims()
     for b in range(c.n - 1):
@@ -136,17 +146,18 @@ def test_clifford_workload_entropies_and_oracle(prec):
     assert abs(F - 1) < 1e-9
 
 
+@pytest.mark.parametrize("eig", EIGS)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x6"])
 @pytest.mark.parametrize("n,chi,a,k,seed", [(12, 37, 4, 2, 0), (14, 64, 5, 4, 1), (16, 100, 6, 3, 2),
                                              (18, 130, 7, 3, 3), (14, 16, 0, 5, 4), (14, 16, 9, 5, 5)])
-def test_step_local_cluster_vs_oracle(prec, n, chi, a, k, seed):
+def test_step_local_cluster_vs_oracle(prec, n, chi, a, k, seed, eig):
     """A cluster applied to a random canonical MPS with ragged bond dimensions
     (several tiles and a partial tail in every GEMM): one oracle cluster update
     against the GPU one, with truncation at chi (also at both chain ends)."""
     dims = feasible_dims(n, chi)
     B, lam = random_mps(n, dims, seed=seed)
     U = haar_unitary(2 ** k, seed=100 + seed)
-    m = P.MPS(n, chi, 1e-12, k_max=k, precision=prec)
+    m = P.MPS(n, chi, 1e-12, k_max=k, precision=prec, eig=eig)
     m.import_state(B, lam)
     m.apply_cluster(list(range(a, a + k)), U)
     ref = CT.MPS([b.copy() for b in B], [l.copy() for l in lam])

@@ -232,15 +232,16 @@ void htd_layout(size_t ld, HtdDesc& h, F take) {
   h.e = (double*)take(nd);
   h.lam = (double*)take(nd);
   h.tau = (double2*)take(nc);
-  h.v = (double2*)take(nc);
-  h.y = (double2*)take(nc);
+  h.PV = (double2*)take(HTD_NB * nc);
+  h.PW = (double2*)take(HTD_NB * nc);
+  h.xb = (double2*)take(nc);
+  h.kpart = (double2*)take((ld / KC_ROWS + 1) * HTD_KP * sizeof(double2));
   h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
   for (int q = 0; q < 2; ++q) {
     h.Q[q] = (double*)take(ld * nd);
     h.D[q] = (double*)take(nd);
   }
-  h.DeltaT = (double*)take(ld * nd);
-  h.U = (double*)take(ld * nd);
+  h.unrm = (double*)take(nd);
   h.dl = (double*)take(nd);
   h.w = (double*)take(nd);
   h.ndcol = (int*)take(ni);
@@ -562,8 +563,99 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
 
 // Tridiagonal divide-and-conquer solves of one split level.  The sizes set
 // by earlier splits of the step are read back first: the host needs them for
-// the launch grids (2 launches per column, 7 per merge level, 3 per block of
-// reflectors).
+// the launch grids and passes them to every kernel by value (2 launches per
+// column and 1 per panel of the reduction, 7 per merge level, 3 per block of
+// reflectors).  Groups of more than HTD_GROUP problems run in chunks.
+void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
+  hipStream_t s = ctx->stream;
+  const int np = sz.np;
+  int nmax = 0;
+  for (int p = 0; p < np; ++p) nmax = std::max(nmax, sz.n[p]);
+  auto total = [&](auto f) {
+    int t = 0;
+    for (int p = 0; p < np; ++p) t += f(sz.n[p]);
+    return t;
+  };
+  auto total_c = [&](auto f) {
+    int t = 0;
+    for (int p = 0; p < np; ++p) t += f(sz.n[p], sz.nc[p]);
+    return t;
+  };
+  const bool timing = ctx->timing;
+  const int c_hemv = timing ? ctx->timer.cls_of("trd_hemv") : -1;
+  const int c_her2k = timing ? ctx->timer.cls_of("trd_her2k") : -1;
+  const int c_bt = timing ? ctx->timer.cls_of("bt") : -1;
+  for (int p0 = 0; p0 + 1 < nmax; p0 += HTD_NB) {
+    for (int j = 0; j < HTD_NB; ++j) {
+      const int k = p0 + j;
+      if (k + 1 >= nmax) break;
+      {
+        Timed tm(ctx, "trd_col");
+        HIP_OK(launch_trd_col(dd, sz, k, total([k](int n) { return htd_col_blocks(n, k); }), s));
+      }
+      {
+        Timed tm(ctx, "trd_hemv");
+        HIP_OK(launch_trd_hemv(dd, sz, k, total([k](int n) { return htd_hemv_blocks(n, k); }), s));
+      }
+      if (timing)  // algorithmic traffic of the HEMV: the trailing block read once
+        for (int p = 0; p < np; ++p) {
+          const double m = sz.n[p] - k - 1;
+          if (m <= 0) continue;
+          ctx->timer.bytes[c_hemv] += 16.0 * m * m;
+          ctx->timer.flop[c_hemv] += 8.0 * m * m;
+        }
+    }
+    {
+      Timed tm(ctx, "trd_her2k");
+      HIP_OK(launch_trd_her2k(dd, sz, p0, total([p0](int n) { return htd_her2k_blocks(n, p0); }), s));
+    }
+    if (timing)  // rank-2 HTD_NB update of the trailing block (Hermitian: count one triangle)
+      for (int p = 0; p < np; ++p) {
+        const double nbp = std::min(HTD_NB, sz.n[p] - 1 - p0);
+        if (nbp <= 0) continue;
+        const double mt = sz.n[p] - p0 - nbp;
+        ctx->timer.flop[c_her2k] += 8.0 * 2.0 * nbp * mt * (mt + 1) / 2;
+      }
+  }
+  {
+    Timed tm(ctx, "dc");
+    HIP_OK(launch_trd_finish(dd, sz, s));
+    HIP_OK(launch_dc_init(dd, sz, total([](int n) { return n; }), s));
+  }
+  int Lmax = 0;
+  while ((1 << Lmax) < nmax) ++Lmax;
+  for (int L = 1; L <= Lmax; ++L) {
+    Timed tm(ctx, "dc");
+    const int nodes = total([L](int n) { return htd_nodes(n, L); });
+    const int rows = total([](int n) { return htd_rows(n); });
+    const int waves = total([](int n) { return htd_waves(n); });
+    HIP_OK(launch_dc_prep(dd, sz, L, nodes, s));
+    HIP_OK(launch_dc_rot(dd, sz, L, rows, s));
+    for (int stage = 1; stage < 4; ++stage) HIP_OK(launch_dc_wave(stage, dd, sz, L, waves, s));
+    HIP_OK(launch_dc_place(dd, sz, L, nodes, s));
+    HIP_OK(launch_dc_gemm(dd, sz, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
+  }
+  {
+    Timed tm(ctx, "bt");
+    HIP_OK(launch_bt_init(dd, sz, Lmax, total([](int n) { return htd_tiles64(n); }), s));
+    HIP_OK(launch_bt_larft(dd, sz, total([](int n) { return htd_nblk(n); }), s));
+  }
+  int nbmax = 0;
+  for (int p = 0; p < np; ++p) nbmax = std::max(nbmax, htd_nblk(sz.n[p]));
+  for (int b = nbmax - 1; b >= 0; --b) {
+    Timed tm(ctx, "bt");
+    HIP_OK(launch_bt_wpart(dd, sz, b, total_c([b](int n, int c) { return htd_wpart_blocks(n, c, b); }), s));
+    HIP_OK(launch_bt_wred(dd, sz, b, total_c([b](int n, int c) { return htd_wred_blocks(n, c, b); }), s));
+    HIP_OK(launch_bt_update(dd, sz, b, total_c([b](int n, int c) { return htd_update_blocks(n, c, b); }), s));
+    if (timing)  // two products of (rows x HTD_NB) by (HTD_NB x nc) complex
+      for (int p = 0; p < np; ++p)
+        if (b < htd_nblk(sz.n[p])) {
+          const double rows = htd_bt_rows(sz.n[p], b), nb = std::min(HTD_NB, sz.n[p] - 1 - HTD_NB * b);
+          ctx->timer.flop[c_bt] += 2.0 * 8.0 * rows * nb * sz.nc[p];
+        }
+  }
+}
+
 void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host) {
   hipStream_t s = ctx->stream;
   const int np = (int)host.size();
@@ -573,78 +665,19 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
     HIP_OK(hipMemcpyAsync(chi_now.data(), ctx->d_chi, chi_now.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
   }
-  std::vector<int> nv(np);
-  int nmax = 0;
-  for (int p = 0; p < np; ++p) {
-    const Dim& dm = host[p].n;
-    const ptrdiff_t at = dm.ptr ? dm.ptr - ctx->d_chi : -1;
-    if (dm.ptr && (at < 0 || at >= (ptrdiff_t)chi_now.size())) fail(ctx, MPS_EINVAL, "tridiagonal solve: size pointer");
-    nv[p] = dm.ptr ? dm.mult * chi_now[at] : dm.mult;
-    if (nv[p] < 1 || nv[p] > HTD_MAX) fail(ctx, MPS_EINVAL, "tridiagonal solve: size out of range");
-    nmax = std::max(nmax, nv[p]);
-  }
-  auto total = [&](auto f) {
-    int t = 0;
-    for (int p = 0; p < np; ++p) t += f(nv[p]);
-    return t;
-  };
-  const bool timing = ctx->timing;
-  const int c_hemv = timing ? ctx->timer.cls_of("trd_hemv") : -1, c_her2 = timing ? ctx->timer.cls_of("trd_her2") : -1;
-  const int c_bt = timing ? ctx->timer.cls_of("bt") : -1;
-  for (int k = 0; k + 1 < nmax; ++k) {
-    {
-      Timed tm(ctx, "trd_hemv");
-      HIP_OK(launch_trd_hemv(dd, np, k, total([k](int n) { return htd_hemv_blocks(n, k); }), s));
+  for (int c0 = 0; c0 < np; c0 += HTD_GROUP) {
+    HtdSizes sz{};
+    sz.np = std::min(HTD_GROUP, np - c0);
+    for (int q = 0; q < sz.np; ++q) {
+      const Dim& dm = host[c0 + q].n;
+      const ptrdiff_t at = dm.ptr ? dm.ptr - ctx->d_chi : -1;
+      if (dm.ptr && (at < 0 || at >= (ptrdiff_t)chi_now.size())) fail(ctx, MPS_EINVAL, "tridiagonal solve: size pointer");
+      const int n = dm.ptr ? dm.mult * chi_now[at] : dm.mult;
+      if (n < 1 || n > HTD_MAX) fail(ctx, MPS_EINVAL, "tridiagonal solve: size out of range");
+      sz.n[q] = n;
+      sz.nc[q] = std::min(n, host[c0 + q].rcap);
     }
-    {
-      Timed tm(ctx, "trd_her2");
-      HIP_OK(launch_trd_her2(dd, np, k, total([k](int n) { return htd_her2_blocks(n, k); }), s));
-    }
-    if (timing) {  // algorithmic traffic: G22 read (HEMV), read and written (HER2)
-      for (int p = 0; p < np; ++p) {
-        const double m = nv[p] - k - 1;
-        if (m <= 0) continue;
-        ctx->timer.bytes[c_hemv] += 16.0 * m * m;
-        ctx->timer.bytes[c_her2] += 32.0 * m * m;
-        ctx->timer.flop[c_hemv] += 8.0 * m * m;
-        ctx->timer.flop[c_her2] += 16.0 * m * m;
-      }
-    }
-  }
-  {
-    Timed tm(ctx, "dc");
-    HIP_OK(launch_trd_finish(dd, np, s));
-    HIP_OK(launch_dc_init(dd, np, total([](int n) { return n; }), s));
-  }
-  int Lmax = 0;
-  while ((1 << Lmax) < nmax) ++Lmax;
-  for (int L = 1; L <= Lmax; ++L) {
-    Timed tm(ctx, "dc");
-    const int nodes = total([L](int n) { return htd_nodes(n, L); });
-    const int rows = total([](int n) { return htd_rows(n); });
-    HIP_OK(launch_dc_prep(dd, np, L, nodes, s));
-    for (int stage = 0; stage < 4; ++stage) HIP_OK(launch_dc_rows(stage, dd, np, L, rows, s));
-    HIP_OK(launch_dc_place(dd, np, L, nodes, s));
-    HIP_OK(launch_dc_gemm(dd, np, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
-  }
-  {
-    Timed tm(ctx, "bt");
-    HIP_OK(launch_bt_init(dd, np, Lmax, total([](int n) { return n; }), s));
-    HIP_OK(launch_bt_larft(dd, np, total([](int n) { return htd_nblk(n); }), s));
-  }
-  int nbmax = 0;
-  for (int p = 0; p < np; ++p) nbmax = std::max(nbmax, htd_nblk(nv[p]));
-  for (int b = nbmax - 1; b >= 0; --b) {
-    Timed tm(ctx, "bt");
-    HIP_OK(launch_bt_wpart(dd, np, b, total([b](int n) { return htd_wpart_blocks(n, b); }), s));
-    HIP_OK(launch_bt_wred(dd, np, b, total([b](int n) { return htd_wred_blocks(n, b); }), s));
-    HIP_OK(launch_bt_update(dd, np, b, total([b](int n) { return htd_update_blocks(n, b); }), s));
-    if (timing)  // two products of (rows x HTD_NB) by (HTD_NB x n) complex
-      for (int p = 0; p < np; ++p)
-        if (b < htd_nblk(nv[p])) {
-          const double rows = htd_bt_rows(nv[p], b), nb = std::min(HTD_NB, nv[p] - 1 - HTD_NB * b);
-          ctx->timer.flop[c_bt] += 2.0 * 8.0 * rows * nb * nv[p];
-        }
+    solve_htd_chunk(ctx, dd + c0, sz);
   }
 }
 
@@ -932,6 +965,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
           h.V = r.V;
           h.n = n2c;
           h.ld = r.ld;
+          h.rcap = lv.r_bound;
           h.skip = r.flags;
           L.htd.push_back(h);
         } else {
@@ -2084,6 +2118,7 @@ mps_status mps_heev(int n, const double* A, double* w, double* V) {
     htd_layout(ld, h, take);
     h.n = Dim{n, nullptr};
     h.ld = (int)ld;
+    h.rcap = n;
     h.skip = nullptr;
     hipStream_t s = tmp.stream;
     HIP_OK(hipMemcpy2DAsync(h.A, ld * sizeof(double2), A, n * sizeof(double2), n * sizeof(double2), n,
@@ -2095,6 +2130,12 @@ mps_status mps_heev(int n, const double* A, double* w, double* V) {
     HIP_OK(hipMemcpy2DAsync(V, n * sizeof(double2), h.V, ld * sizeof(double2), n * sizeof(double2), n,
                             hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    // the solver orders eigenpairs by descending eigenvalue; this entry point ascending
+    std::reverse(w, w + n);
+    for (int i = 0; i < n; ++i) {
+      double2* row = reinterpret_cast<double2*>(V) + (size_t)i * n;
+      std::reverse(row, row + n);
+    }
     return MPS_OK;
   });
   if (tmp.stream) {

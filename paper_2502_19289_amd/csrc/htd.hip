@@ -37,11 +37,22 @@ struct Loc {
   int p, b;
 };
 
-// problem and problem-local block of flat block `bid`
+// problem and problem-local block of flat block `bid`; the sizes come with
+// the launch (kernel arguments), so finding the problem costs no memory access
 template <typename F>
-__device__ __forceinline__ Loc locate(const HtdDesc* ds, int np, int bid, F count) {
-  for (int p = 0; p < np; ++p) {
-    const int c = count(dim_value(ds[p].n));
+__device__ __forceinline__ Loc locate(const HtdSizes& sz, int bid, F count) {
+  for (int p = 0; p < sz.np; ++p) {
+    const int c = count(sz.n[p]);
+    if (bid < c) return Loc{p, bid};
+    bid -= c;
+  }
+  return Loc{-1, 0};
+}
+// the same with counts that also depend on the back-transformed columns
+template <typename F>
+__device__ __forceinline__ Loc locate_d(const HtdSizes& sz, int bid, F count) {
+  for (int p = 0; p < sz.np; ++p) {
+    const int c = count(sz.n[p], sz.nc[p]);
     if (bid < c) return Loc{p, bid};
     bid -= c;
   }
@@ -53,190 +64,418 @@ __device__ __forceinline__ bool skipped(const HtdDesc& d) { return d.skip && *d.
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
 // ======================================================= tridiagonalisation
-// Step k: x = G[k+1:, k] (read as the conjugate of row k), reflector with
-// H^H (alpha, x1)^T = (beta, 0)^T, beta real; y = tau G22 v for this
-// workgroup's HV_ROWS rows; part = sum over them of conj(y_i) v_i.
-__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict__ ds, int np, int k) {
-  __shared__ double2 vs[HTD_MAX];
-  __shared__ double red[256];
-  __shared__ double2 wred[4];
-  const Loc lc = locate(ds, np, blockIdx.x, [k](int n) { return htd_hemv_blocks(n, k); });
+// Block reductions over the four wavefronts of a 256-thread workgroup: wave
+// shuffles, then the wave results combined in a fixed order (deterministic).
+// Wavefront sum on the DPP paths (no LDS permutes): pairs and quads
+// (quad_perm), 8- and 16-lane rows (row_half_mirror, row_mirror), then rows
+// 0+1 and 0..3 through row_bcast15 / row_bcast31, which leaves the total in
+// lane 63; read back as a scalar, so every lane returns the same bits.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_take<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_take<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_take<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_take<0x140, 0xf>(v);  // row_mirror
+  v += dpp_take<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_take<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double block4_max(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+__device__ __forceinline__ double block4_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Blocked (panel) form of the Householder reduction.  Within a panel of
+// HTD_NB columns the trailing matrix stays as it was at the panel start; for
+// column k (panel column j) with the panel's earlier reflectors V[:, <j] and
+// vectors W[:, <j]:
+//   trd_col:   x = G[k+1:, k] - V W[k, :]^H - W V[k, :]^H (the up-to-date
+//              column), its scaled norm and the dots V^H x, W^H x; it also
+//              finalises w_{j-1} = y_{j-1} - (tau/2)(y_{j-1}^H v_{j-1}) v_{j-1}
+//   trd_hemv:  the reflector H^H (alpha, x1)^T = (beta, 0)^T (beta real) and
+//              y = tau (G v - V (W^H v) - W (V^H v)) over the rows, 2 per
+//              wavefront with 4 columns per lane in flight
+// and at the end of the panel trd_her2k applies G -= V W^H + W V^H to the
+// trailing matrix on the matrix cores.  The trailing matrix is thus read once
+// per column (HEMV) and read and written once per panel.
+// dlassq-style running (scale, sum of squares): sum a^2 = scale^2 * ssq
+__device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
+  a = fabs(a);
+  if (a == 0.0) return;
+  if (scale < a) {
+    ssq = 1.0 + ssq * (scale / a) * (scale / a);
+    scale = a;
+  } else {
+    ssq += (a / scale) * (a / scale);
+  }
+}
+
+// One wavefront per KC_ROWS (32) rows.  Lanes 0..31 each bring one row's
+// column entry up to date from that row of V and W (loaded before the
+// reductions that precede their use) and stage the row in LDS; then lane
+// l < 32 forms (V^H x)_l and lane 32 + l (W^H x)_l over the 32 rows from LDS
+// -- no cross-lane reductions.
+__global__ __launch_bounds__(64) void trd_col_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int k) {
+  __shared__ double2 vk[HTD_NB], wk[HTD_NB];
+  __shared__ double2 pan[KC_ROWS][2 * HTD_NB + 1];  // V | W rows of this workgroup
+  __shared__ double2 xs[KC_ROWS];
+  const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_col_blocks(n, k); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), m = n - k - 1, ld = d.ld, tid = threadIdx.x;
-  const double2* rowk = d.A + (int64_t)k * ld + (k + 1);
-  // norms are formed on entries divided by the largest one, so that neither
-  // tiny nor huge Gram entries under- or overflow in the squares
-  double mx = 0.0;
-  for (int j = tid; j < m; j += 256) {
-    const double2 a = rowk[j];
-    vs[j] = make_double2(a.x, -a.y);
-    mx = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, lane = threadIdx.x;
+  const int j = k & (HTD_NB - 1);
+  const int i = lc.b * KC_ROWS + lane;
+  const bool own = lane < KC_ROWS && i < m;
+  const int64_t r = k + 1 + i;
+  // independent loads: the row entry, the row of V and W, partials of alpha
+  double2 a = make_double2(0.0, 0.0);
+  if (own) a = d.A[(int64_t)k * ld + r];
+  double2 vv[HTD_NB], ww[HTD_NB];
+#pragma unroll
+  for (int u = 0; u < HTD_NB; ++u) {
+    vv[u] = own && u < j ? d.PV[r * HTD_NB + u] : make_double2(0.0, 0.0);
+    ww[u] = own && u < j ? d.PW[r * HTD_NB + u] : make_double2(0.0, 0.0);
   }
-  red[tid] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-    __syncthreads();
-  }
-  const double amax = red[0];
-  __syncthreads();
-  double s = 0.0;  // |x_1..|^2 / amax^2 (alpha = x_0 excluded)
-  if (amax > 0.0)
-    for (int j = tid; j < m; j += 256) {
-      if (j == 0) continue;
-      const double2 x = vs[j];
-      s += (x.x / amax) * (x.x / amax) + (x.y / amax) * (x.y / amax);
+  const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int u = 0; u < HTD_MAX / HV_ROWS / 64; ++u) {
+    const int q = lane + 64 * u;
+    if (q < nbp) {
+      const double2 t = d.part[q];
+      sx += t.x;
+      sy += t.y;
     }
-  red[tid] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
   }
-  const double xs2 = red[0];
-  const double2 alpha = vs[0];
+  double2 al = make_double2(0.0, 0.0);  // -(tau/2) y^H v of panel column j-1
+  if (j > 0) {
+    const double2 tp = d.tau[k - 1];
+    al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), make_double2(wave_sum(sx), wave_sum(sy)));
+  }
+  if (lane < j) {
+    const double2 v = d.PV[(int64_t)k * HTD_NB + lane];
+    double2 w = d.PW[(int64_t)k * HTD_NB + lane];
+    if (lane == j - 1) w = cadd(w, cmul(al, v));
+    vk[lane] = v;
+    wk[lane] = w;
+  }
+  __syncthreads();
+  // x_r = conj(G[k][r]) - sum_l V[r][l] conj(w_k[l]) + W[r][l] conj(v_k[l])
+  double2 x = make_double2(a.x, -a.y);
+  if (own) {
+#pragma unroll
+    for (int u = 0; u < HTD_NB; ++u)
+      if (u < j) {
+        if (u == j - 1) {
+          ww[u] = cadd(ww[u], cmul(al, vv[u]));
+          d.PW[r * HTD_NB + u] = ww[u];
+        }
+        x = csub(csub(x, cmulc(wk[u], vv[u])), cmulc(vk[u], ww[u]));
+      }
+    d.xb[i] = x;
+  }
+  const bool tail = own && i > 0;
+  if (lane < KC_ROWS) {
+    xs[lane] = tail ? x : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < HTD_NB; ++u) {
+      pan[lane][u] = vv[u];
+      pan[lane][HTD_NB + u] = ww[u];
+    }
+  }
+  // scaled norm of x_1 ... over this workgroup's rows
+  double amax = tail ? fmax(fabs(x.x), fabs(x.y)) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  double ss = 0.0;
+  if (tail && amax > 0.0) ss = (x.x / amax) * (x.x / amax) + (x.y / amax) * (x.y / amax);
+  ss = wave_sum(ss);
+  __syncthreads();
+  // lane l < 32: (V^H x)_l, lane 32 + l: (W^H x)_l
+  double2 acc = make_double2(0.0, 0.0);
+  if ((lane & (HTD_NB - 1)) < j)
+#pragma unroll
+    for (int t = 0; t < KC_ROWS; ++t) acc = cadd(acc, cmulc(pan[t][lane], xs[t]));
+  double2* rec = d.kpart + (int64_t)lc.b * HTD_KP;
+  if (lane == 0) rec[0] = make_double2(amax, ss);
+  rec[2 + lane] = acc;
+  if (lc.b == 0 && lane == 0) {
+    double dk = d.A[(int64_t)k * ld + k].x;
+    for (int q = 0; q < j; ++q) dk -= 2.0 * (vk[q].x * wk[q].x + vk[q].y * wk[q].y);
+    d.d[k] = dk;
+  }
+}
+
+// One trailing row per wavefront.  Everything that does not depend on the
+// reflector is loaded first: the whole row (up to HTD_MAX columns, 32 per
+// lane), its panel term, the trd_col records and the raw column x (into
+// LDS).  The reflector is then rebuilt from the records (every workgroup
+// does it, in the same order) and applied inside the product:
+// G v = G[:, 0] + scale (G[:, 1:] x[1:]) since v = (1, scale x[1:]).
+__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int k) {
+  __shared__ double2 xs[HTD_MAX];
+  __shared__ double2 vhv[HTD_NB], whv[HTD_NB];
+  __shared__ double2 wred[4];
+  __shared__ double2 hsum[4][2 * HTD_NB];
+  __shared__ double sh2[2];
+  const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_hemv_blocks(n, k); });
+  if (lc.p < 0) return;
+  const HtdDesc& d = ds[lc.p];
+  if (skipped(d)) return;
+  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, tid = threadIdx.x;
+  const int j = k & (HTD_NB - 1);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int i0 = lc.b * HV_ROWS + wave;
+  const bool row = i0 < m;
+  const double2* a0 = d.A + (int64_t)(k + 1 + (row ? i0 : 0)) * ld + (k + 1);
+  constexpr int PL = HTD_MAX / 64;  // row entries per lane
+  double2 p[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int c = lane + 64 * u;
+    p[u] = row && c < m ? a0[c] : make_double2(0.0, 0.0);
+  }
+  const int l = lane & (HTD_NB - 1);
+  const bool isv = lane < HTD_NB;
+  double2 pe = make_double2(0.0, 0.0);
+  if (row && l < j) pe = isv ? d.PV[(int64_t)(k + 1 + i0) * HTD_NB + l] : d.PW[(int64_t)(k + 1 + i0) * HTD_NB + l];
+  for (int jj = tid; jj < m; jj += 256) xs[jj] = d.xb[jj];
+  // trd_col records: thread (g, e) sums entry e over the records q = g mod 4
+  // (their loads issued together); (scale, ssq) by the first wavefront
+  const int nka = htd_col_blocks(n, k);
+  const double2* recs = d.kpart;
+  constexpr int RQ = HTD_MAX / KC_ROWS / 4;  // records per group
+  {
+    const int e = tid & 63, g = tid >> 6;
+    double2 t = make_double2(0.0, 0.0);
+    if ((e & (HTD_NB - 1)) < j) {
+      double2 rv[RQ];
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) {
+        const int q = g + 4 * u;
+        rv[u] = q < nka ? recs[(int64_t)q * HTD_KP + 2 + e] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) t = cadd(t, rv[u]);
+    }
+    hsum[g][e] = t;
+  }
+  double rs = 0.0, rm = 0.0;  // this lane's record (wavefront 0: lane q < nka)
+  if (tid < 64) {
+    double2 rq = make_double2(0.0, 0.0);
+    if (tid < nka) rq = recs[(int64_t)tid * HTD_KP];
+    rm = rq.x;
+    rs = rq.y;
+    double smax = rm;
+    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
+    const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
+    const double ssq_w = wave_sum(c);
+    if (tid == 0) {
+      sh2[0] = smax;
+      sh2[1] = ssq_w;
+    }
+  }
+  __syncthreads();
+  const double smax = sh2[0], ssq = sh2[1];
+  double2 sv = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
+  if (tid < j) {
+    sv = cadd(cadd(hsum[0][tid], hsum[1][tid]), cadd(hsum[2][tid], hsum[3][tid]));
+    sw = cadd(cadd(hsum[0][HTD_NB + tid], hsum[1][HTD_NB + tid]), cadd(hsum[2][HTD_NB + tid], hsum[3][HTD_NB + tid]));
+  }
+  const double2 alpha = d.xb[0];
+  const double amax = fmax(smax, fmax(fabs(alpha.x), fabs(alpha.y)));
   double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
   double beta = alpha.x;
-  if (xs2 > 0.0 || alpha.y != 0.0) {
-    const double ar = alpha.x / amax, ai = alpha.y / amax;
-    beta = -copysign(amax * sqrt(ar * ar + ai * ai + xs2), alpha.x);
-    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-    // scale = 1 / (alpha - beta) by Smith's complex division
-    const double dr = alpha.x - beta, di = alpha.y;
-    if (fabs(dr) >= fabs(di)) {
-      const double r = di / dr, t = 1.0 / (dr + di * r);
-      scale = make_double2(t, -r * t);
-    } else {
-      const double r = dr / di, t = 1.0 / (di + dr * r);
-      scale = make_double2(r * t, -t);
+  if (amax > 0.0) {
+    const double xs2 = ssq * (smax / amax) * (smax / amax);
+    if (xs2 > 0.0 || alpha.y != 0.0) {
+      const double ar = alpha.x / amax, ai = alpha.y / amax;
+      beta = -copysign(amax * sqrt(ar * ar + ai * ai + xs2), alpha.x);
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      // scale = 1 / (alpha - beta) by Smith's complex division
+      const double dr = alpha.x - beta, di = alpha.y;
+      if (fabs(dr) >= fabs(di)) {
+        const double rr = di / dr, t = 1.0 / (dr + di * rr);
+        scale = make_double2(t, -rr * t);
+      } else {
+        const double rr = dr / di, t = 1.0 / (di + dr * rr);
+        scale = make_double2(rr * t, -t);
+      }
     }
   }
   const bool ident = tau.x == 0.0 && tau.y == 0.0;
-  __syncthreads();  // vs[0] read by everyone
-  for (int j = tid; j < m; j += 256)
-    vs[j] = j == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(vs[j], scale));
+  if (tid < j) {
+    // V^H v = conj(V[k+1, l]) + scale sum_{i >= 1} conj(V[k+1+i, l]) x_i, likewise W
+    const double2 v1 = d.PV[(int64_t)(k + 1) * HTD_NB + tid], w1 = d.PW[(int64_t)(k + 1) * HTD_NB + tid];
+    vhv[tid] = cadd(make_double2(v1.x, -v1.y), cmul(scale, sv));
+    whv[tid] = cadd(make_double2(w1.x, -w1.y), cmul(scale, sw));
+  }
   __syncthreads();
 
-  const int wave = tid >> 6, lane = tid & 63;
-  double2 part = make_double2(0.0, 0.0);
-  for (int rr = 0; rr < HV_ROWS / 4; ++rr) {
-    const int i = lc.b * HV_ROWS + wave * (HV_ROWS / 4) + rr;
-    if (i >= m) break;
-    double2 yi = make_double2(0.0, 0.0);
-    if (!ident) {
-      const double2* arow = d.A + (int64_t)(k + 1 + i) * ld + (k + 1);
-      double ax = 0.0, ay = 0.0;
-      for (int j = lane; j < m; j += 64) {
-        const double2 a = arow[j], v = vs[j];
-        ax += a.x * v.x - a.y * v.y;
-        ay += a.x * v.y + a.y * v.x;
+  double2 y0 = make_double2(0.0, 0.0);
+  if (!ident && row) {
+    double rx = 0.0, ry = 0.0;  // G[r][1:] x[1:]
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int c = lane + 64 * u;
+      if (c < m && c > 0) {
+        const double2 v = xs[c];
+        rx += p[u].x * v.x - p[u].y * v.y;
+        ry += p[u].x * v.y + p[u].y * v.x;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        ax += __shfl_xor(ax, off);
-        ay += __shfl_xor(ay, off);
-      }
-      yi = cmul(tau, make_double2(ax, ay));
     }
-    if (lane == 0) d.y[i] = yi;
-    part = cadd(part, cmulc(yi, vs[i]));
+    // panel term: lane l < 32 gives V[r][l] (W^H v)_l, lane 32 + l W[r][l] (V^H v)_l
+    const double2 c0 = l < j ? cmul(pe, isv ? whv[l] : vhv[l]) : make_double2(0.0, 0.0);
+    const double2 g = cmul(scale, make_double2(wave_sum(rx), wave_sum(ry)));
+    const double2 h = make_double2(wave_sum(c0.x), wave_sum(c0.y));
+    const double2 g0 = make_double2(__shfl(p[0].x, 0), __shfl(p[0].y, 0));  // G[r][0] (v_0 = 1)
+    y0 = cmul(tau, csub(cadd(g0, g), h));
+  }
+  double2 part = make_double2(0.0, 0.0);
+  if (row) {
+    if (lane == 0) d.PW[(int64_t)(k + 1 + i0) * HTD_NB + j] = y0;
+    const double2 vi = i0 == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[i0], scale));
+    part = cmulc(y0, vi);
   }
   if (lane == 0) wred[wave] = part;
   __syncthreads();
   if (tid == 0) d.part[lc.b] = cadd(cadd(wred[0], wred[1]), cadd(wred[2], wred[3]));
   if (lc.b == 0) {
-    for (int j = tid; j < m; j += 256) d.v[j] = vs[j];
+    for (int jj = tid; jj < m; jj += 256) {
+      const double2 v = jj == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[jj], scale));
+      d.PV[(int64_t)(k + 1 + jj) * HTD_NB + j] = v;
+      d.A[(int64_t)k * ld + (k + 1 + jj)] = v;
+    }
     if (tid == 0) {
       d.tau[k] = tau;
       d.e[k] = beta;
-      d.d[k] = d.A[(int64_t)k * ld + k].x;
     }
   }
 }
 
-// G22 -= v w^H + w v^H with w = y - (tau/2)(y^H v) v, on 64 x 64 tiles; the
-// first tile row also stores v in row k (columns k+1 ...) for the
-// back-transformation.
-__global__ __launch_bounds__(256) void trd_her2_kernel(const HtdDesc* __restrict__ ds, int np, int k) {
-  __shared__ double2 vr[64], wr[64], vc[64], wc[64];
-  __shared__ double2 red[256];
-  const Loc lc = locate(ds, np, blockIdx.x, [k](int n) { return htd_her2_blocks(n, k); });
+// End of a panel: G[p1:, p1:] -= V W^H + W V^H (p1 = first column after the
+// panel) as C = [V | W] [W | V]^H with K = 2 HTD_NB, on 64 x 64 tiles; the
+// panel's last w is finalised while staging.
+__global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int p0) {
+  __shared__ double2 As[16][64 + 1];
+  __shared__ double2 Bs[16][64 + 1];
+  __shared__ double sh[4];
+  const Loc lc = locate(sz, blockIdx.x, [p0](int n) { return htd_her2k_blocks(n, p0); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), m = n - k - 1, ld = d.ld, tid = threadIdx.x;
-  const int T = (m + 63) / 64, ti = lc.b / T, tj = lc.b % T;
-  const double2 tau = d.tau[k];
-  const bool ident = tau.x == 0.0 && tau.y == 0.0;
-  const int nbp = htd_hemv_blocks(n, k);
-  double2 s = make_double2(0.0, 0.0);
-  for (int q = tid; q < nbp; q += 256) s = cadd(s, d.part[q]);
-  red[tid] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = cadd(red[tid], red[tid + w]);
+  const int n = sz.n[lc.p], ld = d.ld, tid = threadIdx.x;
+  const int nbp = min(HTD_NB, n - 1 - p0), p1 = p0 + nbp, mt = n - p1;
+  const int T = (mt + 63) / 64, ti = lc.b / T, tj = lc.b % T;
+  const int kl = p1 - 1;
+  const int nb = htd_hemv_blocks(n, kl);
+  double sx = 0.0, sy = 0.0;
+  for (int q = tid; q < nb; q += 256) {
+    sx += d.part[q].x;
+    sy += d.part[q].y;
+  }
+  sx = block4_sum(sx, sh);
+  sy = block4_sum(sy, sh);
+  const double2 tl = d.tau[kl];
+  const double2 al = cmul(make_double2(-0.5 * tl.x, -0.5 * tl.y), make_double2(sx, sy));  // finalises the last w
+  const int r0 = p1 + ti * 64, c0 = p1 + tj * 64;
+  const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  // [V | W] (row r, index l < 2 HTD_NB), w of column nbp-1 finalised
+  auto vw = [&](int r, int l) -> double2 {
+    const bool isv = l < HTD_NB;
+    const int q = isv ? l : l - HTD_NB;
+    if (q >= nbp || r >= n) return make_double2(0.0, 0.0);
+    const double2 v = d.PV[(int64_t)r * HTD_NB + q];
+    if (isv) return v;
+    double2 w = d.PW[(int64_t)r * HTD_NB + q];
+    if (q == nbp - 1) w = cadd(w, cmul(al, v));
+    return w;
+  };
+  CAcc<double> acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y].clear();
+  for (int l0 = 0; l0 < 2 * HTD_NB; l0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int row = e >> 4, kk = e & 15, l = l0 + kk;
+      As[kk][row] = vw(r0 + row, l);
+      const double2 b = vw(c0 + row, l < HTD_NB ? l + HTD_NB : l - HTD_NB);  // [W | V] at column c
+      Bs[kk][row] = make_double2(b.x, -b.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      const double2 a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
+      const double2 b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
+      acc[0][0].mac(a0.x, a0.y, b0.x, b0.y);
+      acc[0][1].mac(a0.x, a0.y, b1.x, b1.y);
+      acc[1][0].mac(a1.x, a1.y, b0.x, b0.y);
+      acc[1][1].mac(a1.x, a1.y, b1.x, b1.y);
+    }
     __syncthreads();
   }
-  const double2 alpha = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), red[0]);
-  if (tid < 128) {
-    const int l = tid & 63;
-    const int i = (tid < 64 ? ti : tj) * 64 + l;
-    double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
-    if (i < m) {
-      v = d.v[i];
-      w = cadd(d.y[i], cmul(alpha, v));
-    }
-    if (tid < 64) {
-      vr[l] = v;
-      wr[l] = w;
-    } else {
-      vc[l] = v;
-      wc[l] = w;
-    }
-  }
-  __syncthreads();
-  if (!ident) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int l = e >> 6, c = e & 63;
-      const int i = ti * 64 + l, j = tj * 64 + c;
-      if (i < m && j < m) {
-        double2* p = d.A + (int64_t)(k + 1 + i) * ld + (k + 1 + j);
-        const double2 t1 = cmulc(wc[c], vr[l]);  // v_i conj(w_j)
-        const double2 t2 = cmulc(vc[c], wr[l]);  // w_i conj(v_j)
-        *p = csub(csub(*p, t1), t2);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
+        const int c = c0 + wn * 32 + y * 16 + (lane & 15);
+        if (r < n && c < n) {
+          double2* p = d.A + (int64_t)r * ld + c;
+          *p = make_double2(p->x - acc[x][y].re[q], p->y - acc[x][y].im[q]);
+        }
       }
-    }
-  }
-  if (ti == 0 && tid < 64) {
-    const int j = tj * 64 + tid;
-    if (j < m) d.A[(int64_t)k * ld + (k + 1 + j)] = vc[tid];
-  }
 }
 
-__global__ void trd_finish_kernel(const HtdDesc* __restrict__ ds, int np) {
+__global__ void trd_finish_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
+  if (p >= sz.np) return;
   const HtdDesc& d = ds[p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n);
+  const int n = sz.n[p];
   if (n < 1) return;
   d.d[n - 1] = d.A[(int64_t)(n - 1) * d.ld + (n - 1)].x;
   d.e[n - 1] = 0.0;
 }
 
 // ======================================================= divide and conquer
+// The eigenvector matrices of the nodes are stored by columns: Q[col * ld +
+// row], so that deflation rotations and column copies read whole columns.
+//
 // Level 0: T torn at every off-diagonal entry (d_i -= |e_{i-1}| + |e_i|),
 // 1 x 1 blocks with eigenvector 1.  Both eigenvector buffers start at zero:
-// a merge multiplies whole rows of its node, so the quadrants outside the
+// a merge multiplies whole columns of its node, so the quadrants outside the
 // children's blocks must hold exact zeros (later levels only ever write
 // inside their own node blocks).
-__global__ __launch_bounds__(256) void dc_init_kernel(const HtdDesc* __restrict__ ds, int np) {
-  const Loc lc = locate(ds, np, blockIdx.x, [](int n) { return n; });
+__global__ __launch_bounds__(256) void dc_init_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
+  const Loc lc = locate(sz, blockIdx.x, [](int n) { return n; });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), i = lc.b, ld = d.ld;
+  const int n = sz.n[lc.p], i = lc.b, ld = d.ld;
   double* q0 = d.Q[0] + (int64_t)i * ld;
   double* q1 = d.Q[1] + (int64_t)i * ld;
   for (int c = threadIdx.x; c < n; c += 256) {
@@ -267,17 +506,17 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // z = (last row of Q1, sign(e) first row of Q2) / sqrt(2), rho = 2 |e_{mid-1}|.
 // Sorts the poles, deflates small z components and (after a rotation)
 // close poles, and lists the non-deflated poles for the secular equation.
-__global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict__ ds, int np, int L) {
+__global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
   __shared__ double Ds[HTD_MAX];
   __shared__ double zs[HTD_MAX];
   __shared__ int col[HTD_MAX];
   __shared__ double red[16];
   __shared__ int sh_ndef;
-  const Loc lc = locate(ds, np, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
+  const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), s = 1 << L, tid = threadIdx.x;
+  const int n = sz.n[lc.p], s = 1 << L, tid = threadIdx.x;
   const int lo = lc.b * s, mid = lo + s / 2, hi = min(lo + s, n);
   int* cnt = d.cnt + 4 * lo;
   if (mid >= hi) {
@@ -304,7 +543,7 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
           b = mm;
       }
       rank = t + a;
-      z = Qin[(int64_t)(mid - 1) * ld + lo + t];
+      z = Qin[(int64_t)(lo + t) * ld + (mid - 1)];
     } else {
       const int q = t - nl;
       val = Din[mid + q];
@@ -317,7 +556,7 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
           b = mm;
       }
       rank = q + a;
-      z = sg * Qin[(int64_t)mid * ld + mid + q];
+      z = sg * Qin[(int64_t)(mid + q) * ld + mid];
     }
     Ds[rank] = val;
     zs[rank] = z * r2;
@@ -432,15 +671,23 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   }
 }
 
+// dl_j - lambda_k, formed as (dl_j - dl_origin) - tau so that it keeps full
+// relative accuracy next to either pole
+__device__ __forceinline__ double delta_jk(const double* dl, int j, int o, double tau) {
+  return (dl[j] - dl[o]) - tau;
+}
+
 // Root k of the secular equation 1 + rho sum_j w_j^2 / (dl_j - lambda) = 0 in
-// (dl_k, dl_{k+1}) (last root: (dl_k, dl_k + rho |w|^2]).  lambda is kept as
-// dl_origin + tau with the origin at the nearer pole, so every dl_j - lambda
-// is formed as (dl_j - dl_origin) - tau.  Iteration: each step replaces the
-// two poles' terms by the rational model of Li's middle way (value and slope
-// of both sums matched at the current point) and takes the root of the
-// resulting quadratic; a bracket on the sign of f guards every step and falls
-// back to bisection (geometric when the bracket spans a decade or more).
-__device__ void secular_root(const double* dl, const double* w, int K2, double rho, int k, int& origin,
+// (dl_k, dl_{k+1}) (last root: (dl_k, dl_k + rho |w|^2]), computed by one
+// wavefront (the sums over j are split across the lanes; every lane ends with
+// the same sums, so control flow is uniform).  lambda is kept as
+// dl_origin + tau with the origin at the nearer pole.  Iteration: each step
+// replaces the two poles' terms by the rational model of Li's middle way
+// (value and slope of both sums matched at the current point) and takes the
+// root of the resulting quadratic; a bracket on the sign of f guards every
+// step and falls back to bisection (geometric when the bracket spans a
+// decade or more).
+__device__ void secular_root(const double* dl, const double* w, int K2, double rho, int k, int lane, int& origin,
                              double& tau_out) {
   if (K2 == 1) {
     origin = 0;
@@ -452,8 +699,9 @@ __device__ void secular_root(const double* dl, const double* w, int K2, double r
   double tlo, thi;
   if (!last) {
     const double mid = 0.5 * (dl[k + 1] - dl[k]);
-    double f = 1.0;
-    for (int j = 0; j < K2; ++j) f += rho * w[j] * w[j] / ((dl[j] - dl[k]) - mid);
+    double f = 0.0;
+    for (int j = lane; j < K2; j += 64) f += w[j] * w[j] / ((dl[j] - dl[k]) - mid);
+    f = 1.0 + rho * wave_sum(f);
     if (f >= 0.0) {
       o = k;
       tlo = 0.0;
@@ -466,17 +714,15 @@ __device__ void secular_root(const double* dl, const double* w, int K2, double r
   } else {
     o = k;
     double s = 0.0;
-    for (int j = 0; j < K2; ++j) s += w[j] * w[j];
+    for (int j = lane; j < K2; j += 64) s += w[j] * w[j];
     tlo = 0.0;
-    thi = rho * s;
+    thi = rho * wave_sum(s);
   }
-  const double base = dl[o];
   double tau = 0.5 * (tlo + thi);
   for (int it = 0; it < 200; ++it) {
     double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
-    for (int j = 0; j < K2; ++j) {
-      const double del = (dl[j] - base) - tau;
-      const double t = w[j] / del;
+    for (int j = lane; j < K2; j += 64) {
+      const double t = w[j] / delta_jk(dl, j, o, tau);
       if (j <= k) {
         psi += w[j] * t;
         dpsi += t * t;
@@ -485,10 +731,10 @@ __device__ void secular_root(const double* dl, const double* w, int K2, double r
         dphi += t * t;
       }
     }
-    psi *= rho;
-    phi *= rho;
-    dpsi *= rho;
-    dphi *= rho;
+    psi = rho * wave_sum(psi);
+    phi = rho * wave_sum(phi);
+    dpsi = rho * wave_sum(dpsi);
+    dphi = rho * wave_sum(dphi);
     const double f = 1.0 + psi + phi;
     if (f == 0.0) break;
     if (f < 0.0)
@@ -497,10 +743,10 @@ __device__ void secular_root(const double* dl, const double* w, int K2, double r
       thi = tau;
     const double err = 8.0 * EPS53 * K2 * (1.0 + fabs(psi) + fabs(phi));
     if (fabs(f) <= err || thi - tlo <= 4.0 * EPS53 * fmax(fabs(tlo), fabs(thi))) break;
-    const double di = (dl[k] - base) - tau;
+    const double di = delta_jk(dl, k, o, tau);
     double eta;
     if (!last) {
-      const double dj = (dl[k + 1] - base) - tau;
+      const double dj = delta_jk(dl, k + 1, o, tau);
       const double c = f - di * dpsi - dj * dphi;
       const double a = (di + dj) * f - di * dj * (dpsi + dphi);
       const double b = di * dj * f;
@@ -531,63 +777,75 @@ __device__ void secular_root(const double* dl, const double* w, int K2, double r
   tau_out = tau;
 }
 
-// per-row stages of a merge level (thread per row / root / pole of a node)
-__global__ __launch_bounds__(256) void dc_rows_kernel(const HtdDesc* __restrict__ ds, int np, int L, int stage) {
-  const Loc lc = locate(ds, np, blockIdx.x, [](int n) { return htd_rows(n); });
+// Deflation rotations of a merge level on the children's eigenvector
+// columns, one thread per row.
+__global__ __launch_bounds__(256) void dc_rot_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
+  const Loc lc = locate(sz, blockIdx.x, [](int n) { return htd_rows(n); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), i = lc.b * 256 + threadIdx.x;
+  const int n = sz.n[lc.p], i = lc.b * 256 + threadIdx.x;
   if (i >= n) return;
   const int lo = (i >> L) << L, ld = d.ld;
   const int* cnt = d.cnt + 4 * lo;
   if (!cnt[3]) return;
-  const int K2 = cnt[0];
-  const int k = i - lo;
+  double* q = d.Q[(L - 1) & 1] + i;
+  const int nrot = cnt[2];
+  for (int r = 0; r < nrot; ++r) {
+    const int a = d.rot_a[lo + r], b = d.rot_b[lo + r];
+    const double c = d.rot_c[lo + r], s = d.rot_s[lo + r];
+    const double x = q[(int64_t)a * ld], y = q[(int64_t)b * ld];
+    q[(int64_t)a * ld] = c * x + s * y;
+    q[(int64_t)b * ld] = c * y - s * x;
+  }
+}
+
+// One wavefront per root / pole of a merge level: stage 1 solves the secular
+// equation of root k, stage 2 recomputes z_j from all roots (Loewner:
+// zhat_j^2 = prod_k (lambda_k - dl_j) / (rho prod_{k != j} (dl_k - dl_j))),
+// stage 3 the norm of eigenvector k, u_j = zhat_j / (dl_j - lambda_k).
+__global__ __launch_bounds__(256) void dc_wave_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L, int stage) {
+  const Loc lc = locate(sz, blockIdx.x, [](int n) { return htd_waves(n); });
+  if (lc.p < 0) return;
+  const HtdDesc& d = ds[lc.p];
+  if (skipped(d)) return;
+  const int n = sz.n[lc.p], lane = threadIdx.x & 63;
+  const int i = lc.b * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lo = (i >> L) << L;
+  const int* cnt = d.cnt + 4 * lo;
+  if (!cnt[3]) return;
+  const int K2 = cnt[0], k = i - lo;
+  if (k >= K2) return;
   const double* dl = d.dl + lo;
   const double* w = d.w + lo;
-  if (stage == 0) {
-    // deflation rotations on row i of the children's eigenvectors
-    double* q = d.Q[(L - 1) & 1] + (int64_t)i * ld;
-    const int nrot = cnt[2];
-    for (int r = 0; r < nrot; ++r) {
-      const int a = d.rot_a[lo + r], b = d.rot_b[lo + r];
-      const double c = d.rot_c[lo + r], s = d.rot_s[lo + r];
-      const double x = q[a], y = q[b];
-      q[a] = c * x + s * y;
-      q[b] = c * y - s * x;
-    }
-  } else if (stage == 1) {
-    if (k >= K2) return;
+  const int* org = d.origin + lo;
+  const double* st = d.stau + lo;
+  if (stage == 1) {
     int o;
     double tau;
-    secular_root(dl, w, K2, d.rho[lo], k, o, tau);
-    d.origin[lo + k] = o;
-    d.stau[lo + k] = tau;
-    const double base = dl[o];
-    for (int j = 0; j < K2; ++j) d.DeltaT[(int64_t)(lo + j) * ld + lo + k] = (dl[j] - base) - tau;
+    secular_root(dl, w, K2, d.rho[lo], k, lane, o, tau);
+    if (lane == 0) {
+      d.origin[lo + k] = o;
+      d.stau[lo + k] = tau;
+    }
   } else if (stage == 2) {
-    // zhat_j^2 = prod_k (lambda_k - dl_j) / (rho prod_{k != j} (dl_k - dl_j))
-    if (k >= K2) return;
-    const double* dt = d.DeltaT + (int64_t)(lo + k) * ld + lo;
-    double v = -dt[k] / d.rho[lo];
-    for (int q = 0; q < K2; ++q)
-      if (q != k) v *= (-dt[q]) / (dl[q] - dl[k]);
-    d.zhat[lo + k] = copysign(sqrt(fmax(v, 0.0)), w[k]);
+    const int j = k;
+    double v = 1.0;
+    for (int q = lane; q < K2; q += 64)
+      if (q != j) v *= (-delta_jk(dl, j, org[q], st[q])) / (dl[q] - dl[j]);
+    for (int off = 32; off > 0; off >>= 1) v *= __shfl_xor(v, off);
+    v *= -delta_jk(dl, j, org[j], st[j]) / d.rho[lo];
+    if (lane == 0) d.zhat[lo + j] = copysign(sqrt(fmax(v, 0.0)), w[j]);
   } else {
-    // eigenvector of root k: u_j = zhat_j / (dl_j - lambda_k), normalised
-    if (k >= K2) return;
     const double* zh = d.zhat + lo;
     double s2 = 0.0;
-    for (int j = 0; j < K2; ++j) {
-      const double u = zh[j] / d.DeltaT[(int64_t)(lo + j) * ld + lo + k];
+    for (int j = lane; j < K2; j += 64) {
+      const double u = zh[j] / delta_jk(dl, j, org[k], st[k]);
       s2 += u * u;
     }
-    const double inv = 1.0 / sqrt(s2);
-    for (int j = 0; j < K2; ++j) {
-      const int64_t e = (int64_t)(lo + j) * ld + lo + k;
-      d.U[e] = zh[j] / d.DeltaT[e] * inv;
-    }
+    s2 = wave_sum(s2);
+    if (lane == 0) d.unrm[lo + k] = 1.0 / sqrt(s2);
   }
 }
 
@@ -595,15 +853,15 @@ __global__ __launch_bounds__(256) void dc_rows_kernel(const HtdDesc* __restrict_
 // the next level's list, copies the deflated eigenvectors and records where
 // the GEMM writes each root's eigenvector.  Nodes without a right child are
 // carried over unchanged.
-__global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restrict__ ds, int np, int L) {
+__global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
   __shared__ double lamv[HTD_MAX];
   __shared__ double dv[HTD_MAX];
   __shared__ int pdef[HTD_MAX];
-  const Loc lc = locate(ds, np, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
+  const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), s = 1 << L, tid = threadIdx.x, ld = d.ld;
+  const int n = sz.n[lc.p], s = 1 << L, tid = threadIdx.x, ld = d.ld;
   const int lo = lc.b * s, hi = min(lo + s, n), K = hi - lo;
   const double* Din = d.D[(L - 1) & 1];
   const double* Qin = d.Q[(L - 1) & 1];
@@ -612,8 +870,8 @@ __global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restric
   const int* cnt = d.cnt + 4 * lo;
   if (!cnt[3]) {
     for (int e = tid; e < K * K; e += 1024) {
-      const int r = e / K, c = e % K;
-      Qout[(int64_t)(lo + r) * ld + lo + c] = Qin[(int64_t)(lo + r) * ld + lo + c];
+      const int c = e / K, r = e % K;
+      Qout[(int64_t)(lo + c) * ld + lo + r] = Qin[(int64_t)(lo + c) * ld + lo + r];
     }
     for (int c = tid; c < K; c += 1024) Dout[lo + c] = Din[lo + c];
     return;
@@ -651,46 +909,51 @@ __global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restric
   __syncthreads();
   for (int e = tid; e < ndef * K; e += 1024) {
     const int q = e / K, r = e % K;
-    Qout[(int64_t)(lo + r) * ld + lo + pdef[q]] = Qin[(int64_t)(lo + r) * ld + d.dcol[lo + q]];
+    Qout[(int64_t)(lo + pdef[q]) * ld + lo + r] = Qin[(int64_t)d.dcol[lo + q] * ld + lo + r];
   }
 }
 
-// Q_out[:, pos_k] = Q_in[:, ndcol] U[:, k] for the node's rows, on the matrix
-// cores (f64 16x16x4); each of the four wavefronts owns a 32 x 32 quadrant of
-// the 64 x 64 tile.
-__global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict__ ds, int np, int L) {
+// Eigenvector of root k = Q_in[:, ndcol] u_k, written to column lo + pos_k:
+// with columns stored contiguously this is C = U^T B, C[k][r] =
+// sum_j u_k[j] Q_in[ndcol_j][r]; u_k[j] = zhat_j / (dl_j - lambda_k) / |.|
+// is formed while staging.  Matrix cores (f64 16x16x4), each of the four
+// wavefronts owns a 32 x 32 quadrant of the 64 x 64 tile (roots x rows).
+__global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
   __shared__ double As[16][64 + 1];
   __shared__ double Bs[16][64 + 1];
-  const Loc lc = locate(ds, np, blockIdx.x, [L](int n) { return htd_gemm_tiles(n, L); });
+  const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_gemm_tiles(n, L); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), s = 1 << L, ld = d.ld;
+  const int n = sz.n[lc.p], s = 1 << L, ld = d.ld;
   const int T = (s + 63) / 64, per = T * T;
   const int node = lc.b / per, t = lc.b % per, ti = t / T, tj = t % T;
   const int lo = node * s, hi = min(lo + s, n), K = hi - lo;
   const int* cnt = d.cnt + 4 * lo;
   if (!cnt[3]) return;
   const int K2 = cnt[0];
-  const int r0 = ti * 64, k0 = tj * 64;
-  if (r0 >= K || k0 >= K2) return;
+  const int k0 = ti * 64, r0 = tj * 64;  // roots k0.., rows r0..
+  if (k0 >= K2 || r0 >= K) return;
   const double* Qin = d.Q[(L - 1) & 1];
   double* Qout = d.Q[L & 1];
   const int* ndc = d.ndcol + lo;
+  const double* dl = d.dl + lo;
+  const double* zh = d.zhat + lo;
+  const int* org = d.origin + lo;
+  const double* st = d.stau + lo;
+  const double* un = d.unrm + lo;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   f64x4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<double>::zero();
+    for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::zero();
   for (int j0 = 0; j0 < K2; j0 += 16) {
     for (int e = tid; e < 1024; e += 256) {
-      const int c = e >> 4, kk = e & 15;  // A: row c of the tile, pole j0 + kk
-      const int j = j0 + kk, r = r0 + c;
-      As[kk][c] = (j < K2 && r < K) ? Qin[(int64_t)(lo + r) * ld + ndc[j]] : 0.0;
-      const int kk2 = e >> 6, c2 = e & 63;  // B: pole j0 + kk2, root k0 + c2
-      const int j2 = j0 + kk2, kc = k0 + c2;
-      Bs[kk2][c2] = (j2 < K2 && kc < K2) ? d.U[(int64_t)(lo + j2) * ld + lo + kc] : 0.0;
+      const int kk = e >> 6, c = e & 63;  // pole j0 + kk; root k0 + c / row r0 + c
+      const int j = j0 + kk, k = k0 + c, r = r0 + c;
+      As[kk][c] = (j < K2 && k < K2) ? zh[j] / delta_jk(dl, j, org[k], st[k]) * un[k] : 0.0;
+      Bs[kk][c] = (j < K2 && r < K) ? Qin[(int64_t)ndc[j] * ld + lo + r] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -706,29 +969,48 @@ __global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict_
     __syncthreads();
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + wm * 32 + bi * 16 + Mfma<double>::row(lane, r);
-        const int kc = k0 + wn * 32 + bj * 16 + (lane & 15);
-        if (row < K && kc < K2) Qout[(int64_t)(lo + row) * ld + lo + d.pos_nd[lo + kc]] = acc[bi][bj][r];
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
+        const int r = r0 + wn * 32 + y * 16 + (lane & 15);
+        if (k < K2 && r < K) Qout[(int64_t)(lo + d.pos_nd[lo + k]) * ld + lo + r] = acc[x][y][q];
       }
 }
 
 // ======================================================= back-transformation
-// V = Z (real eigenvectors of T, last level's buffer), lam = its eigenvalues.
-__global__ __launch_bounds__(256) void bt_init_kernel(const HtdDesc* __restrict__ ds, int np, int Lmax) {
-  const Loc lc = locate(ds, np, blockIdx.x, [](int n) { return n; });
+// V = Z (real eigenvectors of T from the last level's column-stored buffer,
+// transposed through LDS in 64 x 64 tiles) and lam, both in descending
+// eigenvalue order: the eigenvectors a split keeps are the first columns
+// (equal eigenvalues are taken lowest index first), so only min(n, rcap)
+// columns need the back-transformation.
+__global__ __launch_bounds__(256) void bt_init_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int Lmax) {
+  __shared__ double tile[64][64 + 1];
+  const Loc lc = locate(sz, blockIdx.x, [](int n) { return htd_tiles64(n); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), j = lc.b, ld = d.ld;
-  const double* z = d.Q[Lmax & 1] + (int64_t)j * ld;
-  double2* v = d.V + (int64_t)j * ld;
-  for (int c = threadIdx.x; c < n; c += 256) v[c] = make_double2(z[c], 0.0);
-  if (threadIdx.x == 0) d.lam[j] = d.D[Lmax & 1][j];
+  const int n = sz.n[lc.p], ld = d.ld, tid = threadIdx.x;
+  const int T = (n + 63) / 64, tr = lc.b / T, tc = lc.b % T;  // rows j, columns c of V
+  const double* Z = d.Q[Lmax & 1];
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int cc = e >> 6, jj = e & 63;
+    const int c = tc * 64 + cc, j = tr * 64 + jj;
+    tile[cc][jj] = (c < n && j < n) ? Z[(int64_t)(n - 1 - c) * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int jj = e >> 6, cc = e & 63;
+    const int c = tc * 64 + cc, j = tr * 64 + jj;
+    if (c < n && j < n) d.V[(int64_t)j * ld + c] = make_double2(tile[cc][jj], 0.0);
+  }
+  if (tr == 0)
+    for (int cc = tid; cc < 64; cc += 256) {
+      const int c = tc * 64 + cc;
+      if (c < n) d.lam[c] = d.D[Lmax & 1][n - 1 - c];
+    }
 }
 
 // reflector i of block b (k = HTD_NB b + i) at row j: 0 for j <= k, else row k of A
@@ -738,15 +1020,15 @@ __device__ __forceinline__ double2 refl(const HtdDesc& d, int k, int j) {
 
 // T of each block: H_k0 ... H_k0+nb-1 = I - V_b T V_b^H (upper triangular T,
 // T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V_b[:, 0:i]^H v_i).
-__global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict__ ds, int np) {
+__global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
   __shared__ double2 S[HTD_NB][HTD_NB];
   __shared__ double2 Ts[HTD_NB][HTD_NB];
   __shared__ double2 tv[HTD_NB];
-  const Loc lc = locate(ds, np, blockIdx.x, [](int n) { return htd_nblk(n); });
+  const Loc lc = locate(sz, blockIdx.x, [](int n) { return htd_nblk(n); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), b = lc.b, k0 = HTD_NB * b, tid = threadIdx.x;
+  const int n = sz.n[lc.p], b = lc.b, k0 = HTD_NB * b, tid = threadIdx.x;
   const int nb = min(HTD_NB, (n - 1) - k0);
   const int wave = tid >> 6, lane = tid & 63;
   // S[a][i] = v_a^H v_i for a < i (v_i vanishes above row k0 + i + 1)
@@ -788,179 +1070,220 @@ __global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict
   for (int e = tid; e < HTD_NB * HTD_NB; e += 256) out[e] = Ts[e / HTD_NB][e % HTD_NB];
 }
 
-// partial W = V_b^H V over a chunk of BT_CH rows (rows from k0 + 1), 64 columns
-__global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict__ ds, int np, int b) {
-  __shared__ double2 Vs[32][64];
-  __shared__ double2 Rs[HTD_NB][32];
-  const Loc lc = locate(ds, np, blockIdx.x, [b](int n) { return htd_wpart_blocks(n, b); });
+// partial W = V_b^H Z over a chunk of BT_CH rows (rows from k0 + 1) and 64
+// eigenvector columns, on the matrix cores: the 32 x 64 output is eight 16 x 16
+// blocks, two per wavefront.
+__global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
+  __shared__ double2 As[16][HTD_NB + 1];  // conj(v_i[j]), k-major
+  __shared__ double2 Bs[16][64 + 1];      // Z[j][c]
+  const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
+    return htd_wpart_blocks(n, nc, b);
+  });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
   const int nb = min(HTD_NB, (n - 1) - k0);
-  const int ct = (n + 63) / 64, ch = lc.b / ct, c0 = (lc.b % ct) * 64;
+  const int ct = (nc + 63) / 64, ch = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int rbeg = k0 + 1 + ch * BT_CH, rend = min(n, rbeg + BT_CH);
-  const int i = tid >> 3, c8 = (tid & 7) * 8;
-  double2 acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int j0 = rbeg; j0 < rend; j0 += 32) {
-    for (int e = tid; e < 32 * 64; e += 256) {
-      const int jj = e >> 6, c = e & 63, j = j0 + jj;
-      Vs[jj][c] = (j < rend && c0 + c < n) ? d.V[(int64_t)j * ld + c0 + c] : make_double2(0.0, 0.0);
+  const int lane = tid & 63, wave = tid >> 6, bi = wave >> 1, bj0 = (wave & 1) * 2;
+  CAcc<double> acc[2];
+  acc[0].clear();
+  acc[1].clear();
+  for (int j0 = rbeg; j0 < rend; j0 += 16) {
+    for (int e = tid; e < 16 * HTD_NB; e += 256) {
+      const int i = e >> 4, kk = e & 15, j = j0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < nb && j < rend) v = refl(d, k0 + i, j);
+      As[kk][i] = make_double2(v.x, -v.y);
     }
-    for (int e = tid; e < HTD_NB * 32; e += 256) {
-      const int ii = e >> 5, jj = e & 31, j = j0 + jj;
-      Rs[ii][jj] = (ii < nb && j < rend) ? refl(d, k0 + ii, j) : make_double2(0.0, 0.0);
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e >> 6, c = e & 63, j = j0 + kk;
+      Bs[kk][c] = (j < rend && c0 + c < nc) ? d.V[(int64_t)j * ld + c0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int jj = 0; jj < 32; ++jj) {
-      const double2 a = Rs[i][jj];  // conj(a) * V
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q] = cadd(acc[q], cmulc(a, Vs[jj][c8 + q]));
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      const double2 a = As[kr][bi * 16 + cl];
+      const double2 b0 = Bs[kr][bj0 * 16 + cl], b1 = Bs[kr][(bj0 + 1) * 16 + cl];
+      acc[0].mac(a.x, a.y, b0.x, b0.y);
+      acc[1].mac(a.x, a.y, b1.x, b1.y);
     }
     __syncthreads();
   }
-  double2* out = d.Wp + ((int64_t)ch * HTD_NB + i) * ld + c0 + c8;
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
-    if (c0 + c8 + q < n) out[q] = acc[q];
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = bi * 16 + Mfma<double>::row(lane, r);
+      const int c = c0 + (bj0 + q) * 16 + (lane & 15);
+      if (c < nc) d.Wp[((int64_t)ch * HTD_NB + i) * ld + c] = make_double2(acc[q].re[r], acc[q].im[r]);
+    }
 }
 
 // W = T (sum of the partials) for 64 columns
-__global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict__ ds, int np, int b) {
+__global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
   __shared__ double2 Ws[HTD_NB][64];
   __shared__ double2 Ts[HTD_NB][HTD_NB];
-  const Loc lc = locate(ds, np, blockIdx.x, [b](int n) { return htd_wred_blocks(n, b); });
+  const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
+    return htd_wred_blocks(n, nc, b);
+  });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), ld = d.ld, tid = threadIdx.x, c0 = lc.b * 64;
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, c0 = lc.b * 64;
   const int nch = (htd_bt_rows(n, b) + BT_CH - 1) / BT_CH;
   const double2* Tb = d.T + (int64_t)b * HTD_NB * HTD_NB;
   for (int e = tid; e < HTD_NB * HTD_NB; e += 256) Ts[e / HTD_NB][e % HTD_NB] = Tb[e];
   for (int e = tid; e < HTD_NB * 64; e += 256) {
     const int i = e >> 6, c = e & 63;
     double2 s = make_double2(0.0, 0.0);
-    if (c0 + c < n)
+    if (c0 + c < nc)
       for (int ch = 0; ch < nch; ++ch) s = cadd(s, d.Wp[((int64_t)ch * HTD_NB + i) * ld + c0 + c]);
     Ws[i][c] = s;
   }
   __syncthreads();
   for (int e = tid; e < HTD_NB * 64; e += 256) {
     const int i = e >> 6, c = e & 63;
-    if (c0 + c >= n) continue;
+    if (c0 + c >= nc) continue;
     double2 s = make_double2(0.0, 0.0);
     for (int l = i; l < HTD_NB; ++l) s = cadd(s, cmul(Ts[i][l], Ws[l][c]));
     d.W[(int64_t)i * ld + c0 + c] = s;
   }
 }
 
-// V[j][c] -= sum_i v_i[j] W[i][c] on 64 x 64 tiles of rows k0 + 1 ...
-__global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restrict__ ds, int np, int b) {
-  __shared__ double2 Rs[16][64];
-  __shared__ double2 Ws[16][64];
-  const Loc lc = locate(ds, np, blockIdx.x, [b](int n) { return htd_update_blocks(n, b); });
+// Z[j][c] -= sum_i v_i[j] W[i][c] on 64 x 64 tiles of rows k0 + 1 ...; each
+// wavefront owns a 32 x 32 quadrant (2 x 2 blocks of 16 x 16), K = HTD_NB.
+__global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
+  __shared__ double2 As[16][64 + 1];  // v_i[j], k-major
+  __shared__ double2 Bs[16][64 + 1];  // W[i][c]
+  const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
+    return htd_update_blocks(n, nc, b);
+  });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = dim_value(d.n), ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
   const int nb = min(HTD_NB, (n - 1) - k0);
-  const int ct = (n + 63) / 64, rt = lc.b / ct, c0 = (lc.b % ct) * 64;
+  const int ct = (nc + 63) / 64, rt = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int j0 = k0 + 1 + rt * 64;
-  const int l = tid >> 2, c16 = (tid & 3) * 16;
-  double2 acc[16];
+  const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  CAcc<double> acc[2][2];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y].clear();
   for (int i0 = 0; i0 < HTD_NB; i0 += 16) {
     for (int e = tid; e < 16 * 64; e += 256) {
       const int ii = e >> 6, x = e & 63;
-      const int j = j0 + x;
-      Rs[ii][x] = (i0 + ii < nb && j < n) ? refl(d, k0 + i0 + ii, j) : make_double2(0.0, 0.0);
-      Ws[ii][x] = (i0 + ii < nb && c0 + x < n) ? d.W[(int64_t)(i0 + ii) * ld + c0 + x] : make_double2(0.0, 0.0);
+      const int i = i0 + ii, j = j0 + x;
+      As[ii][x] = (i < nb && j < n) ? refl(d, k0 + i, j) : make_double2(0.0, 0.0);
+      Bs[ii][x] = (i < nb && c0 + x < nc) ? d.W[(int64_t)i * ld + c0 + x] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int ii = 0; ii < 16; ++ii) {
-      const double2 a = Rs[ii][l];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = cadd(acc[q], cmul(a, Ws[ii][c16 + q]));
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      const double2 a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
+      const double2 b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
+      acc[0][0].mac(a0.x, a0.y, b0.x, b0.y);
+      acc[0][1].mac(a0.x, a0.y, b1.x, b1.y);
+      acc[1][0].mac(a1.x, a1.y, b0.x, b0.y);
+      acc[1][1].mac(a1.x, a1.y, b1.x, b1.y);
     }
     __syncthreads();
   }
-  const int j = j0 + l;
-  if (j < n) {
-    double2* row = d.V + (int64_t)j * ld + c0 + c16;
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (c0 + c16 + q < n) row[q] = csub(row[q], acc[q]);
-  }
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
+        const int c = c0 + wn * 32 + y * 16 + (lane & 15);
+        if (j < n && c < nc) {
+          double2* p = d.V + (int64_t)j * ld + c;
+          *p = make_double2(p->x - acc[x][y].re[r], p->y - acc[x][y].im[r]);
+        }
+      }
 }
 
 }  // namespace
 
-hipError_t launch_trd_hemv(const HtdDesc* d, int np, int k, int blocks, hipStream_t s) {
+hipError_t launch_trd_hemv(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  trd_hemv_kernel<<<blocks, 256, 0, s>>>(d, np, k);
+  trd_hemv_kernel<<<blocks, 256, 0, s>>>(d, sz, k);
   return hipGetLastError();
 }
-hipError_t launch_trd_her2(const HtdDesc* d, int np, int k, int blocks, hipStream_t s) {
+hipError_t launch_trd_col(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  trd_her2_kernel<<<blocks, 256, 0, s>>>(d, np, k);
+  trd_col_kernel<<<blocks, 64, 0, s>>>(d, sz, k);
   return hipGetLastError();
 }
-hipError_t launch_trd_finish(const HtdDesc* d, int np, hipStream_t s) {
-  if (np <= 0) return hipSuccess;
-  trd_finish_kernel<<<(np + 63) / 64, 64, 0, s>>>(d, np);
+hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  trd_her2k_kernel<<<blocks, 256, 0, s>>>(d, sz, p0);
   return hipGetLastError();
 }
-hipError_t launch_dc_init(const HtdDesc* d, int np, int blocks, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  dc_init_kernel<<<blocks, 256, 0, s>>>(d, np);
+hipError_t launch_trd_finish(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) {
+  if (sz.np <= 0) return hipSuccess;
+  trd_finish_kernel<<<(sz.np + 63) / 64, 64, 0, s>>>(d, sz);
   return hipGetLastError();
 }
-hipError_t launch_dc_prep(const HtdDesc* d, int np, int L, int blocks, hipStream_t s) {
+hipError_t launch_dc_init(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_prep_kernel<<<blocks, 1024, 0, s>>>(d, np, L);
+  dc_init_kernel<<<blocks, 256, 0, s>>>(d, sz);
   return hipGetLastError();
 }
-hipError_t launch_dc_rows(int stage, const HtdDesc* d, int np, int L, int blocks, hipStream_t s) {
+hipError_t launch_dc_prep(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_rows_kernel<<<blocks, 256, 0, s>>>(d, np, L, stage);
+  dc_prep_kernel<<<blocks, 1024, 0, s>>>(d, sz, L);
   return hipGetLastError();
 }
-hipError_t launch_dc_place(const HtdDesc* d, int np, int L, int blocks, hipStream_t s) {
+hipError_t launch_dc_rot(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_place_kernel<<<blocks, 1024, 0, s>>>(d, np, L);
+  dc_rot_kernel<<<blocks, 256, 0, s>>>(d, sz, L);
   return hipGetLastError();
 }
-hipError_t launch_dc_gemm(const HtdDesc* d, int np, int L, int blocks, hipStream_t s) {
+hipError_t launch_dc_wave(int stage, const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_gemm_kernel<<<blocks, 256, 0, s>>>(d, np, L);
+  dc_wave_kernel<<<blocks, 256, 0, s>>>(d, sz, L, stage);
   return hipGetLastError();
 }
-hipError_t launch_bt_init(const HtdDesc* d, int np, int Lmax, int blocks, hipStream_t s) {
+hipError_t launch_dc_place(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_init_kernel<<<blocks, 256, 0, s>>>(d, np, Lmax);
+  dc_place_kernel<<<blocks, 1024, 0, s>>>(d, sz, L);
   return hipGetLastError();
 }
-hipError_t launch_bt_larft(const HtdDesc* d, int np, int blocks, hipStream_t s) {
+hipError_t launch_dc_gemm(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_larft_kernel<<<blocks, 256, 0, s>>>(d, np);
+  dc_gemm_kernel<<<blocks, 256, 0, s>>>(d, sz, L);
   return hipGetLastError();
 }
-hipError_t launch_bt_wpart(const HtdDesc* d, int np, int b, int blocks, hipStream_t s) {
+hipError_t launch_bt_init(const HtdDesc* d, const HtdSizes& sz, int Lmax, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_wpart_kernel<<<blocks, 256, 0, s>>>(d, np, b);
+  bt_init_kernel<<<blocks, 256, 0, s>>>(d, sz, Lmax);
   return hipGetLastError();
 }
-hipError_t launch_bt_wred(const HtdDesc* d, int np, int b, int blocks, hipStream_t s) {
+hipError_t launch_bt_larft(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_wred_kernel<<<blocks, 256, 0, s>>>(d, np, b);
+  bt_larft_kernel<<<blocks, 256, 0, s>>>(d, sz);
   return hipGetLastError();
 }
-hipError_t launch_bt_update(const HtdDesc* d, int np, int b, int blocks, hipStream_t s) {
+hipError_t launch_bt_wpart(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_update_kernel<<<blocks, 256, 0, s>>>(d, np, b);
+  bt_wpart_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
+  return hipGetLastError();
+}
+hipError_t launch_bt_wred(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  bt_wred_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
+  return hipGetLastError();
+}
+hipError_t launch_bt_update(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  bt_update_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
   return hipGetLastError();
 }
 

@@ -93,28 +93,33 @@ hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream
 // (Cuppen divide and conquer), eigenvectors Q Z (blocked back-transformation).
 constexpr int HTD_MAX = 2048;  // largest n: per-node lists are staged in LDS
 constexpr int HTD_NB = 32;     // reflectors per back-transformation block
-constexpr int HV_ROWS = 8;     // trailing-matrix rows per HEMV workgroup
+constexpr int HV_ROWS = 4;     // trailing-matrix rows per HEMV workgroup (one per wavefront)
+constexpr int HTD_KP = 2 + 2 * HTD_NB;  // per trd_col workgroup: (max, sum of squares), V^H x, W^H x
+constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (one wavefront)
 constexpr int BT_CH = 256;     // rows per split-K chunk of the back-transformation
 
 struct HtdDesc {
   double2* A;       // n x n Hermitian (ld); row k keeps reflector v_k (cols > k)
-  double2* V;       // out: eigenvectors as columns (ld)
-  double* lam;      // out: eigenvalues, ascending (n)
+  double2* V;       // out: eigenvectors as columns (ld), descending eigenvalues
+  double* lam;      // out: eigenvalues, descending (n)
   Dim n;
   int ld;
+  int rcap;         // eigenvectors needed: the first min(n, rcap) columns of V
   const int* skip;  // nonzero: the problem is solved elsewhere (accepted sketch)
   // reduction to tridiagonal form
   double* d;        // diagonal of T (n)
   double* e;        // off-diagonal of T (n - 1)
   double2* tau;     // reflector scalars (n - 1)
-  double2* v;       // current reflector (n)
-  double2* y;       // tau G v of the current step (n)
+  double2* PV;      // panel reflectors V (n x HTD_NB, row-major)
+  double2* PW;      // panel vectors W (n x HTD_NB, row-major)
+  double2* xb;      // the current column brought up to date (n)
+  double2* kpart;   // per trd_col workgroup: HTD_KP partial results
   double2* part;    // per HEMV workgroup: sum of conj(y_i) v_i
   // divide and conquer (node lists are indexed by the node's first row)
-  double* Q[2];     // n x n (ld) block-diagonal eigenvector matrices, by level parity
+  double* Q[2];     // n x n (ld) block-diagonal eigenvector matrices by level
+                    // parity, stored by columns: Q[col * ld + row]
   double* D[2];     // eigenvalues of the nodes, ascending within a node
-  double* DeltaT;   // ld x ld: DeltaT[lo+j][lo+k] = dl_j - lambda_k
-  double* U;        // ld x ld: eigenvectors of the rank-one updated diagonal
+  double* unrm;     // 1 / norm of the rank-one problem's eigenvector of each root
   double* dl;       // non-deflated poles (ascending)
   double* w;        // their z components
   int* ndcol;       // their columns
@@ -141,11 +146,20 @@ __host__ __device__ inline int htd_hemv_blocks(int n, int k) {
   const int m = n - k - 1;
   return m > 0 ? (m + HV_ROWS - 1) / HV_ROWS : 0;
 }
-__host__ __device__ inline int htd_her2_blocks(int n, int k) {
-  const int m = n - k - 1, t = (m + 63) / 64;
-  return m > 0 ? t * t : 0;
+__host__ __device__ inline int htd_col_blocks(int n, int k) {
+  const int m = n - k - 1;
+  return m > 0 ? (m + KC_ROWS - 1) / KC_ROWS : 0;
+}
+// panel starting at column p0: trailing matrix from p0 + min(HTD_NB, n - 1 - p0)
+__host__ __device__ inline int htd_her2k_blocks(int n, int p0) {
+  const int nbp = n - 1 - p0 < HTD_NB ? n - 1 - p0 : HTD_NB;
+  if (nbp <= 0) return 0;
+  const int t = (n - p0 - nbp + 63) / 64;
+  return t * t;
 }
 __host__ __device__ inline int htd_rows(int n) { return (n + 255) / 256; }
+__host__ __device__ inline int htd_waves(int n) { return (n + 3) / 4; }  // one wavefront per index
+__host__ __device__ inline int htd_tiles64(int n) { return ((n + 63) / 64) * ((n + 63) / 64); }
 __host__ __device__ inline int htd_nodes(int n, int L) { return (n + (1 << L) - 1) >> L; }
 __host__ __device__ inline int htd_gemm_tiles(int n, int L) {
   const int t = ((1 << L) + 63) / 64;
@@ -153,30 +167,41 @@ __host__ __device__ inline int htd_gemm_tiles(int n, int L) {
 }
 __host__ __device__ inline int htd_nblk(int n) { return n >= 2 ? (n - 2) / HTD_NB + 1 : 0; }
 __host__ __device__ inline int htd_bt_rows(int n, int b) { return n - HTD_NB * b - 1; }
-__host__ __device__ inline int htd_wpart_blocks(int n, int b) {
-  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((n + 63) / 64) : 0;
+// nc: eigenvector columns back-transformed, min(n, rcap)
+__host__ __device__ inline int htd_wpart_blocks(int n, int nc, int b) {
+  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((nc + 63) / 64) : 0;
 }
-__host__ __device__ inline int htd_wred_blocks(int n, int b) { return b < htd_nblk(n) ? (n + 63) / 64 : 0; }
-__host__ __device__ inline int htd_update_blocks(int n, int b) {
-  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + 63) / 64) * ((n + 63) / 64) : 0;
+__host__ __device__ inline int htd_wred_blocks(int n, int nc, int b) { return b < htd_nblk(n) ? (nc + 63) / 64 : 0; }
+__host__ __device__ inline int htd_update_blocks(int n, int nc, int b) {
+  return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + 63) / 64) * ((nc + 63) / 64) : 0;
 }
 
-// launches over np descriptors in device memory; `blocks` is the sum of the
+// Sizes of the problems of one launch (at most HTD_GROUP), passed by value.
+constexpr int HTD_GROUP = 64;
+struct HtdSizes {
+  int np;
+  int n[HTD_GROUP];   // matrix sizes
+  int nc[HTD_GROUP];  // eigenvector columns back-transformed: min(n, rcap)
+};
+
+// launches over sz.np descriptors in device memory; `blocks` is the sum of the
 // per-problem counts above for the given step / level / block
-hipError_t launch_trd_hemv(const HtdDesc* d, int np, int k, int blocks, hipStream_t s);
-hipError_t launch_trd_her2(const HtdDesc* d, int np, int k, int blocks, hipStream_t s);
-hipError_t launch_trd_finish(const HtdDesc* d, int np, hipStream_t s);
-hipError_t launch_dc_init(const HtdDesc* d, int np, int blocks, hipStream_t s);
-hipError_t launch_dc_prep(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
-// stage 0: deflation rotations, 1: secular roots, 2: Loewner z, 3: eigenvectors
-hipError_t launch_dc_rows(int stage, const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
-hipError_t launch_dc_place(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
-hipError_t launch_dc_gemm(const HtdDesc* d, int np, int L, int blocks, hipStream_t s);
-hipError_t launch_bt_init(const HtdDesc* d, int np, int Lmax, int blocks, hipStream_t s);
-hipError_t launch_bt_larft(const HtdDesc* d, int np, int blocks, hipStream_t s);
-hipError_t launch_bt_wpart(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
-hipError_t launch_bt_wred(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
-hipError_t launch_bt_update(const HtdDesc* d, int np, int b, int blocks, hipStream_t s);
+hipError_t launch_trd_col(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_hemv(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s);
+hipError_t launch_trd_finish(const HtdDesc* d, const HtdSizes& sz, hipStream_t s);
+hipError_t launch_dc_init(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s);
+hipError_t launch_dc_prep(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s);
+hipError_t launch_dc_rot(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s);
+// stage 1: secular roots, 2: Loewner z, 3: eigenvector norms (one wavefront each)
+hipError_t launch_dc_wave(int stage, const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s);
+hipError_t launch_dc_place(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s);
+hipError_t launch_dc_gemm(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s);
+hipError_t launch_bt_init(const HtdDesc* d, const HtdSizes& sz, int Lmax, int blocks, hipStream_t s);
+hipError_t launch_bt_larft(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s);
+hipError_t launch_bt_wpart(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
+hipError_t launch_bt_wred(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
+hipError_t launch_bt_update(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
 
 // ------------------------------------------------------ learned sketch ----
 constexpr int SK_PROBES = 8;

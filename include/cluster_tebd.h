@@ -222,6 +222,26 @@ mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, double*
  * HIP failures; mps_last_error(NULL) then describes the failure. */
 mps_status mps_heev(int n, const double* A, double* w, double* V);
 
+/* Burst timing of one kernel class, for kernels too short for a pair of
+ * events around each launch (on this GPU each event adds the latency of a
+ * marker packet, several microseconds): every stride-th launch of the class
+ * is followed by reps re-launches of the same kernel on the same inputs
+ * (which it does not write, so the outputs are unchanged) and one pair of
+ * events spans all reps + 1 launches; mps_kernel_times then reports for the
+ * class the summed per-launch time of those bursts and their number, and
+ * mps_kernel_bytes the algorithmic bytes of the sampled launches only.  The
+ * other launches of the class run untimed.  Supported classes: "trd_col"
+ * and "trd_hemv" (the column update and the Hermitian matrix-vector product
+ * of the tridiagonal reduction); one call per class; stride >= 1,
+ * 0 <= reps <= 64, else MPS_EINVAL.  kernel_class NULL or "" switches burst
+ * timing off for all classes. */
+mps_status mps_set_burst_timing(mps_handle h, const char* kernel_class, int stride, int reps);
+
+/* Kernel dispatches of each kernel class since timing was switched on, the
+ * re-launches of burst timing included (what a profiler of the same run
+ * counts); classes in the order of mps_kernel_times. */
+mps_status mps_kernel_dispatches(mps_handle h, int64_t* dispatches, int cap, int* count);
+
 /* Algorithmic HBM bytes of each kernel class since timing was switched on,
  * for the classes bound by memory bandwidth (the HEMV and HER2 launches of
  * the tridiagonal reduction: the trailing Gram block read, and read and

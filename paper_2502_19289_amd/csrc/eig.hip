@@ -506,9 +506,9 @@ hipError_t launch_eig_init(bool fp32, const EigDesc* d, int nprob, int ld_max, h
   if (nprob <= 0) return hipSuccess;
   dim3 grid(min(ld_max, 256), nprob);
   if (fp32)
-    eig_init_kernel<float><<<grid, 256, 0, s>>>(d);
+    launch(eig_init_kernel<float>, dim3(grid), dim3(256), 0, s, d);
   else
-    eig_init_kernel<double><<<grid, 256, 0, s>>>(d);
+    launch(eig_init_kernel<double>, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
@@ -516,9 +516,9 @@ hipError_t launch_eig_pairs(bool fp32, const EigDesc* d, const int* d_base, int 
                             hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (fp32)
-    eig_pairs_kernel<float><<<blocks, EP_THREADS, 0, s>>>(d, d_base, nprob, round);
+    launch(eig_pairs_kernel<float>, dim3(blocks), dim3(EP_THREADS), 0, s, d, d_base, nprob, round);
   else
-    eig_pairs_kernel<double><<<blocks, EP_THREADS, 0, s>>>(d, d_base, nprob, round);
+    launch(eig_pairs_kernel<double>, dim3(blocks), dim3(EP_THREADS), 0, s, d, d_base, nprob, round);
   return hipGetLastError();
 }
 
@@ -526,29 +526,29 @@ hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int
                              hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (fp32)
-    eig_update_kernel<float><<<blocks, UP_THREADS, 0, s>>>(d, d_base, nprob, round);
+    launch(eig_update_kernel<float>, dim3(blocks), dim3(UP_THREADS), 0, s, d, d_base, nprob, round);
   else
-    eig_update_kernel<double><<<blocks, UP_THREADS, 0, s>>>(d, d_base, nprob, round);
+    launch(eig_update_kernel<double>, dim3(blocks), dim3(UP_THREADS), 0, s, d, d_base, nprob, round);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  eig_sweep_end_kernel<<<(nprob + 63) / 64, 64, 0, s>>>(d, nprob);
+  launch(eig_sweep_end_kernel, dim3((nprob + 63) / 64), dim3(64), 0, s, d, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   dim3 grid(min(ld_max, 256), nprob);
-  eig_to64_kernel<<<grid, 256, 0, s>>>(d);
+  launch(eig_to64_kernel, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   dim3 grid((n_max + 255) / 256, nprob);
-  eig_rayleigh_kernel<<<grid, 256, 0, s>>>(d);
+  launch(eig_rayleigh_kernel, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

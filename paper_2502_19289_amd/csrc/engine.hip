@@ -98,6 +98,7 @@ int KernelTimer::cls_of(const char* name) {
   launches.push_back(0);
   flop.push_back(0.0);
   bytes.push_back(0.0);
+  dispatches.push_back(0);
   return (int)names.size() - 1;
 }
 
@@ -126,11 +127,15 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 }
 
 // --------------------------------------------------------------- timing --
+// Times the launches of its scope for kernel class `name` with events on the
+// handle's stream; `div` is the number of launches the scope holds when the
+// class time is to be counted per launch (a burst).
 struct Timed {
   mps_ctx* ctx;
   int cls;
+  int div;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(mps_ctx* c, const char* name) : ctx(c), cls(-1) {
+  Timed(mps_ctx* c, const char* name, int launches = 1) : ctx(c), cls(-1), div(launches) {
     if (!ctx->timing) return;
     cls = ctx->timer.cls_of(name);
     auto take = [&]() {
@@ -150,16 +155,50 @@ struct Timed {
   ~Timed() {
     if (cls < 0) return;
     (void)hipEventRecord(b, ctx->stream);
-    ctx->timer.pending.push_back({cls, a, b});
+    ctx->timer.pending.push_back({cls, a, b, div});
   }
 };
+
+// One launch (`go`) of a kernel that is idempotent on its inputs: running it
+// again reads nothing it writes, so a re-launch reproduces the same outputs.
+// Under burst timing of class `name` (stride, reps) every stride-th launch is
+// followed by reps re-launches and one pair of events spans them all
+// (separate events around every launch add the latency of two marker packets
+// to each measurement); the other launches of the class are not timed.
+// Returns whether the launch is counted in the class statistics.
+template <class F>
+bool timed_repeatable(mps_ctx* ctx, const char* name, F go) {
+  if (!ctx->timing) {
+    HIP_OK(go());
+    return false;
+  }
+  KernelTimer& t = ctx->timer;
+  const int cls = t.cls_of(name);
+  const auto it = t.burst.find(cls);
+  if (it == t.burst.end()) {
+    Timed tm(ctx, name);
+    HIP_OK(go());
+    return true;
+  }
+  if (t.burst_seen.size() < t.names.size()) t.burst_seen.resize(t.names.size(), 0);
+  if (t.burst_seen[cls]++ % it->second.first != 0) {
+    HIP_OK(go());
+    t.dispatches[cls] += 1;
+    return false;
+  }
+  const int reps = it->second.second;
+  Timed tm(ctx, name, 1 + reps);
+  for (int r = 0; r <= reps; ++r) HIP_OK(go());
+  return true;
+}
 
 void collect_timing(mps_ctx* ctx) {
   for (auto& p : ctx->timer.pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      ctx->timer.ms[p.cls] += ms;
+      ctx->timer.ms[p.cls] += ms / p.div;
       ctx->timer.launches[p.cls] += 1;
+      ctx->timer.dispatches[p.cls] += p.div;
     }
     ctx->timer.pool.push_back(p.a);
     ctx->timer.pool.push_back(p.b);
@@ -234,6 +273,7 @@ void htd_layout(size_t ld, HtdDesc& h, F take) {
   h.tau = (double2*)take(nc);
   h.PV = (double2*)take(HTD_NB * nc);
   h.PW = (double2*)take(HTD_NB * nc);
+  h.PY = (double2*)take(nc);
   h.xb = (double2*)take(nc);
   h.kpart = (double2*)take((ld / KC_ROWS + 1) * HTD_KP * sizeof(double2));
   h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
@@ -585,19 +625,26 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
   const int c_hemv = timing ? ctx->timer.cls_of("trd_hemv") : -1;
   const int c_her2k = timing ? ctx->timer.cls_of("trd_her2k") : -1;
   const int c_bt = timing ? ctx->timer.cls_of("bt") : -1;
+  const bool trace = std::getenv("CTEBD_HTD_TRACE") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!trace) return;
+    const double host = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    HIP_OK(hipStreamSynchronize(s));
+    const double all = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::fprintf(stderr, "htd np=%d nmax=%d %s: host enqueue %.2f ms, done %.2f ms\n", np, nmax, what, host, all);
+    t0 = std::chrono::steady_clock::now();
+  };
+  lap("start");
   for (int p0 = 0; p0 + 1 < nmax; p0 += HTD_NB) {
     for (int j = 0; j < HTD_NB; ++j) {
       const int k = p0 + j;
       if (k + 1 >= nmax) break;
-      {
-        Timed tm(ctx, "trd_col");
-        HIP_OK(launch_trd_col(dd, sz, k, total([k](int n) { return htd_col_blocks(n, k); }), s));
-      }
-      {
-        Timed tm(ctx, "trd_hemv");
-        HIP_OK(launch_trd_hemv(dd, sz, k, total([k](int n) { return htd_hemv_blocks(n, k); }), s));
-      }
-      if (timing)  // algorithmic traffic of the HEMV: the trailing block read once
+      const int nb_col = total([k](int n) { return htd_col_blocks(n, k); });
+      timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(dd, sz, k, nb_col, s); });
+      const int nb_hemv = total([k](int n) { return htd_hemv_blocks(n, k); });
+      const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(dd, sz, k, nb_hemv, s); });
+      if (counted)  // algorithmic traffic of the HEMV: the trailing block read once
         for (int p = 0; p < np; ++p) {
           const double m = sz.n[p] - k - 1;
           if (m <= 0) continue;
@@ -617,6 +664,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
         ctx->timer.flop[c_her2k] += 8.0 * 2.0 * nbp * mt * (mt + 1) / 2;
       }
   }
+  lap("reduction");
   {
     Timed tm(ctx, "dc");
     HIP_OK(launch_trd_finish(dd, sz, s));
@@ -635,6 +683,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
     HIP_OK(launch_dc_place(dd, sz, L, nodes, s));
     HIP_OK(launch_dc_gemm(dd, sz, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
   }
+  lap("divide and conquer");
   {
     Timed tm(ctx, "bt");
     HIP_OK(launch_bt_init(dd, sz, Lmax, total([](int n) { return htd_tiles64(n); }), s));
@@ -654,6 +703,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
           ctx->timer.flop[c_bt] += 2.0 * 8.0 * rows * nb * sz.nc[p];
         }
   }
+  lap("back-transformation");
 }
 
 void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host) {
@@ -2056,6 +2106,34 @@ mps_status mps_get_stats(mps_handle ctx, mps_stats* st) {
 mps_status mps_set_timing(mps_handle ctx, int on) {
   if (!ctx) return MPS_EINVAL;
   ctx->timing = on != 0;
+  return MPS_OK;
+}
+
+mps_status mps_set_burst_timing(mps_handle ctx, const char* kernel_class, int stride, int reps) {
+  if (!ctx) return MPS_EINVAL;
+  if (!kernel_class || !*kernel_class) {
+    ctx->timer.burst.clear();
+    return MPS_OK;
+  }
+  const bool known = std::strcmp(kernel_class, "trd_hemv") == 0 || std::strcmp(kernel_class, "trd_col") == 0;
+  if (!known || stride < 1 || reps < 0 || reps > 64) {
+    ctx->err = "mps_set_burst_timing: only trd_col and trd_hemv, with stride >= 1 and 0 <= reps <= 64";
+    return MPS_EINVAL;
+  }
+  auto& t = ctx->timer;
+  const int c = t.cls_of(kernel_class);
+  if (t.burst_seen.size() < t.names.size()) t.burst_seen.resize(t.names.size(), 0);
+  t.burst[c] = {stride, reps};
+  t.burst_seen[c] = 0;
+  return MPS_OK;
+}
+
+mps_status mps_kernel_dispatches(mps_handle ctx, int64_t* dispatches, int cap, int* count) {
+  if (!ctx || !count) return MPS_EINVAL;
+  const int c = (int)ctx->timer.names.size();
+  *count = c;
+  for (int i = 0; i < c && i < cap; ++i)
+    if (dispatches) dispatches[i] = ctx->timer.dispatches[i];
   return MPS_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/cluster_tebd.h"
@@ -74,9 +75,16 @@ struct KernelTimer {
   std::vector<int64_t> launches;
   std::vector<double> flop;  // algorithmic real flops per class (8 per complex MAC)
   std::vector<double> bytes; // algorithmic HBM bytes per class (bandwidth-bound classes)
+  std::vector<int64_t> dispatches;  // kernel dispatches per class, repeats of a burst included
+  // Burst-timed classes (see mps_set_burst_timing): class -> (stride, reps);
+  // every stride-th launch is followed by reps re-launches inside one pair of
+  // events.  burst_seen counts the launches of each class.
+  std::map<int, std::pair<int, int>> burst;
+  std::vector<int64_t> burst_seen;
   struct Pending {
     int cls;
     hipEvent_t a, b;
+    int div;  // launches between the events
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;

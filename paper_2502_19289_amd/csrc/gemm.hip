@@ -335,7 +335,7 @@ int gemm_tiles(const GemmDesc& d) { return d.tm * d.tn * d.ksplit * d.batch; }
 
 hipError_t launch_gemm_bf16x6(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  cgemm_bf16x6_kernel<<<blocks, 256, 0, s>>>(d_desc, d_base, nprob);
+  launch(cgemm_bf16x6_kernel, dim3(blocks), dim3(256), 0, s, d_desc, d_base, nprob);
   return hipGetLastError();
 }
 
@@ -343,11 +343,11 @@ hipError_t launch_gemm_nn(Prec p, const GemmDesc* d_desc, const int* d_base, int
                           hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (p == Prec::FP64)
-    cgemm_kernel<double2, double2, double, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+    launch(cgemm_kernel<double2, double2, double, MODE_NN>, dim3(blocks), dim3(NT), 0, s, d_desc, d_base, nprob);
   else if (p == Prec::BF16X6)
     return launch_gemm_bf16x6(d_desc, d_base, nprob, blocks, s);
   else
-    cgemm_kernel<float2, float2, float, MODE_NN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+    launch(cgemm_kernel<float2, float2, float, MODE_NN>, dim3(blocks), dim3(NT), 0, s, d_desc, d_base, nprob);
   return hipGetLastError();
 }
 
@@ -355,22 +355,22 @@ hipError_t launch_gram(Prec in_prec, const GemmDesc* d_desc, const int* d_base, 
                        hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (in_prec == Prec::FP64)
-    cgemm_kernel<double2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+    launch(cgemm_kernel<double2, double2, double, MODE_GRAM>, dim3(blocks), dim3(NT), 0, s, d_desc, d_base, nprob);
   else
-    cgemm_kernel<float2, double2, double, MODE_GRAM><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+    launch(cgemm_kernel<float2, double2, double, MODE_GRAM>, dim3(blocks), dim3(NT), 0, s, d_desc, d_base, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_cn(const GemmDesc* d_desc, const int* d_base, int nprob, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  cgemm_kernel<double2, double2, double, MODE_CN><<<blocks, NT, 0, s>>>(d_desc, d_base, nprob);
+  launch(cgemm_kernel<double2, double2, double, MODE_CN>, dim3(blocks), dim3(NT), 0, s, d_desc, d_base, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_reduce(const GramReduceDesc* d_desc, const int* d_base, int nprob, int blocks,
                               hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  gram_reduce_kernel<<<blocks, 256, 0, s>>>(d_desc, d_base, nprob);
+  launch(gram_reduce_kernel, dim3(blocks), dim3(256), 0, s, d_desc, d_base, nprob);
   return hipGetLastError();
 }
 

@@ -89,6 +89,19 @@ __device__ __forceinline__ double wave_sum(double v) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// Wavefront maximum on the same DPP paths as wave_sum.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_take<0xb1, 0xf>(v));
+  v = fmax(v, dpp_take<0x4e, 0xf>(v));
+  v = fmax(v, dpp_take<0x141, 0xf>(v));
+  v = fmax(v, dpp_take<0x140, 0xf>(v));
+  v = fmax(v, dpp_take<0x142, 0xa>(v));
+  v = fmax(v, dpp_take<0x143, 0xc>(v));
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double block4_max(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   __syncthreads();
@@ -111,6 +124,8 @@ __device__ __forceinline__ double block4_sum(double v, double* sh) {
 //   trd_col:   x = G[k+1:, k] - V W[k, :]^H - W V[k, :]^H (the up-to-date
 //              column), its scaled norm and the dots V^H x, W^H x; it also
 //              finalises w_{j-1} = y_{j-1} - (tau/2)(y_{j-1}^H v_{j-1}) v_{j-1}
+//              from y_{j-1} (kept apart in PY, so that neither kernel writes
+//              what it reads: each can be launched again on the same inputs)
 //   trd_hemv:  the reflector H^H (alpha, x1)^T = (beta, 0)^T (beta real) and
 //              y = tau (G v - V (W^H v) - W (V^H v)) over the rows, 2 per
 //              wavefront with 4 columns per lane in flight
@@ -147,37 +162,42 @@ __global__ __launch_bounds__(64) void trd_col_kernel(const HtdDesc* __restrict__
   const int i = lc.b * KC_ROWS + lane;
   const bool own = lane < KC_ROWS && i < m;
   const int64_t r = k + 1 + i;
-  // independent loads: the row entry, the row of V and W, partials of alpha
+  // independent loads, the small ones first (memory operations complete in
+  // issue order): partials of alpha, row k of V and W, then this lane's row
+  const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
+  constexpr int PQ = HTD_MAX / HV_ROWS / 64;
+  double2 pq[PQ];
+#pragma unroll
+  for (int u = 0; u < PQ; ++u) {
+    const int q = lane + 64 * u;
+    pq[u] = q < nbp ? d.part[q] : make_double2(0.0, 0.0);
+  }
+  const double2 tp = j > 0 ? d.tau[k - 1] : make_double2(0.0, 0.0);
+  double2 vkl = make_double2(0.0, 0.0), wkl = make_double2(0.0, 0.0);  // row k of V and W
+  if (lane < j) {
+    vkl = d.PV[(int64_t)k * HTD_NB + lane];
+    wkl = lane == j - 1 ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + lane];
+  }
   double2 a = make_double2(0.0, 0.0);
   if (own) a = d.A[(int64_t)k * ld + r];
   double2 vv[HTD_NB], ww[HTD_NB];
 #pragma unroll
   for (int u = 0; u < HTD_NB; ++u) {
     vv[u] = own && u < j ? d.PV[r * HTD_NB + u] : make_double2(0.0, 0.0);
-    ww[u] = own && u < j ? d.PW[r * HTD_NB + u] : make_double2(0.0, 0.0);
+    ww[u] = own && u < j ? (u == j - 1 ? d.PY[r] : d.PW[r * HTD_NB + u]) : make_double2(0.0, 0.0);
   }
-  const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
   double sx = 0.0, sy = 0.0;
 #pragma unroll
-  for (int u = 0; u < HTD_MAX / HV_ROWS / 64; ++u) {
-    const int q = lane + 64 * u;
-    if (q < nbp) {
-      const double2 t = d.part[q];
-      sx += t.x;
-      sy += t.y;
-    }
+  for (int u = 0; u < PQ; ++u) {
+    sx += pq[u].x;
+    sy += pq[u].y;
   }
   double2 al = make_double2(0.0, 0.0);  // -(tau/2) y^H v of panel column j-1
-  if (j > 0) {
-    const double2 tp = d.tau[k - 1];
-    al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), make_double2(wave_sum(sx), wave_sum(sy)));
-  }
+  if (j > 0) al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), make_double2(wave_sum(sx), wave_sum(sy)));
   if (lane < j) {
-    const double2 v = d.PV[(int64_t)k * HTD_NB + lane];
-    double2 w = d.PW[(int64_t)k * HTD_NB + lane];
-    if (lane == j - 1) w = cadd(w, cmul(al, v));
-    vk[lane] = v;
-    wk[lane] = w;
+    if (lane == j - 1) wkl = cadd(wkl, cmul(al, vkl));
+    vk[lane] = vkl;
+    wk[lane] = wkl;
   }
   __syncthreads();
   // x_r = conj(G[k][r]) - sum_l V[r][l] conj(w_k[l]) + W[r][l] conj(v_k[l])
@@ -204,8 +224,7 @@ __global__ __launch_bounds__(64) void trd_col_kernel(const HtdDesc* __restrict__
     }
   }
   // scaled norm of x_1 ... over this workgroup's rows
-  double amax = tail ? fmax(fabs(x.x), fabs(x.y)) : 0.0;
-  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  const double amax = wave_max(tail ? fmax(fabs(x.x), fabs(x.y)) : 0.0);
   double ss = 0.0;
   if (tail && amax > 0.0) ss = (x.x / amax) * (x.x / amax) + (x.y / amax) * (x.y / amax);
   ss = wave_sum(ss);
@@ -248,45 +267,58 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict
   const bool row = i0 < m;
   const double2* a0 = d.A + (int64_t)(k + 1 + (row ? i0 : 0)) * ld + (k + 1);
   constexpr int PL = HTD_MAX / 64;  // row entries per lane
+  // small loads first (memory operations complete in issue order, so the
+  // reductions on them must not wait behind the row): the staged column,
+  // the trd_col records, this row's panel term
+  constexpr int XL = HTD_MAX / 256;
+  double2 xv[XL];
+#pragma unroll
+  for (int u = 0; u < XL; ++u) {
+    const int jj = tid + 256 * u;
+    xv[u] = jj < m ? d.xb[jj] : make_double2(0.0, 0.0);
+  }
+  const int nka = htd_col_blocks(n, k);
+  const double2* recs = d.kpart;
+  constexpr int RQ = HTD_MAX / KC_ROWS / 4;  // records per group
+  const int e = tid & 63, g = tid >> 6;
+  double2 rv[RQ];
+#pragma unroll
+  for (int u = 0; u < RQ; ++u) {
+    const int q = g + 4 * u;
+    rv[u] = (e & (HTD_NB - 1)) < j && q < nka ? recs[(int64_t)q * HTD_KP + 2 + e] : make_double2(0.0, 0.0);
+  }
+  double2 rq = make_double2(0.0, 0.0);  // wavefront 0, lane q < nka: record q's (scale, ssq)
+  if (tid < nka) rq = recs[(int64_t)tid * HTD_KP];
+  const int l = lane & (HTD_NB - 1);
+  const bool isv = lane < HTD_NB;
+  double2 pe = make_double2(0.0, 0.0);
+  if (row && l < j) pe = isv ? d.PV[(int64_t)(k + 1 + i0) * HTD_NB + l] : d.PW[(int64_t)(k + 1 + i0) * HTD_NB + l];
+  double2 v1 = make_double2(0.0, 0.0), w1 = make_double2(0.0, 0.0);
+  if (tid < j) {
+    v1 = d.PV[(int64_t)(k + 1) * HTD_NB + tid];
+    w1 = d.PW[(int64_t)(k + 1) * HTD_NB + tid];
+  }
+  // then the row
   double2 p[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int c = lane + 64 * u;
     p[u] = row && c < m ? a0[c] : make_double2(0.0, 0.0);
   }
-  const int l = lane & (HTD_NB - 1);
-  const bool isv = lane < HTD_NB;
-  double2 pe = make_double2(0.0, 0.0);
-  if (row && l < j) pe = isv ? d.PV[(int64_t)(k + 1 + i0) * HTD_NB + l] : d.PW[(int64_t)(k + 1 + i0) * HTD_NB + l];
-  for (int jj = tid; jj < m; jj += 256) xs[jj] = d.xb[jj];
-  // trd_col records: thread (g, e) sums entry e over the records q = g mod 4
-  // (their loads issued together); (scale, ssq) by the first wavefront
-  const int nka = htd_col_blocks(n, k);
-  const double2* recs = d.kpart;
-  constexpr int RQ = HTD_MAX / KC_ROWS / 4;  // records per group
+#pragma unroll
+  for (int u = 0; u < XL; ++u) {
+    const int jj = tid + 256 * u;
+    if (jj < m) xs[jj] = xv[u];
+  }
   {
-    const int e = tid & 63, g = tid >> 6;
     double2 t = make_double2(0.0, 0.0);
-    if ((e & (HTD_NB - 1)) < j) {
-      double2 rv[RQ];
 #pragma unroll
-      for (int u = 0; u < RQ; ++u) {
-        const int q = g + 4 * u;
-        rv[u] = q < nka ? recs[(int64_t)q * HTD_KP + 2 + e] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < RQ; ++u) t = cadd(t, rv[u]);
-    }
+    for (int u = 0; u < RQ; ++u) t = cadd(t, rv[u]);
     hsum[g][e] = t;
   }
-  double rs = 0.0, rm = 0.0;  // this lane's record (wavefront 0: lane q < nka)
   if (tid < 64) {
-    double2 rq = make_double2(0.0, 0.0);
-    if (tid < nka) rq = recs[(int64_t)tid * HTD_KP];
-    rm = rq.x;
-    rs = rq.y;
-    double smax = rm;
-    for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off));
+    const double rm = rq.x, rs = rq.y;
+    const double smax = wave_max(rm);
     const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
     const double ssq_w = wave_sum(c);
     if (tid == 0) {
@@ -301,7 +333,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict
     sv = cadd(cadd(hsum[0][tid], hsum[1][tid]), cadd(hsum[2][tid], hsum[3][tid]));
     sw = cadd(cadd(hsum[0][HTD_NB + tid], hsum[1][HTD_NB + tid]), cadd(hsum[2][HTD_NB + tid], hsum[3][HTD_NB + tid]));
   }
-  const double2 alpha = d.xb[0];
+  const double2 alpha = xs[0];
   const double amax = fmax(smax, fmax(fabs(alpha.x), fabs(alpha.y)));
   double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
   double beta = alpha.x;
@@ -325,7 +357,6 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict
   const bool ident = tau.x == 0.0 && tau.y == 0.0;
   if (tid < j) {
     // V^H v = conj(V[k+1, l]) + scale sum_{i >= 1} conj(V[k+1+i, l]) x_i, likewise W
-    const double2 v1 = d.PV[(int64_t)(k + 1) * HTD_NB + tid], w1 = d.PW[(int64_t)(k + 1) * HTD_NB + tid];
     vhv[tid] = cadd(make_double2(v1.x, -v1.y), cmul(scale, sv));
     whv[tid] = cadd(make_double2(w1.x, -w1.y), cmul(scale, sw));
   }
@@ -352,7 +383,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict
   }
   double2 part = make_double2(0.0, 0.0);
   if (row) {
-    if (lane == 0) d.PW[(int64_t)(k + 1 + i0) * HTD_NB + j] = y0;
+    if (lane == 0) d.PY[k + 1 + i0] = y0;
     const double2 vi = i0 == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[i0], scale));
     part = cmulc(y0, vi);
   }
@@ -406,9 +437,8 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
     if (q >= nbp || r >= n) return make_double2(0.0, 0.0);
     const double2 v = d.PV[(int64_t)r * HTD_NB + q];
     if (isv) return v;
-    double2 w = d.PW[(int64_t)r * HTD_NB + q];
-    if (q == nbp - 1) w = cadd(w, cmul(al, v));
-    return w;
+    if (q == nbp - 1) return cadd(d.PY[r], cmul(al, v));
+    return d.PW[(int64_t)r * HTD_NB + q];
   };
   CAcc<double> acc[2][2];
 #pragma unroll
@@ -1213,77 +1243,77 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
 
 hipError_t launch_trd_hemv(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  trd_hemv_kernel<<<blocks, 256, 0, s>>>(d, sz, k);
+  launch(trd_hemv_kernel, dim3(blocks), dim3(256), 0, s, d, sz, k);
   return hipGetLastError();
 }
 hipError_t launch_trd_col(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  trd_col_kernel<<<blocks, 64, 0, s>>>(d, sz, k);
+  launch(trd_col_kernel, dim3(blocks), dim3(64), 0, s, d, sz, k);
   return hipGetLastError();
 }
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  trd_her2k_kernel<<<blocks, 256, 0, s>>>(d, sz, p0);
+  launch(trd_her2k_kernel, dim3(blocks), dim3(256), 0, s, d, sz, p0);
   return hipGetLastError();
 }
 hipError_t launch_trd_finish(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) {
   if (sz.np <= 0) return hipSuccess;
-  trd_finish_kernel<<<(sz.np + 63) / 64, 64, 0, s>>>(d, sz);
+  launch(trd_finish_kernel, dim3((sz.np + 63) / 64), dim3(64), 0, s, d, sz);
   return hipGetLastError();
 }
 hipError_t launch_dc_init(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_init_kernel<<<blocks, 256, 0, s>>>(d, sz);
+  launch(dc_init_kernel, dim3(blocks), dim3(256), 0, s, d, sz);
   return hipGetLastError();
 }
 hipError_t launch_dc_prep(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_prep_kernel<<<blocks, 1024, 0, s>>>(d, sz, L);
+  launch(dc_prep_kernel, dim3(blocks), dim3(1024), 0, s, d, sz, L);
   return hipGetLastError();
 }
 hipError_t launch_dc_rot(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_rot_kernel<<<blocks, 256, 0, s>>>(d, sz, L);
+  launch(dc_rot_kernel, dim3(blocks), dim3(256), 0, s, d, sz, L);
   return hipGetLastError();
 }
 hipError_t launch_dc_wave(int stage, const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_wave_kernel<<<blocks, 256, 0, s>>>(d, sz, L, stage);
+  launch(dc_wave_kernel, dim3(blocks), dim3(256), 0, s, d, sz, L, stage);
   return hipGetLastError();
 }
 hipError_t launch_dc_place(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_place_kernel<<<blocks, 1024, 0, s>>>(d, sz, L);
+  launch(dc_place_kernel, dim3(blocks), dim3(1024), 0, s, d, sz, L);
   return hipGetLastError();
 }
 hipError_t launch_dc_gemm(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  dc_gemm_kernel<<<blocks, 256, 0, s>>>(d, sz, L);
+  launch(dc_gemm_kernel, dim3(blocks), dim3(256), 0, s, d, sz, L);
   return hipGetLastError();
 }
 hipError_t launch_bt_init(const HtdDesc* d, const HtdSizes& sz, int Lmax, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_init_kernel<<<blocks, 256, 0, s>>>(d, sz, Lmax);
+  launch(bt_init_kernel, dim3(blocks), dim3(256), 0, s, d, sz, Lmax);
   return hipGetLastError();
 }
 hipError_t launch_bt_larft(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_larft_kernel<<<blocks, 256, 0, s>>>(d, sz);
+  launch(bt_larft_kernel, dim3(blocks), dim3(256), 0, s, d, sz);
   return hipGetLastError();
 }
 hipError_t launch_bt_wpart(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_wpart_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
+  launch(bt_wpart_kernel, dim3(blocks), dim3(256), 0, s, d, sz, b);
   return hipGetLastError();
 }
 hipError_t launch_bt_wred(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_wred_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
+  launch(bt_wred_kernel, dim3(blocks), dim3(256), 0, s, d, sz, b);
   return hipGetLastError();
 }
 hipError_t launch_bt_update(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  bt_update_kernel<<<blocks, 256, 0, s>>>(d, sz, b);
+  launch(bt_update_kernel, dim3(blocks), dim3(256), 0, s, d, sz, b);
   return hipGetLastError();
 }
 

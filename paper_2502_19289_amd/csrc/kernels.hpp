@@ -9,6 +9,12 @@
 
 namespace ctebd {
 
+// Every kernel of the library is launched through here.
+template <typename... KArgs, typename... P>
+inline void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, P... args) {
+  hipLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, s, args...);
+}
+
 // ---------------------------------------------------------------- GEMM ----
 // C = alpha * A * B                         (mode NN)
 // C = (W X)^H (W X), W = diag(w[row>>wshift])  (mode GRAM: A = B = X, FP64 out,
@@ -111,7 +117,8 @@ struct HtdDesc {
   double* e;        // off-diagonal of T (n - 1)
   double2* tau;     // reflector scalars (n - 1)
   double2* PV;      // panel reflectors V (n x HTD_NB, row-major)
-  double2* PW;      // panel vectors W (n x HTD_NB, row-major)
+  double2* PW;      // panel vectors W (n x HTD_NB, row-major), finalised
+  double2* PY;      // y of the latest panel column before its finalisation (n)
   double2* xb;      // the current column brought up to date (n)
   double2* kpart;   // per trd_col workgroup: HTD_KP partial results
   double2* part;    // per HEMV workgroup: sum of conj(y_i) v_i

@@ -293,7 +293,7 @@ hipError_t launch_build_unitary(const UnitaryDesc* d, const int* d_base, int npr
                                 size_t lds_bytes, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   const size_t lds = lds_bytes;
-  build_unitary_kernel<<<blocks, 256, lds, s>>>(d, d_base, nprob);
+  launch(build_unitary_kernel, dim3(blocks), dim3(256), lds, s, d, d_base, nprob);
   return hipGetLastError();
 }
 
@@ -301,15 +301,15 @@ hipError_t launch_apply_1q(Prec p, const Site1QDesc* d, const int* d_base, int n
                            hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (p == Prec::FP64)
-    apply_1q_kernel<double2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(apply_1q_kernel<double2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   else
-    apply_1q_kernel<float2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(apply_1q_kernel<float2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_select(const SelectDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  select_kernel<<<nprob, 1024, 0, s>>>(d);
+  launch(select_kernel, dim3(nprob), dim3(1024), 0, s, d);
   return hipGetLastError();
 }
 
@@ -317,9 +317,9 @@ hipError_t launch_gather(Prec p, const GatherDesc* d, const int* d_base, int npr
                          hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (p == Prec::FP64)
-    gather_kernel<double2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(gather_kernel<double2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   else
-    gather_kernel<float2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(gather_kernel<float2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   return hipGetLastError();
 }
 
@@ -327,29 +327,29 @@ hipError_t launch_finalize(Prec p, const ScaleDesc* d, const int* d_base, int np
                            hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (p == Prec::FP64)
-    finalize_kernel<double2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(finalize_kernel<double2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   else
-    finalize_kernel<float2><<<blocks, 256, 0, s>>>(d, d_base, nprob);
+    launch(finalize_kernel<float2>, dim3(blocks), dim3(256), 0, s, d, d_base, nprob);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_d2f(const double2* src, float2* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
-  convert_kernel<<<blocks, 256, 0, s>>>(src, dst, n);
+  launch(convert_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_f2d(const float2* src, double2* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
-  convert_f2d_kernel<<<blocks, 256, 0, s>>>(src, dst, n);
+  launch(convert_f2d_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
 hipError_t launch_accumulate(const double* v, int n, double* total, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  accumulate_kernel<<<1, 64, 0, s>>>(v, n, total);
+  launch(accumulate_kernel, dim3(1), dim3(64), 0, s, v, n, total);
   return hipGetLastError();
 }
 

@@ -265,31 +265,31 @@ int mlp_chunk() { return MLP_CHUNK; }
 
 hipError_t launch_gauss_fill(const SketchDesc* d, int nprob, int which, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  gauss_fill_kernel<<<dim3(64, nprob), 256, 0, s>>>(d, which);
+  launch(gauss_fill_kernel, dim3(64, nprob), dim3(256), 0, s, d, which);
   return hipGetLastError();
 }
 
 hipError_t launch_orth_scale(const SketchDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  orth_scale_kernel<<<nprob, 256, 0, s>>>(d);
+  launch(orth_scale_kernel, dim3(nprob), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_newton_schulz(const SketchDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  newton_schulz_kernel<<<nprob, 256, 0, s>>>(d);
+  launch(newton_schulz_kernel, dim3(nprob), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_sketch_accept(const SketchDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  accept_kernel<<<nprob, 256, 0, s>>>(d);
+  launch(accept_kernel, dim3(nprob), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const float* P, const float* X, float* y, int B, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  mlp_forward_kernel<<<B, 64, 0, s>>>(P, X, y, B);
+  launch(mlp_forward_kernel, dim3(B), dim3(64), 0, s, P, X, y, B);
   return hipGetLastError();
 }
 
@@ -297,14 +297,14 @@ hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, const
                            float* part, float* loss_part, float* grad, float* loss, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   const int nparts = (B + MLP_CHUNK - 1) / MLP_CHUNK;
-  mlp_backward_kernel<<<nparts, 64, 0, s>>>(P, X, T, idx, B, tau, part, loss_part);
-  mlp_reduce_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(part, nparts, grad, loss_part, loss);
+  launch(mlp_backward_kernel, dim3(nparts), dim3(64), 0, s, P, X, T, idx, B, tau, part, loss_part);
+  launch(mlp_reduce_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, part, nparts, grad, loss_part, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_adam(float* P, const float* g, float* m, float* v, float lr, int t, hipStream_t s) {
   const float c1 = 1.f - powf(0.9f, (float)t), c2 = 1.f - powf(0.999f, (float)t);
-  adam_kernel<<<(NPARAM + 255) / 256, 256, 0, s>>>(P, g, m, v, lr, c1, c2);
+  launch(adam_kernel, dim3((NPARAM + 255) / 256), dim3(256), 0, s, P, g, m, v, lr, c1, c2);
   return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluste
            "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
-           "mps_set_timing", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_last_error", "mps_plan",
+           "mps_set_timing", "mps_set_burst_timing", "mps_kernel_dispatches", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_last_error", "mps_plan",
            "mlp_num_params", "mlp_create", "mlp_destroy", "mlp_get_params", "mlp_set_params",
            "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log"]
 N_FEAT = 12
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_kernel_times.argtypes = [P, C.POINTER(D), C.POINTER(C.c_int64), C.POINTER(D), I, C.c_char_p, I,
                                      C.POINTER(I)]
     lib.mps_kernel_bytes.argtypes = [P, C.POINTER(D), I, C.POINTER(I)]
+    lib.mps_set_burst_timing.argtypes = [P, C.c_char_p, I, I]
+    lib.mps_kernel_dispatches.argtypes = [P, C.POINTER(C.c_int64), I, C.POINTER(I)]
     lib.mps_heev.argtypes = [I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
     lib.mps_last_error.argtypes = [P]
     lib.mps_last_error.restype = C.c_char_p
@@ -272,6 +274,23 @@ class MPS:
 
     def set_timing(self, on: bool = True):
         self._check(self.lib.mps_set_timing(self.h, int(on)))
+
+    def set_burst_timing(self, kernel_class: Optional[str], stride: int = 1, reps: int = 0):
+        """Time `kernel_class` by bursts of reps + 1 launches on every stride-th
+        launch (None: off); see mps_set_burst_timing."""
+        name = kernel_class.encode() if kernel_class else None
+        self._check(self.lib.mps_set_burst_timing(self.h, name, int(stride), int(reps)))
+
+    def kernel_dispatches(self) -> dict:
+        """{class: kernel dispatches since timing was switched on, burst re-launches included}."""
+        cnt = C.c_int()
+        d = np.zeros(64, dtype=np.int64)
+        self._check(self.lib.mps_kernel_dispatches(self.h, d.ctypes.data_as(C.POINTER(C.c_int64)), 64,
+                                                   C.byref(cnt)))
+        names = C.create_string_buffer(4096)
+        self._check(self.lib.mps_kernel_times(self.h, None, None, None, 0, names, 4096, C.byref(cnt)))
+        nm = names.value.decode().split(",") if cnt.value else []
+        return {n: int(d[i]) for i, n in enumerate(nm)}
 
     def kernel_times(self) -> dict:
         """{class: (ms, launches, algorithmic flops, algorithmic HBM bytes)} since

@@ -262,45 +262,6 @@ bool job_htd(const mps_ctx* ctx, const JobRun& j) {
   return false;
 }
 
-// Buffers of the tridiagonal solver for Gram matrices of leading dim ld;
-// take(bytes) returns device memory (or only counts it).
-template <typename F>
-void htd_layout(size_t ld, HtdDesc& h, F take) {
-  const size_t nd = ld * sizeof(double), ni = ld * sizeof(int), nc = ld * sizeof(double2);
-  h.d = (double*)take(nd);
-  h.e = (double*)take(nd);
-  h.lam = (double*)take(nd);
-  h.tau = (double2*)take(nc);
-  h.PV = (double2*)take(HTD_NB * nc);
-  h.PW = (double2*)take(HTD_NB * nc);
-  h.PY = (double2*)take(nc);
-  h.xb = (double2*)take(nc);
-  h.kpart = (double2*)take((ld / KC_ROWS + 1) * HTD_KP * sizeof(double2));
-  h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
-  for (int q = 0; q < 2; ++q) {
-    h.Q[q] = (double*)take(ld * nd);
-    h.D[q] = (double*)take(nd);
-  }
-  h.unrm = (double*)take(nd);
-  h.dl = (double*)take(nd);
-  h.w = (double*)take(nd);
-  h.ndcol = (int*)take(ni);
-  h.dval = (double*)take(nd);
-  h.dcol = (int*)take(ni);
-  h.rot_a = (int*)take(ni);
-  h.rot_b = (int*)take(ni);
-  h.rot_c = (double*)take(nd);
-  h.rot_s = (double*)take(nd);
-  h.origin = (int*)take(ni);
-  h.stau = (double*)take(nd);
-  h.zhat = (double*)take(nd);
-  h.pos_nd = (int*)take(ni);
-  h.cnt = (int*)take(4 * ni);
-  h.rho = (double*)take(nd);
-  h.T = (double2*)take((ld / HTD_NB + 1) * HTD_NB * HTD_NB * sizeof(double2));
-  h.Wp = (double2*)take(((ld + BT_CH - 1) / BT_CH) * HTD_NB * nc);
-  h.W = (double2*)take(HTD_NB * nc);
-}
 
 void plan_job(mps_ctx* ctx, const Job& job, JobRun& j) {
   j.job = &job;
@@ -606,7 +567,7 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
 // the launch grids and passes them to every kernel by value (2 launches per
 // column and 1 per panel of the reduction, 7 per merge level, 3 per block of
 // reflectors).  Groups of more than HTD_GROUP problems run in chunks.
-void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
+void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const HtdArgs& ha) {
   hipStream_t s = ctx->stream;
   const int np = sz.np;
   int nmax = 0;
@@ -641,9 +602,9 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
       const int k = p0 + j;
       if (k + 1 >= nmax) break;
       const int nb_col = total([k](int n) { return htd_col_blocks(n, k); });
-      timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(dd, sz, k, nb_col, s); });
+      timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
       const int nb_hemv = total([k](int n) { return htd_hemv_blocks(n, k); });
-      const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(dd, sz, k, nb_hemv, s); });
+      const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(ha, k, nb_hemv, s); });
       if (counted)  // algorithmic traffic of the HEMV: the trailing block read once
         for (int p = 0; p < np; ++p) {
           const double m = sz.n[p] - k - 1;
@@ -706,6 +667,14 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz) {
   lap("back-transformation");
 }
 
+// The buffers a kernel derives with htd_view are the ones the host laid out.
+bool htd_view_matches(const HtdArgs& a, int q, const HtdDesc& h) {
+  const HtdDesc g = htd_view(a, q);
+  return g.d == h.d && g.e == h.e && g.tau == h.tau && g.PV == h.PV && g.PW == h.PW && g.PY == h.PY &&
+         g.xb == h.xb && g.kpart == h.kpart && g.part == h.part && g.A == h.A && g.ld == h.ld &&
+         g.skip == h.skip;
+}
+
 void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host) {
   hipStream_t s = ctx->stream;
   const int np = (int)host.size();
@@ -717,6 +686,7 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
   }
   for (int c0 = 0; c0 < np; c0 += HTD_GROUP) {
     HtdSizes sz{};
+    HtdArgs ha{};
     sz.np = std::min(HTD_GROUP, np - c0);
     for (int q = 0; q < sz.np; ++q) {
       const Dim& dm = host[c0 + q].n;
@@ -726,8 +696,16 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
       if (n < 1 || n > HTD_MAX) fail(ctx, MPS_EINVAL, "tridiagonal solve: size out of range");
       sz.n[q] = n;
       sz.nc[q] = std::min(n, host[c0 + q].rcap);
+      const HtdDesc& h = host[c0 + q];
+      ha.n[q] = n;
+      ha.ld[q] = h.ld;
+      ha.A[q] = h.A;
+      ha.ws[q] = (char*)h.d;
+      ha.skip[q] = h.skip;
+      if (!htd_view_matches(ha, q, h)) fail(ctx, MPS_EINVAL, "tridiagonal solve: workspace layout");
     }
-    solve_htd_chunk(ctx, dd + c0, sz);
+    ha.np = sz.np;
+    solve_htd_chunk(ctx, dd + c0, sz, ha);
   }
 }
 

@@ -39,8 +39,8 @@ struct Loc {
 
 // problem and problem-local block of flat block `bid`; the sizes come with
 // the launch (kernel arguments), so finding the problem costs no memory access
-template <typename F>
-__device__ __forceinline__ Loc locate(const HtdSizes& sz, int bid, F count) {
+template <typename S, typename F>
+__device__ __forceinline__ Loc locate(const S& sz, int bid, F count) {
   for (int p = 0; p < sz.np; ++p) {
     const int c = count(sz.n[p]);
     if (bid < c) return Loc{p, bid};
@@ -144,102 +144,135 @@ __device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
   }
 }
 
-// One wavefront per KC_ROWS (32) rows.  Lanes 0..31 each bring one row's
-// column entry up to date from that row of V and W (loaded before the
-// reductions that precede their use) and stage the row in LDS; then lane
-// l < 32 forms (V^H x)_l and lane 32 + l (W^H x)_l over the 32 rows from LDS
-// -- no cross-lane reductions.
-__global__ __launch_bounds__(64) void trd_col_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int k) {
-  __shared__ double2 vk[HTD_NB], wk[HTD_NB];
-  __shared__ double2 pan[KC_ROWS][2 * HTD_NB + 1];  // V | W rows of this workgroup
-  __shared__ double2 xs[KC_ROWS];
+// KC_ROWS rows per 256-thread workgroup.  Lane c of every wavefront owns
+// column c of [V | W] (c < HTD_NB: V[:, c], else W[:, c - HTD_NB]) and the
+// wavefront owns rows wv, wv + 4, ... of the workgroup's rows, so that each
+// load reads whole panel rows.  The column entry of row r is a wavefront sum
+// of the lanes' terms; the dots V^H x, W^H x are per-lane sums over the rows,
+// added over the four wavefronts in LDS.
+__global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
+  constexpr int RPW = KC_ROWS / 4;  // rows per wavefront
+  __shared__ double2 dsum[4][2 * HTD_NB];
+  __shared__ double2 kv[2 * HTD_NB];  // row k: w_k (V lanes), v_k (W lanes)
+  __shared__ double2 psum[4];
+  __shared__ double nrm[4][2];
   const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_col_blocks(n, k); });
   if (lc.p < 0) return;
-  const HtdDesc& d = ds[lc.p];
+  const HtdDesc d = htd_view(sz, lc.p);
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, lane = threadIdx.x;
+  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
-  const int i = lc.b * KC_ROWS + lane;
-  const bool own = lane < KC_ROWS && i < m;
-  const int64_t r = k + 1 + i;
+  const int c = tid & 63, wv = tid >> 6;
+  const int u = c & (HTD_NB - 1);
+  const bool isv = c < HTD_NB;
+  const bool live = u < j;                 // panel column u exists
+  const bool vfin = isv && u == j - 1;     // holds w_k[j-1], finalised here
+  const bool fin = !isv && u == j - 1;     // W column j-1, finalised here
   // independent loads, the small ones first (memory operations complete in
-  // issue order): partials of alpha, row k of V and W, then this lane's row
+  // issue order): partials of alpha, row k, then this wavefront's rows
   const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
-  constexpr int PQ = HTD_MAX / HV_ROWS / 64;
+  constexpr int PQ = (HTD_MAX / HV_ROWS + 255) / 256;
   double2 pq[PQ];
 #pragma unroll
-  for (int u = 0; u < PQ; ++u) {
-    const int q = lane + 64 * u;
-    pq[u] = q < nbp ? d.part[q] : make_double2(0.0, 0.0);
+  for (int t = 0; t < PQ; ++t) {
+    const int q = tid + 256 * t;
+    pq[t] = q < nbp ? d.part[q] : make_double2(0.0, 0.0);
   }
   const double2 tp = j > 0 ? d.tau[k - 1] : make_double2(0.0, 0.0);
-  double2 vkl = make_double2(0.0, 0.0), wkl = make_double2(0.0, 0.0);  // row k of V and W
-  if (lane < j) {
-    vkl = d.PV[(int64_t)k * HTD_NB + lane];
-    wkl = lane == j - 1 ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + lane];
-  }
-  double2 a = make_double2(0.0, 0.0);
-  if (own) a = d.A[(int64_t)k * ld + r];
-  double2 vv[HTD_NB], ww[HTD_NB];
+  // lane of V column u: w_k[u]; lane of W column u: v_k[u]
+  double2 rk = make_double2(0.0, 0.0), rkv = make_double2(0.0, 0.0);
+  if (live) rk = isv ? (vfin ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + u]) : d.PV[(int64_t)k * HTD_NB + u];
+  if (vfin) rkv = d.PV[(int64_t)k * HTD_NB + u];
+  const double akk = lc.b == 0 && tid == 0 ? d.A[(int64_t)k * ld + k].x : 0.0;
+  double2 a[RPW], pv[RPW], pf[RPW];
 #pragma unroll
-  for (int u = 0; u < HTD_NB; ++u) {
-    vv[u] = own && u < j ? d.PV[r * HTD_NB + u] : make_double2(0.0, 0.0);
-    ww[u] = own && u < j ? (u == j - 1 ? d.PY[r] : d.PW[r * HTD_NB + u]) : make_double2(0.0, 0.0);
+  for (int q = 0; q < RPW; ++q) {
+    const int i = lc.b * KC_ROWS + wv + 4 * q;
+    const bool own = i < m;
+    const int64_t r = k + 1 + i;
+    a[q] = own && c == 0 ? d.A[(int64_t)k * ld + r] : make_double2(0.0, 0.0);
+    pv[q] = make_double2(0.0, 0.0);
+    pf[q] = make_double2(0.0, 0.0);
+    if (own && live) pv[q] = isv ? d.PV[r * HTD_NB + u] : (fin ? d.PY[r] : d.PW[r * HTD_NB + u]);
+    if (own && fin) pf[q] = d.PV[r * HTD_NB + u];
   }
+  // alpha = -(tau/2) y^H v of panel column j-1 (its HEMV's partial sums)
   double sx = 0.0, sy = 0.0;
 #pragma unroll
-  for (int u = 0; u < PQ; ++u) {
-    sx += pq[u].x;
-    sy += pq[u].y;
+  for (int t = 0; t < PQ; ++t) {
+    sx += pq[t].x;
+    sy += pq[t].y;
   }
-  double2 al = make_double2(0.0, 0.0);  // -(tau/2) y^H v of panel column j-1
-  if (j > 0) al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), make_double2(wave_sum(sx), wave_sum(sy)));
-  if (lane < j) {
-    if (lane == j - 1) wkl = cadd(wkl, cmul(al, vkl));
-    vk[lane] = vkl;
-    wk[lane] = wkl;
-  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if (c == 0) psum[wv] = make_double2(sx, sy);
   __syncthreads();
-  // x_r = conj(G[k][r]) - sum_l V[r][l] conj(w_k[l]) + W[r][l] conj(v_k[l])
-  double2 x = make_double2(a.x, -a.y);
-  if (own) {
-#pragma unroll
-    for (int u = 0; u < HTD_NB; ++u)
-      if (u < j) {
-        if (u == j - 1) {
-          ww[u] = cadd(ww[u], cmul(al, vv[u]));
-          d.PW[r * HTD_NB + u] = ww[u];
-        }
-        x = csub(csub(x, cmulc(wk[u], vv[u])), cmulc(vk[u], ww[u]));
-      }
-    d.xb[i] = x;
+  double2 al = make_double2(0.0, 0.0);
+  if (j > 0) {
+    const double2 ps = cadd(cadd(psum[0], psum[1]), cadd(psum[2], psum[3]));
+    al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), ps);
   }
-  const bool tail = own && i > 0;
-  if (lane < KC_ROWS) {
-    xs[lane] = tail ? x : make_double2(0.0, 0.0);
+  // w_{j-1} = y_{j-1} + alpha v_{j-1}, on row k and on this wavefront's rows
+  if (vfin) rk = cadd(rk, cmul(al, rkv));
+  kv[c] = rk;
+  if (fin) {
 #pragma unroll
-    for (int u = 0; u < HTD_NB; ++u) {
-      pan[lane][u] = vv[u];
-      pan[lane][HTD_NB + u] = ww[u];
+    for (int q = 0; q < RPW; ++q) {
+      const int i = lc.b * KC_ROWS + wv + 4 * q;
+      pv[q] = cadd(pv[q], cmul(al, pf[q]));
+      if (i < m) d.PW[(int64_t)(k + 1 + i) * HTD_NB + u] = pv[q];
     }
   }
-  // scaled norm of x_1 ... over this workgroup's rows
-  const double amax = wave_max(tail ? fmax(fabs(x.x), fabs(x.y)) : 0.0);
-  double ss = 0.0;
-  if (tail && amax > 0.0) ss = (x.x / amax) * (x.x / amax) + (x.y / amax) * (x.y / amax);
-  ss = wave_sum(ss);
-  __syncthreads();
-  // lane l < 32: (V^H x)_l, lane 32 + l: (W^H x)_l
-  double2 acc = make_double2(0.0, 0.0);
-  if ((lane & (HTD_NB - 1)) < j)
+  // x_r = conj(G[k][r]) - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
+  // lane c contributes pv conj(rk), lane 0 also conj(G[k][r])
+  double2 x[RPW];
 #pragma unroll
-    for (int t = 0; t < KC_ROWS; ++t) acc = cadd(acc, cmulc(pan[t][lane], xs[t]));
+  for (int q = 0; q < RPW; ++q) {
+    double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
+    t = make_double2(a[q].x - t.x, -a[q].y - t.y);
+    x[q] = make_double2(wave_sum(t.x), wave_sum(t.y));
+  }
+  // the column, the scaled norm of x_1 (rows i > 0) and the dots over them
+  double amax = 0.0;
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int i = lc.b * KC_ROWS + wv + 4 * q;
+    if (i < m && c == q) d.xb[i] = x[q];
+    if (i > 0 && i < m) {
+      amax = fmax(amax, fmax(fabs(x[q].x), fabs(x[q].y)));
+      if (live) acc = cadd(acc, cmulc(pv[q], x[q]));
+    }
+  }
+  double ss = 0.0;
+  if (amax > 0.0) {
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+      const int i = lc.b * KC_ROWS + wv + 4 * q;
+      if (i > 0 && i < m) ss += (x[q].x / amax) * (x[q].x / amax) + (x[q].y / amax) * (x[q].y / amax);
+    }
+  }
+  dsum[wv][c] = acc;
+  if (c == 0) {
+    nrm[wv][0] = amax;
+    nrm[wv][1] = ss;
+  }
+  __syncthreads();
   double2* rec = d.kpart + (int64_t)lc.b * HTD_KP;
-  if (lane == 0) rec[0] = make_double2(amax, ss);
-  rec[2 + lane] = acc;
-  if (lc.b == 0 && lane == 0) {
-    double dk = d.A[(int64_t)k * ld + k].x;
-    for (int q = 0; q < j; ++q) dk -= 2.0 * (vk[q].x * wk[q].x + vk[q].y * wk[q].y);
+  if (wv == 0) {
+    rec[2 + c] = cadd(cadd(dsum[0][c], dsum[1][c]), cadd(dsum[2][c], dsum[3][c]));
+    if (c == 0) {
+      const double mx = fmax(fmax(nrm[0][0], nrm[1][0]), fmax(nrm[2][0], nrm[3][0]));
+      double tot = 0.0;
+      if (mx > 0.0)
+        for (int w = 0; w < 4; ++w)
+          if (nrm[w][0] > 0.0) tot += nrm[w][1] * (nrm[w][0] / mx) * (nrm[w][0] / mx);
+      rec[0] = make_double2(mx, tot);
+    }
+  }
+  if (lc.b == 0 && tid == 0) {
+    double dk = akk;
+    for (int q = 0; q < j; ++q) dk -= 2.0 * (kv[HTD_NB + q].x * kv[q].x + kv[HTD_NB + q].y * kv[q].y);
     d.d[k] = dk;
   }
 }
@@ -250,7 +283,7 @@ __global__ __launch_bounds__(64) void trd_col_kernel(const HtdDesc* __restrict__
 // LDS).  The reflector is then rebuilt from the records (every workgroup
 // does it, in the same order) and applied inside the product:
 // G v = G[:, 0] + scale (G[:, 1:] x[1:]) since v = (1, scale x[1:]).
-__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int k) {
+__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) {
   __shared__ double2 xs[HTD_MAX];
   __shared__ double2 vhv[HTD_NB], whv[HTD_NB];
   __shared__ double2 wred[4];
@@ -258,7 +291,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdDesc* __restrict
   __shared__ double sh2[2];
   const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_hemv_blocks(n, k); });
   if (lc.p < 0) return;
-  const HtdDesc& d = ds[lc.p];
+  const HtdDesc d = htd_view(sz, lc.p);
   if (skipped(d)) return;
   const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
@@ -1241,14 +1274,14 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
 
 }  // namespace
 
-hipError_t launch_trd_hemv(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
+hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  launch(trd_hemv_kernel, dim3(blocks), dim3(256), 0, s, d, sz, k);
+  launch(trd_hemv_kernel, dim3(blocks), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
-hipError_t launch_trd_col(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s) {
+hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  launch(trd_col_kernel, dim3(blocks), dim3(64), 0, s, d, sz, k);
+  launch(trd_col_kernel, dim3(blocks), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s) {

@@ -101,7 +101,7 @@ constexpr int HTD_MAX = 2048;  // largest n: per-node lists are staged in LDS
 constexpr int HTD_NB = 32;     // reflectors per back-transformation block
 constexpr int HV_ROWS = 4;     // trailing-matrix rows per HEMV workgroup (one per wavefront)
 constexpr int HTD_KP = 2 + 2 * HTD_NB;  // per trd_col workgroup: (max, sum of squares), V^H x, W^H x
-constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (one wavefront)
+constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (8 per wavefront)
 constexpr int BT_CH = 256;     // rows per split-K chunk of the back-transformation
 
 struct HtdDesc {
@@ -191,10 +191,84 @@ struct HtdSizes {
   int nc[HTD_GROUP];  // eigenvector columns back-transformed: min(n, rcap)
 };
 
-// launches over sz.np descriptors in device memory; `blocks` is the sum of the
-// per-problem counts above for the given step / level / block
-hipError_t launch_trd_col(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s);
-hipError_t launch_trd_hemv(const HtdDesc* d, const HtdSizes& sz, int k, int blocks, hipStream_t s);
+// Buffers of the tridiagonal solver for Gram matrices of leading dim ld;
+// take(bytes) returns device memory (or only counts it).  The buffers are
+// taken in this order, each 256-byte aligned, so that a kernel can derive
+// them from the first one (htd_view) without reading a descriptor.
+template <typename F>
+__host__ __device__ inline void htd_layout(size_t ld, HtdDesc& h, F take) {
+  const size_t nd = ld * sizeof(double), ni = ld * sizeof(int), nc = ld * sizeof(double2);
+  h.d = (double*)take(nd);
+  h.e = (double*)take(nd);
+  h.lam = (double*)take(nd);
+  h.tau = (double2*)take(nc);
+  h.PV = (double2*)take(HTD_NB * nc);
+  h.PW = (double2*)take(HTD_NB * nc);
+  h.PY = (double2*)take(nc);
+  h.xb = (double2*)take(nc);
+  h.kpart = (double2*)take((ld / KC_ROWS + 1) * HTD_KP * sizeof(double2));
+  h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
+  for (int q = 0; q < 2; ++q) {
+    h.Q[q] = (double*)take(ld * nd);
+    h.D[q] = (double*)take(nd);
+  }
+  h.unrm = (double*)take(nd);
+  h.dl = (double*)take(nd);
+  h.w = (double*)take(nd);
+  h.ndcol = (int*)take(ni);
+  h.dval = (double*)take(nd);
+  h.dcol = (int*)take(ni);
+  h.rot_a = (int*)take(ni);
+  h.rot_b = (int*)take(ni);
+  h.rot_c = (double*)take(nd);
+  h.rot_s = (double*)take(nd);
+  h.origin = (int*)take(ni);
+  h.stau = (double*)take(nd);
+  h.zhat = (double*)take(nd);
+  h.pos_nd = (int*)take(ni);
+  h.cnt = (int*)take(4 * ni);
+  h.rho = (double*)take(nd);
+  h.T = (double2*)take((ld / HTD_NB + 1) * HTD_NB * HTD_NB * sizeof(double2));
+  h.Wp = (double2*)take(((ld + BT_CH - 1) / BT_CH) * HTD_NB * nc);
+  h.W = (double2*)take(HTD_NB * nc);
+}
+
+// The problems of one launch of the column update and the HEMV, passed by
+// value: with the sizes, the Gram matrix, the first workspace buffer (h.d)
+// and the skip flag of each problem, the kernels reach every buffer without
+// a dependent load of a descriptor (the launch-to-data latency of these short
+// kernels is most of their run time).
+struct HtdArgs {
+  int np;
+  int n[HTD_GROUP];
+  int ld[HTD_GROUP];
+  double2* A[HTD_GROUP];
+  char* ws[HTD_GROUP];
+  const int* skip[HTD_GROUP];
+};
+
+// The buffers of problem p of `a`, laid out as htd_layout takes them.
+__host__ __device__ inline HtdDesc htd_view(const HtdArgs& a, int p) {
+  HtdDesc h{};
+  char* base = a.ws[p];
+  size_t off = 0;
+  htd_layout((size_t)a.ld[p], h, [&](size_t x) -> void* {
+    off = (off + 255) & ~size_t(255);
+    void* q = base + off;
+    off += x;
+    return q;
+  });
+  h.A = a.A[p];
+  h.ld = a.ld[p];
+  h.skip = a.skip[p];
+  return h;
+}
+
+// launches over the problems of sz (descriptors in device memory) or of a;
+// `blocks` is the sum of the per-problem counts above for the given step /
+// level / block
+hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s);
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s);
 hipError_t launch_trd_finish(const HtdDesc* d, const HtdSizes& sz, hipStream_t s);
 hipError_t launch_dc_init(const HtdDesc* d, const HtdSizes& sz, int blocks, hipStream_t s);

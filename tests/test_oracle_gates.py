@@ -1,4 +1,8 @@
-"""Pins of the oracle's gate table against App. A identities."""
+"""Pins of the oracle's gate table against the matrices printed in App. A
+(tests/golden/app_a_gates.json) and the identities they satisfy."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -50,3 +54,29 @@ def test_controlled_convention():
     assert np.allclose(G.CT, np.diag([1, 1, 1, np.exp(1j * np.pi / 4)]))
     assert np.allclose(G.CZ, np.diag([1, 1, 1, -1]))
     assert np.allclose(G.CH[2:, 2:], G.H)
+
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "app_a_gates.json")
+
+
+def _printed(entry):
+    env = {"sqrt": np.sqrt, "exp": np.exp, "cos": np.cos, "sin": np.sin, "pi": np.pi, "i": 1j}
+    return np.array([[complex(eval(x, {"__builtins__": {}}, env)) for x in row] for row in entry["m"]])
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", sorted(_golden()["gates"]))
+def test_printed_matrix(name):
+    assert np.abs(G.matrix(name) - _printed(_golden()["gates"][name])).max() < 1e-15
+
+
+def test_printed_sqrt_w_is_garbled_and_read_as_principal_root():
+    p = _printed(_golden()["garbled"]["SQRTW"])
+    assert np.abs(p.conj().T @ p - np.eye(2)).max() > 0.5
+    # the reading differs from the print only on the diagonal, by conjugation
+    assert np.allclose(np.diag(G.SQRTW), np.conj(np.diag(p)), atol=1e-15)
+    assert np.allclose(G.SQRTW - np.diag(np.diag(G.SQRTW)), p - np.diag(np.diag(p)), atol=1e-15)

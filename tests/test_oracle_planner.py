@@ -1,5 +1,8 @@
 """Pins of the oracle's planner: the worked example of Fig. 6 (Sec. III.A), the
 size formula (Eq. size), the caps, and exactness of the SWAP routing."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -8,34 +11,34 @@ from oracle import statevector as SV
 from workloads import Circuit, Gate, random_structured
 
 
-def fig6_layers():
-    # qubits 1..8 of the figure are 0..7 here
-    L1 = [Gate("CNOT", (0, 1)), Gate("CNOT", (2, 3)), Gate("CNOT", (4, 5)), Gate("CNOT", (6, 7))]
-    L2 = [Gate("CNOT", (0, 1)), Gate("H", (2,)), Gate("CNOT", (4, 5)), Gate("CNOT", (6, 7))]
-    L3 = [Gate("H", (0,)), Gate("CNOT", (2, 3)), Gate("CNOT", (5, 6))]
-    L4 = [Gate("CNOT", (0, 1)), Gate("CNOT", (4, 5))]
-    L5 = [Gate("CNOT", (3, 4))]
-    L6 = [Gate("CNOT", (1, 2))]
-    return [L1, L2, L3, L4, L5, L6]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig6_worked_example.json")
+
+
+def fig6():
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    layers = [[Gate(name, tuple(q)) for name, q in L] for L in g["layers"]]
+    return g, layers
 
 
 def test_fig6_worked_example():
-    subs = PL.legalize(fig6_layers(), k_max=8)
-    assert len(subs) == 6
-    # after layers 1-2: four two-qubit clusters
+    g, layers = fig6()
+    subs = PL.legalize(layers, k_max=8)
+    assert len(subs) == len(layers)
     bond = [False] * 7
     PL.mark_bonds(bond, subs[0]); PL.mark_bonds(bond, subs[1])
-    assert PL.clusters_of(bond) == [(0, 2), (2, 2), (4, 2), (6, 2)]
-    # layer 3: U(6,7) joins clusters 3 and 4 into four qubits
+    assert PL.clusters_of(bond) == [tuple(c) for c in g["clusters_after_layer_2"]]
+    # the third layer's gate on (5, 6) joins the last two clusters
     PL.mark_bonds(bond, subs[2])
-    assert PL.clusters_of(bond) == [(0, 2), (2, 2), (4, 4)]
-    # Eq. size for {5..8}: bonds 5,6,7 marked -> 2^{q_n - q_1 + 2} = 2^4
-    assert PL.cluster_fits(4, 4, [1] * 7, k_max=8, q_max=4)
-    assert not PL.cluster_fits(4, 4, [1] * 7, k_max=8, q_max=3)
-    # with Q_max = 5 the step ends after layer 4 (U(4,5) at layer 5 makes six qubits)
-    end, cl = PL.plan_step(subs, 0, 8, [1] * 7, k_max=8, q_max=5, l_max=1 << 30)
-    assert end == 4
-    assert cl == [(0, 2), (2, 2), (4, 4)]
+    assert PL.clusters_of(bond) == [tuple(c) for c in g["clusters_after_layer_3"]]
+    # Eq. size for the cluster on 4..7 (bonds marked, chi = 1): 2^{q_n - q_1 + 2}
+    e = g["size_exponent_of_cluster_4_to_7"]
+    assert PL.cluster_fits(4, 4, [1] * 7, k_max=8, q_max=e)
+    assert not PL.cluster_fits(4, 4, [1] * 7, k_max=8, q_max=e - 1)
+    # with Q_max = 5 the step ends after layer 4 (layer 5 would make six qubits)
+    end, cl = PL.plan_step(subs, 0, 8, [1] * 7, k_max=8, q_max=g["q_max"], l_max=1 << 30)
+    assert end == g["step_end_layer"]
+    assert cl == [tuple(c) for c in g["step_clusters"]]
 
 
 def test_size_uses_outer_bonds():

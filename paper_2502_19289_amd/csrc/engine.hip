@@ -597,10 +597,11 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     t0 = std::chrono::steady_clock::now();
   };
   lap("start");
-  for (int p0 = 0; p0 + 1 < nmax; p0 += HTD_NB) {
+  int kmain = 0;  // the blocked kernels run the columns below htd_tail_start(n)
+  for (int p = 0; p < np; ++p) kmain = std::max(kmain, htd_tail_start(sz.n[p]));
+  for (int p0 = 0; p0 < kmain; p0 += HTD_NB) {
     for (int j = 0; j < HTD_NB; ++j) {
       const int k = p0 + j;
-      if (k + 1 >= nmax) break;
       const int nb_col = total([k](int n) { return htd_col_blocks(n, k); });
       timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
       const int nb_hemv = total([k](int n) { return htd_hemv_blocks(n, k); });
@@ -608,7 +609,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
       if (counted)  // algorithmic traffic of the HEMV: the trailing block read once
         for (int p = 0; p < np; ++p) {
           const double m = sz.n[p] - k - 1;
-          if (m <= 0) continue;
+          if (m <= 0 || k >= htd_tail_start(sz.n[p])) continue;
           ctx->timer.bytes[c_hemv] += 16.0 * m * m;
           ctx->timer.flop[c_hemv] += 8.0 * m * m;
         }
@@ -620,10 +621,14 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     if (timing)  // rank-2 HTD_NB update of the trailing block (Hermitian: count one triangle)
       for (int p = 0; p < np; ++p) {
         const double nbp = std::min(HTD_NB, sz.n[p] - 1 - p0);
-        if (nbp <= 0) continue;
+        if (nbp <= 0 || p0 >= htd_tail_start(sz.n[p])) continue;
         const double mt = sz.n[p] - p0 - nbp;
         ctx->timer.flop[c_her2k] += 8.0 * 2.0 * nbp * mt * (mt + 1) / 2;
       }
+  }
+  {
+    Timed tm(ctx, "trd_tail");
+    HIP_OK(launch_trd_tail(dd, sz, s));
   }
   lap("reduction");
   {
@@ -641,7 +646,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     HIP_OK(launch_dc_prep(dd, sz, L, nodes, s));
     HIP_OK(launch_dc_rot(dd, sz, L, rows, s));
     for (int stage = 1; stage < 4; ++stage) HIP_OK(launch_dc_wave(stage, dd, sz, L, waves, s));
-    HIP_OK(launch_dc_place(dd, sz, L, nodes, s));
+    HIP_OK(launch_dc_place(dd, sz, L, total([L](int n) { return htd_place_blocks(n, L); }), s));
     HIP_OK(launch_dc_gemm(dd, sz, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
   }
   lap("divide and conquer");
@@ -657,10 +662,10 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     HIP_OK(launch_bt_wpart(dd, sz, b, total_c([b](int n, int c) { return htd_wpart_blocks(n, c, b); }), s));
     HIP_OK(launch_bt_wred(dd, sz, b, total_c([b](int n, int c) { return htd_wred_blocks(n, c, b); }), s));
     HIP_OK(launch_bt_update(dd, sz, b, total_c([b](int n, int c) { return htd_update_blocks(n, c, b); }), s));
-    if (timing)  // two products of (rows x HTD_NB) by (HTD_NB x nc) complex
+    if (timing)  // two products of (rows x BT_NB) by (BT_NB x nc) complex
       for (int p = 0; p < np; ++p)
         if (b < htd_nblk(sz.n[p])) {
-          const double rows = htd_bt_rows(sz.n[p], b), nb = std::min(HTD_NB, sz.n[p] - 1 - HTD_NB * b);
+          const double rows = htd_bt_rows(sz.n[p], b), nb = std::min(BT_NB, sz.n[p] - 1 - BT_NB * b);
           ctx->timer.flop[c_bt] += 2.0 * 8.0 * rows * nb * sz.nc[p];
         }
   }
@@ -698,10 +703,7 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
       sz.nc[q] = std::min(n, host[c0 + q].rcap);
       const HtdDesc& h = host[c0 + q];
       ha.n[q] = n;
-      ha.ld[q] = h.ld;
-      ha.A[q] = h.A;
-      ha.ws[q] = (char*)h.d;
-      ha.skip[q] = h.skip;
+      ha.pr[q] = HtdProb{h.A, (char*)h.d, h.skip, n, h.ld};
       if (!htd_view_matches(ha, q, h)) fail(ctx, MPS_EINVAL, "tridiagonal solve: workspace layout");
     }
     ha.np = sz.np;

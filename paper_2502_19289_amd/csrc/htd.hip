@@ -144,6 +144,34 @@ __device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
   }
 }
 
+// The reflector H = I - tau v v^H with H^H (alpha, x1)^T = (beta, 0)^T, beta
+// real, v = (1, scale x1), from alpha and the scaled norm of x1
+// (||x1||^2 = smax^2 ssq); tau = 0 (H = I) when x1 = 0 and alpha is real.
+__device__ __forceinline__ void householder(double2 alpha, double smax, double ssq, double& beta, double2& tau,
+                                            double2& scale) {
+  const double amax = fmax(smax, fmax(fabs(alpha.x), fabs(alpha.y)));
+  tau = make_double2(0.0, 0.0);
+  scale = make_double2(0.0, 0.0);
+  beta = alpha.x;
+  if (amax > 0.0) {
+    const double xs2 = ssq * (smax / amax) * (smax / amax);
+    if (xs2 > 0.0 || alpha.y != 0.0) {
+      const double ar = alpha.x / amax, ai = alpha.y / amax;
+      beta = -copysign(amax * sqrt(ar * ar + ai * ai + xs2), alpha.x);
+      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      // scale = 1 / (alpha - beta) by Smith's complex division
+      const double dr = alpha.x - beta, di = alpha.y;
+      if (fabs(dr) >= fabs(di)) {
+        const double rr = di / dr, t = 1.0 / (dr + di * rr);
+        scale = make_double2(t, -rr * t);
+      } else {
+        const double rr = dr / di, t = 1.0 / (di + dr * rr);
+        scale = make_double2(rr * t, -t);
+      }
+    }
+  }
+}
+
 // KC_ROWS rows per 256-thread workgroup.  Lane c of every wavefront owns
 // column c of [V | W] (c < HTD_NB: V[:, c], else W[:, c - HTD_NB]) and the
 // wavefront owns rows wv, wv + 4, ... of the workgroup's rows, so that each
@@ -172,13 +200,16 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   // issue order): partials of alpha, row k, then this wavefront's rows
   const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
   constexpr int PQ = (HTD_MAX / HV_ROWS + 255) / 256;
+  // (loads are unconditional at clamped, always valid indexes and masked at
+  // their use, so that no use is folded into a branch right after its load,
+  // which would wait for it before the later loads are issued)
   double2 pq[PQ];
 #pragma unroll
   for (int t = 0; t < PQ; ++t) {
     const int q = tid + 256 * t;
-    pq[t] = q < nbp ? d.part[q] : make_double2(0.0, 0.0);
+    pq[t] = d.part[q < nbp ? q : 0];
   }
-  const double2 tp = j > 0 ? d.tau[k - 1] : make_double2(0.0, 0.0);
+  const double2 tpl = d.tau[k > 0 ? k - 1 : 0];
   // lane of V column u: w_k[u]; lane of W column u: v_k[u]
   double2 rk = make_double2(0.0, 0.0), rkv = make_double2(0.0, 0.0);
   if (live) rk = isv ? (vfin ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + u]) : d.PV[(int64_t)k * HTD_NB + u];
@@ -200,8 +231,9 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   double sx = 0.0, sy = 0.0;
 #pragma unroll
   for (int t = 0; t < PQ; ++t) {
-    sx += pq[t].x;
-    sy += pq[t].y;
+    const bool okq = tid + 256 * t < nbp;
+    sx += okq ? pq[t].x : 0.0;
+    sy += okq ? pq[t].y : 0.0;
   }
   sx = wave_sum(sx);
   sy = wave_sum(sy);
@@ -210,7 +242,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   double2 al = make_double2(0.0, 0.0);
   if (j > 0) {
     const double2 ps = cadd(cadd(psum[0], psum[1]), cadd(psum[2], psum[3]));
-    al = cmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), ps);
+    al = cmul(make_double2(-0.5 * tpl.x, -0.5 * tpl.y), ps);
   }
   // w_{j-1} = y_{j-1} + alpha v_{j-1}, on row k and on this wavefront's rows
   if (vfin) rk = cadd(rk, cmul(al, rkv));
@@ -304,11 +336,14 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   // reductions on them must not wait behind the row): the staged column,
   // the trd_col records, this row's panel term
   constexpr int XL = HTD_MAX / 256;
+  // (unconditional loads at clamped, always valid indexes, masked at their
+  // use: a use folded into a branch right after its load would wait for it
+  // before the later loads are issued)
   double2 xv[XL];
 #pragma unroll
   for (int u = 0; u < XL; ++u) {
     const int jj = tid + 256 * u;
-    xv[u] = jj < m ? d.xb[jj] : make_double2(0.0, 0.0);
+    xv[u] = d.xb[jj < m ? jj : 0];
   }
   const int nka = htd_col_blocks(n, k);
   const double2* recs = d.kpart;
@@ -318,10 +353,11 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
 #pragma unroll
   for (int u = 0; u < RQ; ++u) {
     const int q = g + 4 * u;
-    rv[u] = (e & (HTD_NB - 1)) < j && q < nka ? recs[(int64_t)q * HTD_KP + 2 + e] : make_double2(0.0, 0.0);
+    rv[u] = recs[(int64_t)(q < nka ? q : 0) * HTD_KP + 2 + e];
   }
-  double2 rq = make_double2(0.0, 0.0);  // wavefront 0, lane q < nka: record q's (scale, ssq)
-  if (tid < nka) rq = recs[(int64_t)tid * HTD_KP];
+  // wavefront 0, lane q < nka: record q's (scale, ssq)
+  const double2 rq0 = recs[(int64_t)(tid < nka ? tid : 0) * HTD_KP];
+  const double2 rq = tid < nka ? rq0 : make_double2(0.0, 0.0);
   const int l = lane & (HTD_NB - 1);
   const bool isv = lane < HTD_NB;
   double2 pe = make_double2(0.0, 0.0);
@@ -345,8 +381,10 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   }
   {
     double2 t = make_double2(0.0, 0.0);
+    const bool ev = (e & (HTD_NB - 1)) < j;
 #pragma unroll
-    for (int u = 0; u < RQ; ++u) t = cadd(t, rv[u]);
+    for (int u = 0; u < RQ; ++u)
+      if (ev && g + 4 * u < nka) t = cadd(t, rv[u]);
     hsum[g][e] = t;
   }
   if (tid < 64) {
@@ -367,26 +405,9 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     sw = cadd(cadd(hsum[0][HTD_NB + tid], hsum[1][HTD_NB + tid]), cadd(hsum[2][HTD_NB + tid], hsum[3][HTD_NB + tid]));
   }
   const double2 alpha = xs[0];
-  const double amax = fmax(smax, fmax(fabs(alpha.x), fabs(alpha.y)));
-  double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
-  double beta = alpha.x;
-  if (amax > 0.0) {
-    const double xs2 = ssq * (smax / amax) * (smax / amax);
-    if (xs2 > 0.0 || alpha.y != 0.0) {
-      const double ar = alpha.x / amax, ai = alpha.y / amax;
-      beta = -copysign(amax * sqrt(ar * ar + ai * ai + xs2), alpha.x);
-      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-      // scale = 1 / (alpha - beta) by Smith's complex division
-      const double dr = alpha.x - beta, di = alpha.y;
-      if (fabs(dr) >= fabs(di)) {
-        const double rr = di / dr, t = 1.0 / (dr + di * rr);
-        scale = make_double2(t, -rr * t);
-      } else {
-        const double rr = dr / di, t = 1.0 / (di + dr * rr);
-        scale = make_double2(rr * t, -t);
-      }
-    }
-  }
+  double2 tau, scale;
+  double beta;
+  householder(alpha, smax, ssq, beta, tau, scale);
   const bool ident = tau.x == 0.0 && tau.y == 0.0;
   if (tid < j) {
     // V^H v = conj(V[k+1, l]) + scale sum_{i >= 1} conj(V[k+1+i, l]) x_i, likewise W
@@ -511,6 +532,150 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
           *p = make_double2(p->x - acc[x][y].re[q], p->y - acc[x][y].im[q]);
         }
       }
+}
+
+// The last columns of the reduction, from k0 = htd_tail_start(n) on (all of
+// them when n <= HTD_TAIL): the trailing block, mt = n - k0 <= HTD_TAIL rows,
+// is up to date there (the last panel's trd_her2k ran) and is held in the
+// registers of one 512-thread workgroup as 4 x 8 tiles: thread t owns rows
+// 4 (t / 16) .. +3 and columns 8 (t % 16) .. +7, so that a row is spread over
+// the 16 lanes of one DPP row and each column step reads 12 vector entries.
+// Column by column (unblocked): the column below the diagonal is the
+// conjugated row, the reflector comes from its scaled norm, y = tau A v,
+// w = y - (tau/2)(y^H v) v and A -= v w^H + w v^H; d, e, tau and the
+// reflectors (row k of A) are written as the blocked kernels write them.
+__global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
+  constexpr int TR = 4, TC = 8, CG = HTD_TAIL / TC;  // tile rows, tile columns, column groups
+  static_assert(CG == 16 && (HTD_TAIL / TR) * CG == 512, "tail tiling");
+  __shared__ double2 xs[HTD_TAIL], vs[HTD_TAIL], ys[HTD_TAIL], ws[HTD_TAIL];
+  __shared__ double2 sh_tau, sh_scale;
+  const int p = blockIdx.x;
+  if (p >= sz.np) return;
+  const HtdDesc& d = ds[p];
+  if (skipped(d)) return;
+  const int n = sz.n[p], k0 = htd_tail_start(n), mt = n - k0, ld = d.ld, tid = threadIdx.x;
+  const int r0 = (tid / CG) * TR, c0 = (tid % CG) * TC;
+  // (unconditional loads at clamped, valid addresses, masked afterwards: no
+  // load waits for the one before it)
+  double2 a[TR][TC];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    const int rr = r0 + i < mt ? r0 + i : 0;
+    const double2* row = d.A + (int64_t)(k0 + rr) * ld + k0;
+#pragma unroll
+    for (int j = 0; j < TC; ++j) a[i][j] = row[c0 + j < mt ? c0 + j : 0];
+  }
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int j = 0; j < TC; ++j)
+      if (!(r0 + i < mt && c0 + j < mt)) a[i][j] = make_double2(0.0, 0.0);
+  if (tid < HTD_TAIL) {
+    xs[tid] = make_double2(0.0, 0.0);
+    vs[tid] = make_double2(0.0, 0.0);
+    ys[tid] = make_double2(0.0, 0.0);
+    ws[tid] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int kk = 0; kk + 1 < mt; ++kk) {
+    const int k = k0 + kk;
+    // column kk below the diagonal = conj(row kk) (entries past mt are zero
+    // and stay zero; entries up to kk are read by no one); the diagonal is final
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+      if (r0 + i == kk)
+#pragma unroll
+        for (int j = 0; j < TC; ++j) xs[c0 + j] = make_double2(a[i][j].x, -a[i][j].y);
+    __syncthreads();
+    if (tid == 64) d.d[k] = xs[kk].x;
+    if (tid < 64) {  // reflector from alpha = x[kk+1] and the scaled norm of x[kk+2:]
+      double am = 0.0;
+      for (int c = kk + 2 + tid; c < mt; c += 64) am = fmax(am, fmax(fabs(xs[c].x), fabs(xs[c].y)));
+      const double smax = wave_max(am);
+      double ss = 0.0;
+      if (smax > 0.0)
+        for (int c = kk + 2 + tid; c < mt; c += 64)
+          ss += (xs[c].x / smax) * (xs[c].x / smax) + (xs[c].y / smax) * (xs[c].y / smax);
+      const double ssq = wave_sum(ss);
+      if (tid == 0) {
+        double beta;
+        double2 tau, scale;
+        householder(xs[kk + 1], smax, ssq, beta, tau, scale);
+        sh_tau = tau;
+        sh_scale = scale;
+        d.tau[k] = tau;
+        d.e[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double2 tau = sh_tau, scale = sh_scale;
+    const bool ident = tau.x == 0.0 && tau.y == 0.0;
+    if (tid < mt) {
+      const double2 v = tid == kk + 1 ? make_double2(1.0, 0.0)
+                                      : (tid > kk + 1 && !ident ? cmul(xs[tid], scale) : make_double2(0.0, 0.0));
+      vs[tid] = v;
+      if (tid > kk) d.A[(int64_t)k * ld + k0 + tid] = v;
+    }
+    __syncthreads();
+    if (ident) continue;  // H = I: the trailing block is unchanged
+    // y = tau A v on the rows below kk (each row summed over its 16 lanes)
+    {
+      double2 vc[TC];
+#pragma unroll
+      for (int j = 0; j < TC; ++j) vc[j] = vs[c0 + j];
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < TC; ++j) acc = cadd(acc, cmul(a[i][j], vc[j]));
+        acc.x += dpp_take<0xb1, 0xf>(acc.x);
+        acc.y += dpp_take<0xb1, 0xf>(acc.y);
+        acc.x += dpp_take<0x4e, 0xf>(acc.x);
+        acc.y += dpp_take<0x4e, 0xf>(acc.y);
+        acc.x += dpp_take<0x141, 0xf>(acc.x);
+        acc.y += dpp_take<0x141, 0xf>(acc.y);
+        acc.x += dpp_take<0x140, 0xf>(acc.x);
+        acc.y += dpp_take<0x140, 0xf>(acc.y);
+        const int r = r0 + i;
+        if (c0 == 0 && r < mt) ys[r] = r > kk ? cmul(tau, acc) : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {  // alpha = -(tau/2) y^H v, then w = y + alpha v
+      double2 t = make_double2(0.0, 0.0);
+      for (int c = kk + 1 + tid; c < mt; c += 64) t = cadd(t, cmulc(ys[c], vs[c]));
+      const double2 su = make_double2(wave_sum(t.x), wave_sum(t.y));
+      const double2 al = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), su);
+      for (int c = tid; c < mt; c += 64) ws[c] = cadd(ys[c], cmul(al, vs[c]));
+    }
+    __syncthreads();
+    if (r0 + TR - 1 > kk) {  // A -= v w^H + w v^H (v, w vanish at indexes <= kk and >= mt)
+      double2 vr[TR], wr[TR];
+#pragma unroll
+      for (int i = 0; i < TR; ++i) {
+        vr[i] = vs[r0 + i];
+        wr[i] = ws[r0 + i];
+      }
+#pragma unroll
+      for (int j = 0; j < TC; ++j) {  // one column at a time keeps the live registers few
+        const double2 vcc = make_double2(vs[c0 + j].x, -vs[c0 + j].y);
+        const double2 wcc = make_double2(ws[c0 + j].x, -ws[c0 + j].y);
+#pragma unroll
+        for (int i = 0; i < TR; ++i) a[i][j] = csub(csub(a[i][j], cmul(vr[i], wcc)), cmul(wr[i], vcc));
+      }
+    }
+    __syncthreads();  // xs, vs, ys, ws are rewritten by the next column
+  }
+  // the last diagonal entry, also back into A for trd_finish
+#pragma unroll
+  for (int i = 0; i < TR; ++i)
+#pragma unroll
+    for (int j = 0; j < TC; ++j)
+      if (r0 + i == mt - 1 && c0 + j == mt - 1) {
+        d.d[n - 1] = a[i][j].x;
+        d.A[(int64_t)(n - 1) * ld + (n - 1)] = a[i][j];
+      }
+  if (tid == 0) d.e[n - 1] = 0.0;
 }
 
 __global__ void trd_finish_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
@@ -912,52 +1077,62 @@ __global__ __launch_bounds__(256) void dc_wave_kernel(const HtdDesc* __restrict_
   }
 }
 
-// Orders the node's eigenvalues (roots and deflated values), writes them to
-// the next level's list, copies the deflated eigenvectors and records where
-// the GEMM writes each root's eigenvector.  Nodes without a right child are
-// carried over unchanged.
-__global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
+// Places the merged node's values (ascending: roots and deflated values
+// interleaved) and copies the deflated columns to their places.  One
+// workgroup per 64 columns of a node (the copy of a node of 2048 deflated
+// columns would take one workgroup hundreds of microseconds); the first
+// workgroup of a node also places the roots (dc_gemm writes their columns).
+__global__ __launch_bounds__(256) void dc_place_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
   __shared__ double lamv[HTD_MAX];
   __shared__ double dv[HTD_MAX];
-  __shared__ int pdef[HTD_MAX];
-  const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
+  __shared__ int pdef[64];
+  const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_place_blocks(n, L); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
   const int n = sz.n[lc.p], s = 1 << L, tid = threadIdx.x, ld = d.ld;
-  const int lo = lc.b * s, hi = min(lo + s, n), K = hi - lo;
+  const int per = (s + 63) / 64, node = lc.b / per, c0 = (lc.b % per) * 64;
+  const int lo = node * s, hi = min(lo + s, n), K = hi - lo;
+  if (c0 >= K) return;
   const double* Din = d.D[(L - 1) & 1];
   const double* Qin = d.Q[(L - 1) & 1];
   double* Dout = d.D[L & 1];
   double* Qout = d.Q[L & 1];
   const int* cnt = d.cnt + 4 * lo;
-  if (!cnt[3]) {
-    for (int e = tid; e < K * K; e += 1024) {
-      const int c = e / K, r = e % K;
+  const int cw = min(64, K - c0);
+  if (!cnt[3]) {  // nothing merged: the node's block as it was
+    for (int e = tid; e < cw * K; e += 256) {
+      const int c = c0 + e / K, r = e % K;
       Qout[(int64_t)(lo + c) * ld + lo + r] = Qin[(int64_t)(lo + c) * ld + lo + r];
     }
-    for (int c = tid; c < K; c += 1024) Dout[lo + c] = Din[lo + c];
+    if (tid < cw) Dout[lo + c0 + tid] = Din[lo + c0 + tid];
     return;
   }
   const int K2 = cnt[0], ndef = cnt[1];
-  for (int k = tid; k < K2; k += 1024) lamv[k] = d.dl[lo + d.origin[lo + k]] + d.stau[lo + k];
-  for (int q = tid; q < ndef; q += 1024) dv[q] = d.dval[lo + q];
+  const bool roots = c0 == 0;  // this workgroup also places the roots
+  if (!roots && c0 >= ndef) return;
+  for (int k = tid; k < K2; k += 256) lamv[k] = d.dl[lo + d.origin[lo + k]] + d.stau[lo + k];
+  if (roots)
+    for (int q = tid; q < ndef; q += 256) dv[q] = d.dval[lo + q];
   __syncthreads();
-  for (int k = tid; k < K2; k += 1024) {
-    const double x = lamv[k];
-    int a = 0, b = ndef;  // deflated values below x
-    while (a < b) {
-      const int mm = (a + b) >> 1;
-      if (dv[mm] < x)
-        a = mm + 1;
-      else
-        b = mm;
+  if (roots)
+    for (int k = tid; k < K2; k += 256) {
+      const double x = lamv[k];
+      int a = 0, b = ndef;  // deflated values below x
+      while (a < b) {
+        const int mm = (a + b) >> 1;
+        if (dv[mm] < x)
+          a = mm + 1;
+        else
+          b = mm;
+      }
+      d.pos_nd[lo + k] = k + a;
+      Dout[lo + k + a] = x;
     }
-    d.pos_nd[lo + k] = k + a;
-    Dout[lo + k + a] = x;
-  }
-  for (int q = tid; q < ndef; q += 1024) {
-    const double x = dv[q];
+  const int qn = max(0, min(64, ndef - c0));  // deflated columns c0 .. c0 + qn - 1
+  if (tid < qn) {
+    const int q = c0 + tid;
+    const double x = d.dval[lo + q];
     int a = 0, b = K2;  // roots at or below x
     while (a < b) {
       const int mm = (a + b) >> 1;
@@ -966,13 +1141,13 @@ __global__ __launch_bounds__(1024) void dc_place_kernel(const HtdDesc* __restric
       else
         b = mm;
     }
-    pdef[q] = q + a;
+    pdef[tid] = q + a;
     Dout[lo + q + a] = x;
   }
   __syncthreads();
-  for (int e = tid; e < ndef * K; e += 1024) {
-    const int q = e / K, r = e % K;
-    Qout[(int64_t)(lo + pdef[q]) * ld + lo + r] = Qin[(int64_t)d.dcol[lo + q] * ld + lo + r];
+  for (int e = tid; e < qn * K; e += 256) {
+    const int t = e / K, r = e % K;
+    Qout[(int64_t)(lo + pdef[t]) * ld + lo + r] = Qin[(int64_t)d.dcol[lo + c0 + t] * ld + lo + r];
   }
 }
 
@@ -1076,68 +1251,75 @@ __global__ __launch_bounds__(256) void bt_init_kernel(const HtdDesc* __restrict_
     }
 }
 
-// reflector i of block b (k = HTD_NB b + i) at row j: 0 for j <= k, else row k of A
+// reflector i of block b (k = BT_NB b + i) at row j: 0 for j <= k, else row k of A
 __device__ __forceinline__ double2 refl(const HtdDesc& d, int k, int j) {
   return j > k ? d.A[(int64_t)k * d.ld + j] : make_double2(0.0, 0.0);
 }
 
 // T of each block: H_k0 ... H_k0+nb-1 = I - V_b T V_b^H (upper triangular T,
-// T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] V_b[:, 0:i]^H v_i).
+// T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] S[0:i, i], S = V_b^H V_b).  S is
+// accumulated over 16-row chunks of the reflectors staged in LDS, each thread
+// owning BT_NB^2 / 256 entries; T then replaces S column by column.
 __global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
-  __shared__ double2 S[HTD_NB][HTD_NB];
-  __shared__ double2 Ts[HTD_NB][HTD_NB];
-  __shared__ double2 tv[HTD_NB];
+  constexpr int PPT = BT_NB * BT_NB / 256;  // entries of S per thread
+  __shared__ double2 Vs[16][BT_NB + 1];
+  __shared__ double2 Ts[BT_NB][BT_NB + 1];
+  __shared__ double2 tv[BT_NB];
   const Loc lc = locate(sz, blockIdx.x, [](int n) { return htd_nblk(n); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], b = lc.b, k0 = HTD_NB * b, tid = threadIdx.x;
-  const int nb = min(HTD_NB, (n - 1) - k0);
-  const int wave = tid >> 6, lane = tid & 63;
-  // S[a][i] = v_a^H v_i for a < i (v_i vanishes above row k0 + i + 1)
-  for (int pr = wave; pr < HTD_NB * HTD_NB; pr += 4) {
-    const int a = pr / HTD_NB, i = pr % HTD_NB;
-    if (a >= i || i >= nb) continue;
-    double sx = 0.0, sy = 0.0;
-    const double2* va = d.A + (int64_t)(k0 + a) * d.ld;
-    const double2* vi = d.A + (int64_t)(k0 + i) * d.ld;
-    for (int j = k0 + i + 1 + lane; j < n; j += 64) {
-      const double2 x = va[j], y = vi[j];
-      sx += x.x * y.x + x.y * y.y;
-      sy += x.x * y.y - x.y * y.x;
+  const int n = sz.n[lc.p], b = lc.b, k0 = BT_NB * b, tid = threadIdx.x;
+  const int nb = min(BT_NB, (n - 1) - k0);
+  double2 acc[PPT];
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) acc[t] = make_double2(0.0, 0.0);
+  for (int j0 = k0 + 1; j0 < n; j0 += 16) {
+    for (int e = tid; e < 16 * BT_NB; e += 256) {
+      const int jj = e / BT_NB, i = e % BT_NB, j = j0 + jj;
+      Vs[jj][i] = i < nb && j < n ? refl(d, k0 + i, j) : make_double2(0.0, 0.0);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      sx += __shfl_xor(sx, off);
-      sy += __shfl_xor(sy, off);
-    }
-    if (lane == 0) S[a][i] = make_double2(sx, sy);
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+      for (int t = 0; t < PPT; ++t) {
+        const int e = tid + 256 * t, a = e / BT_NB, i = e % BT_NB;
+        acc[t] = cadd(acc[t], cmulc(Vs[jj][a], Vs[jj][i]));
+      }
+    __syncthreads();
   }
-  for (int e = tid; e < HTD_NB * HTD_NB; e += 256) Ts[e / HTD_NB][e % HTD_NB] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int t = 0; t < PPT; ++t) {
+    const int e = tid + 256 * t, a = e / BT_NB, i = e % BT_NB;
+    Ts[a][i] = a < i ? acc[t] : make_double2(0.0, 0.0);
+  }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
     const double2 ti = d.tau[k0 + i];
     if (tid < i) {
-      const double2 t = cmul(ti, S[tid][i]);
+      const double2 t = cmul(ti, Ts[tid][i]);
       tv[tid] = make_double2(-t.x, -t.y);
     }
     __syncthreads();
-    if (tid < i) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int l = tid; l < i; ++l) acc = cadd(acc, cmul(Ts[tid][l], tv[l]));
-      Ts[tid][i] = acc;
+    if (tid < i) {  // reads columns < i of T, writes column i
+      double2 s2 = make_double2(0.0, 0.0);
+      for (int l = tid; l < i; ++l) s2 = cadd(s2, cmul(Ts[tid][l], tv[l]));
+      Ts[tid][i] = s2;
     }
     if (tid == 0) Ts[i][i] = ti;
     __syncthreads();
   }
-  double2* out = d.T + (int64_t)b * HTD_NB * HTD_NB;
-  for (int e = tid; e < HTD_NB * HTD_NB; e += 256) out[e] = Ts[e / HTD_NB][e % HTD_NB];
+  double2* out = d.T + (int64_t)b * BT_NB * BT_NB;
+  for (int e = tid; e < BT_NB * BT_NB; e += 256) out[e] = Ts[e / BT_NB][e % BT_NB];
 }
 
 // partial W = V_b^H Z over a chunk of BT_CH rows (rows from k0 + 1) and 64
-// eigenvector columns, on the matrix cores: the 32 x 64 output is eight 16 x 16
-// blocks, two per wavefront.
+// eigenvector columns, on the matrix cores: the BT_NB x 64 output is
+// (BT_NB / 16) x 4 blocks of 16 x 16, BT_NB / 16 per wavefront.
 __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
-  __shared__ double2 As[16][HTD_NB + 1];  // conj(v_i[j]), k-major
+  constexpr int BPW = BT_NB / 16;         // output blocks per wavefront
+  __shared__ double2 As[16][BT_NB + 1];   // conj(v_i[j]), k-major
   __shared__ double2 Bs[16][64 + 1];      // Z[j][c]
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
     return htd_wpart_blocks(n, nc, b);
@@ -1145,16 +1327,16 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
-  const int nb = min(HTD_NB, (n - 1) - k0);
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = BT_NB * b;
+  const int nb = min(BT_NB, (n - 1) - k0);
   const int ct = (nc + 63) / 64, ch = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int rbeg = k0 + 1 + ch * BT_CH, rend = min(n, rbeg + BT_CH);
-  const int lane = tid & 63, wave = tid >> 6, bi = wave >> 1, bj0 = (wave & 1) * 2;
-  CAcc<double> acc[2];
-  acc[0].clear();
-  acc[1].clear();
+  const int lane = tid & 63, wave = tid >> 6;
+  CAcc<double> acc[BPW];
+#pragma unroll
+  for (int q = 0; q < BPW; ++q) acc[q].clear();
   for (int j0 = rbeg; j0 < rend; j0 += 16) {
-    for (int e = tid; e < 16 * HTD_NB; e += 256) {
+    for (int e = tid; e < 16 * BT_NB; e += 256) {
       const int i = e >> 4, kk = e & 15, j = j0 + kk;
       double2 v = make_double2(0.0, 0.0);
       if (i < nb && j < rend) v = refl(d, k0 + i, j);
@@ -1168,27 +1350,30 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
-      const double2 a = As[kr][bi * 16 + cl];
-      const double2 b0 = Bs[kr][bj0 * 16 + cl], b1 = Bs[kr][(bj0 + 1) * 16 + cl];
-      acc[0].mac(a.x, a.y, b0.x, b0.y);
-      acc[1].mac(a.x, a.y, b1.x, b1.y);
+#pragma unroll
+      for (int q = 0; q < BPW; ++q) {
+        const int blk = wave * BPW + q, bi = blk >> 2, bj = blk & 3;
+        const double2 a = As[kr][bi * 16 + cl], bb = Bs[kr][bj * 16 + cl];
+        acc[q].mac(a.x, a.y, bb.x, bb.y);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < BPW; ++q) {
+    const int blk = wave * BPW + q, bi = blk >> 2, bj = blk & 3;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = bi * 16 + Mfma<double>::row(lane, r);
-      const int c = c0 + (bj0 + q) * 16 + (lane & 15);
-      if (c < nc) d.Wp[((int64_t)ch * HTD_NB + i) * ld + c] = make_double2(acc[q].re[r], acc[q].im[r]);
+      const int c = c0 + bj * 16 + (lane & 15);
+      if (c < nc) d.Wp[((int64_t)ch * BT_NB + i) * ld + c] = make_double2(acc[q].re[r], acc[q].im[r]);
     }
+  }
 }
 
 // W = T (sum of the partials) for 64 columns
 __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
-  __shared__ double2 Ws[HTD_NB][64];
-  __shared__ double2 Ts[HTD_NB][HTD_NB];
+  __shared__ double2 Ws[BT_NB][64];
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
     return htd_wred_blocks(n, nc, b);
   });
@@ -1197,27 +1382,26 @@ __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict_
   if (skipped(d)) return;
   const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, c0 = lc.b * 64;
   const int nch = (htd_bt_rows(n, b) + BT_CH - 1) / BT_CH;
-  const double2* Tb = d.T + (int64_t)b * HTD_NB * HTD_NB;
-  for (int e = tid; e < HTD_NB * HTD_NB; e += 256) Ts[e / HTD_NB][e % HTD_NB] = Tb[e];
-  for (int e = tid; e < HTD_NB * 64; e += 256) {
+  const double2* Tb = d.T + (int64_t)b * BT_NB * BT_NB;  // row i is uniform per wavefront
+  for (int e = tid; e < BT_NB * 64; e += 256) {
     const int i = e >> 6, c = e & 63;
     double2 s = make_double2(0.0, 0.0);
     if (c0 + c < nc)
-      for (int ch = 0; ch < nch; ++ch) s = cadd(s, d.Wp[((int64_t)ch * HTD_NB + i) * ld + c0 + c]);
+      for (int ch = 0; ch < nch; ++ch) s = cadd(s, d.Wp[((int64_t)ch * BT_NB + i) * ld + c0 + c]);
     Ws[i][c] = s;
   }
   __syncthreads();
-  for (int e = tid; e < HTD_NB * 64; e += 256) {
+  for (int e = tid; e < BT_NB * 64; e += 256) {
     const int i = e >> 6, c = e & 63;
     if (c0 + c >= nc) continue;
     double2 s = make_double2(0.0, 0.0);
-    for (int l = i; l < HTD_NB; ++l) s = cadd(s, cmul(Ts[i][l], Ws[l][c]));
+    for (int l = i; l < BT_NB; ++l) s = cadd(s, cmul(Tb[i * BT_NB + l], Ws[l][c]));
     d.W[(int64_t)i * ld + c0 + c] = s;
   }
 }
 
 // Z[j][c] -= sum_i v_i[j] W[i][c] on 64 x 64 tiles of rows k0 + 1 ...; each
-// wavefront owns a 32 x 32 quadrant (2 x 2 blocks of 16 x 16), K = HTD_NB.
+// wavefront owns a 32 x 32 quadrant (2 x 2 blocks of 16 x 16), K = BT_NB.
 __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
   __shared__ double2 As[16][64 + 1];  // v_i[j], k-major
   __shared__ double2 Bs[16][64 + 1];  // W[i][c]
@@ -1227,8 +1411,8 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = HTD_NB * b;
-  const int nb = min(HTD_NB, (n - 1) - k0);
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, k0 = BT_NB * b;
+  const int nb = min(BT_NB, (n - 1) - k0);
   const int ct = (nc + 63) / 64, rt = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int j0 = k0 + 1 + rt * 64;
   const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
@@ -1237,7 +1421,7 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y].clear();
-  for (int i0 = 0; i0 < HTD_NB; i0 += 16) {
+  for (int i0 = 0; i0 < BT_NB; i0 += 16) {
     for (int e = tid; e < 16 * 64; e += 256) {
       const int ii = e >> 6, x = e & 63;
       const int i = i0 + ii, j = j0 + x;
@@ -1279,6 +1463,11 @@ hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   launch(trd_hemv_kernel, dim3(blocks), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
+hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) {
+  if (sz.np <= 0) return hipSuccess;
+  launch(trd_tail_kernel, dim3(sz.np), dim3(512), 0, s, d, sz);
+  return hipGetLastError();
+}
 hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   launch(trd_col_kernel, dim3(blocks), dim3(256), 0, s, a, k);
@@ -1316,7 +1505,7 @@ hipError_t launch_dc_wave(int stage, const HtdDesc* d, const HtdSizes& sz, int L
 }
 hipError_t launch_dc_place(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  launch(dc_place_kernel, dim3(blocks), dim3(1024), 0, s, d, sz, L);
+  launch(dc_place_kernel, dim3(blocks), dim3(256), 0, s, d, sz, L);
   return hipGetLastError();
 }
 hipError_t launch_dc_gemm(const HtdDesc* d, const HtdSizes& sz, int L, int blocks, hipStream_t s) {

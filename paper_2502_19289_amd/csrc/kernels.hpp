@@ -103,6 +103,7 @@ constexpr int HV_ROWS = 4;     // trailing-matrix rows per HEMV workgroup (one p
 constexpr int HTD_KP = 2 + 2 * HTD_NB;  // per trd_col workgroup: (max, sum of squares), V^H x, W^H x
 constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (8 per wavefront)
 constexpr int BT_CH = 256;     // rows per split-K chunk of the back-transformation
+constexpr int BT_NB = 32;      // reflectors per block of the back-transformation
 
 struct HtdDesc {
   double2* A;       // n x n Hermitian (ld); row k keeps reflector v_k (cols > k)
@@ -143,24 +144,32 @@ struct HtdDesc {
   int* cnt;         // 4 ints per node: non-deflated, deflated, rotations, merged
   double* rho;      // per node: rank-one weight
   // back-transformation
-  double2* T;       // per block of HTD_NB reflectors: HTD_NB x HTD_NB upper triangle
-  double2* Wp;      // split-K partials: ceil(ld / BT_CH) x HTD_NB x ld
-  double2* W;       // T (V_b^H Z): HTD_NB x ld
+  double2* T;       // per block of BT_NB reflectors: BT_NB x BT_NB upper triangle
+  double2* Wp;      // split-K partials: ceil(ld / BT_CH) x BT_NB x ld
+  double2* W;       // T (V_b^H Z): BT_NB x ld
 };
+
+// The columns from htd_tail_start(n) on (a panel boundary where the trailing
+// size is at most HTD_TAIL) are reduced by trd_tail in one workgroup per
+// problem; the blocked kernels stop there.
+constexpr int HTD_TAIL = 128;
+__host__ __device__ inline int htd_tail_start(int n) {
+  return n <= HTD_TAIL ? 0 : ((n - HTD_TAIL + HTD_NB - 1) / HTD_NB) * HTD_NB;
+}
 
 // Per-problem workgroup counts of the launches (identical on host and device).
 __host__ __device__ inline int htd_hemv_blocks(int n, int k) {
   const int m = n - k - 1;
-  return m > 0 ? (m + HV_ROWS - 1) / HV_ROWS : 0;
+  return m > 0 && k < htd_tail_start(n) ? (m + HV_ROWS - 1) / HV_ROWS : 0;
 }
 __host__ __device__ inline int htd_col_blocks(int n, int k) {
   const int m = n - k - 1;
-  return m > 0 ? (m + KC_ROWS - 1) / KC_ROWS : 0;
+  return m > 0 && k < htd_tail_start(n) ? (m + KC_ROWS - 1) / KC_ROWS : 0;
 }
 // panel starting at column p0: trailing matrix from p0 + min(HTD_NB, n - 1 - p0)
 __host__ __device__ inline int htd_her2k_blocks(int n, int p0) {
   const int nbp = n - 1 - p0 < HTD_NB ? n - 1 - p0 : HTD_NB;
-  if (nbp <= 0) return 0;
+  if (nbp <= 0 || p0 >= htd_tail_start(n)) return 0;
   const int t = (n - p0 - nbp + 63) / 64;
   return t * t;
 }
@@ -168,12 +177,14 @@ __host__ __device__ inline int htd_rows(int n) { return (n + 255) / 256; }
 __host__ __device__ inline int htd_waves(int n) { return (n + 3) / 4; }  // one wavefront per index
 __host__ __device__ inline int htd_tiles64(int n) { return ((n + 63) / 64) * ((n + 63) / 64); }
 __host__ __device__ inline int htd_nodes(int n, int L) { return (n + (1 << L) - 1) >> L; }
+// dc_place: one workgroup per 64 columns of every node
+__host__ __device__ inline int htd_place_blocks(int n, int L) { return htd_nodes(n, L) * (((1 << L) + 63) / 64); }
 __host__ __device__ inline int htd_gemm_tiles(int n, int L) {
   const int t = ((1 << L) + 63) / 64;
   return htd_nodes(n, L) * t * t;
 }
-__host__ __device__ inline int htd_nblk(int n) { return n >= 2 ? (n - 2) / HTD_NB + 1 : 0; }
-__host__ __device__ inline int htd_bt_rows(int n, int b) { return n - HTD_NB * b - 1; }
+__host__ __device__ inline int htd_nblk(int n) { return n >= 2 ? (n - 2) / BT_NB + 1 : 0; }
+__host__ __device__ inline int htd_bt_rows(int n, int b) { return n - BT_NB * b - 1; }
 // nc: eigenvector columns back-transformed, min(n, rcap)
 __host__ __device__ inline int htd_wpart_blocks(int n, int nc, int b) {
   return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((nc + 63) / 64) : 0;
@@ -228,9 +239,9 @@ __host__ __device__ inline void htd_layout(size_t ld, HtdDesc& h, F take) {
   h.pos_nd = (int*)take(ni);
   h.cnt = (int*)take(4 * ni);
   h.rho = (double*)take(nd);
-  h.T = (double2*)take((ld / HTD_NB + 1) * HTD_NB * HTD_NB * sizeof(double2));
-  h.Wp = (double2*)take(((ld + BT_CH - 1) / BT_CH) * HTD_NB * nc);
-  h.W = (double2*)take(HTD_NB * nc);
+  h.T = (double2*)take((ld / BT_NB + 1) * BT_NB * BT_NB * sizeof(double2));
+  h.Wp = (double2*)take(((ld + BT_CH - 1) / BT_CH) * BT_NB * nc);
+  h.W = (double2*)take(BT_NB * nc);
 }
 
 // The problems of one launch of the column update and the HEMV, passed by
@@ -238,29 +249,36 @@ __host__ __device__ inline void htd_layout(size_t ld, HtdDesc& h, F take) {
 // and the skip flag of each problem, the kernels reach every buffer without
 // a dependent load of a descriptor (the launch-to-data latency of these short
 // kernels is most of their run time).
+// Kernel arguments live in memory that the scalar cache misses on every
+// launch, so each problem's fields share one 32-byte record (one 64-byte
+// line), and the sizes the workgroups search first share the line of np.
+struct alignas(32) HtdProb {
+  double2* A;
+  char* ws;
+  const int* skip;
+  int n, ld;
+};
 struct HtdArgs {
+  HtdProb pr[HTD_GROUP];
   int np;
   int n[HTD_GROUP];
-  int ld[HTD_GROUP];
-  double2* A[HTD_GROUP];
-  char* ws[HTD_GROUP];
-  const int* skip[HTD_GROUP];
 };
 
 // The buffers of problem p of `a`, laid out as htd_layout takes them.
 __host__ __device__ inline HtdDesc htd_view(const HtdArgs& a, int p) {
+  const HtdProb q = a.pr[p];
   HtdDesc h{};
-  char* base = a.ws[p];
+  char* base = q.ws;
   size_t off = 0;
-  htd_layout((size_t)a.ld[p], h, [&](size_t x) -> void* {
+  htd_layout((size_t)q.ld, h, [&](size_t x) -> void* {
     off = (off + 255) & ~size_t(255);
-    void* q = base + off;
+    void* r = base + off;
     off += x;
-    return q;
+    return r;
   });
-  h.A = a.A[p];
-  h.ld = a.ld[p];
-  h.skip = a.skip[p];
+  h.A = q.A;
+  h.ld = q.ld;
+  h.skip = q.skip;
   return h;
 }
 
@@ -268,6 +286,7 @@ __host__ __device__ inline HtdDesc htd_view(const HtdArgs& a, int p) {
 // `blocks` is the sum of the per-problem counts above for the given step /
 // level / block
 hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s);
+hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s);
 hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s);
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s);
 hipError_t launch_trd_finish(const HtdDesc* d, const HtdSizes& sz, hipStream_t s);

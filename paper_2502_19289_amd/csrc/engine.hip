@@ -602,9 +602,14 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
   for (int p0 = 0; p0 < kmain; p0 += HTD_NB) {
     for (int j = 0; j < HTD_NB; ++j) {
       const int k = p0 + j;
-      const int nb_col = total([k](int n) { return htd_col_blocks(n, k); });
+      auto most = [&](auto f) {
+        int t = 0;
+        for (int p = 0; p < np; ++p) t = std::max(t, f(sz.n[p]));
+        return t;
+      };
+      const int nb_col = most([k](int n) { return htd_col_blocks(n, k); });
       timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
-      const int nb_hemv = total([k](int n) { return htd_hemv_blocks(n, k); });
+      const int nb_hemv = most([k](int n) { return htd_hemv_blocks(n, k); });
       const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(ha, k, nb_hemv, s); });
       if (counted)  // algorithmic traffic of the HEMV: the trailing block read once
         for (int p = 0; p < np; ++p) {

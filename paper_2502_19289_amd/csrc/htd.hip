@@ -184,11 +184,13 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   __shared__ double2 kv[2 * HTD_NB];  // row k: w_k (V lanes), v_k (W lanes)
   __shared__ double2 psum[4];
   __shared__ double nrm[4][2];
-  const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_col_blocks(n, k); });
-  if (lc.p < 0) return;
+  // problem blockIdx.y: its record is the only argument line read before the data
+  const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
+  const int n = sz.pr[lc.p].n;
+  if (lc.b >= htd_col_blocks(n, k)) return;
   const HtdDesc d = htd_view(sz, lc.p);
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, tid = threadIdx.x;
+  const int m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
   const int c = tid & 63, wv = tid >> 6;
   const int u = c & (HTD_NB - 1);
@@ -321,11 +323,13 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   __shared__ double2 wred[4];
   __shared__ double2 hsum[4][2 * HTD_NB];
   __shared__ double sh2[2];
-  const Loc lc = locate(sz, blockIdx.x, [k](int n) { return htd_hemv_blocks(n, k); });
-  if (lc.p < 0) return;
+  // problem blockIdx.y: its record is the only argument line read before the data
+  const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
+  const int n = sz.pr[lc.p].n;
+  if (lc.b >= htd_hemv_blocks(n, k)) return;
   const HtdDesc d = htd_view(sz, lc.p);
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], m = n - k - 1, ld = d.ld, tid = threadIdx.x;
+  const int m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
   const int wave = tid >> 6, lane = tid & 63;
   const int i0 = lc.b * HV_ROWS + wave;
@@ -1460,7 +1464,7 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
 
 hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  launch(trd_hemv_kernel, dim3(blocks), dim3(256), 0, s, a, k);
+  launch(trd_hemv_kernel, dim3(blocks, a.np), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
 hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) {
@@ -1470,7 +1474,7 @@ hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) 
 }
 hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  launch(trd_col_kernel, dim3(blocks), dim3(256), 0, s, a, k);
+  launch(trd_col_kernel, dim3(blocks, a.np), dim3(256), 0, s, a, k);
   return hipGetLastError();
 }
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s) {

@@ -251,7 +251,7 @@ __host__ __device__ inline void htd_layout(size_t ld, HtdDesc& h, F take) {
 // kernels is most of their run time).
 // Kernel arguments live in memory that the scalar cache misses on every
 // launch, so each problem's fields share one 32-byte record (one 64-byte
-// line), and the sizes the workgroups search first share the line of np.
+// line); the launches index the problems by blockIdx.y.
 struct alignas(32) HtdProb {
   double2* A;
   char* ws;
@@ -282,9 +282,9 @@ __host__ __device__ inline HtdDesc htd_view(const HtdArgs& a, int p) {
   return h;
 }
 
-// launches over the problems of sz (descriptors in device memory) or of a;
-// `blocks` is the sum of the per-problem counts above for the given step /
-// level / block
+// launches over the problems of sz (descriptors in device memory; `blocks` is
+// the sum of the per-problem counts above for the given step / level / block)
+// or of a (grid blocks x a.np, `blocks` the largest per-problem count)
 hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s);
 hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s);
 hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s);

@@ -439,22 +439,23 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     const double2 g0 = make_double2(__shfl(p[0].x, 0), __shfl(p[0].y, 0));  // G[r][0] (v_0 = 1)
     y0 = cmul(tau, csub(cadd(g0, g), h));
   }
+  // every wavefront stores its row's y, its reflector entry (panel column j
+  // and row k of A) and the sum of conj(y_i) v_i of the workgroup
   double2 part = make_double2(0.0, 0.0);
   if (row) {
-    if (lane == 0) d.PY[k + 1 + i0] = y0;
     const double2 vi = i0 == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[i0], scale));
     part = cmulc(y0, vi);
+    if (lane == 0) {
+      d.PY[k + 1 + i0] = y0;
+      d.PV[(int64_t)(k + 1 + i0) * HTD_NB + j] = vi;
+      d.A[(int64_t)k * ld + (k + 1 + i0)] = vi;
+    }
   }
   if (lane == 0) wred[wave] = part;
   __syncthreads();
-  if (tid == 0) d.part[lc.b] = cadd(cadd(wred[0], wred[1]), cadd(wred[2], wred[3]));
-  if (lc.b == 0) {
-    for (int jj = tid; jj < m; jj += 256) {
-      const double2 v = jj == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[jj], scale));
-      d.PV[(int64_t)(k + 1 + jj) * HTD_NB + j] = v;
-      d.A[(int64_t)k * ld + (k + 1 + jj)] = v;
-    }
-    if (tid == 0) {
+  if (tid == 0) {
+    d.part[lc.b] = cadd(cadd(wred[0], wred[1]), cadd(wred[2], wred[3]));
+    if (lc.b == 0) {
       d.tau[k] = tau;
       d.e[k] = beta;
     }

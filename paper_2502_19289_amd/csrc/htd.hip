@@ -1376,28 +1376,31 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
   }
 }
 
-// W = T (sum of the partials) for 64 columns
+// W = T (sum of the partials) for BT_WC columns per workgroup
 __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
-  __shared__ double2 Ws[BT_NB][64];
+  __shared__ double2 Ws[BT_NB][BT_WC];
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
     return htd_wred_blocks(n, nc, b);
   });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
   if (skipped(d)) return;
-  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, c0 = lc.b * 64;
+  const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, c0 = lc.b * BT_WC;
   const int nch = (htd_bt_rows(n, b) + BT_CH - 1) / BT_CH;
-  const double2* Tb = d.T + (int64_t)b * BT_NB * BT_NB;  // row i is uniform per wavefront
-  for (int e = tid; e < BT_NB * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
+  const double2* Tb = d.T + (int64_t)b * BT_NB * BT_NB;
+  for (int e = tid; e < BT_NB * BT_WC; e += 256) {
+    const int i = e / BT_WC, c = e % BT_WC;
     double2 s = make_double2(0.0, 0.0);
-    if (c0 + c < nc)
-      for (int ch = 0; ch < nch; ++ch) s = cadd(s, d.Wp[((int64_t)ch * BT_NB + i) * ld + c0 + c]);
+    if (c0 + c < nc) {
+      const double2* w = d.Wp + (int64_t)i * ld + c0 + c;
+#pragma unroll 8
+      for (int ch = 0; ch < nch; ++ch) s = cadd(s, w[(int64_t)ch * BT_NB * ld]);
+    }
     Ws[i][c] = s;
   }
   __syncthreads();
-  for (int e = tid; e < BT_NB * 64; e += 256) {
-    const int i = e >> 6, c = e & 63;
+  for (int e = tid; e < BT_NB * BT_WC; e += 256) {
+    const int i = e / BT_WC, c = e % BT_WC;
     if (c0 + c >= nc) continue;
     double2 s = make_double2(0.0, 0.0);
     for (int l = i; l < BT_NB; ++l) s = cadd(s, cmul(Tb[i * BT_NB + l], Ws[l][c]));

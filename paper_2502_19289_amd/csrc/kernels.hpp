@@ -102,7 +102,7 @@ constexpr int HTD_NB = 32;     // reflectors per back-transformation block
 constexpr int HV_ROWS = 4;     // trailing-matrix rows per HEMV workgroup (one per wavefront)
 constexpr int HTD_KP = 2 + 2 * HTD_NB;  // per trd_col workgroup: (max, sum of squares), V^H x, W^H x
 constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (8 per wavefront)
-constexpr int BT_CH = 256;     // rows per split-K chunk of the back-transformation
+constexpr int BT_CH = 64;      // rows per split-K chunk of the back-transformation
 constexpr int BT_NB = 32;      // reflectors per block of the back-transformation
 
 struct HtdDesc {
@@ -189,7 +189,10 @@ __host__ __device__ inline int htd_bt_rows(int n, int b) { return n - BT_NB * b 
 __host__ __device__ inline int htd_wpart_blocks(int n, int nc, int b) {
   return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((nc + 63) / 64) : 0;
 }
-__host__ __device__ inline int htd_wred_blocks(int n, int nc, int b) { return b < htd_nblk(n) ? (nc + 63) / 64 : 0; }
+constexpr int BT_WC = 16;  // columns of W per reduction workgroup
+__host__ __device__ inline int htd_wred_blocks(int n, int nc, int b) {
+  return b < htd_nblk(n) ? (nc + BT_WC - 1) / BT_WC : 0;
+}
 __host__ __device__ inline int htd_update_blocks(int n, int nc, int b) {
   return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + 63) / 64) * ((nc + 63) / 64) : 0;
 }

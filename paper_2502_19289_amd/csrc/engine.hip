@@ -596,6 +596,11 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     std::fprintf(stderr, "htd np=%d nmax=%d %s: host enqueue %.2f ms, done %.2f ms\n", np, nmax, what, host, all);
     t0 = std::chrono::steady_clock::now();
   };
+  if (trace) {
+    std::fprintf(stderr, "htd sizes:");
+    for (int p = 0; p < np; ++p) std::fprintf(stderr, " %d", sz.n[p]);
+    std::fprintf(stderr, "\n");
+  }
   lap("start");
   int kmain = 0;  // the blocked kernels run the columns below htd_tail_start(n)
   for (int p = 0; p < np; ++p) kmain = std::max(kmain, htd_tail_start(sz.n[p]));

@@ -172,6 +172,45 @@ def test_step_local_cluster_vs_oracle(prec, n, chi, a, k, seed, eig):
     assert infid(m.sites(), ref.B) < INF_TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_cluster_vs_oracle(prec):
+    """Step-local parity at chi_max = 1024 (the benchmark's cap): a 22-qubit
+    state evolved on the GPU (a brickwork of Haar 4-qubit clusters) until its
+    middle bonds hold 1024 Schmidt values, so that its Lambda are the state's
+    own Schmidt values (random canonical sites with unrelated Lambda would make
+    the weighted splits discard directions that carry weight), then one k = 4 cluster
+    whose splits are the 2048 x 2048 Gram matrices of the timed workload's
+    largest SVDs, solved by the tridiagonal route.  The oracle (LAPACK SVDs)
+    applies the same cluster to the same exported state; the discarded weight,
+    the spectra and the state are compared."""
+    n, chi, a, k = 22, 1024, 8, 4
+    m0 = P.MPS(n, chi, 1e-10, k_max=4, precision="fp64")
+    sd = 0
+    for layer in range(7):  # brickwork of Haar 4-qubit clusters
+        for q in range(0 if layer % 2 == 0 else 2, n - 3, 4):
+            m0.apply_cluster(list(range(q, q + 4)), haar_unitary(16, seed=1000 + sd))
+            sd += 1
+    dims = m0.bond_dims()
+    assert dims[a - 1] == 256 and dims[a + k - 1] == chi  # saturated around the cluster
+    B = m0.sites()
+    lam = [m0.schmidt(b) for b in range(n - 1)]
+    U = haar_unitary(2 ** k, seed=11)
+    m = P.MPS(n, chi, 1e-10, k_max=6, precision=prec, eig="auto")
+    m.import_state(B, lam)
+    m.apply_cluster(list(range(a, a + k)), U)
+    ref = CT.MPS([b.copy() for b in B], [l.copy() for l in lam])
+    CT.apply_cluster(ref, a, k, U, chi, 1e-10)
+    assert ref.records[0].full == 2048  # the first split: a 2048 x 2048 SVD
+    F, lf = m.fidelity()
+    assert abs(lf - ref.log_f) < (1e-10 if prec == "fp64" else 1e-6)
+    for b in range(a, a + k - 1):
+        got = m.schmidt(b)
+        exp = ref.lam[b]
+        r = min(got.size, exp.size)
+        assert np.abs(got[:r] - exp[:r]).max() < (1e-9 if prec == "fp64" else 1e-5)
+    assert infid(m.sites(), ref.B) < INF_TOL[prec]
+
+
 def test_batched_equals_unbatched_bitwise():
     c, p = make_workload("clifford_n100_l20", seed=1, layers=8)
     m1 = gpu_run(c, "fp32", batch="step", **p)

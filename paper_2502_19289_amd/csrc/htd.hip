@@ -90,6 +90,13 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 // Wavefront maximum on the same DPP paths as wave_sum.
+// lane 0's value in every lane
+__device__ __forceinline__ double lane0(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_take<0xb1, 0xf>(v));
   v = fmax(v, dpp_take<0x4e, 0xf>(v));
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   double2 rk = make_double2(0.0, 0.0), rkv = make_double2(0.0, 0.0);
   if (live) rk = isv ? (vfin ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + u]) : d.PV[(int64_t)k * HTD_NB + u];
   if (vfin) rkv = d.PV[(int64_t)k * HTD_NB + u];
-  const double akk = lc.b == 0 && tid == 0 ? d.A[(int64_t)k * ld + k].x : 0.0;
+  const double akk = lc.b == 0 && tid == 64 ? d.A[(int64_t)k * ld + k].x : 0.0;
   double2 a[RPW], pv[RPW], pf[RPW];
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
@@ -280,10 +287,11 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   }
   double ss = 0.0;
   if (amax > 0.0) {
+    const double inv = 1.0 / amax;
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
       const int i = lc.b * KC_ROWS + wv + 4 * q;
-      if (i > 0 && i < m) ss += (x[q].x / amax) * (x[q].x / amax) + (x[q].y / amax) * (x[q].y / amax);
+      if (i > 0 && i < m) ss += (x[q].x * inv) * (x[q].x * inv) + (x[q].y * inv) * (x[q].y * inv);
     }
   }
   dsum[wv][c] = acc;
@@ -304,10 +312,11 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
       rec[0] = make_double2(mx, tot);
     }
   }
-  if (lc.b == 0 && tid == 0) {
-    double dk = akk;
-    for (int q = 0; q < j; ++q) dk -= 2.0 * (kv[HTD_NB + q].x * kv[q].x + kv[HTD_NB + q].y * kv[q].y);
-    d.d[k] = dk;
+  if (lc.b == 0 && wv == 1) {  // d_k = G[k][k] - 2 sum_q Re(conj(v_k[q]) w_k[q])
+    double t = 0.0;
+    if (c < j) t = kv[HTD_NB + c].x * kv[c].x + kv[HTD_NB + c].y * kv[c].y;
+    t = wave_sum(t);
+    if (c == 0) d.d[k] = akk - 2.0 * t;
   }
 }
 
@@ -402,6 +411,23 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     }
   }
   __syncthreads();
+  // G[r][1:] x[1:] does not depend on the reflector: formed first, so that its
+  // sums overlap the reflector's arithmetic
+  double2 gx = make_double2(0.0, 0.0), g0 = make_double2(0.0, 0.0);
+  if (row) {
+    double rx = 0.0, ry = 0.0;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int c = lane + 64 * u;
+      if (c < m && c > 0) {
+        const double2 v = xs[c];
+        rx += p[u].x * v.x - p[u].y * v.y;
+        ry += p[u].x * v.y + p[u].y * v.x;
+      }
+    }
+    gx = make_double2(wave_sum(rx), wave_sum(ry));
+    g0 = make_double2(lane0(p[0].x), lane0(p[0].y));  // G[r][0] (v_0 = 1)
+  }
   const double smax = sh2[0], ssq = sh2[1];
   double2 sv = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
   if (tid < j) {
@@ -422,22 +448,10 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
 
   double2 y0 = make_double2(0.0, 0.0);
   if (!ident && row) {
-    double rx = 0.0, ry = 0.0;  // G[r][1:] x[1:]
-#pragma unroll
-    for (int u = 0; u < PL; ++u) {
-      const int c = lane + 64 * u;
-      if (c < m && c > 0) {
-        const double2 v = xs[c];
-        rx += p[u].x * v.x - p[u].y * v.y;
-        ry += p[u].x * v.y + p[u].y * v.x;
-      }
-    }
     // panel term: lane l < 32 gives V[r][l] (W^H v)_l, lane 32 + l W[r][l] (V^H v)_l
     const double2 c0 = l < j ? cmul(pe, isv ? whv[l] : vhv[l]) : make_double2(0.0, 0.0);
-    const double2 g = cmul(scale, make_double2(wave_sum(rx), wave_sum(ry)));
     const double2 h = make_double2(wave_sum(c0.x), wave_sum(c0.y));
-    const double2 g0 = make_double2(__shfl(p[0].x, 0), __shfl(p[0].y, 0));  // G[r][0] (v_0 = 1)
-    y0 = cmul(tau, csub(cadd(g0, g), h));
+    y0 = cmul(tau, csub(cadd(g0, cmul(scale, gx)), h));
   }
   // every wavefront stores its row's y, its reflector entry (panel column j
   // and row k of A) and the sum of conj(y_i) v_i of the workgroup

@@ -388,9 +388,9 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     p[u] = row && c < m ? a0[c] : make_double2(0.0, 0.0);
   }
 #pragma unroll
-  for (int u = 0; u < XL; ++u) {
+  for (int u = 0; u < XL; ++u) {  // zero past m: the product below reads all of xs
     const int jj = tid + 256 * u;
-    if (jj < m) xs[jj] = xv[u];
+    xs[jj] = jj < m ? xv[u] : make_double2(0.0, 0.0);
   }
   {
     double2 t = make_double2(0.0, 0.0);
@@ -415,15 +415,15 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   // sums overlap the reflector's arithmetic
   double2 gx = make_double2(0.0, 0.0), g0 = make_double2(0.0, 0.0);
   if (row) {
+    // branch-free (p is zero past m, and so is xs): a guarded LDS read per
+    // entry would be waited for one at a time
     double rx = 0.0, ry = 0.0;
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
-      const int c = lane + 64 * u;
-      if (c < m && c > 0) {
-        const double2 v = xs[c];
-        rx += p[u].x * v.x - p[u].y * v.y;
-        ry += p[u].x * v.y + p[u].y * v.x;
-      }
+      const double2 v = xs[lane + 64 * u];
+      const double2 q = u == 0 && lane == 0 ? make_double2(0.0, 0.0) : p[u];  // x[0] is alpha
+      rx += q.x * v.x - q.y * v.y;
+      ry += q.x * v.y + q.y * v.x;
     }
     gx = make_double2(wave_sum(rx), wave_sum(ry));
     g0 = make_double2(lane0(p[0].x), lane0(p[0].y));  // G[r][0] (v_0 = 1)

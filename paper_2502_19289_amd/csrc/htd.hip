@@ -89,6 +89,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// N wavefront sums at once, stage by stage, so that the DPP steps of the
+// different values are independent and issue back to back.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0xb1, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0x4e, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0x141, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0x140, 0xf>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0x142, 0xa>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_take<0x143, 0xc>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const long long b = __double_as_longlong(v[i]);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    v[i] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
 // Wavefront maximum on the same DPP paths as wave_sum.
 // lane 0's value in every lane
 __device__ __forceinline__ double lane0(double v) {
@@ -244,8 +268,12 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     sx += okq ? pq[t].x : 0.0;
     sy += okq ? pq[t].y : 0.0;
   }
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
+  {
+    double sp[2] = {sx, sy};
+    wave_sum_n(sp);
+    sx = sp[0];
+    sy = sp[1];
+  }
   if (c == 0) psum[wv] = make_double2(sx, sy);
   __syncthreads();
   double2 al = make_double2(0.0, 0.0);
@@ -267,11 +295,17 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   // x_r = conj(G[k][r]) - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
   // lane c contributes pv conj(rk), lane 0 also conj(G[k][r])
   double2 x[RPW];
+  {
+    double tv[2 * RPW];
 #pragma unroll
-  for (int q = 0; q < RPW; ++q) {
-    double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
-    t = make_double2(a[q].x - t.x, -a[q].y - t.y);
-    x[q] = make_double2(wave_sum(t.x), wave_sum(t.y));
+    for (int q = 0; q < RPW; ++q) {
+      double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
+      tv[2 * q] = a[q].x - t.x;
+      tv[2 * q + 1] = -a[q].y - t.y;
+    }
+    wave_sum_n(tv);
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) x[q] = make_double2(tv[2 * q], tv[2 * q + 1]);
   }
   // the column, the scaled norm of x_1 (rows i > 0) and the dots over them
   double amax = 0.0;
@@ -425,7 +459,9 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
       rx += q.x * v.x - q.y * v.y;
       ry += q.x * v.y + q.y * v.x;
     }
-    gx = make_double2(wave_sum(rx), wave_sum(ry));
+    double sr[2] = {rx, ry};
+    wave_sum_n(sr);
+    gx = make_double2(sr[0], sr[1]);
     g0 = make_double2(lane0(p[0].x), lane0(p[0].y));  // G[r][0] (v_0 = 1)
   }
   const double smax = sh2[0], ssq = sh2[1];
@@ -450,7 +486,9 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   if (!ident && row) {
     // panel term: lane l < 32 gives V[r][l] (W^H v)_l, lane 32 + l W[r][l] (V^H v)_l
     const double2 c0 = l < j ? cmul(pe, isv ? whv[l] : vhv[l]) : make_double2(0.0, 0.0);
-    const double2 h = make_double2(wave_sum(c0.x), wave_sum(c0.y));
+    double sh[2] = {c0.x, c0.y};
+    wave_sum_n(sh);
+    const double2 h = make_double2(sh[0], sh[1]);
     y0 = cmul(tau, csub(cadd(g0, cmul(scale, gx)), h));
   }
   // every wavefront stores its row's y, its reflector entry (panel column j

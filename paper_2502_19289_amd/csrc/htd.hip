@@ -206,15 +206,16 @@ __device__ __forceinline__ void householder(double2 alpha, double smax, double s
 // KC_ROWS rows per 256-thread workgroup.  Lane c of every wavefront owns
 // column c of [V | W] (c < HTD_NB: V[:, c], else W[:, c - HTD_NB]) and the
 // wavefront owns rows wv, wv + 4, ... of the workgroup's rows, so that each
-// load reads whole panel rows.  The column entry of row r is a wavefront sum
-// of the lanes' terms; the dots V^H x, W^H x are per-lane sums over the rows,
-// added over the four wavefronts in LDS.
+// load reads whole panel rows.  The column entry of row r is the sum of the
+// lanes' terms (through LDS); the dots V^H x, W^H x are per-lane sums over the
+// rows, added over the four wavefronts in LDS.
 __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   constexpr int RPW = KC_ROWS / 4;  // rows per wavefront
   __shared__ double2 dsum[4][2 * HTD_NB];
   __shared__ double2 kv[2 * HTD_NB];  // row k: w_k (V lanes), v_k (W lanes)
   __shared__ double2 psum[4];
-  __shared__ double nrm[4][2];
+  __shared__ double2 tx[KC_ROWS][64];  // the terms of x, row by row
+  __shared__ double2 xr[KC_ROWS];
   // problem blockIdx.y: its record is the only argument line read before the data
   const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
   const int n = sz.pr[lc.p].n;
@@ -293,59 +294,55 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     }
   }
   // x_r = conj(G[k][r]) - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
-  // lane c contributes pv conj(rk), lane 0 also conj(G[k][r])
-  double2 x[RPW];
-  {
-    double tv[2 * RPW];
+  // lane c of the row's wavefront contributes pv conj(rk), lane 0 also
+  // conj(G[k][r]).  The sums over the 64 lanes go through LDS (the terms of
+  // the 32 rows, then 8 threads per row with 8 terms each and an 8-lane DPP
+  // sum): far fewer instructions than 16 full wavefront reductions.
 #pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
-      tv[2 * q] = a[q].x - t.x;
-      tv[2 * q + 1] = -a[q].y - t.y;
-    }
-    wave_sum_n(tv);
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) x[q] = make_double2(tv[2 * q], tv[2 * q + 1]);
+  for (int q = 0; q < RPW; ++q) {
+    const double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
+    tx[wv + 4 * q][c] = make_double2(a[q].x - t.x, -a[q].y - t.y);
   }
-  // the column, the scaled norm of x_1 (rows i > 0) and the dots over them
-  double amax = 0.0;
+  __syncthreads();
+  {
+    const int wr = tid >> 3, part = tid & 7;
+    double2 sxy = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sxy = cadd(sxy, tx[wr][part * 8 + e]);
+    sxy.x += dpp_take<0xb1, 0xf>(sxy.x);
+    sxy.y += dpp_take<0xb1, 0xf>(sxy.y);
+    sxy.x += dpp_take<0x4e, 0xf>(sxy.x);
+    sxy.y += dpp_take<0x4e, 0xf>(sxy.y);
+    sxy.x += dpp_take<0x141, 0xf>(sxy.x);
+    sxy.y += dpp_take<0x141, 0xf>(sxy.y);
+    if (part == 0) xr[wr] = sxy;
+  }
+  __syncthreads();
+  const int i0 = lc.b * KC_ROWS;  // row tid of the workgroup is row i0 + tid of the column
+  if (tid < KC_ROWS && i0 + tid < m) d.xb[i0 + tid] = xr[tid];
+  double2* rec = d.kpart + (int64_t)lc.b * HTD_KP;
+  if (wv == 0) {  // scaled norm of x_1 (rows i > 0) over the workgroup's rows
+    const int i = i0 + c;
+    const double2 xv = c < KC_ROWS && i > 0 && i < m ? xr[c] : make_double2(0.0, 0.0);
+    const double amax = wave_max(fmax(fabs(xv.x), fabs(xv.y)));
+    double ss = 0.0;
+    if (amax > 0.0) {
+      const double inv = 1.0 / amax;
+      ss = (xv.x * inv) * (xv.x * inv) + (xv.y * inv) * (xv.y * inv);
+    }
+    ss = wave_sum(ss);
+    if (c == 0) rec[0] = make_double2(amax, ss);
+  }
+  // the dots V^H x_1, W^H x_1: lane c sums its column over the wavefront's rows
   double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
-    const int i = lc.b * KC_ROWS + wv + 4 * q;
-    if (i < m && c == q) d.xb[i] = x[q];
-    if (i > 0 && i < m) {
-      amax = fmax(amax, fmax(fabs(x[q].x), fabs(x[q].y)));
-      if (live) acc = cadd(acc, cmulc(pv[q], x[q]));
-    }
-  }
-  double ss = 0.0;
-  if (amax > 0.0) {
-    const double inv = 1.0 / amax;
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      const int i = lc.b * KC_ROWS + wv + 4 * q;
-      if (i > 0 && i < m) ss += (x[q].x * inv) * (x[q].x * inv) + (x[q].y * inv) * (x[q].y * inv);
-    }
+    const int i = i0 + wv + 4 * q;
+    if (live && i > 0 && i < m) acc = cadd(acc, cmulc(pv[q], xr[wv + 4 * q]));
   }
   dsum[wv][c] = acc;
-  if (c == 0) {
-    nrm[wv][0] = amax;
-    nrm[wv][1] = ss;
-  }
   __syncthreads();
-  double2* rec = d.kpart + (int64_t)lc.b * HTD_KP;
-  if (wv == 0) {
-    rec[2 + c] = cadd(cadd(dsum[0][c], dsum[1][c]), cadd(dsum[2][c], dsum[3][c]));
-    if (c == 0) {
-      const double mx = fmax(fmax(nrm[0][0], nrm[1][0]), fmax(nrm[2][0], nrm[3][0]));
-      double tot = 0.0;
-      if (mx > 0.0)
-        for (int w = 0; w < 4; ++w)
-          if (nrm[w][0] > 0.0) tot += nrm[w][1] * (nrm[w][0] / mx) * (nrm[w][0] / mx);
-      rec[0] = make_double2(mx, tot);
-    }
-  }
+  if (wv == 0) rec[2 + c] = cadd(cadd(dsum[0][c], dsum[1][c]), cadd(dsum[2][c], dsum[3][c]));
   if (lc.b == 0 && wv == 1) {  // d_k = G[k][k] - 2 sum_q Re(conj(v_k[q]) w_k[q])
     double t = 0.0;
     if (c < j) t = kv[HTD_NB + c].x * kv[c].x + kv[HTD_NB + c].y * kv[c].y;

@@ -783,6 +783,28 @@ __device__ __forceinline__ double block_max(double v, double* red) {
   return r;
 }
 
+// Exclusive prefix, over a 1024-thread workgroup, of two ordered flags per
+// thread (entries 2 tid and 2 tid + 1); *total receives the count of all set
+// flags.  Ballots and bit counts within each wavefront, then the 16
+// wavefront totals through LDS.
+__device__ __forceinline__ int block_prefix2(bool f0, bool f1, int* wsum, int& total) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned long long b0 = __ballot(f0), b1 = __ballot(f1);
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int pre = __popcll(b0 & lt) + __popcll(b1 & lt);
+  if (lane == 0) wsum[w] = __popcll(b0) + __popcll(b1);
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int q = 0; q < 16; ++q) {
+    const int v = wsum[q];
+    if (q < w) base += v;
+    tot += v;
+  }
+  total = tot;
+  __syncthreads();  // wsum is reused by the next call
+  return base + pre;
+}
+
 // Merge of node [lo, hi) at level L (children [lo, mid), [mid, hi)):
 // T_node = diag(Q1, Q2) (diag(D1, D2) + rho z z^T) diag(Q1, Q2)^T with
 // z = (last row of Q1, sign(e) first row of Q2) / sqrt(2), rho = 2 |e_{mid-1}|.
@@ -792,6 +814,8 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   __shared__ double Ds[HTD_MAX];
   __shared__ double zs[HTD_MAX];
   __shared__ int col[HTD_MAX];
+  __shared__ int ndl[HTD_MAX];
+  __shared__ int wsum[16];
   __shared__ double red[16];
   __shared__ int sh_ndef;
   const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_nodes(n, L); });
@@ -853,6 +877,58 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   md = block_max(md, red);
   mz = block_max(mz, red);
   const double tol = 8.0 * EPS53 * fmax(md, mz);
+  // Common case in parallel: the small-z deflations, then the close-pole test
+  // of every pair of consecutive remaining poles on the unmodified values.
+  // When no pair calls for a rotation, the scan below would produce exactly
+  // these lists (the remaining poles in order, the deflated values ascending
+  // with ties by column, so no sort either); otherwise it runs as written.
+  {
+    const bool alldef = rho * mz <= tol;
+    const int t0 = 2 * tid, t1 = t0 + 1;
+    const bool nd0 = t0 < K && !alldef && rho * fabs(zs[t0]) > tol;
+    const bool nd1 = t1 < K && !alldef && rho * fabs(zs[t1]) > tol;
+    int knd = 0;
+    const int p = block_prefix2(nd0, nd1, wsum, knd);
+    if (nd0) ndl[p] = t0;
+    if (nd1) ndl[p + (nd0 ? 1 : 0)] = t1;
+    __syncthreads();
+    bool rot = false;
+    for (int i = tid + 1; i < knd; i += 1024) {
+      const int pj = ndl[i - 1], t = ndl[i];
+      double sn = zs[pj], cs = zs[t];
+      const double tau = hypot(cs, sn), tt = Ds[t] - Ds[pj];
+      cs /= tau;
+      sn = -sn / tau;
+      if (fabs(tt * cs * sn) <= tol) rot = true;
+    }
+    if (!__syncthreads_or(rot)) {
+      for (int i = tid; i < knd; i += 1024) {
+        const int t = ndl[i];
+        d.dl[lo + i] = Ds[t];
+        d.w[lo + i] = zs[t];
+        d.ndcol[lo + i] = col[t];
+      }
+      const bool df0 = t0 < K && !nd0, df1 = t1 < K && !nd1;
+      int kdef = 0;
+      const int q = block_prefix2(df0, df1, wsum, kdef);
+      if (df0) {
+        d.dval[lo + q] = Ds[t0];
+        d.dcol[lo + q] = col[t0];
+      }
+      if (df1) {
+        d.dval[lo + q + (df0 ? 1 : 0)] = Ds[t1];
+        d.dcol[lo + q + (df0 ? 1 : 0)] = col[t1];
+      }
+      if (tid == 0) {
+        cnt[0] = knd;
+        cnt[1] = kdef;
+        cnt[2] = 0;
+        cnt[3] = 1;
+        d.rho[lo] = rho;
+      }
+      return;
+    }
+  }
   if (tid == 0) {
     int K2 = 0, ndef = 0, nrot = 0;
     if (rho * mz <= tol) {

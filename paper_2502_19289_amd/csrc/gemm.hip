@@ -74,72 +74,71 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j].clear();
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- stage A (BM x BK) k-major and B (BK x BN)
+  // The loads of slice k0 + BK are issued before the products of slice k0.
+  // They are unconditional, at addresses clamped into the operands, and
+  // masked when staged (a load guarded by its own branch would be waited for
+  // before the next one is issued).
+  CM ra[4], rb[4];
+  TM wv = (TM)0;
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
     if (MODE == MODE_NN) {
       const int r = tid >> 2, c4 = (tid & 3) * 4;
-      const int gm = m0 + r;
+      const int gm = min(m0 + r, M - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gk = k0 + c4 + i;
-        CM v;
-        v.x = 0;
-        v.y = 0;
-        if (gm < M && gk < kend) v = load_c<CI, TM>(A + (int64_t)gm * lda + gk);
-        As[c4 + i][r] = v;
-      }
+      for (int i = 0; i < 4; ++i) ra[i] = load_c<CI, TM>(A + (int64_t)gm * lda + min(k0 + c4 + i, kend - 1));
       const int kk = tid >> 4, n4 = (tid & 15) * 4;
-      const int gk = k0 + kk;
+      const int gk = min(k0 + kk, kend - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gn = n0 + n4 + i;
-        CM v;
-        v.x = 0;
-        v.y = 0;
-        if (gk < kend && gn < N) v = load_c<CI, TM>(Bm + (int64_t)gk * ldb + gn);
-        Bs[kk][n4 + i] = v;
-      }
-    } else if (MODE == MODE_CN) {
-      // A^H B with A (K x M) and B (K x N) row-major
+      for (int i = 0; i < 4; ++i) rb[i] = load_c<CI, TM>(Bm + (int64_t)gk * ldb + min(n0 + n4 + i, N - 1));
+    } else {
+      // rows gk of A (K x M) and of B (K x N; A itself for a Gram matrix)
       const int kk = tid >> 4, c4 = (tid & 15) * 4;
-      const int gk = k0 + kk;
+      const int gk = min(k0 + kk, kend - 1);
+      const CI* Bk = MODE == MODE_GRAM ? A + (int64_t)gk * lda : Bm + (int64_t)gk * ldb;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + c4 + i, gn = n0 + c4 + i;
-        CM va, vb;
-        va.x = va.y = vb.x = vb.y = 0;
-        if (gk < kend && gm < M) {
-          va = load_c<CI, TM>(A + (int64_t)gk * lda + gm);
-          va.y = -va.y;
-        }
-        if (gk < kend && gn < N) vb = load_c<CI, TM>(Bm + (int64_t)gk * ldb + gn);
-        As[kk][c4 + i] = va;
-        Bs[kk][c4 + i] = vb;
+        ra[i] = load_c<CI, TM>(A + (int64_t)gk * lda + min(m0 + c4 + i, M - 1));
+        rb[i] = load_c<CI, TM>(Bk + min(n0 + c4 + i, N - 1));
       }
+      if (MODE == MODE_GRAM) wv = (TM)d.w[gk >> d.wshift];
+    }
+  };
+  // ---- stage A (BM x BK) k-major and B (BK x BN); zero outside the operands
+  auto stage = [&](int k0) __attribute__((always_inline)) {
+    // (component selects: a select of whole values would take their addresses)
+    auto mask = [](bool in, CM v) {
+      v.x = in ? v.x : (TM)0;
+      v.y = in ? v.y : (TM)0;
+      return v;
+    };
+    if (MODE == MODE_NN) {
+      const int r = tid >> 2, c4 = (tid & 3) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) As[c4 + i][r] = mask(m0 + r < M && k0 + c4 + i < kend, ra[i]);
+      const int kk = tid >> 4, n4 = (tid & 15) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Bs[kk][n4 + i] = mask(k0 + kk < kend && n0 + n4 + i < N, rb[i]);
     } else {
       const int kk = tid >> 4, c4 = (tid & 15) * 4;
-      const int gk = k0 + kk;
-      const TM wk = (gk < kend) ? (TM)d.w[gk >> d.wshift] : (TM)0;
+      const bool kin = k0 + kk < kend;
+      const TM wk = MODE == MODE_GRAM ? (kin ? wv : (TM)0) : (TM)1;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + c4 + i, gn = n0 + c4 + i;
-        CM va, vb;
-        va.x = va.y = vb.x = vb.y = 0;
-        if (gk < kend && gm < M) {
-          va = load_c<CI, TM>(A + (int64_t)gk * lda + gm);
-          va.x *= wk;
-          va.y = -va.y * wk;
-        }
-        if (gk < kend && gn < N) {
-          vb = load_c<CI, TM>(A + (int64_t)gk * lda + gn);
-          vb.x *= wk;
-          vb.y *= wk;
-        }
+        CM va = mask(kin && m0 + c4 + i < M, ra[i]), vb = mask(kin && n0 + c4 + i < N, rb[i]);
+        va.x *= wk;
+        va.y = -va.y * wk;  // conjugated (A^H)
+        vb.x *= wk;
+        vb.y *= wk;
         As[kk][c4 + i] = va;
         Bs[kk][c4 + i] = vb;
       }
     }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    stage(k0);
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;

@@ -512,11 +512,17 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
 }
 
 // End of a panel: G[p1:, p1:] -= V W^H + W V^H (p1 = first column after the
-// panel) as C = [V | W] [W | V]^H with K = 2 HTD_NB, on 64 x 64 tiles; the
-// panel's last w is finalised while staging.
+// panel) as C = [V | W] [W | V]^H with K = 2 HTD_NB, on 64 x 64 tiles, in
+// K slices of 16 staged through LDS.  The loads of slice s + 1 (and, during
+// the last slice, the tile of G) are issued before the products of slice s;
+// all are unconditional at clamped addresses and masked when staged.  The
+// panel's last w, y + alpha v, is formed once per row in LDS.
 __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int p0) {
-  __shared__ double2 As[16][64 + 1];
-  __shared__ double2 Bs[16][64 + 1];
+  constexpr int KS = 16, NS = 2 * HTD_NB / KS, EPT = KS * 64 / 256;
+  static_assert(HTD_MAX / HV_ROWS <= 512, "alpha partials: two per thread");
+  __shared__ double2 As[KS][64 + 1];
+  __shared__ double2 Bs[KS][64 + 1];
+  __shared__ double2 wl[128];  // last w at rows r0.. (0..63) and c0.. (64..127)
   __shared__ double sh[4];
   const Loc lc = locate(sz, blockIdx.x, [p0](int n) { return htd_her2k_blocks(n, p0); });
   if (lc.p < 0) return;
@@ -527,42 +533,72 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
   const int T = (mt + 63) / 64, ti = lc.b / T, tj = lc.b % T;
   const int kl = p1 - 1;
   const int nb = htd_hemv_blocks(n, kl);
-  double sx = 0.0, sy = 0.0;
-  for (int q = tid; q < nb; q += 256) {
-    sx += d.part[q].x;
-    sy += d.part[q].y;
-  }
-  sx = block4_sum(sx, sh);
-  sy = block4_sum(sy, sh);
-  const double2 tl = d.tau[kl];
-  const double2 al = cmul(make_double2(-0.5 * tl.x, -0.5 * tl.y), make_double2(sx, sy));  // finalises the last w
   const int r0 = p1 + ti * 64, c0 = p1 + tj * 64;
   const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  // [V | W] (row r, index l < 2 HTD_NB), w of column nbp-1 finalised
-  auto vw = [&](int r, int l) -> double2 {
-    const bool isv = l < HTD_NB;
-    const int q = isv ? l : l - HTD_NB;
-    if (q >= nbp || r >= n) return make_double2(0.0, 0.0);
-    const double2 v = d.PV[(int64_t)r * HTD_NB + q];
-    if (isv) return v;
-    if (q == nbp - 1) return cadd(d.PY[r], cmul(al, v));
-    return d.PW[(int64_t)r * HTD_NB + q];
+  auto clampr = [n](int r) { return r < n ? r : n - 1; };
+  // entry i of this thread in a slice: row e / KS of the tile, index e % KS
+  double2 sa[EPT], sb[EPT];
+  // slice s: As = [V | W] at rows r0.., Bs = [W | V] at rows c0..
+  auto fetch = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + 256 * i, row = e / KS, l = s * KS + e % KS;
+      const int q = l & (HTD_NB - 1);
+      const int qq = q < nbp ? q : 0;
+      const bool av = l < HTD_NB;
+      sa[i] = (av ? d.PV : d.PW)[(int64_t)clampr(r0 + row) * HTD_NB + qq];
+      sb[i] = (av ? d.PW : d.PV)[(int64_t)clampr(c0 + row) * HTD_NB + qq];
+    }
   };
+  fetch(0);
+  const double2 pa = d.part[tid < nb ? tid : 0], pb = d.part[tid + 256 < nb ? tid + 256 : 0];
+  const double2 tl = d.tau[kl];
+  const int wr = clampr((tid < 64 ? r0 : c0 - 64) + tid);
+  const double2 yl = d.PY[wr], vl = d.PV[(int64_t)wr * HTD_NB + nbp - 1];
+  double sx = (tid < nb ? pa.x : 0.0) + (tid + 256 < nb ? pb.x : 0.0);
+  double sy = (tid < nb ? pa.y : 0.0) + (tid + 256 < nb ? pb.y : 0.0);
+  sx = block4_sum(sx, sh);
+  sy = block4_sum(sy, sh);
+  const double2 al = cmul(make_double2(-0.5 * tl.x, -0.5 * tl.y), make_double2(sx, sy));
+  if (tid < 128) wl[tid] = cadd(yl, cmul(al, vl));
+  __syncthreads();
   CAcc<double> acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y].clear();
-  for (int l0 = 0; l0 < 2 * HTD_NB; l0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int row = e >> 4, kk = e & 15, l = l0 + kk;
-      As[kk][row] = vw(r0 + row, l);
-      const double2 b = vw(c0 + row, l < HTD_NB ? l + HTD_NB : l - HTD_NB);  // [W | V] at column c
+  double2 at[2][2][4];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + 256 * i, row = e / KS, kk = e % KS, l = s * KS + kk;
+      const int q = l & (HTD_NB - 1);
+      const bool av = l < HTD_NB, last = q == nbp - 1;
+      double2 a = (!av && last) ? wl[row] : sa[i];
+      double2 b = (av && last) ? wl[64 + row] : sb[i];
+      a = q < nbp && r0 + row < n ? a : make_double2(0.0, 0.0);
+      b = q < nbp && c0 + row < n ? b : make_double2(0.0, 0.0);
+      As[kk][row] = a;
       Bs[kk][row] = make_double2(b.x, -b.y);
     }
     __syncthreads();
+    if (s + 1 < NS) {
+      fetch(s + 1);
+    } else {
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
+            const int c = c0 + wn * 32 + y * 16 + (lane & 15);
+            at[x][y][q] = d.A[(int64_t)clampr(r) * ld + clampr(c)];
+          }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
       const double2 a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
       const double2 b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
@@ -581,10 +617,8 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
       for (int q = 0; q < 4; ++q) {
         const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
-        if (r < n && c < n) {
-          double2* p = d.A + (int64_t)r * ld + c;
-          *p = make_double2(p->x - acc[x][y].re[q], p->y - acc[x][y].im[q]);
-        }
+        if (r < n && c < n)
+          d.A[(int64_t)r * ld + c] = make_double2(at[x][y][q].x - acc[x][y].re[q], at[x][y][q].y - acc[x][y].im[q]);
       }
 }
 

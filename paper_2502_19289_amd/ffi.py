@@ -59,12 +59,26 @@ N_FEAT = 12
 _lib = None
 
 
+def _start_torch_hip() -> None:
+    """PyTorch's ROCm wheel carries its own HIP runtime.  Once this library's
+    runtime has started in a process, torch no longer finds a GPU there, so
+    where torch is installed its runtime is started first (the other order
+    works)."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load(path: str = LIB_PATH) -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2502_19289_amd.build`")
+    _start_torch_hip()
     lib = C.CDLL(path)
     P, I, D = C.c_void_p, C.c_int, C.c_double
     lib.mps_default_options.argtypes = [C.POINTER(Options)]

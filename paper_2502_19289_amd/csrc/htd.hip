@@ -1480,9 +1480,13 @@ __global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict
 
 // partial W = V_b^H Z over a chunk of BT_CH rows (rows from k0 + 1) and 64
 // eigenvector columns, on the matrix cores: the BT_NB x 64 output is
-// (BT_NB / 16) x 4 blocks of 16 x 16, BT_NB / 16 per wavefront.
+// (BT_NB / 16) x 4 blocks of 16 x 16, BT_NB / 16 per wavefront.  The chunk
+// goes through LDS in slices of 16 rows; the loads of slice s + 1 are issued
+// before the products of slice s, unconditionally at clamped addresses and
+// masked when staged.
 __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
   constexpr int BPW = BT_NB / 16;         // output blocks per wavefront
+  constexpr int EA = 16 * BT_NB / 256, EB = 16 * 64 / 256;
   __shared__ double2 As[16][BT_NB + 1];   // conj(v_i[j]), k-major
   __shared__ double2 Bs[16][64 + 1];      // Z[j][c]
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
@@ -1496,21 +1500,38 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
   const int ct = (nc + 63) / 64, ch = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int rbeg = k0 + 1 + ch * BT_CH, rend = min(n, rbeg + BT_CH);
   const int lane = tid & 63, wave = tid >> 6;
+  double2 ra[EA], rb[EB];
+  auto fetch = [&](int j0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + 256 * u, i = e >> 4, j = j0 + (e & 15);
+      ra[u] = d.A[(int64_t)(k0 + min(i, nb - 1)) * ld + min(j, rend - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * u, j = j0 + (e >> 6), c = e & 63;
+      rb[u] = d.V[(int64_t)min(j, rend - 1) * ld + min(c0 + c, nc - 1)];
+    }
+  };
   CAcc<double> acc[BPW];
 #pragma unroll
   for (int q = 0; q < BPW; ++q) acc[q].clear();
+  fetch(rbeg);
   for (int j0 = rbeg; j0 < rend; j0 += 16) {
-    for (int e = tid; e < 16 * BT_NB; e += 256) {
-      const int i = e >> 4, kk = e & 15, j = j0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (i < nb && j < rend) v = refl(d, k0 + i, j);
-      As[kk][i] = make_double2(v.x, -v.y);
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int e = tid + 256 * u, i = e >> 4, kk = e & 15, j = j0 + kk;
+      const bool in = i < nb && j < rend && j > k0 + i;  // v_i is zero up to row k0 + i
+      As[kk][i] = make_double2(in ? ra[u].x : 0.0, in ? -ra[u].y : 0.0);
     }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e >> 6, c = e & 63, j = j0 + kk;
-      Bs[kk][c] = (j < rend && c0 + c < nc) ? d.V[(int64_t)j * ld + c0 + c] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * u, kk = e >> 6, c = e & 63;
+      const bool in = j0 + kk < rend && c0 + c < nc;
+      Bs[kk][c] = make_double2(in ? rb[u].x : 0.0, in ? rb[u].y : 0.0);
     }
     __syncthreads();
+    if (j0 + 16 < rend) fetch(j0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
@@ -1535,9 +1556,14 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
   }
 }
 
-// W = T (sum of the partials) for BT_WC columns per workgroup
+// W = T (sum of the partials) for BT_WC columns per workgroup: one entry
+// (i, c) per thread, all its chunk partials loaded at once (clamped, masked)
+// and T staged in LDS.
 __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
+  constexpr int NCH = HTD_MAX / BT_CH;  // chunks at most
+  static_assert(BT_NB * BT_WC == 256, "one entry of W per thread");
   __shared__ double2 Ws[BT_NB][BT_WC];
+  __shared__ double2 Ts[BT_NB][BT_NB + 1];
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
     return htd_wred_blocks(n, nc, b);
   });
@@ -1547,29 +1573,32 @@ __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict_
   const int n = sz.n[lc.p], nc = sz.nc[lc.p], ld = d.ld, tid = threadIdx.x, c0 = lc.b * BT_WC;
   const int nch = (htd_bt_rows(n, b) + BT_CH - 1) / BT_CH;
   const double2* Tb = d.T + (int64_t)b * BT_NB * BT_NB;
-  for (int e = tid; e < BT_NB * BT_WC; e += 256) {
-    const int i = e / BT_WC, c = e % BT_WC;
-    double2 s = make_double2(0.0, 0.0);
-    if (c0 + c < nc) {
-      const double2* w = d.Wp + (int64_t)i * ld + c0 + c;
-#pragma unroll 8
-      for (int ch = 0; ch < nch; ++ch) s = cadd(s, w[(int64_t)ch * BT_NB * ld]);
-    }
-    Ws[i][c] = s;
+  const int i = tid / BT_WC, c = tid % BT_WC;
+  const double2* w = d.Wp + (int64_t)i * ld + min(c0 + c, nc - 1);
+  double2 v[NCH];
+#pragma unroll
+  for (int q = 0; q < NCH; ++q) v[q] = w[(int64_t)(q < nch ? q : 0) * BT_NB * ld];
+#pragma unroll
+  for (int e = tid; e < BT_NB * BT_NB; e += 256) Ts[e / BT_NB][e % BT_NB] = Tb[e];
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int q = 0; q < NCH; ++q) {
+    sx += q < nch ? v[q].x : 0.0;
+    sy += q < nch ? v[q].y : 0.0;
   }
+  Ws[i][c] = make_double2(sx, sy);
   __syncthreads();
-  for (int e = tid; e < BT_NB * BT_WC; e += 256) {
-    const int i = e / BT_WC, c = e % BT_WC;
-    if (c0 + c >= nc) continue;
-    double2 s = make_double2(0.0, 0.0);
-    for (int l = i; l < BT_NB; ++l) s = cadd(s, cmul(Tb[i * BT_NB + l], Ws[l][c]));
-    d.W[(int64_t)i * ld + c0 + c] = s;
-  }
+  double2 s = make_double2(0.0, 0.0);
+  for (int l = i; l < BT_NB; ++l) s = cadd(s, cmul(Ts[i][l], Ws[l][c]));
+  if (c0 + c < nc) d.W[(int64_t)i * ld + c0 + c] = s;
 }
 
 // Z[j][c] -= sum_i v_i[j] W[i][c] on 64 x 64 tiles of rows k0 + 1 ...; each
-// wavefront owns a 32 x 32 quadrant (2 x 2 blocks of 16 x 16), K = BT_NB.
+// wavefront owns a 32 x 32 quadrant (2 x 2 blocks of 16 x 16), K = BT_NB in
+// slices of 16.  As in the partial product, the next slice (and during the
+// last slice the tile of Z) is loaded before the products of the current one.
 __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int b) {
+  constexpr int EPT = 16 * 64 / 256;
   __shared__ double2 As[16][64 + 1];  // v_i[j], k-major
   __shared__ double2 Bs[16][64 + 1];  // W[i][c]
   const Loc lc = locate_d(sz, blockIdx.x, [b](int n, int nc) {
@@ -1583,19 +1612,47 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
   const int ct = (nc + 63) / 64, rt = lc.b / ct, c0 = (lc.b % ct) * 64;
   const int j0 = k0 + 1 + rt * 64;
   const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  double2 ra[EPT], rb[EPT];
+  auto fetch = [&](int i0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u, i = min(i0 + (e >> 6), nb - 1), x = e & 63;
+      ra[u] = d.A[(int64_t)(k0 + i) * ld + min(j0 + x, n - 1)];
+      rb[u] = d.W[(int64_t)i * ld + min(c0 + x, nc - 1)];
+    }
+  };
   CAcc<double> acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y].clear();
+  double2 zt[2][2][4];
+  fetch(0);
+#pragma unroll
   for (int i0 = 0; i0 < BT_NB; i0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int ii = e >> 6, x = e & 63;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + 256 * u, ii = e >> 6, x = e & 63;
       const int i = i0 + ii, j = j0 + x;
-      As[ii][x] = (i < nb && j < n) ? refl(d, k0 + i, j) : make_double2(0.0, 0.0);
-      Bs[ii][x] = (i < nb && c0 + x < nc) ? d.W[(int64_t)i * ld + c0 + x] : make_double2(0.0, 0.0);
+      const bool ina = i < nb && j < n && j > k0 + i, inb = i < nb && c0 + x < nc;
+      As[ii][x] = make_double2(ina ? ra[u].x : 0.0, ina ? ra[u].y : 0.0);
+      Bs[ii][x] = make_double2(inb ? rb[u].x : 0.0, inb ? rb[u].y : 0.0);
     }
     __syncthreads();
+    if (i0 + 16 < BT_NB) {
+      fetch(i0 + 16);
+    } else {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
+            const int c = c0 + wn * 32 + y * 16 + (lane & 15);
+            zt[x][y][r] = d.V[(int64_t)min(j, n - 1) * ld + min(c, nc - 1)];
+          }
+    }
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
@@ -1616,10 +1673,8 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
       for (int r = 0; r < 4; ++r) {
         const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
-        if (j < n && c < nc) {
-          double2* p = d.V + (int64_t)j * ld + c;
-          *p = make_double2(p->x - acc[x][y].re[r], p->y - acc[x][y].im[r]);
-        }
+        if (j < n && c < nc)
+          d.V[(int64_t)j * ld + c] = make_double2(zt[x][y][r].x - acc[x][y].re[r], zt[x][y][r].y - acc[x][y].im[r]);
       }
 }
 

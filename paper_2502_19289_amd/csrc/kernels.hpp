@@ -189,7 +189,7 @@ __host__ __device__ inline int htd_bt_rows(int n, int b) { return n - BT_NB * b 
 __host__ __device__ inline int htd_wpart_blocks(int n, int nc, int b) {
   return b < htd_nblk(n) ? ((htd_bt_rows(n, b) + BT_CH - 1) / BT_CH) * ((nc + 63) / 64) : 0;
 }
-constexpr int BT_WC = 16;  // columns of W per reduction workgroup
+constexpr int BT_WC = 8;  // columns of W per reduction workgroup (BT_NB x BT_WC = 256 entries)
 __host__ __device__ inline int htd_wred_blocks(int n, int nc, int b) {
   return b < htd_nblk(n) ? (nc + BT_WC - 1) / BT_WC : 0;
 }

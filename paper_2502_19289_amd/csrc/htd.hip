@@ -849,6 +849,8 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   __shared__ double zs[HTD_MAX];
   __shared__ int col[HTD_MAX];
   __shared__ int ndl[HTD_MAX];
+  __shared__ int fl[HTD_MAX];
+  __shared__ unsigned char rf[HTD_MAX];
   __shared__ int wsum[16];
   __shared__ double red[16];
   __shared__ int sh_ndef;
@@ -911,123 +913,121 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   md = block_max(md, red);
   mz = block_max(mz, red);
   const double tol = 8.0 * EPS53 * fmax(md, mz);
-  // Common case in parallel: the small-z deflations, then the close-pole test
-  // of every pair of consecutive remaining poles on the unmodified values.
-  // When no pair calls for a rotation, the scan below would produce exactly
-  // these lists (the remaining poles in order, the deflated values ascending
-  // with ties by column, so no sort either); otherwise it runs as written.
-  {
-    const bool alldef = rho * mz <= tol;
-    const int t0 = 2 * tid, t1 = t0 + 1;
-    const bool nd0 = t0 < K && !alldef && rho * fabs(zs[t0]) > tol;
-    const bool nd1 = t1 < K && !alldef && rho * fabs(zs[t1]) > tol;
-    int knd = 0;
-    const int p = block_prefix2(nd0, nd1, wsum, knd);
-    if (nd0) ndl[p] = t0;
-    if (nd1) ndl[p + (nd0 ? 1 : 0)] = t1;
-    __syncthreads();
-    bool rot = false;
-    for (int i = tid + 1; i < knd; i += 1024) {
-      const int pj = ndl[i - 1], t = ndl[i];
-      double sn = zs[pj], cs = zs[t];
-      const double tau = hypot(cs, sn), tt = Ds[t] - Ds[pj];
-      cs /= tau;
-      sn = -sn / tau;
-      if (fabs(tt * cs * sn) <= tol) rot = true;
-    }
-    if (!__syncthreads_or(rot)) {
-      for (int i = tid; i < knd; i += 1024) {
-        const int t = ndl[i];
-        d.dl[lo + i] = Ds[t];
-        d.w[lo + i] = zs[t];
-        d.ndcol[lo + i] = col[t];
-      }
-      const bool df0 = t0 < K && !nd0, df1 = t1 < K && !nd1;
-      int kdef = 0;
-      const int q = block_prefix2(df0, df1, wsum, kdef);
-      if (df0) {
-        d.dval[lo + q] = Ds[t0];
-        d.dcol[lo + q] = col[t0];
-      }
-      if (df1) {
-        d.dval[lo + q + (df0 ? 1 : 0)] = Ds[t1];
-        d.dcol[lo + q + (df0 ? 1 : 0)] = col[t1];
-      }
-      if (tid == 0) {
-        cnt[0] = knd;
-        cnt[1] = kdef;
-        cnt[2] = 0;
-        cnt[3] = 1;
-        d.rho[lo] = rho;
-      }
-      return;
-    }
+  // The deflation scan (ascending poles; a pole with small rho |z| deflates;
+  // two consecutive remaining poles pj < t too close for the secular equation
+  // are rotated so that z_pj = 0, pj deflates and t carries on with the
+  // rotated value and z) in parallel wherever it can be.  A pair's test only
+  // depends on values a rotation changed when the pair before it rotated, so
+  // the pairs whose test on the unmodified values fails and whose
+  // predecessor pair did not rotate are settled at once.  One thread walks
+  // from each flagged pair (in order) through the rotations that follow it,
+  // exactly as the sequential scan would; everything else is written in
+  // parallel.  With no rotation at all the lists are final here: the
+  // remaining poles in order and the deflated values ascending with ties by
+  // column (no sort).
+  const bool alldef = rho * mz <= tol;
+  const int t0 = 2 * tid, t1 = t0 + 1;
+  const bool nd0 = t0 < K && !alldef && rho * fabs(zs[t0]) > tol;
+  const bool nd1 = t1 < K && !alldef && rho * fabs(zs[t1]) > tol;
+  int knd = 0;
+  const int p = block_prefix2(nd0, nd1, wsum, knd);
+  if (nd0) ndl[p] = t0;
+  if (nd1) ndl[p + (nd0 ? 1 : 0)] = t1;
+  const bool df0 = t0 < K && !nd0, df1 = t1 < K && !nd1;
+  int kdef = 0;
+  const int q = block_prefix2(df0, df1, wsum, kdef);
+  if (df0) {
+    d.dval[lo + q] = Ds[t0];
+    d.dcol[lo + q] = col[t0];
   }
-  if (tid == 0) {
-    int K2 = 0, ndef = 0, nrot = 0;
-    if (rho * mz <= tol) {
-      for (int t = 0; t < K; ++t) {
-        d.dval[lo + ndef] = Ds[t];
-        d.dcol[lo + ndef] = col[t];
-        ++ndef;
-      }
-    } else {
-      int pj = -1;
-      for (int t = 0; t < K; ++t) {
-        if (rho * fabs(zs[t]) <= tol) {
-          d.dval[lo + ndef] = Ds[t];
-          d.dcol[lo + ndef] = col[t];
-          ++ndef;
-          continue;
-        }
-        if (pj < 0) {
-          pj = t;
-          continue;
-        }
-        double sn = zs[pj], cs = zs[t];
-        const double tau = hypot(cs, sn), tt = Ds[t] - Ds[pj];
-        cs /= tau;
-        sn = -sn / tau;
-        if (fabs(tt * cs * sn) <= tol) {
-          // rotate columns pj, t so that z_pj = 0: pj deflates
-          zs[t] = tau;
-          zs[pj] = 0.0;
-          d.rot_a[lo + nrot] = col[pj];
-          d.rot_b[lo + nrot] = col[t];
-          d.rot_c[lo + nrot] = cs;
-          d.rot_s[lo + nrot] = sn;
-          ++nrot;
-          const double t1 = Ds[pj] * cs * cs + Ds[t] * sn * sn;
-          Ds[t] = Ds[pj] * sn * sn + Ds[t] * cs * cs;
-          Ds[pj] = t1;
-          d.dval[lo + ndef] = Ds[pj];
-          d.dcol[lo + ndef] = col[pj];
-          ++ndef;
-        } else {
-          d.dl[lo + K2] = Ds[pj];
-          d.w[lo + K2] = zs[pj];
-          d.ndcol[lo + K2] = col[pj];
-          ++K2;
-        }
+  if (df1) {
+    d.dval[lo + q + (df0 ? 1 : 0)] = Ds[t1];
+    d.dcol[lo + q + (df0 ? 1 : 0)] = col[t1];
+  }
+  __syncthreads();
+  // pair i = (ndl[i-1], ndl[i]), 1 <= i < knd; this thread's pairs 2 tid, 2 tid + 1
+  auto close = [&](int pj, int t, double& cs, double& sn, double& tau) {
+    sn = zs[pj];
+    cs = zs[t];
+    tau = hypot(cs, sn);
+    const double tt = Ds[t] - Ds[pj];
+    cs /= tau;
+    sn = -sn / tau;
+    return fabs(tt * cs * sn) <= tol;
+  };
+  bool f0 = false, f1 = false;
+  {
+    double cs, sn, tau;
+    if (t0 >= 1 && t0 < knd) f0 = close(ndl[t0 - 1], ndl[t0], cs, sn, tau);
+    if (t1 < knd) f1 = close(ndl[t1 - 1], ndl[t1], cs, sn, tau);
+  }
+  int nf = 0;
+  const int pf = block_prefix2(f0, f1, wsum, nf);
+  // flagged pairs in order to fl[]; rf[i] marks a rotation at pair i
+  if (f0) fl[pf] = t0;
+  if (f1) fl[pf + (f0 ? 1 : 0)] = t1;
+  for (int i = tid; i < knd; i += 1024) rf[i] = 0;
+  __syncthreads();
+  if (tid == 0 && nf > 0) {
+    int pos = 1, nrot = 0;  // pairs below pos are settled
+    for (int u = 0; u < nf; ++u) {
+      const int i = fl[u];
+      if (i < pos) continue;
+      int pj = ndl[i - 1], r = i;
+      for (; r < knd; ++r) {
+        const int t = ndl[r];
+        double cs, sn, tau;
+        if (!close(pj, t, cs, sn, tau)) break;
+        zs[t] = tau;
+        zs[pj] = 0.0;
+        d.rot_a[lo + nrot] = col[pj];
+        d.rot_b[lo + nrot] = col[t];
+        d.rot_c[lo + nrot] = cs;
+        d.rot_s[lo + nrot] = sn;
+        const double v1 = Ds[pj] * cs * cs + Ds[t] * sn * sn;
+        Ds[t] = Ds[pj] * sn * sn + Ds[t] * cs * cs;
+        Ds[pj] = v1;
+        d.dval[lo + kdef + nrot] = v1;
+        d.dcol[lo + kdef + nrot] = col[pj];
+        ++nrot;
+        rf[r] = 1;
         pj = t;
       }
-      if (pj >= 0) {
-        d.dl[lo + K2] = Ds[pj];
-        d.w[lo + K2] = zs[pj];
-        d.ndcol[lo + K2] = col[pj];
-        ++K2;
-      }
+      pos = r + 1;
     }
+    sh_ndef = nrot;
+  }
+  if (nf == 0 && tid == 0) sh_ndef = 0;
+  __syncthreads();
+  const int nrot = sh_ndef;
+  // remaining pole j of the chain survives unless pair j + 1 rotated it away
+  const bool s0 = t0 < knd && (t0 == knd - 1 || !rf[t0 + 1]);
+  const bool s1 = t1 < knd && (t1 == knd - 1 || !rf[t1 + 1]);
+  int K2 = 0;
+  const int ps = block_prefix2(s0, s1, wsum, K2);
+  if (s0) {
+    d.dl[lo + ps] = Ds[ndl[t0]];
+    d.w[lo + ps] = zs[ndl[t0]];
+    d.ndcol[lo + ps] = col[ndl[t0]];
+  }
+  if (s1) {
+    const int o = ps + (s0 ? 1 : 0);
+    d.dl[lo + o] = Ds[ndl[t1]];
+    d.w[lo + o] = zs[ndl[t1]];
+    d.ndcol[lo + o] = col[ndl[t1]];
+  }
+  const int ndef = kdef + nrot;
+  if (tid == 0) {
     cnt[0] = K2;
     cnt[1] = ndef;
     cnt[2] = nrot;
     cnt[3] = 1;
     d.rho[lo] = rho;
-    sh_ndef = ndef;
   }
+  if (nrot == 0) return;
   __syncthreads();
-  // deflated eigenvalues ascending (bitonic sort, ties by column)
-  const int ndef = sh_ndef;
+  // deflated eigenvalues ascending (bitonic sort, ties by column): the
+  // values rotated away were appended after the others
   if (ndef > 1) {
     int p2 = 1;
     while (p2 < ndef) p2 <<= 1;

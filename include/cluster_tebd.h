@@ -71,7 +71,9 @@ enum {
  * divide and conquer, back-transformation) needs 2 launches per column and
  * O(log 2c) merge levels. */
 enum {
-  MPS_EIG_AUTO = 0,     /* tridiagonal for 256 <= 2c <= 2048, Jacobi otherwise  */
+  MPS_EIG_AUTO = 0,     /* the faster route by size: at present tridiagonal
+                           whenever 2c <= 2048 (as MPS_EIG_TRIDIAG), Jacobi
+                           above                                                */
   MPS_EIG_JACOBI = 1,   /* FP64 block Jacobi (an FP32 solve with FP64 Rayleigh
                            quotients for large cap-limited splits of FP32 runs) */
   MPS_EIG_TRIDIAG = 2   /* tridiagonal divide and conquer whenever 2c <= 2048   */

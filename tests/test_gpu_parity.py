@@ -53,9 +53,9 @@ def infid(A, B):
     return MT.infidelity(A, B)
 
 
-# eigen-solvers: "auto" (Jacobi below 2c = 256, tridiagonal above) and the
-# tridiagonal divide and conquer forced for every split
-EIGS = ["auto", "tridiag"]
+# eigen-solvers: "auto" (the tridiagonal divide and conquer for every split
+# up to 2c = 2048) and block Jacobi forced for every split
+EIGS = ["auto", "jacobi"]
 
 
 @pytest.mark.parametrize("eig", EIGS)

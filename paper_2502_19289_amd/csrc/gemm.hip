@@ -34,8 +34,8 @@ template <typename CI, typename CO, typename TM, int MODE>
 __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const int* __restrict__ base, int nprob) {
   using CM = typename cpx_of<TM>::type;
-  __shared__ CM As[BK][BM];
-  __shared__ CM Bs[BK][BN];
+  __shared__ CM As[2][BK][BM];
+  __shared__ CM Bs[2][BK][BN];
 
   const int p = find_problem(base, nprob, blockIdx.x);
   const GemmDesc& d = descs[p];
@@ -74,22 +74,24 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j].clear();
 
-  // The loads of slice k0 + BK are issued before the products of slice k0.
-  // They are unconditional, at addresses clamped into the operands, and
-  // masked when staged (a load guarded by its own branch would be waited for
-  // before the next one is issued).
-  CM ra[4], rb[4];
+  // Two LDS buffers: the loads of slice k0 + BK are issued before the
+  // products of slice k0 (from one buffer) and staged into the other buffer
+  // after them, so one barrier per slice separates the two.  The loads are
+  // unconditional, at addresses clamped into the operands, and masked when
+  // staged (a load guarded by its own branch would be waited for before the
+  // next one is issued); they are kept in the input type until staged.
+  CI ra[4], rb[4];
   TM wv = (TM)0;
   auto fetch = [&](int k0) __attribute__((always_inline)) {
     if (MODE == MODE_NN) {
       const int r = tid >> 2, c4 = (tid & 3) * 4;
       const int gm = min(m0 + r, M - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ra[i] = load_c<CI, TM>(A + (int64_t)gm * lda + min(k0 + c4 + i, kend - 1));
+      for (int i = 0; i < 4; ++i) ra[i] = A[(int64_t)gm * lda + min(k0 + c4 + i, kend - 1)];
       const int kk = tid >> 4, n4 = (tid & 15) * 4;
       const int gk = min(k0 + kk, kend - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) rb[i] = load_c<CI, TM>(Bm + (int64_t)gk * ldb + min(n0 + n4 + i, N - 1));
+      for (int i = 0; i < 4; ++i) rb[i] = Bm[(int64_t)gk * ldb + min(n0 + n4 + i, N - 1)];
     } else {
       // rows gk of A (K x M) and of B (K x N; A itself for a Gram matrix)
       const int kk = tid >> 4, c4 = (tid & 15) * 4;
@@ -97,59 +99,67 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
       const CI* Bk = MODE == MODE_GRAM ? A + (int64_t)gk * lda : Bm + (int64_t)gk * ldb;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ra[i] = load_c<CI, TM>(A + (int64_t)gk * lda + min(m0 + c4 + i, M - 1));
-        rb[i] = load_c<CI, TM>(Bk + min(n0 + c4 + i, N - 1));
+        ra[i] = A[(int64_t)gk * lda + min(m0 + c4 + i, M - 1)];
+        rb[i] = Bk[min(n0 + c4 + i, N - 1)];
       }
       if (MODE == MODE_GRAM) wv = (TM)d.w[gk >> d.wshift];
     }
   };
-  // ---- stage A (BM x BK) k-major and B (BK x BN); zero outside the operands
-  auto stage = [&](int k0) __attribute__((always_inline)) {
-    // (component selects: a select of whole values would take their addresses)
-    auto mask = [](bool in, CM v) {
-      v.x = in ? v.x : (TM)0;
-      v.y = in ? v.y : (TM)0;
-      return v;
+  // ---- stage A (BM x BK) k-major and B (BK x BN) into buffer q; zero
+  // outside the operands (component selects: a select of whole values would
+  // take their addresses)
+  auto stage = [&](int q, int k0) __attribute__((always_inline)) {
+    auto cvt = [](bool in, CI v) {
+      CM r;
+      r.x = in ? (TM)v.x : (TM)0;
+      r.y = in ? (TM)v.y : (TM)0;
+      return r;
     };
     if (MODE == MODE_NN) {
       const int r = tid >> 2, c4 = (tid & 3) * 4;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) As[c4 + i][r] = mask(m0 + r < M && k0 + c4 + i < kend, ra[i]);
+      for (int i = 0; i < 4; ++i) As[q][c4 + i][r] = cvt(m0 + r < M && k0 + c4 + i < kend, ra[i]);
       const int kk = tid >> 4, n4 = (tid & 15) * 4;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[kk][n4 + i] = mask(k0 + kk < kend && n0 + n4 + i < N, rb[i]);
+      for (int i = 0; i < 4; ++i) Bs[q][kk][n4 + i] = cvt(k0 + kk < kend && n0 + n4 + i < N, rb[i]);
     } else {
       const int kk = tid >> 4, c4 = (tid & 15) * 4;
       const bool kin = k0 + kk < kend;
       const TM wk = MODE == MODE_GRAM ? (kin ? wv : (TM)0) : (TM)1;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        CM va = mask(kin && m0 + c4 + i < M, ra[i]), vb = mask(kin && n0 + c4 + i < N, rb[i]);
+        CM va = cvt(kin && m0 + c4 + i < M, ra[i]), vb = cvt(kin && n0 + c4 + i < N, rb[i]);
         va.x *= wk;
         va.y = -va.y * wk;  // conjugated (A^H)
         vb.x *= wk;
         vb.y *= wk;
-        As[kk][c4 + i] = va;
-        Bs[kk][c4 + i] = vb;
+        As[q][kk][c4 + i] = va;
+        Bs[q][kk][c4 + i] = vb;
       }
     }
   };
-  if (kbeg < kend) fetch(kbeg);
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stage(0, kbeg);
+  }
+  __syncthreads();
+  int q = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    stage(k0);
-    __syncthreads();
-    if (k0 + BK < kend) fetch(k0 + BK);
+    const bool more = k0 + BK < kend;
+    if (more) fetch(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
-      CM a0 = As[kr][wm * 32 + cl], a1 = As[kr][wm * 32 + 16 + cl];
-      CM b0 = Bs[kr][wn * 32 + cl], b1 = Bs[kr][wn * 32 + 16 + cl];
+      CM a0 = As[q][kr][wm * 32 + cl], a1 = As[q][kr][wm * 32 + 16 + cl];
+      CM b0 = Bs[q][kr][wn * 32 + cl], b1 = Bs[q][kr][wn * 32 + 16 + cl];
       acc[0][0].mac(a0.x, a0.y, b0.x, b0.y);
       acc[0][1].mac(a0.x, a0.y, b1.x, b1.y);
       acc[1][0].mac(a1.x, a1.y, b0.x, b0.y);
       acc[1][1].mac(a1.x, a1.y, b1.x, b1.y);
     }
+    if (more) stage(q ^ 1, k0 + BK);
     __syncthreads();
+    q ^= 1;
   }
 
   const TM alpha = (TM)d.alpha;

@@ -627,21 +627,26 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
 // is up to date there (the last panel's trd_her2k ran) and is held in the
 // registers of one 512-thread workgroup as 4 x 8 tiles: thread t owns rows
 // 4 (t / 16) .. +3 and columns 8 (t % 16) .. +7, so that a row is spread over
-// the 16 lanes of one DPP row and each column step reads 12 vector entries.
-// Column by column (unblocked): the column below the diagonal is the
-// conjugated row, the reflector comes from its scaled norm, y = tau A v,
-// w = y - (tau/2)(y^H v) v and A -= v w^H + w v^H; d, e, tau and the
-// reflectors (row k of A) are written as the blocked kernels write them.
+// the 16 lanes of one DPP row.  Column by column (unblocked): the column below
+// the diagonal is the conjugated row, the reflector comes from its scaled
+// norm, y = tau A v, w = y - (tau/2)(y^H v) v and A -= v w^H + w v^H; d, e,
+// tau and the reflectors (row k of A) are written as the blocked kernels
+// write them.  Per column two barriers: one after the row is staged, one
+// after y; every wavefront forms the reflector and y^H v itself (same
+// operations in the same order, so the same values) and reads v and w from
+// the staged x and y.  x and y alternate between two buffers, so the next
+// column's staging needs no barrier of its own.
 __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
   constexpr int TR = 4, TC = 8, CG = HTD_TAIL / TC;  // tile rows, tile columns, column groups
   static_assert(CG == 16 && (HTD_TAIL / TR) * CG == 512, "tail tiling");
-  __shared__ double2 xs[HTD_TAIL], vs[HTD_TAIL], ys[HTD_TAIL], ws[HTD_TAIL];
-  __shared__ double2 sh_tau, sh_scale;
+  static_assert(HTD_TAIL == 128, "two column entries per lane");
+  __shared__ double2 xs[2][HTD_TAIL], ys[2][HTD_TAIL];
   const int p = blockIdx.x;
   if (p >= sz.np) return;
   const HtdDesc& d = ds[p];
   if (skipped(d)) return;
   const int n = sz.n[p], k0 = htd_tail_start(n), mt = n - k0, ld = d.ld, tid = threadIdx.x;
+  const int lane = tid & 63;
   const int r0 = (tid / CG) * TR, c0 = (tid % CG) * TC;
   // (unconditional loads at clamped, valid addresses, masked afterwards: no
   // load waits for the one before it)
@@ -658,101 +663,99 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
 #pragma unroll
     for (int j = 0; j < TC; ++j)
       if (!(r0 + i < mt && c0 + j < mt)) a[i][j] = make_double2(0.0, 0.0);
-  if (tid < HTD_TAIL) {
-    xs[tid] = make_double2(0.0, 0.0);
-    vs[tid] = make_double2(0.0, 0.0);
-    ys[tid] = make_double2(0.0, 0.0);
-    ws[tid] = make_double2(0.0, 0.0);
+  if (tid < 2 * HTD_TAIL) {  // entries past mt are read as zeros
+    xs[tid >> 7][tid & (HTD_TAIL - 1)] = make_double2(0.0, 0.0);
+    ys[tid >> 7][tid & (HTD_TAIL - 1)] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   for (int kk = 0; kk + 1 < mt; ++kk) {
-    const int k = k0 + kk;
+    const int k = k0 + kk, b = kk & 1;
+    const double2* x = xs[b];
     // column kk below the diagonal = conj(row kk) (entries past mt are zero
     // and stay zero; entries up to kk are read by no one); the diagonal is final
 #pragma unroll
     for (int i = 0; i < TR; ++i)
       if (r0 + i == kk)
 #pragma unroll
-        for (int j = 0; j < TC; ++j) xs[c0 + j] = make_double2(a[i][j].x, -a[i][j].y);
+        for (int j = 0; j < TC; ++j) xs[b][c0 + j] = make_double2(a[i][j].x, -a[i][j].y);
     __syncthreads();
-    if (tid == 64) d.d[k] = xs[kk].x;
-    if (tid < 64) {  // reflector from alpha = x[kk+1] and the scaled norm of x[kk+2:]
-      double am = 0.0;
-      for (int c = kk + 2 + tid; c < mt; c += 64) am = fmax(am, fmax(fabs(xs[c].x), fabs(xs[c].y)));
+    // the reflector from alpha = x[kk+1] and the scaled norm of x[kk+2:], in every wavefront
+    double2 tau, scale;
+    {
+      const int ca = kk + 2 + lane, cb = ca + 64;
+      const double2 xa = x[ca < HTD_TAIL ? ca : 0], xb = x[cb < HTD_TAIL ? cb : 0];
+      const bool ia = ca < mt, ib = cb < mt;
+      const double am = fmax(ia ? fmax(fabs(xa.x), fabs(xa.y)) : 0.0, ib ? fmax(fabs(xb.x), fabs(xb.y)) : 0.0);
       const double smax = wave_max(am);
-      double ss = 0.0;
-      if (smax > 0.0)
-        for (int c = kk + 2 + tid; c < mt; c += 64)
-          ss += (xs[c].x / smax) * (xs[c].x / smax) + (xs[c].y / smax) * (xs[c].y / smax);
+      const double rs = smax > 0.0 ? 1.0 / smax : 0.0;
+      const double ss = (ia ? (xa.x * rs) * (xa.x * rs) + (xa.y * rs) * (xa.y * rs) : 0.0) +
+                        (ib ? (xb.x * rs) * (xb.x * rs) + (xb.y * rs) * (xb.y * rs) : 0.0);
       const double ssq = wave_sum(ss);
+      double beta;
+      householder(x[kk + 1], smax, ssq, beta, tau, scale);
       if (tid == 0) {
-        double beta;
-        double2 tau, scale;
-        householder(xs[kk + 1], smax, ssq, beta, tau, scale);
-        sh_tau = tau;
-        sh_scale = scale;
+        d.d[k] = x[kk].x;
         d.tau[k] = tau;
         d.e[k] = beta;
       }
     }
-    __syncthreads();
-    const double2 tau = sh_tau, scale = sh_scale;
     const bool ident = tau.x == 0.0 && tau.y == 0.0;
-    if (tid < mt) {
-      const double2 v = tid == kk + 1 ? make_double2(1.0, 0.0)
-                                      : (tid > kk + 1 && !ident ? cmul(xs[tid], scale) : make_double2(0.0, 0.0));
-      vs[tid] = v;
-      if (tid > kk) d.A[(int64_t)k * ld + k0 + tid] = v;
-    }
-    __syncthreads();
+    // v = (1 at kk+1, scale x past it), zero elsewhere
+    auto vat = [&](int c) {
+      return c == kk + 1 ? make_double2(1.0, 0.0)
+                         : (c > kk + 1 && !ident ? cmul(x[c], scale) : make_double2(0.0, 0.0));
+    };
+    if (tid > kk && tid < mt) d.A[(int64_t)k * ld + k0 + tid] = vat(tid);
     if (ident) continue;  // H = I: the trailing block is unchanged
     // y = tau A v on the rows below kk (each row summed over its 16 lanes)
+    double2 vc[TC];
+#pragma unroll
+    for (int j = 0; j < TC; ++j) vc[j] = vat(c0 + j);
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < TC; ++j) acc = cadd(acc, cmul(a[i][j], vc[j]));
+      acc.x += dpp_take<0xb1, 0xf>(acc.x);
+      acc.y += dpp_take<0xb1, 0xf>(acc.y);
+      acc.x += dpp_take<0x4e, 0xf>(acc.x);
+      acc.y += dpp_take<0x4e, 0xf>(acc.y);
+      acc.x += dpp_take<0x141, 0xf>(acc.x);
+      acc.y += dpp_take<0x141, 0xf>(acc.y);
+      acc.x += dpp_take<0x140, 0xf>(acc.x);
+      acc.y += dpp_take<0x140, 0xf>(acc.y);
+      const int r = r0 + i;
+      if (c0 == 0 && r < mt) ys[b][r] = r > kk ? cmul(tau, acc) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2* y = ys[b];
+    // alpha = -(tau/2) y^H v in every wavefront, then w = y + alpha v
+    double2 al;
     {
-      double2 vc[TC];
-#pragma unroll
-      for (int j = 0; j < TC; ++j) vc[j] = vs[c0 + j];
-#pragma unroll
-      for (int i = 0; i < TR; ++i) {
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < TC; ++j) acc = cadd(acc, cmul(a[i][j], vc[j]));
-        acc.x += dpp_take<0xb1, 0xf>(acc.x);
-        acc.y += dpp_take<0xb1, 0xf>(acc.y);
-        acc.x += dpp_take<0x4e, 0xf>(acc.x);
-        acc.y += dpp_take<0x4e, 0xf>(acc.y);
-        acc.x += dpp_take<0x141, 0xf>(acc.x);
-        acc.y += dpp_take<0x141, 0xf>(acc.y);
-        acc.x += dpp_take<0x140, 0xf>(acc.x);
-        acc.y += dpp_take<0x140, 0xf>(acc.y);
-        const int r = r0 + i;
-        if (c0 == 0 && r < mt) ys[r] = r > kk ? cmul(tau, acc) : make_double2(0.0, 0.0);
-      }
+      const int ca = kk + 1 + lane, cb = ca + 64;
+      const double2 ya = y[ca < HTD_TAIL ? ca : 0], yb = y[cb < HTD_TAIL ? cb : 0];
+      const double2 ta = ca < mt ? cmulc(ya, vat(ca < HTD_TAIL ? ca : 0)) : make_double2(0.0, 0.0);
+      const double2 tb = cb < mt ? cmulc(yb, vat(cb < HTD_TAIL ? cb : 0)) : make_double2(0.0, 0.0);
+      double su[2] = {ta.x + tb.x, ta.y + tb.y};
+      wave_sum_n(su);
+      al = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(su[0], su[1]));
     }
-    __syncthreads();
-    if (tid < 64) {  // alpha = -(tau/2) y^H v, then w = y + alpha v
-      double2 t = make_double2(0.0, 0.0);
-      for (int c = kk + 1 + tid; c < mt; c += 64) t = cadd(t, cmulc(ys[c], vs[c]));
-      const double2 su = make_double2(wave_sum(t.x), wave_sum(t.y));
-      const double2 al = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), su);
-      for (int c = tid; c < mt; c += 64) ws[c] = cadd(ys[c], cmul(al, vs[c]));
-    }
-    __syncthreads();
     if (r0 + TR - 1 > kk) {  // A -= v w^H + w v^H (v, w vanish at indexes <= kk and >= mt)
       double2 vr[TR], wr[TR];
 #pragma unroll
       for (int i = 0; i < TR; ++i) {
-        vr[i] = vs[r0 + i];
-        wr[i] = ws[r0 + i];
+        vr[i] = vat(r0 + i);
+        wr[i] = cadd(y[r0 + i], cmul(al, vr[i]));
       }
 #pragma unroll
       for (int j = 0; j < TC; ++j) {  // one column at a time keeps the live registers few
-        const double2 vcc = make_double2(vs[c0 + j].x, -vs[c0 + j].y);
-        const double2 wcc = make_double2(ws[c0 + j].x, -ws[c0 + j].y);
+        const double2 vj = vc[j];
+        const double2 wj = cadd(y[c0 + j], cmul(al, vj));
+        const double2 vcc = make_double2(vj.x, -vj.y), wcc = make_double2(wj.x, -wj.y);
 #pragma unroll
         for (int i = 0; i < TR; ++i) a[i][j] = csub(csub(a[i][j], cmul(vr[i], wcc)), cmul(wr[i], vcc));
       }
     }
-    __syncthreads();  // xs, vs, ys, ws are rewritten by the next column
   }
   // the last diagonal entry, also back into A for trd_finish
 #pragma unroll

@@ -617,11 +617,11 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
       timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
       const int nb_hemv = most([k](int n) { return htd_hemv_blocks(n, k); });
       const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(ha, k, nb_hemv, s); });
-      if (counted)  // algorithmic traffic of the HEMV: the trailing block read once
+      if (counted)  // algorithmic traffic of the HEMV: one triangle of the trailing block read once
         for (int p = 0; p < np; ++p) {
           const double m = sz.n[p] - k - 1;
           if (m <= 0 || k >= htd_tail_start(sz.n[p])) continue;
-          ctx->timer.bytes[c_hemv] += 16.0 * m * m;
+          ctx->timer.bytes[c_hemv] += 16.0 * m * (m + 1) / 2;
           ctx->timer.flop[c_hemv] += 8.0 * m * m;
         }
     }
@@ -686,7 +686,7 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
 // The buffers a kernel derives with htd_view are the ones the host laid out.
 bool htd_view_matches(const HtdArgs& a, int q, const HtdDesc& h) {
   const HtdDesc g = htd_view(a, q);
-  return g.d == h.d && g.e == h.e && g.tau == h.tau && g.PV == h.PV && g.PW == h.PW && g.PY == h.PY &&
+  return g.d == h.d && g.e == h.e && g.tau == h.tau && g.PV == h.PV && g.PW == h.PW && g.Y == h.Y &&
          g.xb == h.xb && g.kpart == h.kpart && g.part == h.part && g.A == h.A && g.ld == h.ld &&
          g.skip == h.skip;
 }

@@ -155,14 +155,16 @@ __device__ __forceinline__ double block4_sum(double v, double* sh) {
 //   trd_col:   x = G[k+1:, k] - V W[k, :]^H - W V[k, :]^H (the up-to-date
 //              column), its scaled norm and the dots V^H x, W^H x; it also
 //              finalises w_{j-1} = y_{j-1} - (tau/2)(y_{j-1}^H v_{j-1}) v_{j-1}
-//              from y_{j-1} (kept apart in PY, so that neither kernel writes
-//              what it reads: each can be launched again on the same inputs)
+//              from y_{j-1} (summed from the HEMV's slots; neither kernel
+//              writes what it reads, so each can be launched again on the
+//              same inputs)
 //   trd_hemv:  the reflector H^H (alpha, x1)^T = (beta, 0)^T (beta real) and
-//              y = tau (G v - V (W^H v) - W (V^H v)) over the rows, 2 per
-//              wavefront with 4 columns per lane in flight
+//              y = tau (G v - V (W^H v) - W (V^H v)) from the lower triangle
+//              of G, as partial sums per 64 x 64 tile (slots)
 // and at the end of the panel trd_her2k applies G -= V W^H + W V^H to the
-// trailing matrix on the matrix cores.  The trailing matrix is thus read once
-// per column (HEMV) and read and written once per panel.
+// trailing matrix on the matrix cores.  One triangle of the trailing matrix
+// is thus read once per column (HEMV); all of it is read and written once per
+// panel.
 // dlassq-style running (scale, sum of squares): sum a^2 = scale^2 * ssq
 __device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
   a = fabs(a);
@@ -216,6 +218,9 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   __shared__ double2 psum[4];
   __shared__ double2 tx[KC_ROWS][64];  // the terms of x, row by row
   __shared__ double2 xr[KC_ROWS];
+  __shared__ double2 yp[8][KC_ROWS];  // y_{j-1} of the workgroup's rows: slot sums
+  __shared__ double2 y0p[HV_SLOTS];   // and of row k
+  __shared__ double2 yfin[KC_ROWS + 1];
   // problem blockIdx.y: its record is the only argument line read before the data
   const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
   const int n = sz.pr[lc.p].n;
@@ -233,7 +238,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   // independent loads, the small ones first (memory operations complete in
   // issue order): partials of alpha, row k, then this wavefront's rows
   const int nbp = j > 0 ? htd_hemv_blocks(n, k - 1) : 0;
-  constexpr int PQ = (HTD_MAX / HV_ROWS + 255) / 256;
+  constexpr int PQ = (HV_PARTS + 255) / 256;
   // (loads are unconditional at clamped, always valid indexes and masked at
   // their use, so that no use is folded into a branch right after its load,
   // which would wait for it before the later loads are issued)
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   const double2 tpl = d.tau[k > 0 ? k - 1 : 0];
   // lane of V column u: w_k[u]; lane of W column u: v_k[u]
   double2 rk = make_double2(0.0, 0.0), rkv = make_double2(0.0, 0.0);
-  if (live) rk = isv ? (vfin ? d.PY[k] : d.PW[(int64_t)k * HTD_NB + u]) : d.PV[(int64_t)k * HTD_NB + u];
+  if (live && !vfin) rk = isv ? d.PW[(int64_t)k * HTD_NB + u] : d.PV[(int64_t)k * HTD_NB + u];
   if (vfin) rkv = d.PV[(int64_t)k * HTD_NB + u];
   const double akk = lc.b == 0 && tid == 64 ? d.A[(int64_t)k * ld + k].x : 0.0;
   double2 a[RPW], pv[RPW], pf[RPW];
@@ -258,9 +263,19 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     a[q] = own && c == 0 ? d.A[(int64_t)k * ld + r] : make_double2(0.0, 0.0);
     pv[q] = make_double2(0.0, 0.0);
     pf[q] = make_double2(0.0, 0.0);
-    if (own && live) pv[q] = isv ? d.PV[r * HTD_NB + u] : (fin ? d.PY[r] : d.PW[r * HTD_NB + u]);
+    if (own && live && !fin) pv[q] = isv ? d.PV[r * HTD_NB + u] : d.PW[r * HTD_NB + u];
     if (own && fin) pf[q] = d.PV[r * HTD_NB + u];
   }
+  // y_{j-1} (the HEMV's slot sums over the rows of column k-1's trailing
+  // block, which starts at row k): rows k + 1 + i of this workgroup, 4 slots
+  // per thread, and row k, one slot per thread
+  constexpr int YU = (HV_SLOTS + 7) / 8;
+  const int ty = j > 0 ? htd_hemv_rows(n, k - 1) + 2 : 0, tyc = ty > 0 ? ty : 1;
+  const int yrow = min(1 + lc.b * KC_ROWS + (tid & 31), m);  // m: last row of that block
+  double2 ys[YU];
+#pragma unroll
+  for (int q = 0; q < YU; ++q) ys[q] = d.Y[(int64_t)min((tid >> 5) + 8 * q, tyc - 1) * ld + yrow];
+  const double2 y0l = d.Y[(int64_t)min(tid < HV_SLOTS ? tid : 0, tyc - 1) * ld];
   // alpha = -(tau/2) y^H v of panel column j-1 (its HEMV's partial sums)
   double sx = 0.0, sy = 0.0;
 #pragma unroll
@@ -276,7 +291,31 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     sy = sp[1];
   }
   if (c == 0) psum[wv] = make_double2(sx, sy);
+  {
+    double2 ya = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < YU; ++q)
+      if ((tid >> 5) + 8 * q < ty) ya = cadd(ya, ys[q]);
+    yp[tid >> 5][tid & 31] = ya;
+    if (tid < HV_SLOTS) y0p[tid] = tid < ty ? y0l : make_double2(0.0, 0.0);
+  }
   __syncthreads();
+  if (tid < KC_ROWS) {
+    double2 ya = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) ya = cadd(ya, yp[g][tid]);
+    yfin[1 + tid] = ya;
+  } else if (tid == 64) {
+    double2 ya = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int g = 0; g < HV_SLOTS; ++g) ya = cadd(ya, y0p[g]);
+    yfin[0] = ya;
+  }
+  __syncthreads();
+  if (vfin) rk = yfin[0];
+  if (fin)
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) pv[q] = yfin[1 + wv + 4 * q];
   double2 al = make_double2(0.0, 0.0);
   if (j > 0) {
     const double2 ps = cadd(cadd(psum[0], psum[1]), cadd(psum[2], psum[3]));
@@ -351,160 +390,229 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   }
 }
 
-// One trailing row per wavefront.  Everything that does not depend on the
-// reflector is loaded first: the whole row (up to HTD_MAX columns, 32 per
-// lane), its panel term, the trd_col records and the raw column x (into
-// LDS).  The reflector is then rebuilt from the records (every workgroup
-// does it, in the same order) and applied inside the product:
-// G v = G[:, 0] + scale (G[:, 1:] x[1:]) since v = (1, scale x[1:]).
+// The product with the trailing block from its lower triangle (G is
+// Hermitian).  Workgroups t < T (T + 1) / 2 take the 64 x 64 tiles (I, J),
+// J <= I, of the trailing rows and columns: a tile adds tau G[I, J] v_J to
+// y_I and, below the diagonal, tau G[I, J]^H v_I to y_J.  The next 2 T
+// workgroups take the panel term -tau (V (W^H v) + W (V^H v)) of 64 rows,
+// the V half or the W half (the V half also writes the reflector).  Each sum
+// goes to a slot of its own: y_I's share of tile (I, J) to slot J, y_J's
+// share to slot I, the panel halves to slots T and T + 1, so y_r is the sum
+// of the T + 2 slots of row r, formed where y is used (trd_col, trd_her2k);
+// every workgroup also leaves its share of y^H v.  All rebuild the reflector
+// from the trd_col records (same operations, same values) while their loads
+// are in flight; the products with x (v = (1, scale x[1:])) come first.
+// Thread layout: wavefront w, lane 16 s + c holds rows 16 w + 4 q + s (q < 4)
+// and columns 16 p + c of the tile (p < 4) or of the panel half (p < 2): a
+// load instruction reads four row segments of 256 bytes, a row's sum is a
+// 16-lane DPP reduction, a column's sum runs over 4 rows in registers, then
+// through LDS.
 __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) {
-  __shared__ double2 xs[HTD_MAX];
-  __shared__ double2 vhv[HTD_NB], whv[HTD_NB];
+  __shared__ double2 hsum[8][HTD_NB];    // panel: record sums by group
+  __shared__ double2 cpart[16][64 + 1];  // tile: column sums of (wavefront, s)
   __shared__ double2 wred[4];
-  __shared__ double2 hsum[4][2 * HTD_NB];
   __shared__ double sh2[2];
   // problem blockIdx.y: its record is the only argument line read before the data
-  const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
-  const int n = sz.pr[lc.p].n;
-  if (lc.b >= htd_hemv_blocks(n, k)) return;
-  const HtdDesc d = htd_view(sz, lc.p);
+  const int p = blockIdx.y, t = blockIdx.x;
+  const int n = sz.pr[p].n;
+  const int T = htd_hemv_rows(n, k), NT = T * (T + 1) / 2;
+  if (t >= NT + 2 * T) return;
+  const HtdDesc d = htd_view(sz, p);
   if (skipped(d)) return;
+  const bool panel = t >= NT;
+  int I = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);  // t = I (I + 1) / 2 + J
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  int J = t - I * (I + 1) / 2;
+  const int h = (t - NT) & 1;  // panel half: 0 V, 1 W
+  if (panel) I = J = (t - NT) >> 1;
+  const bool diag = I == J;
   const int m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
-  const int wave = tid >> 6, lane = tid & 63;
-  const int i0 = lc.b * HV_ROWS + wave;
-  const bool row = i0 < m;
-  const double2* a0 = d.A + (int64_t)(k + 1 + (row ? i0 : 0)) * ld + (k + 1);
-  constexpr int PL = HTD_MAX / 64;  // row entries per lane
-  // small loads first (memory operations complete in issue order, so the
-  // reductions on them must not wait behind the row): the staged column,
-  // the trd_col records, this row's panel term
-  constexpr int XL = HTD_MAX / 256;
-  // (unconditional loads at clamped, always valid indexes, masked at their
-  // use: a use folded into a branch right after its load would wait for it
-  // before the later loads are issued)
-  double2 xv[XL];
-#pragma unroll
-  for (int u = 0; u < XL; ++u) {
-    const int jj = tid + 256 * u;
-    xv[u] = d.xb[jj < m ? jj : 0];
-  }
+  const int wave = tid >> 6, lane = tid & 63, s4 = lane >> 4, cl = lane & 15;
+  const int i0 = I * HV_T, c0 = J * HV_T;  // offsets in the trailing block
+  auto rowof = [&](int q) { return i0 + 16 * wave + 4 * q + s4; };
+  auto colof = [&](int pp) { return c0 + 16 * pp + cl; };
+  // small loads first (memory operations complete in issue order), all
+  // unconditional at clamped, valid indexes and masked at their use (a use
+  // folded into a branch right after its load would wait for it before the
+  // later loads are issued)
   const int nka = htd_col_blocks(n, k);
-  const double2* recs = d.kpart;
-  constexpr int RQ = HTD_MAX / KC_ROWS / 4;  // records per group
-  const int e = tid & 63, g = tid >> 6;
-  double2 rv[RQ];
-#pragma unroll
-  for (int u = 0; u < RQ; ++u) {
-    const int q = g + 4 * u;
-    rv[u] = recs[(int64_t)(q < nka ? q : 0) * HTD_KP + 2 + e];
-  }
-  // wavefront 0, lane q < nka: record q's (scale, ssq)
-  const double2 rq0 = recs[(int64_t)(tid < nka ? tid : 0) * HTD_KP];
+  const double2 rq0 = d.kpart[(int64_t)(tid < nka ? tid : 0) * HTD_KP];
   const double2 rq = tid < nka ? rq0 : make_double2(0.0, 0.0);
-  const int l = lane & (HTD_NB - 1);
-  const bool isv = lane < HTD_NB;
-  double2 pe = make_double2(0.0, 0.0);
-  if (row && l < j) pe = isv ? d.PV[(int64_t)(k + 1 + i0) * HTD_NB + l] : d.PW[(int64_t)(k + 1 + i0) * HTD_NB + l];
-  double2 v1 = make_double2(0.0, 0.0), w1 = make_double2(0.0, 0.0);
-  if (tid < j) {
-    v1 = d.PV[(int64_t)(k + 1) * HTD_NB + tid];
-    w1 = d.PW[(int64_t)(k + 1) * HTD_NB + tid];
-  }
-  // then the row
-  double2 p[PL];
+  const double2 alpha = d.xb[0];
+  double2 xr[4];
 #pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int c = lane + 64 * u;
-    p[u] = row && c < m ? a0[c] : make_double2(0.0, 0.0);
-  }
-#pragma unroll
-  for (int u = 0; u < XL; ++u) {  // zero past m: the product below reads all of xs
-    const int jj = tid + 256 * u;
-    xs[jj] = jj < m ? xv[u] : make_double2(0.0, 0.0);
-  }
-  {
-    double2 t = make_double2(0.0, 0.0);
-    const bool ev = (e & (HTD_NB - 1)) < j;
-#pragma unroll
-    for (int u = 0; u < RQ; ++u)
-      if (ev && g + 4 * u < nka) t = cadd(t, rv[u]);
-    hsum[g][e] = t;
-  }
-  if (tid < 64) {
-    const double rm = rq.x, rs = rq.y;
-    const double smax = wave_max(rm);
-    const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
-    const double ssq_w = wave_sum(c);
-    if (tid == 0) {
-      sh2[0] = smax;
-      sh2[1] = ssq_w;
+  for (int q = 0; q < 4; ++q) xr[q] = d.xb[min(rowof(q), m - 1)];
+  auto reflector_norm = [&]() {
+    if (tid < 64) {
+      const double rm = rq.x, rs = rq.y;
+      const double smax = wave_max(rm);
+      const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
+      const double ssq_w = wave_sum(c);
+      if (tid == 0) {
+        sh2[0] = smax;
+        sh2[1] = ssq_w;
+      }
     }
-  }
-  __syncthreads();
-  // G[r][1:] x[1:] does not depend on the reflector: formed first, so that its
-  // sums overlap the reflector's arithmetic
-  double2 gx = make_double2(0.0, 0.0), g0 = make_double2(0.0, 0.0);
-  if (row) {
-    // branch-free (p is zero past m, and so is xs): a guarded LDS read per
-    // entry would be waited for one at a time
-    double rx = 0.0, ry = 0.0;
-#pragma unroll
-    for (int u = 0; u < PL; ++u) {
-      const double2 v = xs[lane + 64 * u];
-      const double2 q = u == 0 && lane == 0 ? make_double2(0.0, 0.0) : p[u];  // x[0] is alpha
-      rx += q.x * v.x - q.y * v.y;
-      ry += q.x * v.y + q.y * v.x;
-    }
-    double sr[2] = {rx, ry};
-    wave_sum_n(sr);
-    gx = make_double2(sr[0], sr[1]);
-    g0 = make_double2(lane0(p[0].x), lane0(p[0].y));  // G[r][0] (v_0 = 1)
-  }
-  const double smax = sh2[0], ssq = sh2[1];
-  double2 sv = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
-  if (tid < j) {
-    sv = cadd(cadd(hsum[0][tid], hsum[1][tid]), cadd(hsum[2][tid], hsum[3][tid]));
-    sw = cadd(cadd(hsum[0][HTD_NB + tid], hsum[1][HTD_NB + tid]), cadd(hsum[2][HTD_NB + tid], hsum[3][HTD_NB + tid]));
-  }
-  const double2 alpha = xs[0];
+  };
   double2 tau, scale;
   double beta;
-  householder(alpha, smax, ssq, beta, tau, scale);
-  const bool ident = tau.x == 0.0 && tau.y == 0.0;
-  if (tid < j) {
-    // V^H v = conj(V[k+1, l]) + scale sum_{i >= 1} conj(V[k+1+i, l]) x_i, likewise W
-    vhv[tid] = cadd(make_double2(v1.x, -v1.y), cmul(scale, sv));
-    whv[tid] = cadd(make_double2(w1.x, -w1.y), cmul(scale, sw));
-  }
-  __syncthreads();
-
-  double2 y0 = make_double2(0.0, 0.0);
-  if (!ident && row) {
-    // panel term: lane l < 32 gives V[r][l] (W^H v)_l, lane 32 + l W[r][l] (V^H v)_l
-    const double2 c0 = l < j ? cmul(pe, isv ? whv[l] : vhv[l]) : make_double2(0.0, 0.0);
-    double sh[2] = {c0.x, c0.y};
-    wave_sum_n(sh);
-    const double2 h = make_double2(sh[0], sh[1]);
-    y0 = cmul(tau, csub(cadd(g0, cmul(scale, gx)), h));
-  }
-  // every wavefront stores its row's y, its reflector entry (panel column j
-  // and row k of A) and the sum of conj(y_i) v_i of the workgroup
-  double2 part = make_double2(0.0, 0.0);
-  if (row) {
-    const double2 vi = i0 == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xs[i0], scale));
-    part = cmulc(y0, vi);
-    if (lane == 0) {
-      d.PY[k + 1 + i0] = y0;
-      d.PV[(int64_t)(k + 1 + i0) * HTD_NB + j] = vi;
-      d.A[(int64_t)k * ld + (k + 1 + i0)] = vi;
+  double2 dot = make_double2(0.0, 0.0);
+  if (!panel) {
+    double2 xc[4];
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) xc[pp] = d.xb[min(colof(pp), m - 1)];
+    const double2 xcol = d.xb[min(c0 + lane, m - 1)];
+    const double2* g0 = d.A + (int64_t)(k + 1) * ld + (k + 1);
+    double2 a[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) a[q][pp] = g0[(int64_t)min(rowof(q), m - 1) * ld + min(colof(pp), m - 1)];
+    reflector_norm();
+    // row sums over this thread's columns (x_0 = alpha left out: v_0 = 1 is
+    // added through G[r][0] itself); column sums over its rows (rows > 0
+    // below the diagonal)
+    double2 gr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const int c = colof(pp);
+        acc = cadd(acc, cmul(a[q][pp], c > 0 && c < m ? xc[pp] : make_double2(0.0, 0.0)));
+      }
+      gr[q] = acc;
+    }
+    if (!diag)
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = cadd(acc, cmulc(a[q][pp], rowof(q) < m ? xr[q] : make_double2(0.0, 0.0)));
+        cpart[wave * 4 + s4][16 * pp + cl] = acc;
+      }
+    __syncthreads();
+    householder(alpha, sh2[0], sh2[1], beta, tau, scale);
+    const bool ident = tau.x == 0.0 && tau.y == 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 acc = cmul(scale, gr[q]);
+      acc.x += dpp_take<0xb1, 0xf>(acc.x);
+      acc.y += dpp_take<0xb1, 0xf>(acc.y);
+      acc.x += dpp_take<0x4e, 0xf>(acc.x);
+      acc.y += dpp_take<0x4e, 0xf>(acc.y);
+      acc.x += dpp_take<0x141, 0xf>(acc.x);
+      acc.y += dpp_take<0x141, 0xf>(acc.y);
+      acc.x += dpp_take<0x140, 0xf>(acc.x);
+      acc.y += dpp_take<0x140, 0xf>(acc.y);
+      const int r = rowof(q);
+      if (cl == 0 && r < m) {
+        if (J == 0) acc = cadd(acc, a[q][0]);  // G[r][0] v_0
+        const double2 y = ident ? make_double2(0.0, 0.0) : cmul(tau, acc);
+        const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
+        d.Y[(int64_t)J * ld + r] = y;
+        dot = cadd(dot, cmulc(y, vi));
+      }
+    }
+    if (!diag && tid < 64 && c0 + tid < m) {  // column c = c0 + tid
+      const int c = c0 + tid;
+      double2 cs = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cs = cadd(cs, cpart[r][tid]);
+      const double2 y = ident ? make_double2(0.0, 0.0) : cmul(tau, cmul(scale, cs));
+      const double2 vc = c == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xcol, scale));
+      d.Y[(int64_t)I * ld + c] = y;
+      dot = cadd(dot, cmulc(y, vc));
+    }
+  } else {
+    // half h: sum_l P[r][l] c_l over the panel columns l < j, P = V (h = 0) or
+    // W (h = 1), c = W^H v or V^H v = conj(Q[k+1, l]) + scale (Q^H x[1:])_l
+    // with Q the other one; (Q^H x[1:])_l from the records of trd_col
+    const double2* P = h == 0 ? d.PV : d.PW;
+    const double2* Q = h == 0 ? d.PW : d.PV;
+    const int e = tid & 31, g = tid >> 5;
+    constexpr int RQ = HTD_MAX / KC_ROWS / 8;  // records per group
+    double2 rv[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const int q = g + 8 * u;
+      rv[u] = d.kpart[(int64_t)(q < nka ? q : 0) * HTD_KP + 2 + (h == 0 ? HTD_NB : 0) + e];
+    }
+    double2 q1[2], pe[4][2];
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) q1[pp] = Q[(int64_t)(k + 1) * HTD_NB + 16 * pp + cl];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) pe[q][pp] = P[(int64_t)(k + 1 + min(rowof(q), m - 1)) * HTD_NB + 16 * pp + cl];
+    // (columns l >= j are not written yet in this panel: masked by selects,
+    // never by a zero factor)
+    {
+      double2 tt = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < RQ; ++u)
+        if (g + 8 * u < nka) tt = cadd(tt, rv[u]);
+      hsum[g][e] = tt;
+    }
+    reflector_norm();
+    __syncthreads();
+    // the two parts of each row's sum: with conj(Q[k+1, l]) and with (Q^H x[1:])_l
+    double2 h1[4], h2[4];
+    {
+      double2 c1[2], c2[2];
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        const int l = 16 * pp + cl;
+        double2 sgl = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int gg = 0; gg < 8; ++gg) sgl = cadd(sgl, hsum[gg][l]);
+        c1[pp] = l < j ? make_double2(q1[pp].x, -q1[pp].y) : make_double2(0.0, 0.0);
+        c2[pp] = l < j ? sgl : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp)
+          if (16 * pp + cl >= j) pe[q][pp] = make_double2(0.0, 0.0);
+        h1[q] = cadd(cmul(pe[q][0], c1[0]), cmul(pe[q][1], c1[1]));
+        h2[q] = cadd(cmul(pe[q][0], c2[0]), cmul(pe[q][1], c2[1]));
+      }
+    }
+    householder(alpha, sh2[0], sh2[1], beta, tau, scale);
+    const bool ident = tau.x == 0.0 && tau.y == 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2 acc = cadd(h1[q], cmul(scale, h2[q]));
+      acc.x += dpp_take<0xb1, 0xf>(acc.x);
+      acc.y += dpp_take<0xb1, 0xf>(acc.y);
+      acc.x += dpp_take<0x4e, 0xf>(acc.x);
+      acc.y += dpp_take<0x4e, 0xf>(acc.y);
+      acc.x += dpp_take<0x141, 0xf>(acc.x);
+      acc.y += dpp_take<0x141, 0xf>(acc.y);
+      acc.x += dpp_take<0x140, 0xf>(acc.x);
+      acc.y += dpp_take<0x140, 0xf>(acc.y);
+      const int r = rowof(q);
+      if (cl == 0 && r < m) {
+        const double2 y = ident ? make_double2(0.0, 0.0) : cmul(make_double2(-tau.x, -tau.y), acc);
+        const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
+        d.Y[(int64_t)(T + h) * ld + r] = y;
+        dot = cadd(dot, cmulc(y, vi));
+        if (h == 0) {  // the reflector: panel column j and row k of A
+          d.PV[(int64_t)(k + 1 + r) * HTD_NB + j] = vi;
+          d.A[(int64_t)k * ld + (k + 1 + r)] = vi;
+        }
+      }
     }
   }
-  if (lane == 0) wred[wave] = part;
+  double sd[2] = {dot.x, dot.y};
+  wave_sum_n(sd);
+  if (lane == 0) wred[wave] = make_double2(sd[0], sd[1]);
   __syncthreads();
   if (tid == 0) {
-    d.part[lc.b] = cadd(cadd(wred[0], wred[1]), cadd(wred[2], wred[3]));
-    if (lc.b == 0) {
+    d.part[t] = cadd(cadd(wred[0], wred[1]), cadd(wred[2], wred[3]));
+    if (t == 0) {
       d.tau[k] = tau;
       d.e[k] = beta;
     }
@@ -519,10 +627,11 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
 // panel's last w, y + alpha v, is formed once per row in LDS.
 __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int p0) {
   constexpr int KS = 16, NS = 2 * HTD_NB / KS, EPT = KS * 64 / 256;
-  static_assert(HTD_MAX / HV_ROWS <= 512, "alpha partials: two per thread");
+  constexpr int PQ = (HV_PARTS + 255) / 256, YU = (HV_SLOTS + 1) / 2;
   __shared__ double2 As[KS][64 + 1];
   __shared__ double2 Bs[KS][64 + 1];
   __shared__ double2 wl[128];  // last w at rows r0.. (0..63) and c0.. (64..127)
+  __shared__ double2 yh[2][128];
   __shared__ double sh[4];
   const Loc lc = locate(sz, blockIdx.x, [p0](int n) { return htd_her2k_blocks(n, p0); });
   if (lc.p < 0) return;
@@ -551,16 +660,35 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
     }
   };
   fetch(0);
-  const double2 pa = d.part[tid < nb ? tid : 0], pb = d.part[tid + 256 < nb ? tid + 256 : 0];
+  double2 pq[PQ];
+#pragma unroll
+  for (int u = 0; u < PQ; ++u) pq[u] = d.part[tid + 256 * u < nb ? tid + 256 * u : 0];
   const double2 tl = d.tau[kl];
-  const int wr = clampr((tid < 64 ? r0 : c0 - 64) + tid);
-  const double2 yl = d.PY[wr], vl = d.PV[(int64_t)wr * HTD_NB + nbp - 1];
-  double sx = (tid < nb ? pa.x : 0.0) + (tid + 256 < nb ? pb.x : 0.0);
-  double sy = (tid < nb ? pa.y : 0.0) + (tid + 256 < nb ? pb.y : 0.0);
+  // the last column's y at this thread's row (rows r0.., then c0..) from the
+  // HEMV's slots (its trailing block starts at row p1): YU slots per thread
+  const int wr = clampr((tid & 127) < 64 ? r0 + (tid & 127) : c0 + (tid & 127) - 64);
+  const int ty = htd_hemv_rows(n, kl) + 2;
+  double2 ys[YU];
+#pragma unroll
+  for (int u = 0; u < YU; ++u) ys[u] = d.Y[(int64_t)min((tid >> 7) + 2 * u, ty - 1) * ld + (wr - p1)];
+  const double2 vl = d.PV[(int64_t)wr * HTD_NB + nbp - 1];
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int u = 0; u < PQ; ++u) {
+    sx += tid + 256 * u < nb ? pq[u].x : 0.0;
+    sy += tid + 256 * u < nb ? pq[u].y : 0.0;
+  }
+  {
+    double2 ya = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < YU; ++u)
+      if ((tid >> 7) + 2 * u < ty) ya = cadd(ya, ys[u]);
+    yh[tid >> 7][tid & 127] = ya;
+  }
   sx = block4_sum(sx, sh);
   sy = block4_sum(sy, sh);
   const double2 al = cmul(make_double2(-0.5 * tl.x, -0.5 * tl.y), make_double2(sx, sy));
-  if (tid < 128) wl[tid] = cadd(yl, cmul(al, vl));
+  if (tid < 128) wl[tid] = cadd(cadd(yh[0][tid], yh[1][tid]), cmul(al, vl));
   __syncthreads();
   CAcc<double> acc[2][2];
 #pragma unroll

@@ -99,7 +99,10 @@ hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream
 // (Cuppen divide and conquer), eigenvectors Q Z (blocked back-transformation).
 constexpr int HTD_MAX = 2048;  // largest n: per-node lists are staged in LDS
 constexpr int HTD_NB = 32;     // reflectors per back-transformation block
-constexpr int HV_ROWS = 4;     // trailing-matrix rows per HEMV workgroup (one per wavefront)
+constexpr int HV_T = 64;       // edge of the HEMV tiles of the trailing block's lower triangle
+constexpr int HV_TMAX = HTD_MAX / HV_T;  // tile rows at most
+constexpr int HV_SLOTS = HV_TMAX + 2;    // y slots at most: one per tile column, two panel terms
+constexpr int HV_PARTS = HV_TMAX * (HV_TMAX + 1) / 2 + 2 * HV_TMAX;  // HEMV workgroups at most
 constexpr int HTD_KP = 2 + 2 * HTD_NB;  // per trd_col workgroup: (max, sum of squares), V^H x, W^H x
 constexpr int KC_ROWS = 32;    // column rows per trd_col workgroup (8 per wavefront)
 constexpr int BT_CH = 64;      // rows per split-K chunk of the back-transformation
@@ -119,10 +122,10 @@ struct HtdDesc {
   double2* tau;     // reflector scalars (n - 1)
   double2* PV;      // panel reflectors V (n x HTD_NB, row-major)
   double2* PW;      // panel vectors W (n x HTD_NB, row-major), finalised
-  double2* PY;      // y of the latest panel column before its finalisation (n)
+  double2* Y;       // HEMV partial sums of y (slot s, trailing row r at s * ld + r)
   double2* xb;      // the current column brought up to date (n)
   double2* kpart;   // per trd_col workgroup: HTD_KP partial results
-  double2* part;    // per HEMV workgroup: sum of conj(y_i) v_i
+  double2* part;    // per HEMV tile: its share of y^H v
   // divide and conquer (node lists are indexed by the node's first row)
   double* Q[2];     // n x n (ld) block-diagonal eigenvector matrices by level
                     // parity, stored by columns: Q[col * ld + row]
@@ -158,9 +161,15 @@ __host__ __device__ inline int htd_tail_start(int n) {
 }
 
 // Per-problem workgroup counts of the launches (identical on host and device).
-__host__ __device__ inline int htd_hemv_blocks(int n, int k) {
+// HEMV: tile rows T of the trailing block; T (T + 1) / 2 workgroups for the
+// tiles of its lower triangle and 2 T for the panel terms; T + 2 y slots
+__host__ __device__ inline int htd_hemv_rows(int n, int k) {
   const int m = n - k - 1;
-  return m > 0 && k < htd_tail_start(n) ? (m + HV_ROWS - 1) / HV_ROWS : 0;
+  return m > 0 && k < htd_tail_start(n) ? (m + HV_T - 1) / HV_T : 0;
+}
+__host__ __device__ inline int htd_hemv_blocks(int n, int k) {
+  const int t = htd_hemv_rows(n, k);
+  return t * (t + 1) / 2 + 2 * t;
 }
 __host__ __device__ inline int htd_col_blocks(int n, int k) {
   const int m = n - k - 1;
@@ -218,10 +227,13 @@ __host__ __device__ inline void htd_layout(size_t ld, HtdDesc& h, F take) {
   h.tau = (double2*)take(nc);
   h.PV = (double2*)take(HTD_NB * nc);
   h.PW = (double2*)take(HTD_NB * nc);
-  h.PY = (double2*)take(nc);
+  h.Y = (double2*)take(((ld + HV_T - 1) / HV_T + 2) * nc);
   h.xb = (double2*)take(nc);
   h.kpart = (double2*)take((ld / KC_ROWS + 1) * HTD_KP * sizeof(double2));
-  h.part = (double2*)take((ld / HV_ROWS + 1) * sizeof(double2));
+  {
+    const size_t t = (ld + HV_T - 1) / HV_T;
+    h.part = (double2*)take((t * (t + 1) / 2 + 2 * t) * sizeof(double2));
+  }
   for (int q = 0; q < 2; ++q) {
     h.Q[q] = (double*)take(ld * nd);
     h.D[q] = (double*)take(nd);

@@ -218,9 +218,6 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   __shared__ double2 psum[4];
   __shared__ double2 tx[KC_ROWS][64];  // the terms of x, row by row
   __shared__ double2 xr[KC_ROWS];
-  __shared__ double2 yp[8][KC_ROWS];  // y_{j-1} of the workgroup's rows: slot sums
-  __shared__ double2 y0p[HV_SLOTS];   // and of row k
-  __shared__ double2 yfin[KC_ROWS + 1];
   // problem blockIdx.y: its record is the only argument line read before the data
   const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
   const int n = sz.pr[lc.p].n;
@@ -266,16 +263,17 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     if (own && live && !fin) pv[q] = isv ? d.PV[r * HTD_NB + u] : d.PW[r * HTD_NB + u];
     if (own && fin) pf[q] = d.PV[r * HTD_NB + u];
   }
-  // y_{j-1} (the HEMV's slot sums over the rows of column k-1's trailing
-  // block, which starts at row k): rows k + 1 + i of this workgroup, 4 slots
-  // per thread, and row k, one slot per thread
+  // y_{j-1}: the sums of the HEMV's slots over the rows of column k-1's
+  // trailing block (which starts at row k), per wavefront: lane c takes
+  // slots c / 8 + 8 u of the wavefront's row q = c % 8, and slot c of row k
+  static_assert(RPW == 8, "one row of the wavefront per lane residue mod 8");
   constexpr int YU = (HV_SLOTS + 7) / 8;
   const int ty = j > 0 ? htd_hemv_rows(n, k - 1) + 2 : 0, tyc = ty > 0 ? ty : 1;
-  const int yrow = min(1 + lc.b * KC_ROWS + (tid & 31), m);  // m: last row of that block
+  const int yrow = min(1 + lc.b * KC_ROWS + wv + 4 * (c & 7), m);  // m: last row of that block
   double2 ys[YU];
 #pragma unroll
-  for (int q = 0; q < YU; ++q) ys[q] = d.Y[(int64_t)min((tid >> 5) + 8 * q, tyc - 1) * ld + yrow];
-  const double2 y0l = d.Y[(int64_t)min(tid < HV_SLOTS ? tid : 0, tyc - 1) * ld];
+  for (int q = 0; q < YU; ++q) ys[q] = d.Y[(int64_t)min((c >> 3) + 8 * q, tyc - 1) * ld + yrow];
+  const double2 y0l = d.Y[(int64_t)min(c, tyc - 1) * ld];
   // alpha = -(tau/2) y^H v of panel column j-1 (its HEMV's partial sums)
   double sx = 0.0, sy = 0.0;
 #pragma unroll
@@ -292,30 +290,32 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   }
   if (c == 0) psum[wv] = make_double2(sx, sy);
   {
-    double2 ya = make_double2(0.0, 0.0);
+    // row q = c % 8: the 8 lanes with that residue (c ^ 8 by DPP row_ror:8,
+    // c ^ 16 and c ^ 32 by shuffles); row k: the whole wavefront
+    double ya[2] = {0.0, 0.0}, y0[2];
 #pragma unroll
     for (int q = 0; q < YU; ++q)
-      if ((tid >> 5) + 8 * q < ty) ya = cadd(ya, ys[q]);
-    yp[tid >> 5][tid & 31] = ya;
-    if (tid < HV_SLOTS) y0p[tid] = tid < ty ? y0l : make_double2(0.0, 0.0);
+      if ((c >> 3) + 8 * q < ty) {
+        ya[0] += ys[q].x;
+        ya[1] += ys[q].y;
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      ya[x] += dpp_take<0x128, 0xf>(ya[x]);
+      ya[x] += __shfl_xor(ya[x], 16);
+      ya[x] += __shfl_xor(ya[x], 32);
+    }
+    y0[0] = c < ty ? y0l.x : 0.0;
+    y0[1] = c < ty ? y0l.y : 0.0;
+    wave_sum_n(y0);
+    if (vfin) rk = make_double2(y0[0], y0[1]);
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {  // row q's sum from lane q, in every lane
+      const double2 yq = make_double2(__shfl(ya[0], q), __shfl(ya[1], q));
+      if (fin) pv[q] = yq;
+    }
   }
   __syncthreads();
-  if (tid < KC_ROWS) {
-    double2 ya = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int g = 0; g < 8; ++g) ya = cadd(ya, yp[g][tid]);
-    yfin[1 + tid] = ya;
-  } else if (tid == 64) {
-    double2 ya = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int g = 0; g < HV_SLOTS; ++g) ya = cadd(ya, y0p[g]);
-    yfin[0] = ya;
-  }
-  __syncthreads();
-  if (vfin) rk = yfin[0];
-  if (fin)
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) pv[q] = yfin[1 + wv + 4 * q];
   double2 al = make_double2(0.0, 0.0);
   if (j > 0) {
     const double2 ps = cadd(cadd(psum[0], psum[1]), cadd(psum[2], psum[3]));

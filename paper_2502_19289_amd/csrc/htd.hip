@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
     const int i = lc.b * KC_ROWS + wv + 4 * q;
     const bool own = i < m;
     const int64_t r = k + 1 + i;
-    a[q] = own && c == 0 ? d.A[(int64_t)k * ld + r] : make_double2(0.0, 0.0);
+    a[q] = own && c == 0 ? d.A[r * ld + k] : make_double2(0.0, 0.0);  // G[r][k], lower triangle
     pv[q] = make_double2(0.0, 0.0);
     pf[q] = make_double2(0.0, 0.0);
     if (own && live && !fin) pv[q] = isv ? d.PV[r * HTD_NB + u] : d.PW[r * HTD_NB + u];
@@ -332,15 +332,15 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
       if (i < m) d.PW[(int64_t)(k + 1 + i) * HTD_NB + u] = pv[q];
     }
   }
-  // x_r = conj(G[k][r]) - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
+  // x_r = G[r][k] - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
   // lane c of the row's wavefront contributes pv conj(rk), lane 0 also
-  // conj(G[k][r]).  The sums over the 64 lanes go through LDS (the terms of
+  // G[r][k].  The sums over the 64 lanes go through LDS (the terms of
   // the 32 rows, then 8 threads per row with 8 terms each and an 8-lane DPP
   // sum): far fewer instructions than 16 full wavefront reductions.
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
     const double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
-    tx[wv + 4 * q][c] = make_double2(a[q].x - t.x, -a[q].y - t.y);
+    tx[wv + 4 * q][c] = make_double2(a[q].x - t.x, a[q].y - t.y);
   }
   __syncthreads();
   {
@@ -465,11 +465,21 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     for (int pp = 0; pp < 4; ++pp) xc[pp] = d.xb[min(colof(pp), m - 1)];
     const double2 xcol = d.xb[min(c0 + lane, m - 1)];
     const double2* g0 = d.A + (int64_t)(k + 1) * ld + (k + 1);
+    // (only the lower triangle is up to date: a diagonal tile reads its
+    // upper entries as conj(G[c][r]))
     double2 a[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp) a[q][pp] = g0[(int64_t)min(rowof(q), m - 1) * ld + min(colof(pp), m - 1)];
+      for (int pp = 0; pp < 4; ++pp) {
+        const int r = min(rowof(q), m - 1), c = min(colof(pp), m - 1);
+        a[q][pp] = g0[c > r ? (int64_t)c * ld + r : (int64_t)r * ld + c];
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        if (min(colof(pp), m - 1) > min(rowof(q), m - 1)) a[q][pp].y = -a[q][pp].y;
     reflector_norm();
     // row sums over this thread's columns (x_0 = alpha left out: v_0 = 1 is
     // added through G[r][0] itself); column sums over its rows (rows > 0
@@ -639,7 +649,11 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
   if (skipped(d)) return;
   const int n = sz.n[lc.p], ld = d.ld, tid = threadIdx.x;
   const int nbp = min(HTD_NB, n - 1 - p0), p1 = p0 + nbp, mt = n - p1;
-  const int T = (mt + 63) / 64, ti = lc.b / T, tj = lc.b % T;
+  // tile (ti, tj), tj <= ti, of the lower triangle: b = ti (ti + 1) / 2 + tj
+  int ti = (int)((sqrtf(8.0f * (float)lc.b + 1.0f) - 1.0f) * 0.5f);
+  while (ti * (ti + 1) / 2 > lc.b) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= lc.b) ++ti;
+  const int tj = lc.b - ti * (ti + 1) / 2;
   const int kl = p1 - 1;
   const int nb = htd_hemv_blocks(n, kl);
   const int r0 = p1 + ti * 64, c0 = p1 + tj * 64;
@@ -778,19 +792,25 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
   const int r0 = (tid / CG) * TR, c0 = (tid % CG) * TC;
   // (unconditional loads at clamped, valid addresses, masked afterwards: no
   // load waits for the one before it)
+  // (only the lower triangle is up to date: upper entries as conj(G[c][r]))
   double2 a[TR][TC];
+  const double2* blk = d.A + (int64_t)k0 * ld + k0;
 #pragma unroll
   for (int i = 0; i < TR; ++i) {
     const int rr = r0 + i < mt ? r0 + i : 0;
-    const double2* row = d.A + (int64_t)(k0 + rr) * ld + k0;
 #pragma unroll
-    for (int j = 0; j < TC; ++j) a[i][j] = row[c0 + j < mt ? c0 + j : 0];
+    for (int j = 0; j < TC; ++j) {
+      const int cc = c0 + j < mt ? c0 + j : 0;
+      a[i][j] = blk[cc > rr ? (int64_t)cc * ld + rr : (int64_t)rr * ld + cc];
+    }
   }
 #pragma unroll
   for (int i = 0; i < TR; ++i)
 #pragma unroll
-    for (int j = 0; j < TC; ++j)
+    for (int j = 0; j < TC; ++j) {
+      if (c0 + j > r0 + i) a[i][j].y = -a[i][j].y;
       if (!(r0 + i < mt && c0 + j < mt)) a[i][j] = make_double2(0.0, 0.0);
+    }
   if (tid < 2 * HTD_TAIL) {  // entries past mt are read as zeros
     xs[tid >> 7][tid & (HTD_TAIL - 1)] = make_double2(0.0, 0.0);
     ys[tid >> 7][tid & (HTD_TAIL - 1)] = make_double2(0.0, 0.0);

@@ -23,6 +23,9 @@ SOURCES = ["planner.cpp", "gemm.hip", "eig.hip", "htd.hip", "site_ops.hip", "ske
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core accumulators in ordinary VGPRs: the AGPR form copied
+         # every loop-carried accumulator into AGPRs once per K step
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I" + os.path.join(ROOT, "include")]
 
 

@@ -34,8 +34,8 @@ template <typename CI, typename CO, typename TM, int MODE>
 __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const int* __restrict__ base, int nprob) {
   using CM = typename cpx_of<TM>::type;
-  __shared__ CM As[2][BK][BM];
-  __shared__ CM Bs[2][BK][BN];
+  __shared__ CM As[2][BK][BM + 1];  // (rows padded: the staging writes of
+  __shared__ CM Bs[2][BK][BN + 1];  // consecutive k rows fall in different banks)
 
   const int p = find_problem(base, nprob, blockIdx.x);
   const GemmDesc& d = descs[p];
@@ -88,19 +88,19 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
       const int gm = min(m0 + r, M - 1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) ra[i] = A[(int64_t)gm * lda + min(k0 + c4 + i, kend - 1)];
-      const int kk = tid >> 4, n4 = (tid & 15) * 4;
+      const int kk = tid >> 4, n1 = tid & 15;
       const int gk = min(k0 + kk, kend - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) rb[i] = Bm[(int64_t)gk * ldb + min(n0 + n4 + i, N - 1)];
+      for (int i = 0; i < 4; ++i) rb[i] = Bm[(int64_t)gk * ldb + min(n0 + n1 + 16 * i, N - 1)];
     } else {
       // rows gk of A (K x M) and of B (K x N; A itself for a Gram matrix)
-      const int kk = tid >> 4, c4 = (tid & 15) * 4;
+      const int kk = tid >> 4, c1 = tid & 15;
       const int gk = min(k0 + kk, kend - 1);
       const CI* Bk = MODE == MODE_GRAM ? A + (int64_t)gk * lda : Bm + (int64_t)gk * ldb;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ra[i] = A[(int64_t)gk * lda + min(m0 + c4 + i, M - 1)];
-        rb[i] = Bk[min(n0 + c4 + i, N - 1)];
+        ra[i] = A[(int64_t)gk * lda + min(m0 + c1 + 16 * i, M - 1)];
+        rb[i] = Bk[min(n0 + c1 + 16 * i, N - 1)];
       }
       if (MODE == MODE_GRAM) wv = (TM)d.w[gk >> d.wshift];
     }
@@ -119,22 +119,22 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
       const int r = tid >> 2, c4 = (tid & 3) * 4;
 #pragma unroll
       for (int i = 0; i < 4; ++i) As[q][c4 + i][r] = cvt(m0 + r < M && k0 + c4 + i < kend, ra[i]);
-      const int kk = tid >> 4, n4 = (tid & 15) * 4;
+      const int kk = tid >> 4, n1 = tid & 15;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Bs[q][kk][n4 + i] = cvt(k0 + kk < kend && n0 + n4 + i < N, rb[i]);
+      for (int i = 0; i < 4; ++i) Bs[q][kk][n1 + 16 * i] = cvt(k0 + kk < kend && n0 + n1 + 16 * i < N, rb[i]);
     } else {
-      const int kk = tid >> 4, c4 = (tid & 15) * 4;
+      const int kk = tid >> 4, c1 = tid & 15;
       const bool kin = k0 + kk < kend;
       const TM wk = MODE == MODE_GRAM ? (kin ? wv : (TM)0) : (TM)1;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        CM va = cvt(kin && m0 + c4 + i < M, ra[i]), vb = cvt(kin && n0 + c4 + i < N, rb[i]);
+        CM va = cvt(kin && m0 + c1 + 16 * i < M, ra[i]), vb = cvt(kin && n0 + c1 + 16 * i < N, rb[i]);
         va.x *= wk;
         va.y = -va.y * wk;  // conjugated (A^H)
         vb.x *= wk;
         vb.y *= wk;
-        As[q][kk][c4 + i] = va;
-        Bs[q][kk][c4 + i] = vb;
+        As[q][kk][c1 + 16 * i] = va;
+        Bs[q][kk][c1 + 16 * i] = vb;
       }
     }
   };

@@ -465,21 +465,13 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
     for (int pp = 0; pp < 4; ++pp) xc[pp] = d.xb[min(colof(pp), m - 1)];
     const double2 xcol = d.xb[min(c0 + lane, m - 1)];
     const double2* g0 = d.A + (int64_t)(k + 1) * ld + (k + 1);
-    // (only the lower triangle is up to date: a diagonal tile reads its
-    // upper entries as conj(G[c][r]))
+    // (the lower triangle and the band of 64 above the diagonal are up to
+    // date, which covers a diagonal tile)
     double2 a[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp) {
-        const int r = min(rowof(q), m - 1), c = min(colof(pp), m - 1);
-        a[q][pp] = g0[c > r ? (int64_t)c * ld + r : (int64_t)r * ld + c];
-      }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int pp = 0; pp < 4; ++pp)
-        if (min(colof(pp), m - 1) > min(rowof(q), m - 1)) a[q][pp].y = -a[q][pp].y;
+      for (int pp = 0; pp < 4; ++pp) a[q][pp] = g0[(int64_t)min(rowof(q), m - 1) * ld + min(colof(pp), m - 1)];
     reflector_norm();
     // row sums over this thread's columns (x_0 = alpha left out: v_0 = 1 is
     // added through G[r][0] itself); column sums over its rows (rows > 0
@@ -649,11 +641,19 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
   if (skipped(d)) return;
   const int n = sz.n[lc.p], ld = d.ld, tid = threadIdx.x;
   const int nbp = min(HTD_NB, n - 1 - p0), p1 = p0 + nbp, mt = n - p1;
-  // tile (ti, tj), tj <= ti, of the lower triangle: b = ti (ti + 1) / 2 + tj
+  // tile (ti, tj): b < T (T + 1) / 2 the lower triangle, b = ti (ti + 1) / 2 + tj;
+  // then the tiles (u, u + 1) just above the diagonal, so that every entry
+  // less than 64 above the diagonal is up to date too (whatever the tiles'
+  // anchoring, such an entry lies in a diagonal or superdiagonal tile)
+  const int T = (mt + 63) / 64, NL = T * (T + 1) / 2;
   int ti = (int)((sqrtf(8.0f * (float)lc.b + 1.0f) - 1.0f) * 0.5f);
   while (ti * (ti + 1) / 2 > lc.b) --ti;
   while ((ti + 1) * (ti + 2) / 2 <= lc.b) ++ti;
-  const int tj = lc.b - ti * (ti + 1) / 2;
+  int tj = lc.b - ti * (ti + 1) / 2;
+  if (lc.b >= NL) {
+    ti = lc.b - NL;
+    tj = ti + 1;
+  }
   const int kl = p1 - 1;
   const int nb = htd_hemv_blocks(n, kl);
   const int r0 = p1 + ti * 64, c0 = p1 + tj * 64;
@@ -792,7 +792,8 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
   const int r0 = (tid / CG) * TR, c0 = (tid % CG) * TC;
   // (unconditional loads at clamped, valid addresses, masked afterwards: no
   // load waits for the one before it)
-  // (only the lower triangle is up to date: upper entries as conj(G[c][r]))
+  // (the panel updates keep the lower triangle and only a band above the
+  // diagonal up to date: upper entries as conj(G[c][r]))
   double2 a[TR][TC];
   const double2* blk = d.A + (int64_t)k0 * ld + k0;
 #pragma unroll

@@ -110,7 +110,8 @@ constexpr int BT_NB = 32;      // reflectors per block of the back-transformatio
 
 struct HtdDesc {
   double2* A;       // n x n Hermitian (ld); the reduction keeps the lower triangle
-                    // of the trailing block up to date; row k keeps reflector v_k (cols > k)
+                    // of the trailing block and the entries less than 64 above
+                    // its diagonal up to date; row k keeps reflector v_k (cols > k)
   double2* V;       // out: eigenvectors as columns (ld), descending eigenvalues
   double* lam;      // out: eigenvalues, descending (n)
   Dim n;
@@ -177,12 +178,12 @@ __host__ __device__ inline int htd_col_blocks(int n, int k) {
   return m > 0 && k < htd_tail_start(n) ? (m + KC_ROWS - 1) / KC_ROWS : 0;
 }
 // panel starting at column p0: trailing matrix from p0 + min(HTD_NB, n - 1 - p0),
-// the 64 x 64 tiles of its lower triangle
+// the 64 x 64 tiles of its lower triangle and those just above the diagonal
 __host__ __device__ inline int htd_her2k_blocks(int n, int p0) {
   const int nbp = n - 1 - p0 < HTD_NB ? n - 1 - p0 : HTD_NB;
   if (nbp <= 0 || p0 >= htd_tail_start(n)) return 0;
   const int t = (n - p0 - nbp + 63) / 64;
-  return t * (t + 1) / 2;
+  return t * (t + 1) / 2 + t - 1;
 }
 __host__ __device__ inline int htd_rows(int n) { return (n + 255) / 256; }
 __host__ __device__ inline int htd_waves(int n) { return (n + 3) / 4; }  // one wavefront per index

@@ -1401,7 +1401,7 @@ __global__ __launch_bounds__(256) void dc_wave_kernel(const HtdDesc* __restrict_
 __global__ __launch_bounds__(256) void dc_place_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz, int L) {
   __shared__ double lamv[HTD_MAX];
   __shared__ double dv[HTD_MAX];
-  __shared__ int pdef[64];
+  __shared__ int pdef[64], srcc[64];
   const Loc lc = locate(sz, blockIdx.x, [L](int n) { return htd_place_blocks(n, L); });
   if (lc.p < 0) return;
   const HtdDesc& d = ds[lc.p];
@@ -1416,11 +1416,22 @@ __global__ __launch_bounds__(256) void dc_place_kernel(const HtdDesc* __restrict
   double* Qout = d.Q[L & 1];
   const int* cnt = d.cnt + 4 * lo;
   const int cw = min(64, K - c0);
-  if (!cnt[3]) {  // nothing merged: the node's block as it was
-    for (int e = tid; e < cw * K; e += 256) {
-      const int c = c0 + e / K, r = e % K;
-      Qout[(int64_t)(lo + c) * ld + lo + r] = Qin[(int64_t)(lo + c) * ld + lo + r];
+  const int wave = tid >> 6, lane = tid & 63;
+  // one column of K rows by one wavefront, 4 loads per lane in flight
+  // (clamped, the stores guarded)
+  auto copy_col = [&](const double* src, double* dst) {
+    for (int r0 = 0; r0 < K; r0 += 256) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = src[min(r0 + 64 * u + lane, K - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r0 + 64 * u + lane < K) dst[r0 + 64 * u + lane] = v[u];
     }
+  };
+  if (!cnt[3]) {  // nothing merged: the node's block as it was
+    for (int t = wave; t < cw; t += 4)
+      copy_col(Qin + (int64_t)(lo + c0 + t) * ld + lo, Qout + (int64_t)(lo + c0 + t) * ld + lo);
     if (tid < cw) Dout[lo + c0 + tid] = Din[lo + c0 + tid];
     return;
   }
@@ -1458,13 +1469,12 @@ __global__ __launch_bounds__(256) void dc_place_kernel(const HtdDesc* __restrict
         b = mm;
     }
     pdef[tid] = q + a;
+    srcc[tid] = d.dcol[lo + q];
     Dout[lo + q + a] = x;
   }
   __syncthreads();
-  for (int e = tid; e < qn * K; e += 256) {
-    const int t = e / K, r = e % K;
-    Qout[(int64_t)(lo + pdef[t]) * ld + lo + r] = Qin[(int64_t)d.dcol[lo + c0 + t] * ld + lo + r];
-  }
+  for (int t = wave; t < qn; t += 4)
+    copy_col(Qin + (int64_t)srcc[t] * ld + lo, Qout + (int64_t)(lo + pdef[t]) * ld + lo);
 }
 
 // Eigenvector of root k = Q_in[:, ndcol] u_k, written to column lo + pos_k:

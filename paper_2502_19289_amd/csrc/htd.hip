@@ -1512,14 +1512,38 @@ __global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict_
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::zero();
+  // this thread stages column c = tid % 64 (root k0 + c, row r0 + c) of rows
+  // kk = tid / 64 + 4 i (pole j0 + kk): the root's values are loaded once;
+  // the next slice's pole values and Q_in entries are loaded (unconditionally,
+  // at clamped indexes) before the products of the current one
+  const int c = tid & 63, kk0 = tid >> 6;
+  const int kc = min(k0 + c, K2 - 1), rc = min(r0 + c, K - 1);
+  const int ok = org[kc];
+  const double dlo = dl[ok], stk = st[kc], unk = un[kc];
+  double pz[4], pd[4], pq[4];
+  auto fetch = [&](int j0) {
+    int nj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = min(j0 + kk0 + 4 * i, K2 - 1);
+      pz[i] = zh[j];
+      pd[i] = dl[j];
+      nj[i] = ndc[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pq[i] = Qin[(int64_t)nj[i] * ld + lo + rc];
+  };
+  fetch(0);
   for (int j0 = 0; j0 < K2; j0 += 16) {
-    for (int e = tid; e < 1024; e += 256) {
-      const int kk = e >> 6, c = e & 63;  // pole j0 + kk; root k0 + c / row r0 + c
-      const int j = j0 + kk, k = k0 + c, r = r0 + c;
-      As[kk][c] = (j < K2 && k < K2) ? zh[j] / delta_jk(dl, j, org[k], st[k]) * un[k] : 0.0;
-      Bs[kk][c] = (j < K2 && r < K) ? Qin[(int64_t)ndc[j] * ld + lo + r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kk = kk0 + 4 * i, j = j0 + kk;
+      // u_k[j] = zhat_j / (dl_j - lambda_k) / |.|, lambda_k = dl[origin_k] + stau_k
+      As[kk][c] = (j < K2 && k0 + c < K2) ? pz[i] / ((pd[i] - dlo) - stk) * unk : 0.0;
+      Bs[kk][c] = (j < K2 && r0 + c < K) ? pq[i] : 0.0;
     }
     __syncthreads();
+    if (j0 + 16 < K2) fetch(j0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 16; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;

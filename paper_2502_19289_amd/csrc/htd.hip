@@ -438,6 +438,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   // folded into a branch right after its load would wait for it before the
   // later loads are issued)
   const int nka = htd_col_blocks(n, k);
+  static_assert(HTD_MAX / KC_ROWS <= 64, "the norm records are reduced by one wavefront");
   const double2 rq0 = d.kpart[(int64_t)(tid < nka ? tid : 0) * HTD_KP];
   const double2 rq = tid < nka ? rq0 : make_double2(0.0, 0.0);
   const double2 alpha = d.xb[0];
@@ -1023,6 +1024,15 @@ __global__ __launch_bounds__(1024) void dc_prep_kernel(const HtdDesc* __restrict
   const double eb = d.e[mid - 1];
   const double rho = 2.0 * fabs(eb), sg = eb >= 0.0 ? 1.0 : -1.0;
   const double r2 = 0.70710678118654752440;
+  // Every slot starts valid: with NaN values (a corrupted input) the ranks
+  // below can collide and leave slots unwritten, and their columns are used
+  // as indexes by the later kernels of the merge.
+  for (int t = tid; t < K; t += 1024) {
+    Ds[t] = 0.0;
+    zs[t] = 0.0;
+    col[t] = lo + t;
+  }
+  __syncthreads();
   for (int t = tid; t < K; t += 1024) {
     double val, z;
     int rank;

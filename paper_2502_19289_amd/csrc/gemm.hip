@@ -21,30 +21,6 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
-// Complex 16x16 accumulator block with three real products per complex
-// product (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi),
-// re = P1 - P2, im = P3 - P1 - P2.  Used for the FP64 Gram matrix: a quarter
-// fewer matrix-core products; the error of an entry stays of order
-// u sum |a| |b| (at most about twice the four-product bound on the
-// imaginary part).
-template <typename T>
-struct CAcc3 {
-  typename Mfma<T>::acc_t p1, p2, p3;
-  __device__ __forceinline__ void clear() { p1 = p2 = p3 = Mfma<T>::zero(); }
-  __device__ __forceinline__ void mac(T ar, T ai, T br, T bi) {
-    p1 = Mfma<T>::mac(ar, br, p1);
-    p2 = Mfma<T>::mac(ai, bi, p2);
-    p3 = Mfma<T>::mac(ar + ai, br + bi, p3);
-  }
-};
-template <typename T>
-__device__ __forceinline__ T acc_re(const CAcc<T>& a, int r) { return a.re[r]; }
-template <typename T>
-__device__ __forceinline__ T acc_im(const CAcc<T>& a, int r) { return a.im[r]; }
-template <typename T>
-__device__ __forceinline__ T acc_re(const CAcc3<T>& a, int r) { return a.p1[r] - a.p2[r]; }
-template <typename T>
-__device__ __forceinline__ T acc_im(const CAcc3<T>& a, int r) { return a.p3[r] - a.p1[r] - a.p2[r]; }
 
 enum { MODE_NN = 0, MODE_GRAM = 1, MODE_CN = 2 };
 

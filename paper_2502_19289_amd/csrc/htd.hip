@@ -705,7 +705,7 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
   const double2 al = cmul(make_double2(-0.5 * tl.x, -0.5 * tl.y), make_double2(sx, sy));
   if (tid < 128) wl[tid] = cadd(cadd(yh[0][tid], yh[1][tid]), cmul(al, vl));
   __syncthreads();
-  CAcc<double> acc[2][2];
+  CAcc3<double> acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -761,7 +761,8 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
         const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
         if (r < n && c < n)
-          d.A[(int64_t)r * ld + c] = make_double2(at[x][y][q].x - acc[x][y].re[q], at[x][y][q].y - acc[x][y].im[q]);
+          d.A[(int64_t)r * ld + c] =
+              make_double2(at[x][y][q].x - acc_re(acc[x][y], q), at[x][y][q].y - acc_im(acc[x][y], q));
       }
 }
 
@@ -1709,7 +1710,7 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
       rb[u] = d.V[(int64_t)min(j, rend - 1) * ld + min(c0 + c, nc - 1)];
     }
   };
-  CAcc<double> acc[BPW];
+  CAcc3<double> acc[BPW];
 #pragma unroll
   for (int q = 0; q < BPW; ++q) acc[q].clear();
   fetch(rbeg);
@@ -1747,7 +1748,7 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
     for (int r = 0; r < 4; ++r) {
       const int i = bi * 16 + Mfma<double>::row(lane, r);
       const int c = c0 + bj * 16 + (lane & 15);
-      if (c < nc) d.Wp[((int64_t)ch * BT_NB + i) * ld + c] = make_double2(acc[q].re[r], acc[q].im[r]);
+      if (c < nc) d.Wp[((int64_t)ch * BT_NB + i) * ld + c] = make_double2(acc_re(acc[q], r), acc_im(acc[q], r));
     }
   }
 }
@@ -1817,7 +1818,7 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
       rb[u] = d.W[(int64_t)i * ld + min(c0 + x, nc - 1)];
     }
   };
-  CAcc<double> acc[2][2];
+  CAcc3<double> acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -1870,7 +1871,8 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
         const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
         if (j < n && c < nc)
-          d.V[(int64_t)j * ld + c] = make_double2(zt[x][y][r].x - acc[x][y].re[r], zt[x][y][r].y - acc[x][y].im[r]);
+          d.V[(int64_t)j * ld + c] =
+              make_double2(zt[x][y][r].x - acc_re(acc[x][y], r), zt[x][y][r].y - acc_im(acc[x][y], r));
       }
 }
 

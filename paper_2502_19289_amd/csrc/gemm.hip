@@ -9,8 +9,6 @@
 // wavefronts own 32x32 quadrants made of 2x2 MFMA blocks.  K advances in slices
 // of 16 staged in LDS k-major (As[k][m], Bs[k][n]) so that the sixteen lanes
 // that share a k read consecutive addresses.
-#include <type_traits>
-
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -71,8 +69,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  using Acc = typename std::conditional<MODE == MODE_GRAM && sizeof(TM) == 8, CAcc3<TM>, CAcc<TM>>::type;
-  Acc acc[2][2];
+  CAcc3<TM> acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -58,10 +58,11 @@ struct CAcc {
 
 // Complex 16x16 accumulator block with three real products per complex
 // product (Gauss): P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi),
-// re = P1 - P2, im = P3 - P1 - P2.  Used for the FP64 products (Gram matrix,
-// panel update, back-transformation): a quarter fewer matrix-core products;
-// the error of an entry stays of order u sum |a| |b| (at most about twice
-// the four-product bound on the imaginary part).
+// re = P1 - P2, im = P3 - P1 - P2.  Used by all complex GEMMs (FP32 and
+// FP64: contractions, Gram matrix, panel update, back-transformation): a
+// quarter fewer matrix-core products; the error of an entry stays of order
+// u sum |a| |b| (at most about twice the four-product bound on the
+// imaginary part).
 template <typename T>
 struct CAcc3 {
   typename Mfma<T>::acc_t p1, p2, p3;

@@ -6,8 +6,9 @@
 //   D (16x16): accumulator element r of a lane is D[row(lane, r)][lane % 16],
 //              row = 4*(lane/16) + r for f32 but 4*r + lane/16 for f64
 //              (both measured on gfx950)
-// A complex product is split into four real products sharing the fragments:
-//   Dre += Ar Br - Ai Bi,  Dim += Ar Bi + Ai Br   (8 real flops per complex MAC).
+// A complex product is split into real products sharing the fragments: four
+// (CAcc: Dre += Ar Br - Ai Bi, Dim += Ar Bi + Ai Br; 8 real flops per complex
+// MAC) or three (CAcc3, Gauss's form, below).
 #pragma once
 #include <hip/hip_runtime.h>
 

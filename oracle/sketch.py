@@ -1,10 +1,11 @@
 """Oracle of the learned-sketch truncated SVD (FP64, CPU).
 
-The paper says nothing about sketching; this is the build's addition: a small
-network predicts the rank a truncated SVD will keep, and that prediction sets
-the size of a randomized range finder (N. Halko, P.-G. Martinsson, J. A. Tropp,
-SIAM Rev. 53, 217 (2011), Algs. 4.1 and 5.1, a-posteriori error estimate of
-Sec. 4.3).  The exact truncated SVD remains the fallback and the judge.
+The paper says nothing about sketching; this is an addition to the method: a
+small network predicts the rank a truncated SVD will keep, and that prediction
+sets the size of a randomized range finder (N. Halko, P.-G. Martinsson,
+J. A. Tropp, SIAM Rev. 53, 217 (2011), Algs. 4.1 and 5.1, a-posteriori error
+estimate of Sec. 4.3).  The exact truncated SVD remains the fallback and the
+reference.
 
 Contents
   mlp_forward / mlp_backward : 12 -> 64 -> 64 -> 1 network with GELU (tanh form),

@@ -4,14 +4,20 @@ A step is one cluster-TEBD iteration (arXiv:2502.19289, Sec. III.A) of the
 chi_max = 1024 workload (200 qubits, 50 random-structured layers, T density 0.2,
 clusters of at most 6 qubits, eps = 1e-10): plan the clusters, build each
 cluster unitary, merge its MPS block, apply the unitary, split it back with
-truncated SVDs and record the discarded weight.  The state evolves from
-|0...0>; untimed warm-up steps bring a quarter of the bonds up to chi_max
-(the state lives in HBM from then on), then K steps are timed with the
-batched mixed-precision path and, from the same state, with the plain FP64
-path (FP64 contractions and eigen-solver, one cluster per launch); a replay
-of the timed steps with HIP events around the launches gives the per-kernel
-times and the roofline of the dominant kernel (the short kernels of the
-tridiagonal reduction are timed by bursts of re-launches on the same inputs).
+truncated SVDs and record the discarded weight.
+
+The state evolves from |0...0>.  Preparation steps (untimed, always run,
+reported as ``config.prep_steps``) continue until a quarter of the bonds hold
+chi_max Schmidt values, so the timed steps run at the cap the metric names;
+then ``--warmup`` further untimed steps, then ``--steps`` timed steps with the
+state resident in HBM, with the batched mixed-precision path and, from the
+same state, with the plain FP64 path (FP64 contractions and eigen-solver, one
+cluster per launch).  A replay of the timed steps with HIP events around the
+launches gives the per-kernel times and the roofline of the dominant kernel
+(the short kernels of the tridiagonal reduction are timed by bursts of
+re-launches on the same inputs).  A timed window that starts with no bond at
+chi_max is not the metric's workload: the line then carries
+``"unmeasured": true``, ``value`` null, and the exit status is 1.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
 ``--copy-calibration BYTES`` instead runs one device copy of that size (the
@@ -62,8 +68,11 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=12)
-    ap.add_argument("--warmup", type=int, default=-1,
-                    help="untimed steps first; -1: until a quarter of the bonds reach chi_max")
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed steps after the preparation steps (which always run until a quarter "
+                         "of the bonds hold chi_max values)")
+    ap.add_argument("--saturation", type=float, default=0.25,
+                    help="fraction of bonds at chi_max that ends the preparation steps")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
     ap.add_argument("--eig", default="auto", choices=["auto", "jacobi", "tridiag"],
                     help="eigen-solver of the exact splits")
@@ -71,7 +80,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0: skip)")
-    ap.add_argument("--warmup-budget", type=float, default=240.0, help="seconds cap of the auto warm-up")
+    ap.add_argument("--warmup-budget", type=float, default=300.0, help="seconds cap of the preparation steps")
     ap.add_argument("--copy-calibration", type=int, default=0)
     ap.add_argument("--profile-window", action="store_true",
                     help="ask an attached rocprofv3 to collect only during the timed steps")
@@ -177,9 +186,13 @@ def class_totals(kt: dict, disp: dict, reps: int = BURST_REPS) -> dict:
 def roofline(kt: dict, disp: dict, dtype: str, reps: int = BURST_REPS) -> dict:
     """Dominant kernel class of the timed region against its peak: HBM
     bandwidth for the classes that report algorithmic bytes, else the flop
-    peak of its unit."""
+    peak of its unit.  Only classes with an algorithmic work count compete
+    (a class without one would give a fraction that follows from nothing)."""
     totals = class_totals(kt, disp, reps)
-    name = max(totals, key=totals.get)
+    counted = {k: v for k, v in totals.items() if kt[k][2] > 0 or kt[k][3] > 0}
+    if not counted:
+        return None
+    name = max(counted, key=counted.get)
     ms, launches, flop, nbytes = kt[name]
     avg_ms = ms / max(1, launches)
     timing = {"launches_timed": launches, "dispatches": disp.get(name, launches)}
@@ -211,42 +224,50 @@ def mfma_share(kt: dict, dtype: str) -> dict:
     return out
 
 
-def cpu_baseline(m, circ, p, remaining: int, budget: float) -> dict:
-    """The FP64 oracle on the clusters of the next step of the same workload
-    (their site tensors exported from the GPU state), until `budget` seconds.
-    `remaining` is the number of sub-layers the library still holds."""
+def cpu_baseline(m, circ, p, remaining: int, steps: int, budget: float) -> dict:
+    """The FP64 oracle on the clusters of the timed steps, in order, until
+    `budget` seconds of oracle time: a clone of the GPU state walks the same
+    steps, and before each one the site tensors of its clusters are exported
+    and handed to the oracle's cluster update.  `remaining` is the number of
+    sub-layers the library still holds at the start of the timed steps."""
     from oracle import ctebd as CT
     from oracle import planner as PL
     subs = PL.legalize(circ.layers, p["k_max"])
     start = len(subs) - remaining
-    chi = m.bond_dims()
-    end, clusters = PL.plan_step(subs, start, circ.n, chi, p["k_max"], PL.default_q_max(p["k_max"], p["chi_max"]),
-                                 1 << 30)
-    per_cluster, _ = PL.step_gates(subs, start, end, clusters, circ.n)
+    q_max = PL.default_q_max(p["k_max"], p["chi_max"])
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    done, t_used, shapes = 0, 0.0, []
-    order = sorted(range(len(clusters)), key=lambda i: clusters[i][1])
-    for ci in order:
-        a, k = clusters[ci]
-        B = [m.site(j) for j in range(a, a + k)]
-        lam_l = m.schmidt(a - 1) if a > 0 else np.ones(1)
-        U = CT.cluster_unitary(a, k, per_cluster[ci])
-        psi = CT.MPS([np.ones((1, 2, B[0].shape[0]))] + B, [lam_l] + [np.ones(b.shape[2]) for b in B[:-1]])
-        t0 = time.perf_counter()
-        CT.apply_cluster(psi, 1, k, U, p["chi_max"], p["eps"])
-        t_used += time.perf_counter() - t0
-        done += 1
-        shapes.append([k, int(B[0].shape[0]), int(B[-1].shape[2])])
-        if t_used > budget:
+    walker = m.clone()
+    done, t_used, shapes, steps_seen = 0, 0.0, [], 0
+    for _ in range(steps):
+        if start >= len(subs) or t_used > budget:
             break
+        chi = walker.bond_dims()
+        end, clusters = PL.plan_step(subs, start, circ.n, chi, p["k_max"], q_max, 1 << 30)
+        per_cluster, _ = PL.step_gates(subs, start, end, clusters, circ.n)
+        steps_seen += 1
+        for ci, (a, k) in enumerate(clusters):
+            B = [walker.site(j) for j in range(a, a + k)]
+            lam_l = walker.schmidt(a - 1) if a > 0 else np.ones(1)
+            U = CT.cluster_unitary(a, k, per_cluster[ci])
+            psi = CT.MPS([np.ones((1, 2, B[0].shape[0]))] + B, [lam_l] + [np.ones(b.shape[2]) for b in B[:-1]])
+            t0 = time.perf_counter()
+            CT.apply_cluster(psi, 1, k, U, p["chi_max"], p["eps"])
+            t_used += time.perf_counter() - t0
+            done += 1
+            shapes.append([k, int(B[0].shape[0]), int(B[-1].shape[2])])
+            if t_used > budget:
+                break
+        walker.step()
+        start = end
+    walker.close()
     return {"value": done / t_used if t_used > 0 else None, "unit": "cluster updates/s", "cores": threads,
-            "kind": "oracle", "sample": f"{done} of the {len(clusters)} clusters of the first timed step, "
-            f"smallest k first ([k, chi_l, chi_r] = {shapes}), FP64 NumPy/LAPACK on the host, "
-            f"{t_used:.1f} s"}
+            "kind": "oracle", "sample": f"the first {done} clusters of the timed steps in step order "
+            f"({steps_seen} steps; [k, chi_l, chi_r] = {shapes}), each an FP64 NumPy/LAPACK cluster update "
+            f"on the site tensors the GPU state holds before that step; {t_used:.1f} s of oracle time"}
 
 
 def main():
@@ -270,29 +291,41 @@ def main():
     for layer in circ.layers:
         m.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
 
-    # ---- warm-up (untimed): evolve until the bonds saturate
+    # ---- preparation (untimed, always): evolve until the bonds saturate
     t0 = time.time()
-    wsteps = 0
+    psteps = 0
     rem = None
     while True:
-        if args.warmup >= 0 and wsteps >= args.warmup:
+        d = np.array(m.bond_dims())
+        if (d >= p["chi_max"]).mean() >= args.saturation or time.time() - t0 > args.warmup_budget:
             break
-        if args.warmup < 0:
-            d = np.array(m.bond_dims())
-            if (d >= p["chi_max"]).mean() >= 0.25 or time.time() - t0 > args.warmup_budget:
-                break
         _, rem = m.step()
-        wsteps += 1
+        psteps += 1
         if rem == 0:
             break
-        if wsteps % 50 == 0:
-            print(f"# warm-up step {wsteps}, {time.time() - t0:.0f} s", file=sys.stderr, flush=True)
-    warm_s = time.time() - t0
+        if psteps % 25 == 0:
+            print(f"# preparation step {psteps}, max chi {int(d.max())}, {time.time() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+    prep_s = time.time() - t0
+    print(f"# preparation: {psteps} steps, {prep_s:.1f} s", file=sys.stderr, flush=True)
+    # ---- warm-up (untimed): the requested number of further steps
+    wsteps = 0
+    while wsteps < args.warmup and rem != 0:
+        _, rem = m.step()
+        wsteps += 1
     dims0 = np.array(m.bond_dims())
+    saturated = int((dims0 >= p["chi_max"]).sum())
+    if rem == 0:
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "cluster updates/s", "unmeasured": True,
+                          "reason": "the circuit ended before the timed steps", "n_gpus": 1,
+                          "steps": 0, "warmup": args.warmup, "config": {"workload": args.workload,
+                                                                          "prep_steps": psteps}}))
+        sys.exit(1)
 
     cpu = None
     if args.cpu_seconds > 0 and rem:
-        cpu = cpu_baseline(m, circ, p, rem, args.cpu_seconds)
+        cpu = cpu_baseline(m, circ, p, rem, args.steps, args.cpu_seconds)
+        print(f"# cpu baseline: {cpu['sample'][:120]}", file=sys.stderr, flush=True)
 
     ref = None
     if not args.no_fp64:
@@ -316,14 +349,15 @@ def main():
           flush=True)
     kt = prof.kernel_times()
     disp = prof.kernel_dispatches()
-    value = updates / dt
+    unmeasured = saturated == 0
+    value = None if unmeasured else updates / dt
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "cluster updates/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": wsteps,
+        "warmup": args.warmup,
         "ms_per_step": 1e3 * dt / max(1, steps),
         "higher_is_better": True,
         "scaling": "weak",
@@ -333,15 +367,17 @@ def main():
         "config": {"workload": args.workload, "n": circ.n, "layers": len(circ.layers),
                    "chi_max": p["chi_max"], "k_max": p["k_max"], "eps": p["eps"],
                    "batch": "step", "eig": args.eig, "seed": args.seed,
-                   "bonds_at_chi_max_at_start": int((dims0 >= p["chi_max"]).sum()),
-                   "max_chi_at_start": int(dims0.max())},
+                   "prep_steps": psteps, "warmup_steps_run": wsteps,
+                   "bonds_at_chi_max_at_start": saturated,
+                   "max_chi_at_start": int(dims0.max()),
+                   "mean_chi_at_start": round(float(dims0.mean()), 1)},
         "roofline": roofline(kt, disp, args.precision, args.burst_reps),
         "cpu_baseline": cpu,
         "mfma_frac": mfma_share(kt, args.precision),
         "kernel_ms": {k: round(v, 3) for k, v in class_totals(kt, disp, args.burst_reps).items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "kernel_dispatches": disp,
-        "warmup_s": round(warm_s, 1),
+        "prep_s": round(prep_s, 1),
         "event_timed_ms_per_step": 1e3 * dt_p / max(1, steps_p),
     }
     if ref is not None:
@@ -352,7 +388,12 @@ def main():
         out["infidelity_vs_fp64_path"] = m.infidelity(ref)
         out["F_est"] = m.fidelity()[0]
         out["F_est_fp64_path"] = ref.fidelity()[0]
+    if unmeasured:
+        out["unmeasured"] = True
+        out["reason"] = "no bond held chi_max Schmidt values when the timed steps started"
     print(json.dumps(out))
+    if unmeasured:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -166,6 +166,32 @@ mps_status mps_step(mps_handle h, int* clusters, int* remaining);
  * eps are those of h.  Synchronises. */
 mps_status mps_clone(mps_handle h, const mps_options* opt, mps_handle* out);
 
+/* Changes the options of a live handle (Sec. II.B's chi_max and eta stay
+ * those given to mps_create).  When k_max changes, the buffered layers are
+ * contracted first with the old options (they were routed for the old k_max).
+ * A new precision converts the site tensors on the device (FP64 <-> FP32 is
+ * a rounding; FP32 <-> BF16X6 keeps them as they are); a new hip_stream (NULL:
+ * a stream of the handle's own) is used from the next call on.  Counters,
+ * timing state, the attached sketch network and the fidelity sum carry over.
+ * Synchronises.  MPS_EINVAL for invalid options (h unchanged). */
+mps_status mps_set_options(mps_handle h, const mps_options* opt);
+
+/* Writes the whole handle to the file `path` (replaced atomically through
+ * path + ".part"): n, chi_max, eps, the options (hip_stream excepted), sum
+ * log f, the counters, the sketch generator state, the bond dimensions, every
+ * site tensor as stored (complex64 or complex128, bit for bit), the Schmidt
+ * values and the buffered sub-layers, then a 64-bit FNV-1a checksum of the
+ * preceding bytes; little-endian.  A handle loaded from the file continues
+ * exactly as h would (the same kernels on the same bits).  Synchronises.
+ * MPS_EIO when the file cannot be written. */
+mps_status mps_save(mps_handle h, const char* path);
+
+/* Creates a new handle from a file written by mps_save (its own stream; use
+ * mps_set_options for another).  The file is read and checked on the host
+ * first: MPS_EIO when it cannot be read, is truncated, fails its checksum or
+ * holds out-of-range sizes; mps_last_error(NULL) then says why. */
+mps_status mps_load(const char* path, mps_handle* out);
+
 /* <a|b> of the current states of two handles with the same n (buffered
  * layers are not applied), by a transfer-matrix sweep in FP64 on the device
  * (E <- sum_s A_s^dagger E B_s).  Synchronises. */

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <iterator>
 
 #include "engine.hpp"
 
@@ -120,6 +121,15 @@ struct Fail {
   } while (0)
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Size and timing traces on stderr (CTEBD_EIG_TRACE, CTEBD_HTD_TRACE,
+// CTEBD_SKETCH_TRACE) synchronise the stream; they exist only in builds with
+// -DCTEBD_DEBUG_TRACE.
+#ifdef CTEBD_DEBUG_TRACE
+constexpr bool kDebugTrace = true;
+#else
+constexpr bool kDebugTrace = false;
+#endif
 
 [[noreturn]] void fail(mps_ctx* ctx, mps_status st, const char* msg) {
   ctx->err = msg;
@@ -525,7 +535,7 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
     nb += nb & 1;
     nb_all = std::max(nb_all, std::min(nb, e.nb_max));
   }
-  const bool trace = std::getenv("CTEBD_EIG_TRACE") != nullptr;
+  const bool trace = kDebugTrace && std::getenv("CTEBD_EIG_TRACE") != nullptr;
   const auto t_start = std::chrono::steady_clock::now();
   int sweeps = 0;
   for (int sw = 0; sw < 30; ++sw) {
@@ -587,7 +597,10 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
   const int c_hemv = timing ? ctx->timer.cls_of("trd_hemv") : -1;
   const int c_her2k = timing ? ctx->timer.cls_of("trd_her2k") : -1;
   const int c_bt = timing ? ctx->timer.cls_of("bt") : -1;
-  const bool trace = std::getenv("CTEBD_HTD_TRACE") != nullptr;
+  const int c_col = timing ? ctx->timer.cls_of("trd_col") : -1;
+  const int c_tail = timing ? ctx->timer.cls_of("trd_tail") : -1;
+  const int c_dc = timing ? ctx->timer.cls_of("dc") : -1;
+  const bool trace = kDebugTrace && std::getenv("CTEBD_HTD_TRACE") != nullptr;
   auto t0 = std::chrono::steady_clock::now();
   auto lap = [&](const char* what) {
     if (!trace) return;
@@ -614,7 +627,15 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
         return t;
       };
       const int nb_col = most([k](int n) { return htd_col_blocks(n, k); });
-      timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
+      const bool col_counted = timed_repeatable(ctx, "trd_col", [&] { return launch_trd_col(ha, k, nb_col, s); });
+      if (col_counted)  // algorithmic traffic of the column update: the column, the panel rows of V and W
+                        // written so far and y, once each
+        for (int p = 0; p < np; ++p) {
+          const double m = sz.n[p] - k - 1;
+          if (m <= 0 || k >= htd_tail_start(sz.n[p])) continue;
+          ctx->timer.bytes[c_col] += 16.0 * m * (2.0 + 2.0 * j);
+          ctx->timer.flop[c_col] += 8.0 * 2.0 * j * m;
+        }
       const int nb_hemv = most([k](int n) { return htd_hemv_blocks(n, k); });
       const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(ha, k, nb_hemv, s); });
       if (counted)  // algorithmic traffic of the HEMV: one triangle of the trailing block read once
@@ -641,6 +662,12 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     Timed tm(ctx, "trd_tail");
     HIP_OK(launch_trd_tail(dd, sz, s));
   }
+  if (timing)  // unblocked tail: a Hermitian rank-2 update and a HEMV of the trailing block per column
+    for (int p = 0; p < np; ++p)
+      for (int k = htd_tail_start(sz.n[p]); k < sz.n[p] - 1; ++k) {
+        const double mt = sz.n[p] - k - 1;
+        ctx->timer.flop[c_tail] += 8.0 * 3.0 * mt * mt;
+      }
   lap("reduction");
   {
     Timed tm(ctx, "dc");
@@ -659,6 +686,12 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
     for (int stage = 1; stage < 4; ++stage) HIP_OK(launch_dc_wave(stage, dd, sz, L, waves, s));
     HIP_OK(launch_dc_place(dd, sz, L, total([L](int n) { return htd_place_blocks(n, L); }), s));
     HIP_OK(launch_dc_gemm(dd, sz, L, total([L](int n) { return htd_gemm_tiles(n, L); }), s));
+    if (timing)  // merge products of the real eigenvector blocks: two (h x h) by (h x s) per node, h = s / 2
+      for (int p = 0; p < np; ++p)
+        for (int a = 0; a < sz.n[p]; a += 1 << L) {
+          const double sn = std::min(1 << L, sz.n[p] - a), h = sn / 2;
+          ctx->timer.flop[c_dc] += 2.0 * 2.0 * h * h * sn;
+        }
   }
   lap("divide and conquer");
   {
@@ -1450,7 +1483,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       else
         ctx->stats.sketch_fallback += 1;
     }
-    if (std::getenv("CTEBD_SKETCH_TRACE")) {
+    if (kDebugTrace && std::getenv("CTEBD_SKETCH_TRACE")) {
       for (int q = 0; q < nsk; ++q) {
         double est[2];
         HIP_OK(hipMemcpy(est, sk[q].est, sizeof(est), hipMemcpyDeviceToHost));
@@ -1624,6 +1657,64 @@ void destroy_ctx(mps_ctx* ctx) {
   delete ctx;
 }
 
+bool options_valid(const mps_options& o) {
+  return o.k_max >= 2 && o.k_max <= 12 && o.precision >= 0 && o.precision <= 2 && o.svd_mode >= 0 &&
+         o.svd_mode <= 1 && o.batch >= 0 && o.batch <= 1 && o.eig_method >= 0 && o.eig_method <= 2 &&
+         o.floor_c >= 0.0;
+}
+
+// ---- saved-state files (mps_save / mps_load): little-endian fields in the
+// order mps_save writes them, then a 64-bit FNV-1a checksum of the bytes before
+constexpr char kSaveMagic[8] = {'C', 'T', 'E', 'B', 'D', 'M', 'P', 'S'};
+constexpr uint32_t kSaveVersion = 1;
+
+uint64_t fnv1a(const char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= (unsigned char)p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+struct Writer {
+  std::vector<char> buf;
+  void raw(const void* p, size_t n) { buf.insert(buf.end(), (const char*)p, (const char*)p + n); }
+  template <typename T>
+  void put(T v) {
+    raw(&v, sizeof(T));
+  }
+};
+
+struct Reader {
+  const char* data;
+  size_t end;
+  size_t pos = 0;
+  bool ok = true;
+  template <typename T>
+  T get() {
+    T v{};
+    if (!ok || pos + sizeof(T) > end) {
+      ok = false;
+      return v;
+    }
+    std::memcpy(&v, data + pos, sizeof(T));
+    pos += sizeof(T);
+    return v;
+  }
+  const char* skip(size_t n) {
+    if (!ok || pos + n > end) {
+      ok = false;
+      return data;
+    }
+    const char* p = data + pos;
+    pos += n;
+    return p;
+  }
+};
+
+thread_local std::string g_err;  // message of the last failed call without a handle
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1654,9 +1745,7 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
     else
       mps_default_options(&ctx->opt);
     const mps_options& o = ctx->opt;
-    if (o.k_max < 2 || o.k_max > 12 || o.precision < 0 || o.precision > 2 || o.svd_mode < 0 ||
-        o.svd_mode > 1 || o.batch < 0 || o.batch > 1 || o.eig_method < 0 || o.eig_method > 2 ||
-        !(o.floor_c >= 0.0)) {
+    if (!options_valid(o)) {
       ctx->err = "invalid options";
       return MPS_EINVAL;
     }
@@ -1870,6 +1959,220 @@ mps_status mps_clone(mps_handle src, const mps_options* opt, mps_handle* out) {
     return st;
   }
   *out = dst;
+  return MPS_OK;
+}
+
+mps_status mps_set_options(mps_handle ctx, const mps_options* opt) {
+  if (!ctx || !opt) return MPS_EINVAL;
+  if (!options_valid(*opt)) {
+    ctx->err = "invalid options";
+    return MPS_EINVAL;
+  }
+  return guarded(ctx, [&]() -> mps_status {
+    // buffered sub-layers were routed for the current k_max: run them first
+    if (opt->k_max != ctx->opt.k_max) flush_all(ctx);
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    // the state goes into a handle built with the new options (site tensors
+    // converted when the precision changes); the two handles then trade
+    // contents, and what a clone does not copy comes along explicitly
+    mps_handle fresh = nullptr;
+    const mps_status st = mps_clone(ctx, opt, &fresh);
+    if (st != MPS_OK) {
+      ctx->err = "mps_set_options: the state could not be moved to the new options";
+      return st;
+    }
+    fresh->pending = ctx->pending;
+    fresh->stats = ctx->stats;
+    fresh->timing = ctx->timing;
+    std::swap(fresh->timer, ctx->timer);
+    fresh->mlp_params = ctx->mlp_params;
+    fresh->log_x.swap(ctx->log_x);
+    fresh->log_t.swap(ctx->log_t);
+    fresh->sketch_seed = ctx->sketch_seed;
+    fresh->sketch_stream = ctx->sketch_stream;
+    std::swap(*ctx, *fresh);
+    destroy_ctx(fresh);  // now holds the previous state and stream
+    return MPS_OK;
+  });
+}
+
+mps_status mps_save(mps_handle ctx, const char* path) {
+  if (!ctx || !path) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    Writer w;
+    w.raw(kSaveMagic, 8);
+    w.put<uint32_t>(kSaveVersion);
+    w.put<int32_t>(ctx->n);
+    w.put<int32_t>(ctx->chi_max);
+    w.put<double>(ctx->eps);
+    const mps_options& o = ctx->opt;
+    for (int v : {o.k_max, o.q_max, o.l_max, o.precision, o.svd_mode, o.batch, o.eig_method}) w.put<int32_t>(v);
+    w.put<double>(o.floor_c);
+    double lf = 0;
+    HIP_OK(hipMemcpy(&lf, ctx->d_logf, sizeof(double), hipMemcpyDeviceToHost));
+    w.put<double>(lf);
+    const mps_stats& st = ctx->stats;
+    for (int64_t v : {st.steps, st.cluster_updates, st.svds, st.site_updates, st.sketch_accepted,
+                      st.sketch_fallback, st.jacobi_sweeps})
+      w.put<int64_t>(v);
+    w.put<double>(st.discarded_weight);
+    w.put<uint64_t>(ctx->sketch_seed);
+    w.put<uint32_t>(ctx->sketch_stream);
+    for (int b = 0; b < ctx->n - 1; ++b) w.put<int32_t>(ctx->chi[b]);
+    std::vector<char> tmp;
+    for (int j = 0; j < ctx->n; ++j) {  // site tensors as stored (complex64 or complex128)
+      const size_t bytes = (size_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j) * ctx->esz;
+      tmp.resize(bytes);
+      HIP_OK(hipMemcpy(tmp.data(), ctx->site[j], bytes, hipMemcpyDeviceToHost));
+      w.raw(tmp.data(), bytes);
+    }
+    for (int b = 0; b < ctx->n - 1; ++b) {
+      tmp.resize(ctx->chi[b] * sizeof(double));
+      HIP_OK(hipMemcpy(tmp.data(), ctx->lam[b], tmp.size(), hipMemcpyDeviceToHost));
+      w.raw(tmp.data(), tmp.size());
+    }
+    w.put<uint32_t>((uint32_t)ctx->pending.size());
+    for (const auto& sl : ctx->pending) {
+      w.put<uint32_t>((uint32_t)sl.size());
+      for (const auto& g : sl) {
+        w.put<int32_t>(g.nq);
+        w.put<int32_t>(g.q[0]);
+        w.put<int32_t>(g.q[1]);
+        for (int e = 0; e < 16; ++e) {
+          w.put<double>(g.u[e].real());
+          w.put<double>(g.u[e].imag());
+        }
+      }
+    }
+    w.put<uint64_t>(fnv1a(w.buf.data(), w.buf.size()));
+    const std::string part = std::string(path) + ".part";
+    {
+      std::ofstream f(part, std::ios::binary | std::ios::trunc);
+      if (!f) fail(ctx, MPS_EIO, "mps_save: cannot open the file for writing");
+      f.write(w.buf.data(), (std::streamsize)w.buf.size());
+      if (!f) fail(ctx, MPS_EIO, "mps_save: write failed");
+    }
+    if (std::rename(part.c_str(), path) != 0) fail(ctx, MPS_EIO, "mps_save: cannot move the file into place");
+    return MPS_OK;
+  });
+}
+
+mps_status mps_load(const char* path, mps_handle* out) {
+  if (!path || !out) {
+    g_err = "mps_load: null argument";
+    return MPS_EINVAL;
+  }
+  *out = nullptr;
+  std::vector<char> buf;
+  {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) {
+      g_err = "mps_load: cannot open the file";
+      return MPS_EIO;
+    }
+    buf.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+  }
+  // everything is read and checked on the host before a handle exists
+  Reader r{buf.data(), buf.size() >= 8 ? buf.size() - 8 : 0};
+  auto bad = [&](const char* why) {
+    g_err = std::string("mps_load: ") + why;
+    return MPS_EIO;
+  };
+  if (buf.size() < 16 || std::memcmp(buf.data(), kSaveMagic, 8) != 0) return bad("not a saved state");
+  uint64_t sum = 0;
+  std::memcpy(&sum, buf.data() + buf.size() - 8, 8);
+  if (sum != fnv1a(buf.data(), buf.size() - 8)) return bad("checksum mismatch");
+  r.pos = 8;
+  if (r.get<uint32_t>() != kSaveVersion) return bad("unknown version");
+  const int n = r.get<int32_t>(), chi_max = r.get<int32_t>();
+  const double eps = r.get<double>();
+  mps_options o{};
+  o.k_max = r.get<int32_t>();
+  o.q_max = r.get<int32_t>();
+  o.l_max = r.get<int32_t>();
+  o.precision = r.get<int32_t>();
+  o.svd_mode = r.get<int32_t>();
+  o.batch = r.get<int32_t>();
+  o.eig_method = r.get<int32_t>();
+  o.floor_c = r.get<double>();
+  o.hip_stream = nullptr;
+  const double log_f = r.get<double>();
+  mps_stats st{};
+  st.steps = r.get<int64_t>();
+  st.cluster_updates = r.get<int64_t>();
+  st.svds = r.get<int64_t>();
+  st.site_updates = r.get<int64_t>();
+  st.sketch_accepted = r.get<int64_t>();
+  st.sketch_fallback = r.get<int64_t>();
+  st.jacobi_sweeps = r.get<int64_t>();
+  st.discarded_weight = r.get<double>();
+  const uint64_t sk_seed = r.get<uint64_t>();
+  const uint32_t sk_stream = r.get<uint32_t>();
+  if (!r.ok || n < 2 || n > (1 << 24) || chi_max < 1 || chi_max > 2048 || !options_valid(o))
+    return bad("malformed header");
+  std::vector<int> chi(n - 1);
+  for (int b = 0; b < n - 1; ++b) {
+    chi[b] = r.get<int32_t>();
+    const int e = std::min(b + 1, n - b - 1);
+    const int cap = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
+    if (!r.ok || chi[b] < 1 || chi[b] > cap) return bad("bond dimension out of range");
+  }
+  const size_t esz = o.precision == MPS_PREC_FP64 ? 16 : 8;
+  std::vector<const char*> site_at(n), lam_at(n - 1);
+  for (int j = 0; j < n; ++j) {
+    const size_t bytes = (size_t)(j > 0 ? chi[j - 1] : 1) * 2 * (j < n - 1 ? chi[j] : 1) * esz;
+    site_at[j] = r.skip(bytes);
+  }
+  for (int b = 0; b < n - 1; ++b) lam_at[b] = r.skip(chi[b] * sizeof(double));
+  std::vector<SubLayer> pending(r.get<uint32_t>());
+  for (auto& sl : pending) {
+    sl.resize(r.ok ? r.get<uint32_t>() : 0);
+    if (sl.size() > (size_t)n) return bad("malformed sub-layer");
+    for (auto& g : sl) {
+      g.nq = r.get<int32_t>();
+      g.q[0] = r.get<int32_t>();
+      g.q[1] = r.get<int32_t>();
+      for (int e = 0; e < 16; ++e) {
+        const double re = r.get<double>(), im = r.get<double>();
+        g.u[e] = cplx(re, im);
+      }
+      if (g.nq < 1 || g.nq > 2 || g.q[0] < 0 || g.q[0] >= n || g.q[1] < 0 || g.q[1] >= n)
+        return bad("malformed gate");
+    }
+  }
+  if (!r.ok || r.pos != buf.size() - 8) return bad("truncated or oversized file");
+  mps_handle h = nullptr;
+  mps_status cs = mps_create(n, chi_max, eps, &o, &h);
+  if (cs != MPS_OK) {
+    g_err = "mps_load: could not create the handle";
+    return cs;
+  }
+  mps_ctx* ctx = h;
+  cs = guarded(ctx, [&]() -> mps_status {
+    hipStream_t s = ctx->stream;
+    ctx->chi = chi;
+    for (int j = 0; j < n; ++j) {
+      const size_t bytes = (size_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j) * esz;
+      HIP_OK(hipMemcpyAsync(ctx->site[j], site_at[j], bytes, hipMemcpyHostToDevice, s));
+    }
+    for (int b = 0; b < n - 1; ++b)
+      HIP_OK(hipMemcpyAsync(ctx->lam[b], lam_at[b], chi[b] * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->d_chi, ctx->chi.data(), (n - 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));  // the host buffers above are released on return
+    ctx->stats = st;
+    ctx->sketch_seed = sk_seed;
+    ctx->sketch_stream = sk_stream;
+    ctx->pending.swap(pending);
+    return MPS_OK;
+  });
+  if (cs != MPS_OK) {
+    g_err = "mps_load: " + ctx->err;
+    mps_destroy(h);
+    return cs;
+  }
+  *out = h;
   return MPS_OK;
 }
 
@@ -2149,9 +2452,6 @@ mps_status mps_kernel_times(mps_handle ctx, double* ms, int64_t* launches, doubl
   return MPS_OK;
 }
 
-namespace {
-thread_local std::string g_err;  // message of the last failed call without a handle
-}
 
 mps_status mps_heev(int n, const double* A, double* w, double* V) {
   if (n < 1 || n > HTD_MAX || !A || !w || !V) {

@@ -47,7 +47,8 @@ class CtebdError(RuntimeError):
         self.status = status
 
 
-EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster",
+EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster", "mps_set_options",
+           "mps_save", "mps_load",
            "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
@@ -90,6 +91,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_queue_layer.argtypes = [P, C.POINTER(GateC), I]
     lib.mps_step.argtypes = [P, C.POINTER(I), C.POINTER(I)]
     lib.mps_clone.argtypes = [P, C.POINTER(Options), C.POINTER(P)]
+    lib.mps_set_options.argtypes = [P, C.POINTER(Options)]
+    lib.mps_save.argtypes = [P, C.c_char_p]
+    lib.mps_load.argtypes = [C.c_char_p, C.POINTER(P)]
     lib.mps_overlap.argtypes = [P, P, C.POINTER(D), C.POINTER(D)]
     lib.mps_fidelity.argtypes = [P, C.POINTER(D), C.POINTER(D)]
     lib.mps_bond_dims.argtypes = [P, C.POINTER(I)]
@@ -228,6 +232,65 @@ class MPS:
         self._check(self.lib.mps_clone(self.h, C.byref(o), C.byref(h)))
         m = MPS.__new__(MPS)
         m.lib, m.h, m.n, m._opt = self.lib, h, self.n, o
+        return m
+
+    def options(self) -> dict:
+        o = self._opt
+        inv = lambda d, v: next(k for k, x in d.items() if x == v)  # noqa: E731
+        return {"k_max": o.k_max, "q_max": o.q_max, "l_max": o.l_max, "precision": inv(PREC, o.precision),
+                "batch": inv(BATCH, o.batch), "svd": inv(SVD, o.svd_mode), "eig": inv(EIG, o.eig_method),
+                "floor_c": o.floor_c}
+
+    def set_options(self, k_max: Optional[int] = None, q_max: Optional[int] = None, l_max: Optional[int] = None,
+                    precision: Optional[str] = None, batch: Optional[str] = None, svd: Optional[str] = None,
+                    eig: Optional[str] = None, floor_c: Optional[float] = None, hip_stream: Optional[int] = None):
+        """mps_set_options: fields left at None keep their current value."""
+        o = Options()
+        C.memmove(C.byref(o), C.byref(self._opt), C.sizeof(Options))
+        if k_max is not None:
+            o.k_max = k_max
+        if q_max is not None:
+            o.q_max = q_max
+        if l_max is not None:
+            o.l_max = l_max
+        if precision is not None:
+            o.precision = PREC[precision]
+        if batch is not None:
+            o.batch = BATCH[batch]
+        if svd is not None:
+            o.svd_mode = SVD[svd]
+        if eig is not None:
+            o.eig_method = EIG[eig]
+        if floor_c is not None:
+            o.floor_c = floor_c
+        o.hip_stream = hip_stream
+        self._check(self.lib.mps_set_options(self.h, C.byref(o)))
+        self._opt = o
+
+    def save(self, path: str):
+        """mps_save: the whole handle to a file."""
+        self._check(self.lib.mps_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str) -> "MPS":
+        """mps_load: a new handle from a file written by save()."""
+        lib = load()
+        h = C.c_void_p()
+        st = lib.mps_load(os.fsencode(path), C.byref(h))
+        if st != MPS_OK:
+            raise CtebdError(st, lib.mps_last_error(None).decode())
+        m = MPS.__new__(MPS)
+        m.lib, m.h = lib, h
+        # the saved n and options, read back from the file's header
+        with open(path, "rb") as f:
+            head = f.read(8 + 4 + 4 + 4 + 8 + 7 * 4 + 8)
+        n = int.from_bytes(head[12:16], "little", signed=True)
+        vals = np.frombuffer(head[28:56], dtype="<i4")
+        o = Options()
+        o.k_max, o.q_max, o.l_max, o.precision, o.svd_mode, o.batch, o.eig_method = (int(v) for v in vals)
+        o.floor_c = float(np.frombuffer(head[56:64], dtype="<f8")[0])
+        o.hip_stream = None
+        m.n, m._opt = n, o
         return m
 
     def overlap(self, other: "MPS") -> complex:

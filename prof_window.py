@@ -6,8 +6,8 @@ dispatch count the benchmark line reports (``kernel_dispatches``).  Counter
 runs (``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``) are scaled by the same
 counter read on a device copy of known size.
 
-    python -m paper_2502_19289_amd.prof_window trace DIR CLASS BENCH_JSON
-    python -m paper_2502_19289_amd.prof_window pmc DIR CLASS D [COPY_BYTES]
+    python prof_window.py trace DIR CLASS BENCH_JSON
+    python prof_window.py pmc DIR CLASS D [COPY_BYTES]
 """
 from __future__ import annotations
 
@@ -100,6 +100,6 @@ if __name__ == "__main__":
     elif a and a[0] == "pmc" and len(a) in (4, 5):
         pmc(a[1], a[2], int(a[3]), int(a[4]) if len(a) == 5 else 0)
     elif a and a[0] == "sha256":
-        print(sources_sha256(a[1].split(","), os.path.dirname(os.path.dirname(os.path.abspath(__file__)))))
+        print(sources_sha256(a[1].split(","), os.path.dirname(os.path.abspath(__file__))))
     else:
         raise SystemExit(__doc__)

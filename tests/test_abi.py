@@ -66,3 +66,24 @@ def test_planner_matches_oracle(seed, k_max, q_max, l_max):
         start = e_o
         steps += 1
     assert steps > 3
+
+
+def test_load_rejects_missing_and_corrupt_files(tmp_path):
+    """mps_load reads and checks the whole file on the host before it creates
+    a handle, so these errors need no GPU."""
+    ffi = _lib()
+    with pytest.raises(ffi.CtebdError) as e:
+        ffi.MPS.load(str(tmp_path / "absent.ctebd"))
+    assert e.value.status == ffi.MPS_EIO
+    junk = tmp_path / "junk.ctebd"
+    junk.write_bytes(b"not a saved state at all, just some bytes" * 3)
+    with pytest.raises(ffi.CtebdError) as e:
+        ffi.MPS.load(str(junk))
+    assert e.value.status == ffi.MPS_EIO
+    # the right magic with a wrong checksum
+    bad = tmp_path / "bad.ctebd"
+    bad.write_bytes(b"CTEBDMPS" + bytes(64))
+    with pytest.raises(ffi.CtebdError) as e:
+        ffi.MPS.load(str(bad))
+    assert e.value.status == ffi.MPS_EIO
+    assert "checksum" in str(e.value)

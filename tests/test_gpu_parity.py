@@ -80,18 +80,16 @@ def test_dense_exact_vs_statevector(prec, seed, k_max, eig):
     m = gpu_run(c, prec, eig=eig, chi_max=1024, eps=0.0, k_max=k_max)
     sv = SV.simulate(c)
     amp = m.amplitudes()
-    # FP32 contractions and an FP32 Jacobi solve, which resolves eigenvalues of
-    # the Gram matrix only to ~1e-7 of its trace: singular values below ~3e-4
-    # are mixed with the null space, so single amplitudes may move by ~1e-4;
-    # the bar that matters is the state infidelity
-    tol = 1e-11 if prec == "fp64" else 2e-4
+    # FP32 contractions round each product to about 6e-8 relative; amplitudes
+    # of these 10-qubit states stay within 5e-6 of the statevector
+    tol = 1e-11 if prec == "fp64" else 5e-6
     assert np.abs(amp - sv).max() < tol
     inf = 1 - abs(np.vdot(sv, amp)) ** 2 / np.vdot(amp, amp).real
     assert inf < (1e-14 if prec == "fp64" else 1e-7)
     # Schmidt values of every bond
     for b in range(c.n - 1):
         ref = MT.schmidt_from_state(sv, c.n, b + 1)
-        ref = ref[ref > (1e-6 if prec == "fp64" else 1e-3)]
+        ref = ref[ref > 1e-6]
         got = m.schmidt(b)
         assert np.abs(got[: ref.size] - ref).max() < (1e-10 if prec == "fp64" else 1e-5)
 
@@ -109,7 +107,7 @@ def test_apply_cluster_haar_vs_statevector(prec, eig):
         m.apply_cluster(qs, U)
         sv = SV.apply_gate(sv, n, U, list(qs))
     amp = m.amplitudes()
-    tol = 1e-11 if prec == "fp64" else 2e-4
+    tol = 1e-11 if prec == "fp64" else 5e-6
     assert np.abs(amp - sv).max() < tol
     inf = 1 - abs(np.vdot(sv, amp)) ** 2 / np.vdot(amp, amp).real
     assert inf < (1e-14 if prec == "fp64" else 1e-7)

@@ -67,13 +67,16 @@ def class_peak(name: str, dtype: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2,
                     help="untimed steps after the preparation steps (which always run until a quarter "
                          "of the bonds hold chi_max values)")
     ap.add_argument("--saturation", type=float, default=0.25,
                     help="fraction of bonds at chi_max that ends the preparation steps")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x6", "fp64"])
+    ap.add_argument("--batch", default="wave", choices=["wave", "step", "none"],
+                    help="launch grouping of the timed steps (wave: the clusters of all timed steps as one "
+                         "dependency graph)")
     ap.add_argument("--eig", default="auto", choices=["auto", "jacobi", "tridiag"],
                     help="eigen-solver of the exact splits")
     ap.add_argument("--workload", default=WORKLOAD)
@@ -119,22 +122,18 @@ class ProfilerWindow:
             self.lib.roctxProfilerResume(0)
 
 
-def timed_steps(m, k, progress=None):
+def timed_steps(m, k):
+    """K steps through mps_run_steps (one window: with the wavefront executor
+    the clusters of all K steps form one dependency graph)."""
     import torch
     torch.cuda.synchronize()
-    c0 = m.stats()["cluster_updates"]
+    st0 = m.stats()
     t0 = time.perf_counter()
-    done = 0
-    for _ in range(k):
-        _, rem = m.step()
-        done += 1
-        if progress:
-            print(f"# {progress} step {done}", file=sys.stderr, flush=True)
-        if rem == 0:
-            break
+    m.run_steps(k)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return done, m.stats()["cluster_updates"] - c0, dt
+    st1 = m.stats()
+    return st1["steps"] - st0["steps"], st1["cluster_updates"] - st0["cluster_updates"], dt
 
 
 def measured_traffic(kernel: str):
@@ -286,7 +285,7 @@ def main():
     from workloads import make_workload
 
     circ, p = make_workload(args.workload, seed=args.seed)
-    m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=args.precision, batch="step",
+    m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=p["k_max"], precision=args.precision, batch=args.batch,
               eig=args.eig)
     for layer in circ.layers:
         m.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
@@ -310,9 +309,10 @@ def main():
     print(f"# preparation: {psteps} steps, {prep_s:.1f} s", file=sys.stderr, flush=True)
     # ---- warm-up (untimed): the requested number of further steps
     wsteps = 0
-    while wsteps < args.warmup and rem != 0:
-        _, rem = m.step()
-        wsteps += 1
+    if args.warmup > 0 and rem != 0:
+        s0 = m.stats()["steps"]
+        _, rem = m.run_steps(args.warmup)
+        wsteps = m.stats()["steps"] - s0
     dims0 = np.array(m.bond_dims())
     saturated = int((dims0 >= p["chi_max"]).sum())
     if rem == 0:
@@ -343,7 +343,7 @@ def main():
     steps, updates, dt = timed_steps(m, args.steps)
     print(f"# timed {steps} steps, {updates} cluster updates, {dt:.1f} s", file=sys.stderr, flush=True)
     window.resume()
-    steps_p, updates_p, dt_p = timed_steps(prof, steps, progress="event-timed replay")
+    steps_p, updates_p, dt_p = timed_steps(prof, steps)
     window.pause()
     print(f"# event-timed replay {steps_p} steps, {updates_p} cluster updates, {dt_p:.1f} s", file=sys.stderr,
           flush=True)
@@ -366,7 +366,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": circ.n, "layers": len(circ.layers),
                    "chi_max": p["chi_max"], "k_max": p["k_max"], "eps": p["eps"],
-                   "batch": "step", "eig": args.eig, "seed": args.seed,
+                   "batch": args.batch, "eig": args.eig, "seed": args.seed,
                    "prep_steps": psteps, "warmup_steps_run": wsteps,
                    "bonds_at_chi_max_at_start": saturated,
                    "max_chi_at_start": int(dims0.max()),

@@ -79,10 +79,21 @@ enum {
   MPS_EIG_TRIDIAG = 2   /* tridiagonal divide and conquer whenever 2c <= 2048   */
 };
 
-/* How the independent clusters of one step are launched. */
+/* How the independent clusters are launched.  All three give the same site
+ * tensors and Schmidt values bit for bit; the fidelity sum may differ in its
+ * last bits (another summation order). */
 enum {
-  MPS_BATCH_NONE = 0,   /* one cluster per launch sequence                      */
-  MPS_BATCH_STEP = 1    /* every cluster of a step in the same launches         */
+  MPS_BATCH_NONE = 0,   /* one cluster per launch sequence, step by step        */
+  MPS_BATCH_STEP = 1,   /* every cluster of a step in the same launches          */
+  MPS_BATCH_WAVE = 2    /* the clusters of several steps as a dependency graph:
+                           in every round each cluster whose sites and left
+                           Schmidt values are final starts, each running cluster
+                           takes its next split level, all in the same launches
+                           (a k-qubit cluster runs k-1 rounds); mps_run_steps,
+                           mps_flush and mps_run_layer hand it all the steps
+                           they execute at once.  Needs the plan to be free of
+                           bond dimensions (q_max at its default) and exact SVDs;
+                           otherwise steps run as with MPS_BATCH_STEP            */
 };
 
 typedef struct {
@@ -159,6 +170,13 @@ mps_status mps_queue_layer(mps_handle h, const mps_gate* gates, int ngates);
  * (k >= 2) of that step (0 when nothing is buffered) and *remaining the
  * sub-layers still buffered; either pointer may be NULL.  Synchronises. */
 mps_status mps_step(mps_handle h, int* clusters, int* remaining);
+
+/* Contracts the next nsteps planned steps (Sec. III.A) of the buffered
+ * sub-layers, fewer when the buffer runs out; with MPS_BATCH_WAVE as one
+ * dependency graph, else one step after the other.  *clusters receives the
+ * number of clusters (k >= 2) contracted and *remaining the sub-layers still
+ * buffered; either may be NULL.  Synchronises.  MPS_EINVAL for nsteps < 0. */
+mps_status mps_run_steps(mps_handle h, int nsteps, int* clusters, int* remaining);
 
 /* Copies the state (sites, Schmidt values, bond dimensions, fidelity sum and
  * buffered sub-layers) into a new handle whose options come from opt (the

@@ -91,6 +91,33 @@ void DescBlob::release() {
   host.clear();
 }
 
+hipError_t BlockPool::get(size_t bytes, char** out, size_t* cap) {
+  const size_t want = (bytes + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+  auto it = free_blocks.lower_bound(want);
+  if (it != free_blocks.end() && it->first <= 2 * want) {
+    *out = it->second;
+    *cap = it->first;
+    free_blocks.erase(it);
+    return hipSuccess;
+  }
+  char* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  all.push_back({p, want});
+  *out = p;
+  *cap = want;
+  return hipSuccess;
+}
+
+void BlockPool::release() {
+  for (auto& b : all) (void)hipFree(b.first);
+  all.clear();
+  free_blocks.clear();
+}
+
 int KernelTimer::cls_of(const char* name) {
   for (size_t i = 0; i < names.size(); ++i)
     if (names[i] == name) return (int)i;
@@ -348,8 +375,7 @@ size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
   return b;
 }
 
-void assign_job(mps_ctx* ctx, JobRun& j) {
-  DeviceArena& A = ctx->arena;
+void assign_job(mps_ctx* ctx, JobRun& j, DeviceArena& A) {
   const size_t dimU = (size_t)1 << (2 * j.k);
   j.U64 = A.take(dimU * sizeof(double2));
   j.Uw = (ctx->prec == Prec::FP64) ? j.U64 : A.take(dimU * ctx->esz);
@@ -384,37 +410,40 @@ void assign_job(mps_ctx* ctx, JobRun& j) {
   if (j.htd) htd_layout(ld, j.hw, [&](size_t x) { return A.take(x); });
 }
 
-// Algorithmic flops of a finished step per kernel class (sizes are final on
-// the host once the step's bond dimensions are back): merge and unitary
-// products as written, the Hermitian half of each Gram matrix, the projection,
-// the FP64 Rayleigh product, and the tiles eig_update counted on the device.
+// Algorithmic flops per kernel class, once the sizes are final on the host:
+// merge and unitary products as written (account_merge), and per split level
+// (account_level, after that level's truncation is back) the Hermitian half of
+// the Gram matrix, the projection and the FP64 Rayleigh product.
+void account_merge(mps_ctx* ctx, const JobRun& r) {
+  double merge = 0;
+  for (int j = 1; j < r.k; ++j) {
+    const double M = (double)r.chi_l * (1 << j), K = r.mid[j - 1];
+    const double N = 2.0 * ((j == r.k - 1) ? r.chi_r : r.mid[j]);
+    merge += M * N * K;
+  }
+  const double apply = (double)(1 << r.k) * (1 << r.k) * r.chi_l * r.chi_r;
+  ctx->timer.flop[ctx->timer.cls_of("merge")] += 8.0 * merge;
+  ctx->timer.flop[ctx->timer.cls_of("apply")] += 8.0 * apply;
+}
+
+void account_level(mps_ctx* ctx, const JobRun& r, int t, bool mixed) {
+  const int m = r.lv[t].m;
+  const double c = (t == 0) ? r.chi_r : ctx->chi[r.a + m];
+  const double rr = ctx->chi[r.a + m - 1];
+  const double n2 = 2.0 * c, rows = r.lv[t].rows;
+  ctx->timer.flop[ctx->timer.cls_of("gram")] += 8.0 * n2 * (n2 + 1) / 2 * rows;
+  ctx->timer.flop[ctx->timer.cls_of("project")] += 8.0 * rows * n2 * rr;
+  if (mixed) ctx->timer.flop[ctx->timer.cls_of("eig_rayleigh")] += 8.0 * n2 * n2 * n2;
+}
+
+// All of a finished step's, plus the rotation tiles eig_update counted on the device.
 void account_flops(mps_ctx* ctx, const std::vector<JobRun>& runs, bool mixed, double eig_cmac,
                    double pair_flops) {
-  double merge = 0, apply = 0, gram = 0, proj = 0, ray = 0;
   for (const auto& r : runs) {
-    for (int j = 1; j < r.k; ++j) {
-      const double M = (double)r.chi_l * (1 << j), K = r.mid[j - 1];
-      const double N = 2.0 * ((j == r.k - 1) ? r.chi_r : r.mid[j]);
-      merge += M * N * K;
-    }
-    apply += (double)(1 << r.k) * (1 << r.k) * r.chi_l * r.chi_r;
-    for (size_t t = 0; t < r.lv.size(); ++t) {
-      const int m = r.lv[t].m;
-      const double c = (t == 0) ? r.chi_r : ctx->chi[r.a + m];
-      const double rr = ctx->chi[r.a + m - 1];
-      const double n2 = 2.0 * c, rows = r.lv[t].rows;
-      gram += n2 * (n2 + 1) / 2 * rows;
-      proj += rows * n2 * rr;
-      if (mixed) ray += n2 * n2 * n2;
-    }
+    account_merge(ctx, r);
+    for (size_t t = 0; t < r.lv.size(); ++t) account_level(ctx, r, (int)t, mixed);
   }
-  auto add = [&](const char* name, double cmac) { ctx->timer.flop[ctx->timer.cls_of(name)] += 8.0 * cmac; };
-  add("merge", merge);
-  add("apply", apply);
-  add("gram", gram);
-  add("project", proj);
-  if (mixed) add("eig_rayleigh", ray);
-  add("eig_update", eig_cmac);
+  ctx->timer.flop[ctx->timer.cls_of("eig_update")] += 8.0 * eig_cmac;
   ctx->timer.flop[ctx->timer.cls_of("eig_pairs")] += pair_flops;
 }
 
@@ -755,6 +784,302 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
   }
 }
 
+struct LevelDescs {
+  std::vector<int> jobs;
+  std::vector<GemmDesc> gram, proj;
+  std::vector<GramReduceDesc> red;
+  // exact solves: group 0 in FP64, group 1 in FP32 (+ FP64 Rayleigh quotients)
+  std::vector<EigDesc> eig[2];
+  std::vector<int> eig_jobs[2];
+  std::vector<HtdDesc> htd;   // tridiagonal solves
+  std::vector<EigDesc> eig_h;  // their trace / flag initialisation
+  size_t o_htd = 0, o_eig_h = 0;
+  std::vector<SelectDesc> sel;
+  std::vector<GemmDesc> ray;  // FP32 solve: W = G V in FP64
+  std::vector<GatherDesc> gat;
+  size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_sel, o_gat, b_gat;
+  size_t o_eig[2] = {0, 0}, b_pair[2] = {0, 0}, b_upd[2] = {0, 0};
+  int n_pair[2] = {0, 0}, n_upd[2] = {0, 0};
+  size_t o_ray = 0, b_ray = 0;
+  int n_gram, n_proj, n_red, n_gat, n_ray = 0;
+  int nb_max_all;
+};
+
+int upload_gemms(DescBlob& B, const std::vector<GemmDesc>& v, size_t& off, size_t& boff) {
+  std::vector<int> base{0};
+  for (const auto& d : v) base.push_back(base.back() + gemm_tiles(d));
+  off = B.add_vec(v);
+  boff = B.add_vec(base);
+  return base.back();
+}
+
+// Serialises the descriptors of one level into the step's blob.
+void upload_level(DescBlob& B, LevelDescs& L) {
+  L.n_gram = upload_gemms(B, L.gram, L.o_gram, L.b_gram);
+  L.n_proj = upload_gemms(B, L.proj, L.o_proj, L.b_proj);
+  L.n_red = 0;
+  if (!L.red.empty()) {
+    std::vector<int> base{0};
+    for (const auto& g : L.red) base.push_back(base.back() + g.tiles);
+    L.o_red = B.add_vec(L.red);
+    L.b_red = B.add_vec(base);
+    L.n_red = base.back();
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (L.eig[g].empty()) continue;
+    std::vector<int> pb{0}, ub{0};
+    for (const auto& e : L.eig[g]) {
+      pb.push_back(pb.back() + e.nb_max / 2);
+      ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+    }
+    L.o_eig[g] = B.add_vec(L.eig[g]);
+    L.b_pair[g] = B.add_vec(pb);
+    L.b_upd[g] = B.add_vec(ub);
+    L.n_pair[g] = pb.back();
+    L.n_upd[g] = ub.back();
+  }
+  if (!L.htd.empty()) {
+    L.o_htd = B.add_vec(L.htd);
+    L.o_eig_h = B.add_vec(L.eig_h);
+  }
+  L.o_sel = B.add_vec(L.sel);
+  if (!L.ray.empty()) L.n_ray = upload_gemms(B, L.ray, L.o_ray, L.b_ray);
+  std::vector<int> gb{0};
+  for (const auto& g : L.gat) gb.push_back(gb.back() + g.tiles);
+  L.o_gat = B.add_vec(L.gat);
+  L.b_gat = B.add_vec(gb);
+  L.n_gat = gb.back();
+}
+
+// Launches of one split level: Gram matrices, eigen-solver initialisation,
+// `between` (the learned-sketch launches of the level, if any), the exact
+// solves, selection, gather and projection.  flags holds the convergence
+// flags of the level's jobs, 4 ints per job index, nflag_ints in all.
+template <class F>
+void launch_level(mps_ctx* ctx, DescBlob& B, LevelDescs& L, int* flags, int nflag_ints, F between) {
+  hipStream_t s = ctx->stream;
+  const Prec P = ctx->prec;
+  const int np = (int)L.jobs.size();
+  {
+    Timed tm(ctx, "gram");
+    HIP_OK(launch_gram(P == Prec::FP64 ? Prec::FP64 : Prec::FP32, B.at<GemmDesc>(L.o_gram),
+                       B.at<int>(L.b_gram), np, L.n_gram, s));
+  }
+  if (L.n_red) {
+    Timed tm(ctx, "gram_reduce");
+    HIP_OK(launch_gram_reduce(B.at<GramReduceDesc>(L.o_red), B.at<int>(L.b_red), (int)L.red.size(), L.n_red, s));
+  }
+  int ldmax = 0;
+  for (int g = 0; g < 2; ++g)
+    for (const auto& e : L.eig[g]) ldmax = std::max(ldmax, e.ld);
+  for (const auto& e : L.eig_h) ldmax = std::max(ldmax, e.ld);
+  if (!L.eig_h.empty()) {
+    Timed tm(ctx, "eig_init");
+    HIP_OK(launch_eig_init(false, B.at<EigDesc>(L.o_eig_h), (int)L.eig_h.size(), ldmax, s));
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (L.eig[g].empty()) continue;
+    Timed tm(ctx, "eig_init");
+    HIP_OK(launch_eig_init(g == 1, B.at<EigDesc>(L.o_eig[g]), (int)L.eig[g].size(), ldmax, s));
+  }
+  between();
+  for (int g = 0; g < 2; ++g) {
+    if (L.eig[g].empty()) continue;
+    std::vector<int> at;
+    for (int q : L.eig_jobs[g]) at.push_back(4 * q);
+    solve_eig(ctx, g == 1, B.at<EigDesc>(L.o_eig[g]), L.eig[g], B.at<int>(L.b_pair[g]), B.at<int>(L.b_upd[g]),
+              L.n_pair[g], L.n_upd[g], flags, nflag_ints, at);
+  }
+  if (!L.htd.empty()) solve_htd(ctx, B.at<HtdDesc>(L.o_htd), L.htd);
+  if (!L.eig[1].empty()) {
+    Timed tm(ctx, "eig_rayleigh");
+    EigDesc* de32 = B.at<EigDesc>(L.o_eig[1]);
+    const int n32 = (int)L.eig[1].size();
+    HIP_OK(launch_eig_to64(de32, n32, ldmax, s));
+    HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(L.o_ray), B.at<int>(L.b_ray), n32, L.n_ray, s));
+    HIP_OK(launch_eig_rayleigh(de32, n32, ldmax, s));
+  }
+  {
+    Timed tm(ctx, "select");
+    HIP_OK(launch_select(B.at<SelectDesc>(L.o_sel), np, s));
+  }
+  {
+    Timed tm(ctx, "gather");
+    HIP_OK(launch_gather(P, B.at<GatherDesc>(L.o_gat), B.at<int>(L.b_gat), np, L.n_gat, s));
+  }
+  {
+    Timed tm(ctx, "project");
+    HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(L.o_proj), B.at<int>(L.b_proj), np, L.n_proj, s));
+  }
+}
+
+// Descriptors of split level t of job run r (index i in the caller's job
+// list, which also indexes its convergence flags) appended to L; skr is the
+// split's learned-sketch run or null.  Advances r's buffer parity.
+void add_level(mps_ctx* ctx, LevelDescs& L, JobRun& r, int i, int t, const SkRun* skr) {
+  const bool mixed = ctx->prec != Prec::FP64;  // FP32 Jacobi + FP64 Rayleigh quotients
+  L.jobs.push_back(i);
+  const Level& lv = r.lv[t];
+  const int m = lv.m;
+  const Dim n2c = c_dim(ctx, r, t, 2);
+  void* X = r.buf[r.cur];
+  void* Y = r.buf[r.cur ^ 1];
+  {
+    GemmDesc d{};
+    d.A = X;
+    d.B = X;
+    d.C = lv.ksplit > 1 ? (void*)r.part : (void*)r.G;
+    d.M = n2c;
+    d.N = n2c;
+    d.K = fixed(lv.rows);
+    d.lda = n2c;
+    d.ldb = n2c;
+    d.ldc = fixed(r.ld);
+    d.batch = 1;
+    d.tm = d.tn = ceil_div(2 * lv.c_bound, 64);
+    d.ksplit = lv.ksplit;
+    d.part = (int64_t)r.ld * r.ld;
+    d.w = r.a > 0 ? ctx->lam[r.a - 1] : ctx->d_ones;
+    d.wshift = m;
+    d.alpha = 1.0;
+    L.gram.push_back(d);
+    if (lv.ksplit > 1) {
+      GramReduceDesc g{};
+      g.part = r.part;
+      g.G = r.G;
+      g.n = n2c;
+      g.ld = fixed(r.ld);
+      g.ksplit = lv.ksplit;
+      g.stride = (int64_t)r.ld * r.ld;
+      const int T = ceil_div(2 * lv.c_bound, 64);
+      g.tiles = T * T;
+      L.red.push_back(g);
+    }
+  }
+  {
+    // The FP32 solve resolves eigenvalues of G only to ~1e-7 of its trace;
+    // it serves large splits whose rank bound exceeds chi_max, where the
+    // cut lies far above that level.  Other splits use the FP64 solve.
+    const bool uh = level_htd(ctx, lv);
+    const bool e32 =
+        !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
+    EigDesc e{};
+    e.G = r.G;
+    e.V = r.V;
+    e.J = r.J;
+    e.Gw = e32 ? r.Gw : (void*)r.G;
+    e.Vw = e32 ? r.Vw : (void*)r.V;
+    e.W = r.W;
+    e.lam = r.lamR;
+    e.pair_rot = r.pair_rot;
+    e.flags = r.flags;
+    e.scale = r.scale;
+    e.work = ctx->timing ? ctx->d_work + (e32 ? 2 : 0) : nullptr;
+    e.n = n2c;
+    e.ld = r.ld;
+    int nb = ceil_div(2 * lv.c_bound, JB);
+    nb = std::max(nb, 2);
+    nb += nb & 1;
+    e.nb_max = nb;
+    e.tol = e32 ? 2e-6 : 1e-13;
+    if (uh) {
+      L.eig_h.push_back(e);
+      HtdDesc h = r.hw;
+      h.A = r.G;
+      h.V = r.V;
+      h.n = n2c;
+      h.ld = r.ld;
+      h.rcap = lv.r_bound;
+      h.skip = r.flags;
+      L.htd.push_back(h);
+    } else {
+      L.nb_max_all = std::max(L.nb_max_all, nb);
+      L.eig[e32].push_back(e);
+      L.eig_jobs[e32].push_back(i);
+    }
+    if (e32) {
+      GemmDesc g{};
+      g.A = r.G;
+      g.B = r.V;
+      g.C = r.W;
+      g.M = n2c;
+      g.N = n2c;
+      g.K = n2c;
+      g.lda = g.ldb = g.ldc = fixed(r.ld);
+      g.batch = 1;
+      g.tm = g.tn = ceil_div(2 * lv.c_bound, 64);
+      g.ksplit = 1;
+      g.alpha = 1.0;
+      if (skr) g.skip = skr->use;
+      L.ray.push_back(g);
+    }
+  }
+  int* r_out = ctx->d_chi + (r.a + m - 1);
+  {
+    const bool uh = level_htd(ctx, lv);
+    const bool e32 =
+        !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
+    SelectDesc sd{};
+    sd.G = r.G;
+    sd.lam_in = uh ? r.hw.lam : e32 ? r.lamR : nullptr;
+    sd.ldg = r.ld;
+    sd.n = n2c;
+    sd.rows = lv.rows;
+    sd.chi_max = ctx->chi_max;
+    sd.eps_eff = ctx->eps_eff;
+    sd.perm = r.perm;
+    sd.r_out = r_out;
+    sd.lam_out = ctx->lam[r.a + m - 1];
+    sd.logf_acc = r.logf;
+    sd.rec = r.rec + 4 * t;
+    if (skr) {
+      const SkRun& k = *skr;
+      sd.use_sk = k.use;
+      sd.lam_sk = k.lam;
+      sd.tot_sk = r.scale;
+      sd.s_sk = k.s;
+    }
+    L.sel.push_back(sd);
+  }
+  {
+    GatherDesc g{};
+    g.V = r.V;
+    g.ldv = r.ld;
+    g.perm = r.perm;
+    g.r = r_out;
+    g.n = n2c;
+    g.B = ctx->site[r.a + m];
+    g.Vr = r.Vr;
+    g.tiles = ceil_div(lv.r_bound, 64) * ceil_div(2 * lv.c_bound, 64);
+    if (skr) {
+      const SkRun& k = *skr;
+      g.use_sk = k.use;
+      g.Vs = k.Vs;
+      g.ld_sk = k.ld_s;
+    }
+    L.gat.push_back(g);
+  }
+  {
+    GemmDesc d{};
+    d.A = X;
+    d.B = r.Vr;
+    d.C = Y;
+    d.M = fixed(lv.rows);
+    d.K = n2c;
+    d.N = Dim{1, r_out};
+    d.lda = n2c;
+    d.ldb = Dim{1, r_out};
+    d.ldc = Dim{1, r_out};
+    d.batch = 1;
+    d.tm = ceil_div(lv.rows, 64);
+    d.tn = ceil_div(lv.r_bound, 64);
+    d.ksplit = 1;
+    d.alpha = 1.0;
+    L.proj.push_back(d);
+  }
+  r.cur ^= 1;
+}
+
 void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q, int nsub) {
   hipStream_t s = ctx->stream;
   const Prec P = ctx->prec;
@@ -830,7 +1155,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   double* logf_all = (double*)ctx->arena.take(std::max(1, nj) * sizeof(double));
   int* flags_all = (int*)ctx->arena.take(std::max(1, nj) * 4 * sizeof(int));
   for (int i = 0; i < nj; ++i) {
-    assign_job(ctx, runs[i]);
+    assign_job(ctx, runs[i], ctx->arena);
     runs[i].logf = logf_all + i;
     runs[i].flags = flags_all + 4 * i;
     runs[i].flag_index = i;
@@ -932,202 +1257,18 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   }
 
   auto upload_gemm = [&](const std::vector<GemmDesc>& v, size_t& off, size_t& boff) {
-    std::vector<int> base{0};
-    for (const auto& d : v) base.push_back(base.back() + gemm_tiles(d));
-    off = B.add_vec(v);
-    boff = B.add_vec(base);
-    return base.back();
+    return upload_gemms(B, v, off, boff);
   };
 
   // Split levels: descriptors are built for every level up front.
   const int tmax = kmax - 1;
-  struct LevelDescs {
-    std::vector<int> jobs;
-    std::vector<GemmDesc> gram, proj;
-    std::vector<GramReduceDesc> red;
-    // exact solves: group 0 in FP64, group 1 in FP32 (+ FP64 Rayleigh quotients)
-    std::vector<EigDesc> eig[2];
-    std::vector<int> eig_jobs[2];
-    std::vector<HtdDesc> htd;   // tridiagonal solves
-    std::vector<EigDesc> eig_h;  // their trace / flag initialisation
-    size_t o_htd = 0, o_eig_h = 0;
-    std::vector<SelectDesc> sel;
-    std::vector<GemmDesc> ray;  // FP32 solve: W = G V in FP64
-    std::vector<GatherDesc> gat;
-    size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_sel, o_gat, b_gat;
-    size_t o_eig[2] = {0, 0}, b_pair[2] = {0, 0}, b_upd[2] = {0, 0};
-    int n_pair[2] = {0, 0}, n_upd[2] = {0, 0};
-    size_t o_ray = 0, b_ray = 0;
-    int n_gram, n_proj, n_red, n_gat, n_ray = 0;
-    int nb_max_all;
-  };
   std::vector<LevelDescs> LD(std::max(0, tmax));
   for (int t = 0; t < tmax; ++t) {
     LevelDescs& L = LD[t];
     L.nb_max_all = 0;
     for (int i = 0; i < nj; ++i) {
-      JobRun& r = runs[i];
-      if (t >= r.k - 1) continue;
-      L.jobs.push_back(i);
-      const Level& lv = r.lv[t];
-      const int m = lv.m;
-      const Dim n2c = c_dim(ctx, r, t, 2);
-      void* X = r.buf[r.cur];
-      void* Y = r.buf[r.cur ^ 1];
-      {
-        GemmDesc d{};
-        d.A = X;
-        d.B = X;
-        d.C = lv.ksplit > 1 ? (void*)r.part : (void*)r.G;
-        d.M = n2c;
-        d.N = n2c;
-        d.K = fixed(lv.rows);
-        d.lda = n2c;
-        d.ldb = n2c;
-        d.ldc = fixed(r.ld);
-        d.batch = 1;
-        d.tm = d.tn = ceil_div(2 * lv.c_bound, 64);
-        d.ksplit = lv.ksplit;
-        d.part = (int64_t)r.ld * r.ld;
-        d.w = r.a > 0 ? ctx->lam[r.a - 1] : ctx->d_ones;
-        d.wshift = m;
-        d.alpha = 1.0;
-        L.gram.push_back(d);
-        if (lv.ksplit > 1) {
-          GramReduceDesc g{};
-          g.part = r.part;
-          g.G = r.G;
-          g.n = n2c;
-          g.ld = fixed(r.ld);
-          g.ksplit = lv.ksplit;
-          g.stride = (int64_t)r.ld * r.ld;
-          const int T = ceil_div(2 * lv.c_bound, 64);
-          g.tiles = T * T;
-          L.red.push_back(g);
-        }
-      }
-      {
-        // The FP32 solve resolves eigenvalues of G only to ~1e-7 of its trace;
-        // it serves large splits whose rank bound exceeds chi_max, where the
-        // cut lies far above that level.  Other splits use the FP64 solve.
-        const bool uh = level_htd(ctx, lv);
-        const bool e32 =
-            !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
-        EigDesc e{};
-        e.G = r.G;
-        e.V = r.V;
-        e.J = r.J;
-        e.Gw = e32 ? r.Gw : (void*)r.G;
-        e.Vw = e32 ? r.Vw : (void*)r.V;
-        e.W = r.W;
-        e.lam = r.lamR;
-        e.pair_rot = r.pair_rot;
-        e.flags = r.flags;
-        e.scale = r.scale;
-        e.work = ctx->timing ? ctx->d_work + (e32 ? 2 : 0) : nullptr;
-        e.n = n2c;
-        e.ld = r.ld;
-        int nb = ceil_div(2 * lv.c_bound, JB);
-        nb = std::max(nb, 2);
-        nb += nb & 1;
-        e.nb_max = nb;
-        e.tol = e32 ? 2e-6 : 1e-13;
-        if (uh) {
-          L.eig_h.push_back(e);
-          HtdDesc h = r.hw;
-          h.A = r.G;
-          h.V = r.V;
-          h.n = n2c;
-          h.ld = r.ld;
-          h.rcap = lv.r_bound;
-          h.skip = r.flags;
-          L.htd.push_back(h);
-        } else {
-          L.nb_max_all = std::max(L.nb_max_all, nb);
-          L.eig[e32].push_back(e);
-          L.eig_jobs[e32].push_back(i);
-        }
-        if (e32) {
-          GemmDesc g{};
-          g.A = r.G;
-          g.B = r.V;
-          g.C = r.W;
-          g.M = n2c;
-          g.N = n2c;
-          g.K = n2c;
-          g.lda = g.ldb = g.ldc = fixed(r.ld);
-          g.batch = 1;
-          g.tm = g.tn = ceil_div(2 * lv.c_bound, 64);
-          g.ksplit = 1;
-          g.alpha = 1.0;
-          if (sk_of[i][t] >= 0) g.skip = sk[sk_of[i][t]].use;
-          L.ray.push_back(g);
-        }
-      }
-      int* r_out = ctx->d_chi + (r.a + m - 1);
-      {
-        const bool uh = level_htd(ctx, lv);
-        const bool e32 =
-            !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
-        SelectDesc sd{};
-        sd.G = r.G;
-        sd.lam_in = uh ? r.hw.lam : e32 ? r.lamR : nullptr;
-        sd.ldg = r.ld;
-        sd.n = n2c;
-        sd.rows = lv.rows;
-        sd.chi_max = ctx->chi_max;
-        sd.eps_eff = ctx->eps_eff;
-        sd.perm = r.perm;
-        sd.r_out = r_out;
-        sd.lam_out = ctx->lam[r.a + m - 1];
-        sd.logf_acc = r.logf;
-        sd.rec = r.rec + 4 * t;
-        if (sk_of[i][t] >= 0) {
-          const SkRun& k = sk[sk_of[i][t]];
-          sd.use_sk = k.use;
-          sd.lam_sk = k.lam;
-          sd.tot_sk = r.scale;
-          sd.s_sk = k.s;
-        }
-        L.sel.push_back(sd);
-      }
-      {
-        GatherDesc g{};
-        g.V = r.V;
-        g.ldv = r.ld;
-        g.perm = r.perm;
-        g.r = r_out;
-        g.n = n2c;
-        g.B = ctx->site[r.a + m];
-        g.Vr = r.Vr;
-        g.tiles = ceil_div(lv.r_bound, 64) * ceil_div(2 * lv.c_bound, 64);
-        if (sk_of[i][t] >= 0) {
-          const SkRun& k = sk[sk_of[i][t]];
-          g.use_sk = k.use;
-          g.Vs = k.Vs;
-          g.ld_sk = k.ld_s;
-        }
-        L.gat.push_back(g);
-      }
-      {
-        GemmDesc d{};
-        d.A = X;
-        d.B = r.Vr;
-        d.C = Y;
-        d.M = fixed(lv.rows);
-        d.K = n2c;
-        d.N = Dim{1, r_out};
-        d.lda = n2c;
-        d.ldb = Dim{1, r_out};
-        d.ldc = Dim{1, r_out};
-        d.batch = 1;
-        d.tm = ceil_div(lv.rows, 64);
-        d.tn = ceil_div(lv.r_bound, 64);
-        d.ksplit = 1;
-        d.alpha = 1.0;
-        L.proj.push_back(d);
-      }
-      r.cur ^= 1;
+      if (t >= runs[i].k - 1) continue;
+      add_level(ctx, L, runs[i], i, t, sk_of[i][t] >= 0 ? &sk[sk_of[i][t]] : nullptr);
     }
   }
   // Learned-sketch descriptors per level: range finder on G, two s x s solves,
@@ -1254,42 +1395,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   for (int j = 1; j < kmax; ++j) n_mg[j] = upload_gemm(mg[j], o_mg[j], b_mg[j]);
   size_t o_ap = 0, b_ap = 0;
   const int n_ap = nj ? upload_gemm(ap, o_ap, b_ap) : 0;
-  for (auto& L : LD) {
-    L.n_gram = upload_gemm(L.gram, L.o_gram, L.b_gram);
-    L.n_proj = upload_gemm(L.proj, L.o_proj, L.b_proj);
-    L.n_red = 0;
-    if (!L.red.empty()) {
-      std::vector<int> base{0};
-      for (const auto& g : L.red) base.push_back(base.back() + g.tiles);
-      L.o_red = B.add_vec(L.red);
-      L.b_red = B.add_vec(base);
-      L.n_red = base.back();
-    }
-    for (int g = 0; g < 2; ++g) {
-      if (L.eig[g].empty()) continue;
-      std::vector<int> pb{0}, ub{0};
-      for (const auto& e : L.eig[g]) {
-        pb.push_back(pb.back() + e.nb_max / 2);
-        ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
-      }
-      L.o_eig[g] = B.add_vec(L.eig[g]);
-      L.b_pair[g] = B.add_vec(pb);
-      L.b_upd[g] = B.add_vec(ub);
-      L.n_pair[g] = pb.back();
-      L.n_upd[g] = ub.back();
-    }
-    if (!L.htd.empty()) {
-      L.o_htd = B.add_vec(L.htd);
-      L.o_eig_h = B.add_vec(L.eig_h);
-    }
-    L.o_sel = B.add_vec(L.sel);
-    if (!L.ray.empty()) L.n_ray = upload_gemm(L.ray, L.o_ray, L.b_ray);
-    std::vector<int> gb{0};
-    for (const auto& g : L.gat) gb.push_back(gb.back() + g.tiles);
-    L.o_gat = B.add_vec(L.gat);
-    L.b_gat = B.add_vec(gb);
-    L.n_gat = gb.back();
-  }
+  for (auto& L : LD) upload_level(B, L);
   for (auto& S : SL) {
     if (S.ids.empty()) continue;
     S.o_sd = B.add_vec(S.sd);
@@ -1344,102 +1450,52 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(o_ap), B.at<int>(b_ap), nj, n_ap, s));
   }
   for (int t = 0; t < tmax; ++t) {
-    LevelDescs& L = LD[t];
-    const int np = (int)L.jobs.size();
-    {
-      Timed tm(ctx, "gram");
-      HIP_OK(launch_gram(P == Prec::FP64 ? Prec::FP64 : Prec::FP32, B.at<GemmDesc>(L.o_gram),
-                         B.at<int>(L.b_gram), np, L.n_gram, s));
-    }
-    if (L.n_red) {
-      Timed tm(ctx, "gram_reduce");
-      HIP_OK(launch_gram_reduce(B.at<GramReduceDesc>(L.o_red), B.at<int>(L.b_red), (int)L.red.size(), L.n_red, s));
-    }
-    int ldmax = 0;
-    for (int g = 0; g < 2; ++g)
-      for (const auto& e : L.eig[g]) ldmax = std::max(ldmax, e.ld);
-    for (const auto& e : L.eig_h) ldmax = std::max(ldmax, e.ld);
-    if (!L.eig_h.empty()) {
-      Timed tm(ctx, "eig_init");
-      HIP_OK(launch_eig_init(false, B.at<EigDesc>(L.o_eig_h), (int)L.eig_h.size(), ldmax, s));
-    }
-    for (int g = 0; g < 2; ++g) {
-      if (L.eig[g].empty()) continue;
-      Timed tm(ctx, "eig_init");
-      HIP_OK(launch_eig_init(g == 1, B.at<EigDesc>(L.o_eig[g]), (int)L.eig[g].size(), ldmax, s));
-    }
-    SkLevel& S = SL[t];
-    if (!S.ids.empty()) {
-      // learned sketch of this level's predicted-low-rank splits
-      const int ns = (int)S.ids.size();
-      SketchDesc* dsk = B.at<SketchDesc>(S.o_sd);
-      auto nn = [&](int g) { HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
-      auto cn = [&](int g) { HIP_OK(launch_gemm_cn(B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
-      int ldy = 0;
-      for (int q : S.ids) ldy = std::max(ldy, sk[q].ld_y);
-      {
-        Timed tm(ctx, "sketch");
-        HIP_OK(launch_gauss_fill(dsk, ns, 0, s));
-        HIP_OK(launch_gauss_fill(dsk, ns, 1, s));
-        nn(0);
-        HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
-        HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
-      }
-      solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
-                skflags_all, 12 * nsk, S.flag_a);
-      {
-        Timed tm(ctx, "sketch");
-        HIP_OK(launch_orth_scale(dsk, ns, s));
-        nn(2);
-        for (int it = 0; it < 2; ++it) {
-          HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[9 + 2 * it]), B.at<int>(S.b[9 + 2 * it]), ns,
-                             S.n[9 + 2 * it], s));
-          HIP_OK(launch_newton_schulz(dsk, ns, s));
-          nn(10 + 2 * it);
+    launch_level(ctx, B, LD[t], flags_all, 4 * nj, [&] {
+      SkLevel& S = SL[t];
+      if (!S.ids.empty()) {
+        // learned sketch of this level's predicted-low-rank splits
+        const int ns = (int)S.ids.size();
+        SketchDesc* dsk = B.at<SketchDesc>(S.o_sd);
+        auto nn = [&](int g) { HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+        auto cn = [&](int g) { HIP_OK(launch_gemm_cn(B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+        int ldy = 0;
+        for (int q : S.ids) ldy = std::max(ldy, sk[q].ld_y);
+        {
+          Timed tm(ctx, "sketch");
+          HIP_OK(launch_gauss_fill(dsk, ns, 0, s));
+          HIP_OK(launch_gauss_fill(dsk, ns, 1, s));
+          nn(0);
+          HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
+          HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
         }
-        nn(3);
-        cn(4);
-        HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
+        solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+                  skflags_all, 12 * nsk, S.flag_a);
+        {
+          Timed tm(ctx, "sketch");
+          HIP_OK(launch_orth_scale(dsk, ns, s));
+          nn(2);
+          for (int it = 0; it < 2; ++it) {
+            HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[9 + 2 * it]), B.at<int>(S.b[9 + 2 * it]), ns,
+                               S.n[9 + 2 * it], s));
+            HIP_OK(launch_newton_schulz(dsk, ns, s));
+            nn(10 + 2 * it);
+          }
+          nn(3);
+          cn(4);
+          HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
+        }
+        solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+                  skflags_all, 12 * nsk, S.flag_b);
+        {
+          Timed tm(ctx, "sketch");
+          nn(5);
+          cn(6);
+          nn(7);
+          nn(8);
+          HIP_OK(launch_sketch_accept(dsk, ns, s));
+        }
       }
-      solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
-                skflags_all, 12 * nsk, S.flag_b);
-      {
-        Timed tm(ctx, "sketch");
-        nn(5);
-        cn(6);
-        nn(7);
-        nn(8);
-        HIP_OK(launch_sketch_accept(dsk, ns, s));
-      }
-    }
-    for (int g = 0; g < 2; ++g) {
-      if (L.eig[g].empty()) continue;
-      std::vector<int> at;
-      for (int q : L.eig_jobs[g]) at.push_back(4 * q);
-      solve_eig(ctx, g == 1, B.at<EigDesc>(L.o_eig[g]), L.eig[g], B.at<int>(L.b_pair[g]), B.at<int>(L.b_upd[g]),
-                L.n_pair[g], L.n_upd[g], flags_all, 4 * nj, at);
-    }
-    if (!L.htd.empty()) solve_htd(ctx, B.at<HtdDesc>(L.o_htd), L.htd);
-    if (!L.eig[1].empty()) {
-      Timed tm(ctx, "eig_rayleigh");
-      EigDesc* de32 = B.at<EigDesc>(L.o_eig[1]);
-      const int n32 = (int)L.eig[1].size();
-      HIP_OK(launch_eig_to64(de32, n32, ldmax, s));
-      HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(L.o_ray), B.at<int>(L.b_ray), n32, L.n_ray, s));
-      HIP_OK(launch_eig_rayleigh(de32, n32, ldmax, s));
-    }
-    {
-      Timed tm(ctx, "select");
-      HIP_OK(launch_select(B.at<SelectDesc>(L.o_sel), np, s));
-    }
-    {
-      Timed tm(ctx, "gather");
-      HIP_OK(launch_gather(P, B.at<GatherDesc>(L.o_gat), B.at<int>(L.b_gat), np, L.n_gat, s));
-    }
-    {
-      Timed tm(ctx, "project");
-      HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(L.o_proj), B.at<int>(L.b_proj), np, L.n_proj, s));
-    }
+    });
   }
   if (nj) {
     Timed tm(ctx, "finalize");
@@ -1520,6 +1576,442 @@ void run_jobs(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc
   ctx->stats.steps += 1;
 }
 
+int execute_step(mps_ctx* ctx, int end_hint);
+
+// ------------------------------------------------ wavefront executor --
+// The clusters of several consecutive steps (the "window") run as a
+// dependency graph instead of step by step.  A cluster on sites a..a+k-1
+// reads those sites and the Schmidt values of bond a-1 and writes the sites
+// and its inner bonds a..a+k-2; it waits for the last earlier writer of each
+// site and of bond a-1, and for every earlier reader of an inner bond (which
+// still weights its Gram matrices with it).  One-qubit site updates wait for
+// the last writer of their site.  Execution proceeds in rounds: every cluster
+// whose inputs are final starts (unitary, merge chain, unitary application)
+// and every running cluster takes its next split level, all in the same
+// launches as the step executor builds them for one step, so each cluster
+// computes exactly what the step executor computes (only the sum of log f is
+// added up in another order).  A k-qubit cluster runs k-1 rounds.  The window
+// is planned up front, which is exact because the plan does not depend on
+// the bond dimensions when Eq. cond_cTEBD cannot bind (q_max at its default).
+struct WaveTask {
+  bool site = false;   // one-qubit update of site q (else a cluster)
+  Job job;
+  int q = -1;
+  std::array<cplx, 4> u1{};
+  int nsub = 0;        // sub-layers of the task's step (a feature of its splits)
+  std::vector<int> deps;
+  int state = 0;       // 0 waiting, 1 running, 2 done
+  int level = 0;       // split level to run next
+  JobRun run;
+  char* ws = nullptr;  // workspace block of the pool
+  size_t ws_cap = 0;
+  std::vector<float> feats;
+};
+
+bool plan_is_chi_free(const mps_ctx* ctx) {
+  return ctx->q_max_eff >= default_q_max(ctx->opt.k_max, ctx->chi_max);
+}
+
+// Tasks of the next `nsteps` planned steps (all buffered sub-layers when
+// nsteps < 0); returns the number of sub-layers they consume.
+int plan_window(mps_ctx* ctx, int nsteps, std::vector<WaveTask>& T, int* steps_out) {
+  const int n = ctx->n;
+  std::vector<int> last_site(n, -1), last_bond(std::max(0, n - 1), -1);
+  std::vector<std::vector<int>> readers(std::max(0, n - 1));
+  int start = 0, steps = 0;
+  const int total = (int)ctx->pending.size();
+  while (start < total && (nsteps < 0 || steps < nsteps)) {
+    std::vector<Cluster> cl;
+    const int end = plan_step(ctx->pending, start, n, ctx->chi, ctx->opt.k_max, ctx->q_max_eff,
+                              ctx->l_max_eff, cl);
+    std::vector<int> owner(n, -1);
+    const int base = (int)T.size();
+    for (size_t c = 0; c < cl.size(); ++c) {
+      WaveTask w;
+      w.job.a = cl[c].a;
+      w.job.k = cl[c].k;
+      w.nsub = end - start;
+      T.push_back(std::move(w));
+      for (int q = cl[c].a; q < cl[c].a + cl[c].k; ++q) owner[q] = base + (int)c;
+    }
+    std::vector<int> site_task(n, -1);
+    for (int sl = start; sl < end; ++sl)
+      for (const auto& g : ctx->pending[sl]) {
+        const int o = owner[g.q[0]];
+        if (o >= 0) {
+          T[o].job.gates.push_back(g);
+          continue;
+        }
+        const int q = g.q[0];
+        if (site_task[q] < 0) {
+          site_task[q] = (int)T.size();
+          WaveTask w;
+          w.site = true;
+          w.q = q;
+          w.u1 = {cplx(1), cplx(0), cplx(0), cplx(1)};
+          T.push_back(std::move(w));
+        }
+        auto& m = T[site_task[q]].u1;
+        std::array<cplx, 4> r;
+        r[0] = g.u[0] * m[0] + g.u[1] * m[2];
+        r[1] = g.u[0] * m[1] + g.u[1] * m[3];
+        r[2] = g.u[2] * m[0] + g.u[3] * m[2];
+        r[3] = g.u[2] * m[1] + g.u[3] * m[3];
+        m = r;
+      }
+    for (int t = base; t < (int)T.size(); ++t) {
+      WaveTask& w = T[t];
+      auto dep = [&](int d) {
+        if (d >= 0 && std::find(w.deps.begin(), w.deps.end(), d) == w.deps.end()) w.deps.push_back(d);
+      };
+      if (w.site) {
+        dep(last_site[w.q]);
+        last_site[w.q] = t;
+        continue;
+      }
+      const int a = w.job.a, k = w.job.k;
+      for (int q = a; q < a + k; ++q) dep(last_site[q]);
+      if (a > 0) dep(last_bond[a - 1]);
+      for (int b = a; b < a + k - 1; ++b)
+        for (int rd : readers[b]) dep(rd);
+      for (int q = a; q < a + k; ++q) last_site[q] = t;
+      for (int b = a; b < a + k - 1; ++b) {
+        last_bond[b] = t;
+        readers[b].clear();
+      }
+      if (a > 0) readers[a - 1].push_back(t);
+    }
+    start = end;
+    ++steps;
+  }
+  if (steps_out) *steps_out = steps;
+  return start;
+}
+
+// One round: the site updates and cluster starts in `sites` / `starting`,
+// the next split level of every task in `active` (the starting ones included),
+// the final scaling of the tasks whose last level this is.
+void wave_round(mps_ctx* ctx, std::vector<WaveTask>& T, const std::vector<int>& sites,
+                const std::vector<int>& starting, const std::vector<int>& active) {
+  hipStream_t s = ctx->stream;
+  const Prec P = ctx->prec;
+  const bool mixed = P != Prec::FP64;
+  // workspaces of the starting clusters
+  for (int i : starting) {
+    WaveTask& w = T[i];
+    plan_job(ctx, w.job, w.run);
+    const size_t bytes = job_bytes(ctx, w.run) + 4096;
+    HIP_OK(ctx->pool.get(bytes, &w.ws, &w.ws_cap));
+    DeviceArena view;
+    view.base = w.ws;
+    view.cap = w.ws_cap;
+    assign_job(ctx, w.run, view);
+    w.run.logf = (double*)view.take(sizeof(double));
+    HIP_OK(hipMemsetAsync(w.run.logf, 0, sizeof(double), s));
+    job_features(ctx, w.run, w.job, w.nsub, w.feats);
+    if (ctx->timing) account_merge(ctx, w.run);
+  }
+  const int na = (int)active.size();
+  ctx->arena.reset();
+  HIP_OK(ctx->arena.reserve((size_t)std::max(1, na) * 4 * sizeof(int) + 4096));
+  int* flags_round = (int*)ctx->arena.take((size_t)std::max(1, na) * 4 * sizeof(int));
+  for (int p = 0; p < na; ++p) {
+    JobRun& r = T[active[p]].run;
+    r.flags = flags_round + 4 * p;
+    r.flag_index = p;
+  }
+  if (ctx->timing) HIP_OK(hipMemsetAsync(ctx->d_work, 0, 4 * sizeof(unsigned long long), s));
+
+  DescBlob& B = ctx->blob;
+  B.host.clear();
+  // one-qubit site updates
+  std::vector<Site1QDesc> s1;
+  std::vector<int> sbase{0};
+  for (int i : sites) {
+    const WaveTask& w = T[i];
+    Site1QDesc d{};
+    d.B = ctx->site[w.q];
+    d.chi_l = bond_dim(ctx, w.q - 1);
+    d.chi_r = bond_dim(ctx, w.q);
+    for (int e = 0; e < 4; ++e) {
+      d.u[2 * e] = w.u1[e].real();
+      d.u[2 * e + 1] = w.u1[e].imag();
+    }
+    d.blocks = std::max(1, std::min(256, ceil_div((int64_t)d.chi_l * d.chi_r, 256)));
+    s1.push_back(d);
+    sbase.push_back(sbase.back() + d.blocks);
+  }
+  // unitaries, merge chains and unitary applications of the starting clusters
+  int kmax = 0;
+  for (int i : starting) kmax = std::max(kmax, T[i].job.k);
+  std::vector<UnitaryDesc> ud;
+  std::vector<int> ubase{0};
+  std::vector<size_t> gate_off;
+  size_t ulds = 0;
+  for (int i : starting) {
+    const Job& jb = T[i].job;
+    std::vector<UGate> ug;
+    for (const auto& g : jb.gates) {
+      UGate u{};
+      u.nq = g.nq;
+      u.q0 = g.q[0] - jb.a;
+      u.q1 = g.nq > 1 ? g.q[1] - jb.a : 0;
+      const int dd = 1 << (2 * g.nq);
+      for (int e = 0; e < dd; ++e) {
+        u.u[2 * e] = g.u[e].real();
+        u.u[2 * e + 1] = g.u[e].imag();
+      }
+      ug.push_back(u);
+    }
+    gate_off.push_back(ug.empty() ? 0 : B.add_vec(ug));
+    UnitaryDesc d{};
+    d.ngates = (int)ug.size();
+    d.k = jb.k;
+    d.U64 = (double2*)T[i].run.U64;
+    d.U32 = (P == Prec::FP64) ? nullptr : (float2*)T[i].run.Uw;
+    const int dim = 1 << jb.k;
+    d.cols = std::max(1, std::min(16, 4096 / dim));
+    d.blocks = ceil_div(dim, d.cols);
+    ulds = std::max(ulds, (size_t)d.cols * dim * sizeof(double2));
+    ud.push_back(d);
+    ubase.push_back(ubase.back() + d.blocks);
+  }
+  std::vector<std::vector<GemmDesc>> mg(std::max(1, kmax));
+  std::vector<GemmDesc> ap;
+  for (int i : starting) {
+    JobRun& r = T[i].run;
+    for (int j = 1; j < r.k; ++j) {
+      GemmDesc d{};
+      const int M = r.chi_l << j;
+      const int K = r.mid[j - 1];
+      const int N = 2 * ((j == r.k - 1) ? r.chi_r : r.mid[j]);
+      d.A = (j == 1) ? ctx->site[r.a] : r.buf[(j - 1) & 1];
+      d.B = ctx->site[r.a + j];
+      d.C = r.buf[j & 1];
+      d.M = fixed(M);
+      d.N = fixed(N);
+      d.K = fixed(K);
+      d.lda = fixed(K);
+      d.ldb = fixed(N);
+      d.ldc = fixed(N);
+      d.batch = 1;
+      d.tm = ceil_div(M, 64);
+      d.tn = ceil_div(N, 64);
+      d.ksplit = 1;
+      d.alpha = 1.0;
+      mg[j].push_back(d);
+    }
+    r.cur = (r.k - 1) & 1;
+    GemmDesc d{};
+    const int D = 1 << r.k;
+    d.A = r.Uw;
+    d.B = r.buf[r.cur];
+    d.C = r.buf[r.cur ^ 1];
+    d.M = fixed(D);
+    d.N = fixed(r.chi_r);
+    d.K = fixed(D);
+    d.lda = fixed(D);
+    d.ldb = fixed(r.chi_r);
+    d.ldc = fixed(r.chi_r);
+    d.sA = 0;
+    d.sB = d.sC = (int64_t)D * r.chi_r;
+    d.batch = r.chi_l;
+    d.tm = ceil_div(D, 64);
+    d.tn = ceil_div(r.chi_r, 64);
+    d.ksplit = 1;
+    d.alpha = 1.0;
+    ap.push_back(d);
+    r.cur ^= 1;
+  }
+  // split levels of every running cluster, final scaling of those that end
+  LevelDescs L;
+  L.nb_max_all = 0;
+  std::vector<ScaleDesc> fin;
+  std::vector<int> fbase{0};
+  std::vector<const double*> fin_logf;
+  for (int p = 0; p < na; ++p) {
+    WaveTask& w = T[active[p]];
+    JobRun& r = w.run;
+    add_level(ctx, L, r, p, w.level, nullptr);
+    if (w.level == r.k - 2) {
+      ScaleDesc d{};
+      d.X = r.buf[r.cur];
+      d.B = ctx->site[r.a];
+      d.count = Dim{2 * r.chi_l, ctx->d_chi + r.a};
+      d.logf = r.logf;
+      const int64_t bound = (int64_t)2 * r.chi_l * std::min(ctx->chi_max, 2 * r.chi_l);
+      d.blocks = std::max(1, std::min(1024, ceil_div(bound, 256)));
+      fin.push_back(d);
+      fbase.push_back(fbase.back() + d.blocks);
+      fin_logf.push_back(r.logf);
+    }
+  }
+  // serialise
+  size_t o_s1 = 0, b_s1 = 0, o_ud = 0, b_ud = 0, o_ap = 0, b_ap = 0, o_fin = 0, b_fin = 0, o_lf = 0;
+  if (!s1.empty()) {
+    o_s1 = B.add_vec(s1);
+    b_s1 = B.add_vec(sbase);
+  }
+  if (!ud.empty()) {
+    o_ud = B.add_vec(ud);
+    b_ud = B.add_vec(ubase);
+  }
+  std::vector<size_t> o_mg(mg.size(), 0), b_mg(mg.size(), 0);
+  std::vector<int> n_mg(mg.size(), 0);
+  for (size_t j = 1; j < mg.size(); ++j) n_mg[j] = upload_gemms(B, mg[j], o_mg[j], b_mg[j]);
+  const int n_ap = ap.empty() ? 0 : upload_gemms(B, ap, o_ap, b_ap);
+  if (na) upload_level(B, L);
+  if (!fin.empty()) {
+    o_fin = B.add_vec(fin);
+    b_fin = B.add_vec(fbase);
+    o_lf = B.add_vec(fin_logf);
+  }
+  HIP_OK(B.prepare());
+  for (size_t q = 0; q < ud.size(); ++q) {
+    UnitaryDesc* d = B.host_at<UnitaryDesc>(o_ud) + q;
+    d->gates = d->ngates ? B.at<UGate>(gate_off[q]) : nullptr;
+  }
+  HIP_OK(B.upload(s));
+  // launches
+  if (!s1.empty()) {
+    Timed tm(ctx, "one_qubit");
+    HIP_OK(launch_apply_1q(P, B.at<Site1QDesc>(o_s1), B.at<int>(b_s1), (int)s1.size(), sbase.back(), s));
+  }
+  if (!ud.empty()) {
+    Timed tm(ctx, "unitary");
+    HIP_OK(launch_build_unitary(B.at<UnitaryDesc>(o_ud), B.at<int>(b_ud), (int)ud.size(), ubase.back(), ulds, s));
+  }
+  for (size_t j = 1; j < mg.size(); ++j) {
+    if (mg[j].empty()) continue;
+    Timed tm(ctx, "merge");
+    HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(o_mg[j]), B.at<int>(b_mg[j]), (int)mg[j].size(), n_mg[j], s));
+  }
+  if (!ap.empty()) {
+    Timed tm(ctx, "apply");
+    HIP_OK(launch_gemm_nn(P, B.at<GemmDesc>(o_ap), B.at<int>(b_ap), (int)ap.size(), n_ap, s));
+  }
+  if (na) launch_level(ctx, B, L, flags_round, 4 * na, [] {});
+  if (!fin.empty()) {
+    Timed tm(ctx, "finalize");
+    HIP_OK(launch_finalize(P, B.at<ScaleDesc>(o_fin), B.at<int>(b_fin), (int)fin.size(), fbase.back(), s));
+    HIP_OK(launch_accumulate_ptrs(B.at<const double*>(o_lf), (int)fin.size(), ctx->d_logf, s));
+  }
+  // end of round: bond dimensions and the finished clusters' records
+  std::vector<double> rec;
+  std::vector<int> ending;
+  for (int i : active)
+    if (T[i].level == T[i].run.k - 2) ending.push_back(i);
+  size_t nrec = 0;
+  for (int i : ending) nrec += 4 * (T[i].run.k - 1);
+  rec.resize(nrec);
+  HIP_OK(hipMemcpyAsync(ctx->chi.data(), ctx->d_chi, (ctx->n - 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  {
+    size_t off = 0;
+    for (int i : ending) {
+      const JobRun& r = T[i].run;
+      HIP_OK(hipMemcpyAsync(rec.data() + off, r.rec, 4 * (r.k - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      off += 4 * (r.k - 1);
+    }
+  }
+  unsigned long long eig_work[4] = {0, 0, 0, 0};
+  if (ctx->timing) HIP_OK(hipMemcpyAsync(eig_work, ctx->d_work, sizeof(eig_work), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (ctx->timing) {
+    collect_timing(ctx);
+    for (int i : active) account_level(ctx, T[i].run, T[i].level, mixed);
+    ctx->timer.flop[ctx->timer.cls_of("eig_update")] += 8.0 * (double)eig_work[0];
+    ctx->timer.flop[ctx->timer.cls_of("eig_pairs")] += (double)eig_work[1];
+    ctx->timer.flop[ctx->timer.cls_of("eig_update32")] += 8.0 * (double)eig_work[2];
+    ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
+  }
+  for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
+  // (features, log2 kept rank) of the splits of this round
+  for (int i : active) {
+    const WaveTask& w = T[i];
+    const int t = w.level;
+    if (ctx->log_t.size() >= (size_t)4000000) break;
+    const int rk = ctx->chi[w.run.a + w.run.lv[t].m - 1];
+    ctx->log_x.insert(ctx->log_x.end(), w.feats.begin() + (size_t)t * N_FEAT,
+                      w.feats.begin() + (size_t)(t + 1) * N_FEAT);
+    ctx->log_t.push_back(std::log2((float)rk));
+  }
+  for (int i : active) {
+    WaveTask& w = T[i];
+    if (++w.level == w.run.k - 1) {
+      w.state = 2;
+      ctx->pool.put(w.ws, w.ws_cap);
+      w.ws = nullptr;
+      ctx->stats.cluster_updates += 1;
+      ctx->stats.svds += w.run.k - 1;
+    }
+  }
+  for (int i : sites) {
+    T[i].state = 2;
+    ctx->stats.site_updates += 1;
+  }
+}
+
+void run_wave(mps_ctx* ctx, std::vector<WaveTask>& T) {
+  std::vector<int> running;
+  size_t done = 0;
+  while (done < T.size()) {
+    std::vector<int> sites, starting;
+    for (int i = 0; i < (int)T.size(); ++i) {
+      if (T[i].state != 0) continue;
+      bool ready = true;
+      for (int d : T[i].deps)
+        if (T[d].state != 2) {
+          ready = false;
+          break;
+        }
+      if (!ready) continue;
+      (T[i].site ? sites : starting).push_back(i);
+    }
+    for (int i : starting) {
+      T[i].state = 1;
+      running.push_back(i);
+    }
+    if (sites.empty() && running.empty()) fail(ctx, MPS_ESTATE, "wavefront executor: no task can run");
+    wave_round(ctx, T, sites, starting, running);
+    std::vector<int> still;
+    for (int i : running)
+      if (T[i].state != 2) still.push_back(i);
+    running.swap(still);
+    done = 0;
+    for (const auto& w : T) done += w.state == 2;
+  }
+}
+
+// Executes the next `nsteps` planned steps (every buffered one when nsteps < 0)
+// with the wavefront executor; returns the number of steps.  Falls back to
+// one step at a time where the window cannot be planned up front (a binding
+// q_max) or where the step executor is the one asked for.
+int execute_window(mps_ctx* ctx, int nsteps) {
+  if (ctx->pending.empty() || nsteps == 0) return 0;
+  const bool wave = ctx->opt.batch == MPS_BATCH_WAVE && ctx->opt.svd_mode == MPS_SVD_EXACT && plan_is_chi_free(ctx);
+  if (!wave) {
+    int done = 0;
+    while (!ctx->pending.empty() && (nsteps < 0 || done < nsteps)) {
+      execute_step(ctx, 0);
+      ++done;
+    }
+    return done;
+  }
+  std::vector<WaveTask> T;
+  int steps = 0;
+  const int used = plan_window(ctx, nsteps, T, &steps);
+  try {
+    run_wave(ctx, T);
+  } catch (...) {
+    for (auto& w : T)
+      if (w.ws) ctx->pool.put(w.ws, w.ws_cap);
+    throw;
+  }
+  ctx->pending.erase(ctx->pending.begin(), ctx->pending.begin() + used);
+  ctx->stats.steps += steps;
+  return steps;
+}
+
 // Executes one planned step from the pending sub-layers; returns the number
 // of sub-layers consumed.
 int execute_step(mps_ctx* ctx, int end_hint) {
@@ -1577,8 +2069,22 @@ int execute_step(mps_ctx* ctx, int end_hint) {
   return end;
 }
 
-void flush_all(mps_ctx* ctx) {
-  while (!ctx->pending.empty()) execute_step(ctx, 0);
+void flush_all(mps_ctx* ctx) { execute_window(ctx, -1); }
+
+// Steps of the buffered sub-layers that can no longer grow (the last planned
+// step may still take sub-layers of a later layer).
+int complete_steps(mps_ctx* ctx) {
+  int start = 0, cnt = 0;
+  const int total = (int)ctx->pending.size();
+  while (start < total) {
+    std::vector<Cluster> cl;
+    const int end = plan_step(ctx->pending, start, ctx->n, ctx->chi, ctx->opt.k_max, ctx->q_max_eff,
+                              ctx->l_max_eff, cl);
+    if (end >= total) break;
+    ++cnt;
+    start = end;
+  }
+  return cnt;
 }
 
 HostGate to_host_gate(const mps_gate& g) {
@@ -1643,6 +2149,7 @@ void destroy_ctx(mps_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   ctx->arena.release();
+  ctx->pool.release();
   ctx->blob.release();
   if (ctx->state_mem) (void)hipFree(ctx->state_mem);
   if (ctx->d_chi) (void)hipFree(ctx->d_chi);
@@ -1659,7 +2166,7 @@ void destroy_ctx(mps_ctx* ctx) {
 
 bool options_valid(const mps_options& o) {
   return o.k_max >= 2 && o.k_max <= 12 && o.precision >= 0 && o.precision <= 2 && o.svd_mode >= 0 &&
-         o.svd_mode <= 1 && o.batch >= 0 && o.batch <= 1 && o.eig_method >= 0 && o.eig_method <= 2 &&
+         o.svd_mode <= 1 && o.batch >= 0 && o.batch <= 2 && o.eig_method >= 0 && o.eig_method <= 2 &&
          o.floor_c >= 0.0;
 }
 
@@ -1883,6 +2390,10 @@ mps_status mps_run_layer(mps_handle ctx, const mps_gate* gates, int ngates) {
     for (int i = 0; i < ngates; ++i) layer.push_back(to_host_gate(gates[i]));
     legalize_layer(layer, ctx->opt.k_max, ctx->pending);
     // execute every step that can no longer grow
+    if (ctx->opt.batch == MPS_BATCH_WAVE && plan_is_chi_free(ctx)) {
+      execute_window(ctx, complete_steps(ctx));
+      return MPS_OK;
+    }
     while (!ctx->pending.empty()) {
       std::vector<Cluster> cl;
       const int end = plan_step(ctx->pending, 0, ctx->n, ctx->chi, ctx->opt.k_max, ctx->q_max_eff,
@@ -1919,6 +2430,17 @@ mps_status mps_step(mps_handle ctx, int* clusters, int* remaining) {
   return guarded(ctx, [&]() -> mps_status {
     const int64_t before = ctx->stats.cluster_updates;
     if (!ctx->pending.empty()) execute_step(ctx, 0);
+    if (clusters) *clusters = (int)(ctx->stats.cluster_updates - before);
+    if (remaining) *remaining = (int)ctx->pending.size();
+    return MPS_OK;
+  });
+}
+
+mps_status mps_run_steps(mps_handle ctx, int nsteps, int* clusters, int* remaining) {
+  if (!ctx || nsteps < 0) return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    const int64_t before = ctx->stats.cluster_updates;
+    execute_window(ctx, nsteps);
     if (clusters) *clusters = (int)(ctx->stats.cluster_updates - before);
     if (remaining) *remaining = (int)ctx->pending.size();
     return MPS_OK;

@@ -31,6 +31,19 @@ struct DeviceArena {
   void release();
 };
 
+// Device blocks for the workspaces of the wavefront executor's tasks, which
+// live for several rounds: a freed block goes to a free list and serves a
+// later request that fits in it and needs at least half of it (sizes are
+// rounded up to 2 MiB multiples).  Blocks return to the runtime only with the
+// handle.
+struct BlockPool {
+  std::multimap<size_t, char*> free_blocks;  // capacity -> block
+  std::vector<std::pair<char*, size_t>> all;
+  hipError_t get(size_t bytes, char** out, size_t* cap);
+  void put(char* p, size_t cap) { free_blocks.emplace(cap, p); }
+  void release();
+};
+
 // Host-side blob of descriptors uploaded once per step (pinned host staging).
 struct DescBlob {
   std::vector<char> host;
@@ -112,6 +125,7 @@ struct mps_ctx {
   double* d_ones = nullptr;         // weights of a left edge (all ones)
   int ones_len = 0;
   ctebd::DeviceArena arena;
+  ctebd::BlockPool pool;            // task workspaces of the wavefront executor
   ctebd::DescBlob blob;
   int* h_flags = nullptr;           // pinned: eigen convergence flags
   std::vector<ctebd::SubLayer> pending;

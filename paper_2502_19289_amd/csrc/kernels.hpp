@@ -445,5 +445,7 @@ hipError_t launch_convert_f2d(const float2* src, double2* dst, int64_t n, hipStr
 
 // Log-f accumulation in a fixed order (deterministic): total += sum_i v[i]
 hipError_t launch_accumulate(const double* v, int n, double* total, hipStream_t s);
+// total += *v[0] + ... + *v[n-1] (v: device array of n device pointers)
+hipError_t launch_accumulate_ptrs(const double* const* v, int n, double* total, hipStream_t s);
 
 }  // namespace ctebd

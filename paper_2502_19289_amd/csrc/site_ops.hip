@@ -287,7 +287,24 @@ __global__ void accumulate_kernel(const double* __restrict__ v, int n, double* t
   }
 }
 
+// total += *v[0] + ... + *v[n-1], in that order (the log f of the clusters
+// that finished in one round of the wavefront executor, each in its own
+// workspace)
+__global__ void accumulate_ptrs_kernel(const double* const* __restrict__ v, int n, double* total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = *total;
+    for (int i = 0; i < n; ++i) s += *v[i];
+    *total = s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_accumulate_ptrs(const double* const* v, int n, double* total, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  launch(accumulate_ptrs_kernel, dim3(1), dim3(64), 0, s, v, n, total);
+  return hipGetLastError();
+}
 
 hipError_t launch_build_unitary(const UnitaryDesc* d, const int* d_base, int nprob, int blocks,
                                 size_t lds_bytes, hipStream_t s) {

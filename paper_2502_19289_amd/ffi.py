@@ -20,7 +20,7 @@ MPS_OK, MPS_EINVAL, MPS_ENOMEM, MPS_ESPAN, MPS_ENOTUNITARY, MPS_EDEVICE, MPS_EST
     0, -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "fp32": 1, "bf16x6": 2}
 SVD = {"exact": 0, "learned": 1}
-BATCH = {"none": 0, "step": 1}
+BATCH = {"none": 0, "step": 1, "wave": 2}
 EIG = {"auto": 0, "jacobi": 1, "tridiag": 2}
 
 
@@ -49,7 +49,7 @@ class CtebdError(RuntimeError):
 
 EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster", "mps_set_options",
            "mps_save", "mps_load",
-           "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_clone", "mps_overlap",
+           "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_run_steps", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
            "mps_set_timing", "mps_set_burst_timing", "mps_kernel_dispatches", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_last_error", "mps_plan",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_flush.argtypes = [P]
     lib.mps_queue_layer.argtypes = [P, C.POINTER(GateC), I]
     lib.mps_step.argtypes = [P, C.POINTER(I), C.POINTER(I)]
+    lib.mps_run_steps.argtypes = [P, I, C.POINTER(I), C.POINTER(I)]
     lib.mps_clone.argtypes = [P, C.POINTER(Options), C.POINTER(P)]
     lib.mps_set_options.argtypes = [P, C.POINTER(Options)]
     lib.mps_save.argtypes = [P, C.c_char_p]
@@ -218,6 +219,12 @@ class MPS:
         """Executes one cluster-TEBD step; returns (clusters, sub-layers left)."""
         c, r = C.c_int(), C.c_int()
         self._check(self.lib.mps_step(self.h, C.byref(c), C.byref(r)))
+        return c.value, r.value
+
+    def run_steps(self, nsteps: int) -> Tuple[int, int]:
+        """mps_run_steps: the next nsteps steps; returns (clusters, sub-layers left)."""
+        c, r = C.c_int(), C.c_int()
+        self._check(self.lib.mps_run_steps(self.h, int(nsteps), C.byref(c), C.byref(r)))
         return c.value, r.value
 
     def clone(self, precision: Optional[str] = None, batch: Optional[str] = None,

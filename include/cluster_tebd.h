@@ -268,6 +268,22 @@ mps_status mps_kernel_times(mps_handle h, double* ms, int64_t* launches, double*
  * HIP failures; mps_last_error(NULL) then describes the failure. */
 mps_status mps_heev(int n, const double* A, double* w, double* V);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mps_heev on
+ * caller-owned DEVICE buffers, with every intermediate in a 16 MiB array of
+ * static device memory that the library holds on each GPU it runs on until
+ * the process ends.  A: n x n Hermitian (interleaved complex128, row-major,
+ * both triangles read, not modified); w: n eigenvalues, ascending; V: n x n,
+ * V[i*n + j] the i-th component of the j-th eigenvector; the same kernels as
+ * mps_heev, so the same results.  stream: hipStream_t to run on (NULL: the
+ * null stream); the call returns after the stream has finished its work.
+ * 1 <= n <= 512, else MPS_EINVAL (nothing runs); MPS_EDEVICE for HIP
+ * failures; mps_last_error(NULL) says why.  No hipMalloc, hipFree or other
+ * allocation of device memory happens in this call.  Every call on one GPU
+ * uses the same array: calls that overlap on one GPU (two host threads, or
+ * two streams) race and must be serialised by the caller. */
+mps_status mps_heev_noalloc(int n, const double* A, double* w, double* V, void* stream);
+
 /* Burst timing of one kernel class, for kernels too short for a pair of
  * events around each launch (on this GPU each event adds the latency of a
  * marker packet, several microseconds): every stride-th launch of the class

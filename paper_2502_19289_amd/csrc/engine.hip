@@ -20,6 +20,7 @@
 #include <cstring>
 #include <fstream>
 #include <iterator>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -3035,6 +3036,84 @@ mps_status mps_heev(int n, const double* A, double* w, double* V) {
   }
   if (mem) (void)hipFree(mem);
   if (st != MPS_OK) g_err = "mps_heev: " + tmp.err;
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+// Workspace of mps_heev_noalloc: the working matrix, the eigenvector matrix,
+// the tridiagonal solver's buffers and its descriptor for n <= 512 (15.2 MiB
+// of the 16 MiB).  Every GPU that runs the call holds its own copy until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device.
+constexpr int HEEV_NOALLOC_MAX_N = 512;
+constexpr size_t HEEV_SCRATCH_BYTES = size_t(16) << 20;
+__device__ __align__(256) char scratch[HEEV_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_at[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+hipError_t scratch_address(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_at[dev] = (char*)p;
+  }
+  *out = g_scratch_at[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+mps_status mps_heev_noalloc(int n, const double* A, double* w, double* V, void* stream) {
+  if (n < 1 || n > HEEV_NOALLOC_MAX_N || !A || !w || !V) {
+    g_err = "mps_heev_noalloc: need 1 <= n <= 512 and non-null device pointers";
+    return MPS_EINVAL;
+  }
+  mps_ctx tmp;
+  tmp.n = 1;
+  tmp.stream = (hipStream_t)stream;
+  const mps_status st = guarded(&tmp, [&]() -> mps_status {
+    mps_ctx* ctx = &tmp;
+    char* base = nullptr;
+    HIP_OK(scratch_address(&base));
+    const size_t ld = (size_t)ceil_div(n, 64) * 64;
+    size_t used = 0;
+    auto take = [&](size_t x) -> void* {
+      const size_t off = (used + 255) & ~size_t(255);
+      used = off + x;
+      return base + off;
+    };
+    HtdDesc h{};
+    h.A = (double2*)take(ld * ld * sizeof(double2));
+    h.V = (double2*)take(ld * ld * sizeof(double2));
+    htd_layout(ld, h, take);
+    HtdDesc* dd = (HtdDesc*)take(sizeof(HtdDesc));
+    if (used > HEEV_SCRATCH_BYTES) fail(ctx, MPS_EINVAL, "workspace larger than the scratch array");
+    h.n = Dim{n, nullptr};
+    h.ld = (int)ld;
+    h.rcap = n;
+    h.skip = nullptr;
+    hipStream_t s = tmp.stream;
+    HIP_OK(hipMemcpy2DAsync(h.A, ld * sizeof(double2), A, n * sizeof(double2), n * sizeof(double2), n,
+                            hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(dd, &h, sizeof(HtdDesc), hipMemcpyHostToDevice, s));
+    solve_htd(ctx, dd, std::vector<HtdDesc>{h});
+    HIP_OK(launch_heev_out(h.V, (int)ld, h.lam, n, (double2*)V, w, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return MPS_OK;
+  });
+  if (st != MPS_OK) g_err = "mps_heev_noalloc: " + tmp.err;
+  tmp.stream = nullptr;  // the caller's stream
   return st;
 }
 

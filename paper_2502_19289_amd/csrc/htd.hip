@@ -1959,4 +1959,25 @@ hipError_t launch_bt_update(const HtdDesc* d, const HtdSizes& sz, int b, int blo
   return hipGetLastError();
 }
 
+// Eigenpairs of one solve in ascending order into caller buffers: w[j] and
+// column j of V (row-major n x n) from the solver's descending lam / columns
+// of Vw (leading dimension ld).
+__global__ void heev_out_kernel(const double2* __restrict__ Vw, int ld, const double* __restrict__ lam, int n,
+                                double2* __restrict__ V, double* __restrict__ w) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    V[e] = Vw[(int64_t)i * ld + (n - 1 - j)];
+    if (i == 0) w[j] = lam[n - 1 - j];
+  }
+}
+
+hipError_t launch_heev_out(const double2* Vw, int ld, const double* lam, int n, double2* V, double* w,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, ((int64_t)n * n + 255) / 256);
+  hipLaunchKernelGGL(heev_out_kernel, dim3(blocks), dim3(256), 0, s, Vw, ld, lam, n, V, w);
+  return hipGetLastError();
+}
+
 }  // namespace ctebd

@@ -320,6 +320,9 @@ hipError_t launch_bt_larft(const HtdDesc* d, const HtdSizes& sz, int blocks, hip
 hipError_t launch_bt_wpart(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
 hipError_t launch_bt_wred(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
 hipError_t launch_bt_update(const HtdDesc* d, const HtdSizes& sz, int b, int blocks, hipStream_t s);
+// w ascending and V's columns to match, from one solve's descending output
+hipError_t launch_heev_out(const double2* Vw, int ld, const double* lam, int n, double2* V, double* w,
+                           hipStream_t s);
 
 // ------------------------------------------------------ learned sketch ----
 constexpr int SK_PROBES = 8;

@@ -52,7 +52,7 @@ EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluste
            "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_run_steps", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
-           "mps_set_timing", "mps_set_burst_timing", "mps_kernel_dispatches", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_last_error", "mps_plan",
+           "mps_set_timing", "mps_set_burst_timing", "mps_kernel_dispatches", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_heev_noalloc", "mps_last_error", "mps_plan",
            "mlp_num_params", "mlp_create", "mlp_destroy", "mlp_get_params", "mlp_set_params",
            "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log"]
 N_FEAT = 12
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_set_burst_timing.argtypes = [P, C.c_char_p, I, I]
     lib.mps_kernel_dispatches.argtypes = [P, C.POINTER(C.c_int64), I, C.POINTER(I)]
     lib.mps_heev.argtypes = [I, C.POINTER(D), C.POINTER(D), C.POINTER(D)]
+    lib.mps_heev_noalloc.argtypes = [I, P, P, P, P]
     lib.mps_last_error.argtypes = [P]
     lib.mps_last_error.restype = C.c_char_p
     lib.mps_plan.argtypes = [I, I, I, I, C.POINTER(I), C.POINTER(GateC), C.POINTER(I), I, I,

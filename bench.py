@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="oracle sample budget (0: skip)")
     ap.add_argument("--warmup-budget", type=float, default=300.0, help="seconds cap of the preparation steps")
     ap.add_argument("--copy-calibration", type=int, default=0)
+    ap.add_argument("--compare-tebd", default="",
+                    help="instead of the benchmark line: whole-circuit runtime of cluster-TEBD and of gate-by-gate "
+                         "TEBD (k_max 2, one sub-layer per step) on the named workload, one JSON line")
     ap.add_argument("--profile-window", action="store_true",
                     help="ask an attached rocprofv3 to collect only during the timed steps")
     ap.add_argument("--burst-reps", type=int, default=BURST_REPS,
@@ -269,8 +272,46 @@ def cpu_baseline(m, circ, p, remaining: int, steps: int, budget: float) -> dict:
             f"on the site tensors the GPU state holds before that step; {t_used:.1f} s of oracle time"}
 
 
+def compare_tebd(args):
+    """The synthetic analogue of the paper's cluster-TEBD versus TEBD runtime
+    comparison (Sec. IV.B): the same circuit from |0...0> to its end with both
+    algorithms on the same kernels and executor, FP32 contractions."""
+    import torch
+
+    import paper_2502_19289_amd as P
+    from workloads import make_workload
+
+    circ, p = make_workload(args.compare_tebd, seed=args.seed)
+    out = {"comparison": "cluster-TEBD vs gate-by-gate TEBD, whole circuit", "workload": args.compare_tebd,
+           "n": circ.n, "layers": len(circ.layers), "chi_max": p["chi_max"], "eps": p["eps"],
+           "precision": args.precision, "batch": args.batch}
+    runs = {}
+    for algo, k_max, l_max in (("ctebd", p["k_max"], 0), ("tebd", 2, 1)):
+        m = P.MPS(circ.n, p["chi_max"], p["eps"], k_max=k_max, l_max=l_max, precision=args.precision,
+                  batch=args.batch, eig=args.eig)
+        for layer in circ.layers:
+            m.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.run_steps(1 << 30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = m.stats()
+        out[algo] = {"seconds": dt, "k_max": k_max, "steps": st["steps"], "svds": st["svds"],
+                     "cluster_updates": st["cluster_updates"], "F_est": m.fidelity()[0],
+                     "max_chi": max(m.bond_dims())}
+        runs[algo] = m
+        print(f"# {algo}: {dt:.2f} s, {st['svds']} SVDs", file=sys.stderr, flush=True)
+    out["speedup"] = out["tebd"]["seconds"] / out["ctebd"]["seconds"]
+    out["infidelity_ctebd_vs_tebd"] = runs["ctebd"].infidelity(runs["tebd"])
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.compare_tebd:
+        compare_tebd(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)

@@ -100,6 +100,48 @@ def random_structured(n: int, n_layers: int, d_max: int, symbols: Sequence[str],
                              seed=seed, workload_id=workload_id))
 
 
+# The paper's own random-structured circuits (Sec. IV.A): in every layer each
+# qubit receives either a single-qubit or a two-qubit gate with probability
+# p = 0.5, gates drawn uniformly from the version's sets; version 1 is
+# Clifford, version 2 adds four non-Clifford gates to each set (half of each
+# set is then non-Clifford).
+PAPER_ONE_QUBIT = {1: ("H", "X", "Y", "Z"), 2: ("H", "X", "Y", "Z", "T", "P3PI4", "X4", "SQRTW")}
+PAPER_TWO_QUBIT = {1: ("CNOT", "CY", "CZ", "SWAP"), 2: ("CNOT", "CY", "CZ", "SWAP", "CH", "CS", "CT", "SQRTSWAP")}
+
+
+def paper_random_structured(n: int, n_layers: int, version: int, p_two: float = 0.5, d_max: int = 1,
+                            seed: int = 0, workload_id: int = 0) -> Circuit:
+    """Per layer, the qubits are visited in a random order; a qubit still free
+    in this layer draws a two-qubit gate with probability p_two (else a
+    single-qubit gate); a two-qubit gate takes as second qubit a free qubit at
+    distance 1..d_max drawn uniformly (the first drawn qubit is the control of
+    a controlled gate); with no free qubit in reach the qubit gets a
+    single-qubit gate.  Every qubit thus carries exactly one gate per layer."""
+    rng = _rng(workload_id, seed)
+    ones, twos = PAPER_ONE_QUBIT[version], PAPER_TWO_QUBIT[version]
+    layers: List[List[Gate]] = []
+    for _ in range(n_layers):
+        free = np.ones(n, dtype=bool)
+        gates: List[Gate] = []
+        for a in rng.permutation(n):
+            a = int(a)
+            if not free[a]:
+                continue
+            free[a] = False
+            if rng.random() < p_two:
+                cand = [b for d in range(1, d_max + 1) for b in (a - d, a + d) if 0 <= b < n and free[b]]
+                if cand:
+                    b = int(cand[int(rng.integers(0, len(cand)))])
+                    free[b] = False
+                    gates.append(Gate(twos[int(rng.integers(0, len(twos)))], (a, b)))
+                    continue
+            gates.append(Gate(ones[int(rng.integers(0, len(ones)))], (a,)))
+        gates.sort(key=lambda g: (min(g.qubits), g.qubits))
+        layers.append(gates)
+    return Circuit(n=n, layers=layers, meta=dict(generator="paper", version=version, p_two=p_two, d_max=d_max,
+                                                 seed=seed, workload_id=workload_id))
+
+
 # Named workloads: the circuit recipe plus the truncation / clustering parameters
 # (cap chi_max, cutoff eps, largest cluster k_max) each one is simulated with.
 WORKLOADS = {
@@ -113,6 +155,18 @@ WORKLOADS = {
                              rho_t=0.2, k_max=6, chi_max=1024, eps=1e-10),
     "learned_n500_l60": dict(wid=5, n=500, layers=60, d_max=10, symbols=("H", "S", "CNOT"),
                              rho_t=0.15, k_max=6, chi_max=512, eps=1e-10),
+    # the paper's generator (Sec. IV.A): Clifford and non-Clifford versions,
+    # nearest-neighbour two-qubit gates, 40 qubits and 40 layers (the size at
+    # which the paper reports its largest cluster-TEBD speed-ups)
+    "paper_clifford_n40_l40": dict(wid=6, n=40, layers=40, version=1, d_max=1, k_max=6, chi_max=1024, eps=1e-12),
+    "paper_nonclifford_n40_l40": dict(wid=7, n=40, layers=40, version=2, d_max=1, k_max=6, chi_max=1024,
+                                      eps=1e-12),
+    # deeper and wider: entanglement reaches the cap (the regime of the paper's
+    # 100-layer Clifford and 80-layer non-Clifford comparisons)
+    "paper_clifford_n100_l100": dict(wid=8, n=100, layers=100, version=1, d_max=1, k_max=6, chi_max=1024,
+                                     eps=1e-12),
+    "paper_nonclifford_n100_l80": dict(wid=9, n=100, layers=80, version=2, d_max=1, k_max=6, chi_max=1024,
+                                       eps=1e-12),
 }
 
 
@@ -122,7 +176,10 @@ def make_workload(name: str, seed: int = 0, n: int | None = None, layers: int | 
     w = dict(WORKLOADS[name])
     nn = w["n"] if n is None else n
     ll = w["layers"] if layers is None else layers
-    c = random_structured(nn, ll, min(w["d_max"], nn - 1), w["symbols"], w["rho_t"], seed, w["wid"])
+    if "version" in w:
+        c = paper_random_structured(nn, ll, w["version"], 0.5, min(w["d_max"], nn - 1), seed, w["wid"])
+    else:
+        c = random_structured(nn, ll, min(w["d_max"], nn - 1), w["symbols"], w["rho_t"], seed, w["wid"])
     c.meta["workload"] = name
     params = dict(k_max=w["k_max"], chi_max=w["chi_max"], eps=w["eps"])
     return c, params

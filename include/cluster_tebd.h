@@ -323,10 +323,11 @@ const char* mps_last_error(mps_handle h);
  * accepted only when its 8-probe residual estimate shows that every
  * eigenvalue it missed lies below the truncation threshold, and otherwise
  * redone by the exact solve.  Features of a split (12 FP32): k, log2 chi_l,
- * log2 chi_r, m/k, log2 rows, log2 (2c bound), 2q gates crossing the bond,
- * 2q gates of the cluster, non-Clifford phase gates of the cluster,
- * sub-layers of the step, log2 of the bond's dimension before the step,
- * log2 chi_max.  Parameters are a flat FP32 vector: W1 (64x12), b1, W2
+ * log2 chi_r, m/k, log10 of the discarded weight of the bond's previous split,
+ * log2 (2c bound), 2q gates crossing the bond, 2q gates of the cluster,
+ * non-Clifford phase gates of the cluster, sub-layers of the step, log2 of
+ * the bond's dimension before the step, log10 of the smallest kept over the
+ * largest singular value of the bond's previous split.  Parameters are a flat FP32 vector: W1 (64x12), b1, W2
  * (64x64), b2, w3 (64), b3. */
 typedef struct mlp_ctx* mlp_handle;
 
@@ -348,6 +349,19 @@ mps_status mlp_train(mlp_handle h, const float* X, const float* t, int n, int ep
                      float lr, float tau, uint64_t seed, float* final_loss);
 /* Attaches a network to a handle (NULL detaches); it must outlive that use. */
 mps_status mps_set_sketch_model(mps_handle h, mlp_handle model);
+/* The learned sketch's range finder on its own, for checking it against an
+ * independent implementation: on the Hermitian Gram matrix G (n x n, host,
+ * interleaved complex128, row-major) with the given Gaussian test matrix
+ * Omega (n x s) and probes Probe (n x 8) instead of the device-drawn ones:
+ * Y = G Omega, Q = an orthonormal basis of Y, H = Q^H G Q = W diag(mu) W^H,
+ * V = Q W (n x s, row-major), est[0] = sqrt(mean_i ||G (I - Q Q^H) g_i||^2),
+ * est[1] = trace(G); *accepted (may be NULL) tells whether est <= eps_eff^2
+ * trace(G) with the handle's eps_eff (every eigenvalue left out below the
+ * truncation threshold).  mu and the columns of V come in the order the
+ * s x s solve leaves them.  2 <= n <= 2048, 1 <= s <= n.  Synchronises. */
+mps_status mps_sketch_range(mps_handle h, int n, int s, const double* G, const double* Omega,
+                            const double* Probe, double* mu, double* V, double* est, int* accepted);
+
 /* Moves up to cap logged (features, log2 kept rank) pairs of the handle's
  * truncated SVDs into X (cap x 12) and t; *count = pairs held before the
  * call.  With X or t NULL only *count is set. */

@@ -115,3 +115,21 @@ def range_finder(A, omega, probes):
     Pg = probes - Q @ (Q.conj().T @ probes)
     est = np.sqrt(np.mean(np.sum(np.abs(A @ Pg) ** 2, axis=0)))
     return sigma, Q @ W, est
+
+
+def gram_range_finder(G, omega, probes):
+    """The same range finder with the Hermitian Gram matrix G (n x n) as the
+    operator, as the split sweep uses it: Y = G omega, Q an orthonormal basis
+    of Y (Householder QR here), H = Q^H G Q = W diag(mu) W^H, V = Q W, and the
+    probe estimate sqrt(mean_i ||G (I - Q Q^H) g_i||^2) of ||G (I - Q Q^H)||_F.
+    Returns (mu descending, V, est, Q)."""
+    Y = G @ omega
+    Q, _ = np.linalg.qr(Y)
+    H = Q.conj().T @ G @ Q
+    H = (H + H.conj().T) / 2
+    mu, W = np.linalg.eigh(H)
+    order = np.argsort(mu)[::-1]
+    mu, W = mu[order], W[:, order]
+    Pg = probes - Q @ (Q.conj().T @ probes)
+    est = np.sqrt(np.mean(np.sum(np.abs(G @ Pg) ** 2, axis=0)))
+    return mu, Q @ W, est, Q

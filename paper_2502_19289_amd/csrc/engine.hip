@@ -472,10 +472,21 @@ void job_features(const mps_ctx* ctx, const JobRun& r, const Job& job, int nsub,
     for (const auto& g : job.gates)
       if (g.nq == 2 && g.lo() <= b && b < g.hi()) ++cross;
     const float f[N_FEAT] = {(float)r.k, std::log2((float)r.chi_l), std::log2((float)r.chi_r),
-                             (float)L.m / (float)r.k, std::log2((float)L.rows), std::log2(2.f * L.c_bound),
-                             (float)cross, (float)n2q, (float)nt, (float)nsub,
-                             std::log2((float)ctx->chi[b]), std::log2((float)ctx->chi_max)};
+                             (float)L.m / (float)r.k, std::log10(std::max(ctx->prev_dw[b], 1e-30f)),
+                             std::log2(2.f * L.c_bound), (float)cross, (float)n2q, (float)nt, (float)nsub,
+                             std::log2((float)ctx->chi[b]), std::log10(std::max(ctx->prev_tail[b], 1e-30f))};
     out.insert(out.end(), f, f + N_FEAT);
+  }
+}
+
+// Spectrum tail of the splits of a finished cluster (records: f, smallest
+// kept / largest singular value, discarded weight, degenerate-cut flag per
+// level) into the per-bond history the features read.
+void record_tails(mps_ctx* ctx, const JobRun& r, const double* rec) {
+  for (size_t t = 0; t < r.lv.size(); ++t) {
+    const int b = r.a + r.lv[t].m - 1;
+    ctx->prev_tail[b] = (float)rec[4 * t + 1];
+    ctx->prev_dw[b] = (float)rec[4 * t + 2];
   }
 }
 
@@ -547,7 +558,7 @@ GemmDesc gemm64(const void* A, const void* B, void* C, Dim M, Dim N, Dim K, Dim 
 // ints per problem at the indices given.
 void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>& host, const int* b_pair,
                const int* b_upd, int n_pair, int n_upd, const int* flags_dev, int nflag_ints,
-               const std::vector<int>& flag_at) {
+               const std::vector<int>& flag_at, bool sketch = false) {
   hipStream_t s = ctx->stream;
   const int np = (int)host.size();
   if (!np) return;
@@ -572,11 +583,11 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
     ++sweeps;
     for (int round = 0; round < nb_all - 1; ++round) {
       {
-        Timed tm(ctx, fp32 ? "eig_pairs32" : "eig_pairs");
+        Timed tm(ctx, sketch ? "sketch_eig" : fp32 ? "eig_pairs32" : "eig_pairs");
         HIP_OK(launch_eig_pairs(fp32, de, b_pair, np, n_pair, round, s));
       }
       {
-        Timed tm(ctx, fp32 ? "eig_update32" : "eig_update");
+        Timed tm(ctx, sketch ? "sketch_eig" : fp32 ? "eig_update32" : "eig_update");
         HIP_OK(launch_eig_update(fp32, de, b_upd, np, n_upd, round, s));
       }
     }
@@ -754,19 +765,38 @@ bool htd_view_matches(const HtdArgs& a, int q, const HtdDesc& h) {
          g.skip == h.skip;
 }
 
-void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host) {
+void solve_htd(mps_ctx* ctx, const HtdDesc* dd_all, const std::vector<HtdDesc>& host_all) {
   hipStream_t s = ctx->stream;
-  const int np = (int)host.size();
-  if (!np) return;
+  if (host_all.empty()) return;
   std::vector<int> chi_now(std::max(0, ctx->n - 1));
-  if (!chi_now.empty()) {
+  if (!chi_now.empty())
     HIP_OK(hipMemcpyAsync(chi_now.data(), ctx->d_chi, chi_now.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-  }
+  // problems whose learned sketch was accepted need no exact solve: leave them
+  // out of the launches (their kernels would return at once, but every column
+  // would still cost two launches)
+  std::vector<int> skip(host_all.size(), 0);
+  for (size_t q = 0; q < host_all.size(); ++q)
+    if (host_all[q].skip) HIP_OK(hipMemcpyAsync(&skip[q], host_all[q].skip, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<HtdDesc> host;
+  std::vector<const HtdDesc*> dev;
+  for (size_t q = 0; q < host_all.size(); ++q)
+    if (!skip[q]) {
+      host.push_back(host_all[q]);
+      dev.push_back(dd_all + q);
+    }
+  const int np = (int)host.size();
   for (int c0 = 0; c0 < np; c0 += HTD_GROUP) {
     HtdSizes sz{};
     HtdArgs ha{};
     sz.np = std::min(HTD_GROUP, np - c0);
+    // the chunk's descriptors must be consecutive in device memory
+    const HtdDesc* dd = dev[c0];
+    for (int q = 1; q < sz.np; ++q)
+      if (dev[c0 + q] != dd + q) {
+        sz.np = q;
+        break;
+      }
     for (int q = 0; q < sz.np; ++q) {
       const Dim& dm = host[c0 + q].n;
       const ptrdiff_t at = dm.ptr ? dm.ptr - ctx->d_chi : -1;
@@ -781,7 +811,8 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd, const std::vector<HtdDesc>& host
       if (!htd_view_matches(ha, q, h)) fail(ctx, MPS_EINVAL, "tridiagonal solve: workspace layout");
     }
     ha.np = sz.np;
-    solve_htd_chunk(ctx, dd + c0, sz, ha);
+    solve_htd_chunk(ctx, dd, sz, ha);
+    c0 -= HTD_GROUP - sz.np;  // a chunk cut short by a skipped problem resumes after it
   }
 }
 
@@ -1081,6 +1112,165 @@ void add_level(mps_ctx* ctx, LevelDescs& L, JobRun& r, int i, int t, const SkRun
   r.cur ^= 1;
 }
 
+struct SkLevel {
+  std::vector<int> ids;
+  std::vector<SketchDesc> sd;
+  std::vector<EigDesc> ea, eb;
+  std::vector<GemmDesc> g[13];  // Y, Y^H Y, Q, G Q, H, Vs, C8, R1, R2, two Newton-Schulz steps
+  size_t o_sd = 0, o_ea = 0, o_eb = 0, bp_a = 0, bu_a = 0, bp_b = 0, bu_b = 0;
+  size_t o[13] = {0}, b[13] = {0};
+  int n[13] = {0};
+  int np_a = 0, nu_a = 0, np_b = 0, nu_b = 0;
+  std::vector<int> flag_a, flag_b;
+};
+
+// Descriptors of one learned-sketch range finder (problem q of its level, its
+// flags at 12 q of the level's flag array) on the Gram matrix G (leading
+// dimension ld, size n2c, bound nb); trace: the device value of trace(G);
+// exact_flags: set when the sketch is accepted (the exact solve is skipped).
+void add_sketch(mps_ctx* ctx, SkLevel& S, SkRun& k, int q, double2* G, int ld, Dim n2c, int nb, double* trace,
+                int* exact_flags) {
+  const Dim fs = fixed(k.s), fls = fixed(k.ld_s), fly = fixed(k.ld_y), fld = fixed(ld), f8 = fixed(SK_PROBES);
+  SketchDesc d{};
+  d.n = n2c;
+  d.s = k.s;
+  d.ld_s = k.ld_s;
+  d.ld_y = k.ld_y;
+  d.seed = ctx->sketch_seed;
+  d.stream = ctx->sketch_stream++;
+  d.Omega = k.Omega;
+  d.Probe = k.Probe;
+  d.Bq = k.Bq;
+  d.R1 = k.R1;
+  d.R2 = k.R2;
+  d.Gy = k.Gy;
+  d.Uy = k.Uy;
+  d.Hw = k.Hw;
+  d.lam = k.lam;
+  d.trace = trace;
+  d.eps_eff = ctx->eps_eff;
+  d.use = k.use;
+  d.est = k.est;
+  d.exact_flags = exact_flags;
+  S.sd.push_back(d);
+  S.g[0].push_back(gemm64(G, k.Omega, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));  // Y = G Omega
+  {
+    GemmDesc g = gemm64(k.Y, k.Y, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);     // Y^H Y
+    g.w = ctx->d_ones;
+    g.wshift = 0;
+    S.g[1].push_back(g);
+  }
+  S.g[2].push_back(gemm64(k.Y, k.Bq, k.Q, n2c, fs, fs, fls, fls, fls, nb, k.s));      // Q = Y Bq
+  S.g[3].push_back(gemm64(G, k.Q, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));      // G Q (into Y)
+  S.g[4].push_back(gemm64(k.Q, k.Y, k.Hw, fs, fs, n2c, fls, fls, fly, k.s, k.s));     // H = Q^H G Q
+  S.g[5].push_back(gemm64(k.Q, k.Wh, k.Vs, n2c, fs, fs, fls, fly, fls, nb, k.s));     // Vs = Q W
+  S.g[6].push_back(gemm64(k.Q, k.Probe, k.C8, fs, f8, n2c, fls, fls, fls, k.s, SK_PROBES));  // Q^H g
+  S.g[7].push_back(gemm64(G, k.Probe, k.R1, n2c, f8, n2c, fld, fls, fls, nb, SK_PROBES));  // G g
+  S.g[8].push_back(gemm64(k.Y, k.C8, k.R2, n2c, f8, fs, fls, fls, fls, nb, SK_PROBES));      // G Q Q^H g
+  for (int it = 0; it < 2; ++it) {  // Newton-Schulz: S = X^H X, X' = X (1.5 I - 0.5 S)
+    double2* from = it == 0 ? k.Q : k.Vs;
+    double2* to = it == 0 ? k.Vs : k.Q;
+    GemmDesc g = gemm64(from, from, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);
+    g.w = ctx->d_ones;
+    g.wshift = 0;
+    S.g[9 + 2 * it].push_back(g);
+    S.g[10 + 2 * it].push_back(gemm64(from, k.Bq, to, n2c, fs, fs, fls, fls, fls, nb, k.s));
+  }
+  EigDesc ea{};
+  ea.G = k.Gy;
+  ea.V = k.Uy;
+  ea.Gw = k.Gy;
+  ea.Vw = k.Uy;
+  ea.J = k.Ja;
+  ea.pair_rot = k.pr_a;
+  ea.flags = k.flags_a;
+  ea.scale = k.scale_a;
+  ea.work = ctx->timing ? ctx->d_work : nullptr;
+  ea.n = fs;
+  ea.ld = k.ld_y;
+  ea.nb_max = k.nb;
+  ea.tol = 1e-13;
+  EigDesc eb = ea;
+  eb.G = k.Hw;
+  eb.V = k.Wh;
+  eb.Gw = k.Hw;
+  eb.Vw = k.Wh;
+  eb.J = k.Jb;
+  eb.pair_rot = k.pr_b;
+  eb.flags = k.flags_b;
+  eb.scale = k.scale_b;
+  S.ea.push_back(ea);
+  S.eb.push_back(eb);
+  S.flag_a.push_back(12 * q);
+  S.flag_b.push_back(12 * q + 4);
+}
+
+void upload_sketch(DescBlob& B, SkLevel& S) {
+  S.o_sd = B.add_vec(S.sd);
+  for (int g = 0; g < 13; ++g) S.n[g] = upload_gemms(B, S.g[g], S.o[g], S.b[g]);
+  std::vector<int> pa{0}, ua{0};
+  for (const auto& e : S.ea) {
+    pa.push_back(pa.back() + e.nb_max / 2);
+    ua.push_back(ua.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
+  }
+  S.o_ea = B.add_vec(S.ea);
+  S.o_eb = B.add_vec(S.eb);
+  S.bp_a = B.add_vec(pa);
+  S.bu_a = B.add_vec(ua);
+  S.np_a = pa.back();
+  S.nu_a = ua.back();
+}
+
+// Launches of one level's range finders; fill: draw the Gaussian test and
+// probe matrices on the device (else they are already in place).
+void launch_sketch(mps_ctx* ctx, DescBlob& B, SkLevel& S, const std::vector<SkRun>& sk, int* skflags_all, int nsk,
+                   bool fill) {
+  hipStream_t s = ctx->stream;
+  // learned sketch of this level's predicted-low-rank splits
+  const int ns = (int)S.ids.size();
+  SketchDesc* dsk = B.at<SketchDesc>(S.o_sd);
+  auto nn = [&](int g) { HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+  auto cn = [&](int g) { HIP_OK(launch_gemm_cn(B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
+  int ldy = 0;
+  for (int q : S.ids) ldy = std::max(ldy, sk[q].ld_y);
+  {
+    Timed tm(ctx, "sketch");
+    if (fill) {
+      HIP_OK(launch_gauss_fill(dsk, ns, 0, s));
+      HIP_OK(launch_gauss_fill(dsk, ns, 1, s));
+    }
+    nn(0);
+    HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
+    HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
+  }
+  solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+            skflags_all, 12 * nsk, S.flag_a, true);
+  {
+    Timed tm(ctx, "sketch");
+    HIP_OK(launch_orth_scale(dsk, ns, s));
+    nn(2);
+    for (int it = 0; it < 2; ++it) {
+      HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[9 + 2 * it]), B.at<int>(S.b[9 + 2 * it]), ns,
+                         S.n[9 + 2 * it], s));
+      HIP_OK(launch_newton_schulz(dsk, ns, s));
+      nn(10 + 2 * it);
+    }
+    nn(3);
+    cn(4);
+    HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
+  }
+  solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+            skflags_all, 12 * nsk, S.flag_b, true);
+  {
+    Timed tm(ctx, "sketch");
+    nn(5);
+    cn(6);
+    nn(7);
+    nn(8);
+    HIP_OK(launch_sketch_accept(dsk, ns, s));
+  }
+}
+
 void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q, int nsub) {
   hipStream_t s = ctx->stream;
   const Prec P = ctx->prec;
@@ -1274,99 +1464,12 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   }
   // Learned-sketch descriptors per level: range finder on G, two s x s solves,
   // residual probes, acceptance (see sketch.hip).
-  struct SkLevel {
-    std::vector<int> ids;
-    std::vector<SketchDesc> sd;
-    std::vector<EigDesc> ea, eb;
-    std::vector<GemmDesc> g[13];  // Y, Y^H Y, Q, G Q, H, Vs, C8, R1, R2, two Newton-Schulz steps
-    size_t o_sd = 0, o_ea = 0, o_eb = 0, bp_a = 0, bu_a = 0, bp_b = 0, bu_b = 0;
-    size_t o[13] = {0}, b[13] = {0};
-    int n[13] = {0};
-    int np_a = 0, nu_a = 0, np_b = 0, nu_b = 0;
-    std::vector<int> flag_a, flag_b;
-  };
   std::vector<SkLevel> SL(std::max(0, tmax));
   for (int q = 0; q < nsk; ++q) {
     SkRun& k = sk[q];
     JobRun& r = runs[k.job];
-    const Level& lv = r.lv[k.t];
-    SkLevel& S = SL[k.t];
-    S.ids.push_back(q);
-    const Dim n2c = c_dim(ctx, r, k.t, 2);
-    const int nb = 2 * lv.c_bound;
-    const Dim fs = fixed(k.s), fls = fixed(k.ld_s), fly = fixed(k.ld_y), fld = fixed(r.ld), f8 = fixed(SK_PROBES);
-    SketchDesc d{};
-    d.n = n2c;
-    d.s = k.s;
-    d.ld_s = k.ld_s;
-    d.ld_y = k.ld_y;
-    d.seed = ctx->sketch_seed;
-    d.stream = ctx->sketch_stream++;
-    d.Omega = k.Omega;
-    d.Probe = k.Probe;
-    d.Bq = k.Bq;
-    d.R1 = k.R1;
-    d.R2 = k.R2;
-    d.Gy = k.Gy;
-    d.Uy = k.Uy;
-    d.Hw = k.Hw;
-    d.lam = k.lam;
-    d.trace = r.scale;
-    d.eps_eff = ctx->eps_eff;
-    d.use = k.use;
-    d.est = k.est;
-    d.exact_flags = r.flags;
-    S.sd.push_back(d);
-    S.g[0].push_back(gemm64(r.G, k.Omega, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));  // Y = G Omega
-    {
-      GemmDesc g = gemm64(k.Y, k.Y, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);     // Y^H Y
-      g.w = ctx->d_ones;
-      g.wshift = 0;
-      S.g[1].push_back(g);
-    }
-    S.g[2].push_back(gemm64(k.Y, k.Bq, k.Q, n2c, fs, fs, fls, fls, fls, nb, k.s));      // Q = Y Bq
-    S.g[3].push_back(gemm64(r.G, k.Q, k.Y, n2c, fs, n2c, fld, fls, fls, nb, k.s));      // G Q (into Y)
-    S.g[4].push_back(gemm64(k.Q, k.Y, k.Hw, fs, fs, n2c, fls, fls, fly, k.s, k.s));     // H = Q^H G Q
-    S.g[5].push_back(gemm64(k.Q, k.Wh, k.Vs, n2c, fs, fs, fls, fly, fls, nb, k.s));     // Vs = Q W
-    S.g[6].push_back(gemm64(k.Q, k.Probe, k.C8, fs, f8, n2c, fls, fls, fls, k.s, SK_PROBES));  // Q^H g
-    S.g[7].push_back(gemm64(r.G, k.Probe, k.R1, n2c, f8, n2c, fld, fls, fls, nb, SK_PROBES));  // G g
-    S.g[8].push_back(gemm64(k.Y, k.C8, k.R2, n2c, f8, fs, fls, fls, fls, nb, SK_PROBES));      // G Q Q^H g
-    for (int it = 0; it < 2; ++it) {  // Newton-Schulz: S = X^H X, X' = X (1.5 I - 0.5 S)
-      double2* from = it == 0 ? k.Q : k.Vs;
-      double2* to = it == 0 ? k.Vs : k.Q;
-      GemmDesc g = gemm64(from, from, k.Gy, fs, fs, n2c, fls, fls, fly, k.s, k.s);
-      g.w = ctx->d_ones;
-      g.wshift = 0;
-      S.g[9 + 2 * it].push_back(g);
-      S.g[10 + 2 * it].push_back(gemm64(from, k.Bq, to, n2c, fs, fs, fls, fls, fls, nb, k.s));
-    }
-    EigDesc ea{};
-    ea.G = k.Gy;
-    ea.V = k.Uy;
-    ea.Gw = k.Gy;
-    ea.Vw = k.Uy;
-    ea.J = k.Ja;
-    ea.pair_rot = k.pr_a;
-    ea.flags = k.flags_a;
-    ea.scale = k.scale_a;
-    ea.work = ctx->timing ? ctx->d_work : nullptr;
-    ea.n = fs;
-    ea.ld = k.ld_y;
-    ea.nb_max = k.nb;
-    ea.tol = 1e-13;
-    EigDesc eb = ea;
-    eb.G = k.Hw;
-    eb.V = k.Wh;
-    eb.Gw = k.Hw;
-    eb.Vw = k.Wh;
-    eb.J = k.Jb;
-    eb.pair_rot = k.pr_b;
-    eb.flags = k.flags_b;
-    eb.scale = k.scale_b;
-    S.ea.push_back(ea);
-    S.eb.push_back(eb);
-    S.flag_a.push_back(12 * q);
-    S.flag_b.push_back(12 * q + 4);
+    SL[k.t].ids.push_back(q);
+    add_sketch(ctx, SL[k.t], k, q, r.G, r.ld, c_dim(ctx, r, k.t, 2), 2 * r.lv[k.t].c_bound, r.scale, r.flags);
   }
 
   std::vector<ScaleDesc> fin;
@@ -1397,22 +1500,8 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   size_t o_ap = 0, b_ap = 0;
   const int n_ap = nj ? upload_gemm(ap, o_ap, b_ap) : 0;
   for (auto& L : LD) upload_level(B, L);
-  for (auto& S : SL) {
-    if (S.ids.empty()) continue;
-    S.o_sd = B.add_vec(S.sd);
-    for (int g = 0; g < 13; ++g) S.n[g] = upload_gemm(S.g[g], S.o[g], S.b[g]);
-    std::vector<int> pa{0}, ua{0};
-    for (const auto& e : S.ea) {
-      pa.push_back(pa.back() + e.nb_max / 2);
-      ua.push_back(ua.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
-    }
-    S.o_ea = B.add_vec(S.ea);
-    S.o_eb = B.add_vec(S.eb);
-    S.bp_a = B.add_vec(pa);
-    S.bu_a = B.add_vec(ua);
-    S.np_a = pa.back();
-    S.nu_a = ua.back();
-  }
+  for (auto& S : SL)
+    if (!S.ids.empty()) upload_sketch(B, S);
   size_t o_fin = 0, b_fin = 0;
   if (nj) {
     o_fin = B.add_vec(fin);
@@ -1452,50 +1541,7 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
   }
   for (int t = 0; t < tmax; ++t) {
     launch_level(ctx, B, LD[t], flags_all, 4 * nj, [&] {
-      SkLevel& S = SL[t];
-      if (!S.ids.empty()) {
-        // learned sketch of this level's predicted-low-rank splits
-        const int ns = (int)S.ids.size();
-        SketchDesc* dsk = B.at<SketchDesc>(S.o_sd);
-        auto nn = [&](int g) { HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
-        auto cn = [&](int g) { HIP_OK(launch_gemm_cn(B.at<GemmDesc>(S.o[g]), B.at<int>(S.b[g]), ns, S.n[g], s)); };
-        int ldy = 0;
-        for (int q : S.ids) ldy = std::max(ldy, sk[q].ld_y);
-        {
-          Timed tm(ctx, "sketch");
-          HIP_OK(launch_gauss_fill(dsk, ns, 0, s));
-          HIP_OK(launch_gauss_fill(dsk, ns, 1, s));
-          nn(0);
-          HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
-          HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
-        }
-        solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
-                  skflags_all, 12 * nsk, S.flag_a);
-        {
-          Timed tm(ctx, "sketch");
-          HIP_OK(launch_orth_scale(dsk, ns, s));
-          nn(2);
-          for (int it = 0; it < 2; ++it) {
-            HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[9 + 2 * it]), B.at<int>(S.b[9 + 2 * it]), ns,
-                               S.n[9 + 2 * it], s));
-            HIP_OK(launch_newton_schulz(dsk, ns, s));
-            nn(10 + 2 * it);
-          }
-          nn(3);
-          cn(4);
-          HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
-        }
-        solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
-                  skflags_all, 12 * nsk, S.flag_b);
-        {
-          Timed tm(ctx, "sketch");
-          nn(5);
-          cn(6);
-          nn(7);
-          nn(8);
-          HIP_OK(launch_sketch_accept(dsk, ns, s));
-        }
-      }
+      if (!SL[t].ids.empty()) launch_sketch(ctx, B, SL[t], sk, skflags_all, nsk, true);
     });
   }
   if (nj) {
@@ -1531,6 +1577,13 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
     ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
   }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
+  {
+    size_t off = 0;
+    for (auto& r : runs) {
+      record_tails(ctx, r, rec.data() + off);
+      off += 4 * (r.k - 1);
+    }
+  }
   if (nsk) {
     std::vector<int> skf(12 * nsk);
     HIP_OK(hipMemcpy(skf.data(), skflags_all, skf.size() * sizeof(int), hipMemcpyDeviceToHost));
@@ -1926,6 +1979,13 @@ void wave_round(mps_ctx* ctx, std::vector<WaveTask>& T, const std::vector<int>& 
     ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
   }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
+  {
+    size_t off = 0;
+    for (int i : ending) {
+      record_tails(ctx, T[i].run, rec.data() + off);
+      off += 4 * (T[i].run.k - 1);
+    }
+  }
   // (features, log2 kept rank) of the splits of this round
   for (int i : active) {
     const WaveTask& w = T[i];
@@ -2174,7 +2234,7 @@ bool options_valid(const mps_options& o) {
 // ---- saved-state files (mps_save / mps_load): little-endian fields in the
 // order mps_save writes them, then a 64-bit FNV-1a checksum of the bytes before
 constexpr char kSaveMagic[8] = {'C', 'T', 'E', 'B', 'D', 'M', 'P', 'S'};
-constexpr uint32_t kSaveVersion = 1;
+constexpr uint32_t kSaveVersion = 2;
 
 uint64_t fnv1a(const char* p, size_t n) {
   uint64_t h = 1469598103934665603ull;
@@ -2280,6 +2340,8 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
     }
     ctx->cap.resize(n - 1);
     ctx->chi.assign(n - 1, 1);
+    ctx->prev_dw.assign(n - 1, 0.f);
+    ctx->prev_tail.assign(n - 1, 1.f);
     for (int b = 0; b < n - 1; ++b) {
       const int e = std::min(b + 1, n - b - 1);
       ctx->cap[b] = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
@@ -2473,6 +2535,8 @@ mps_status mps_clone(mps_handle src, const mps_options* opt, mps_handle* out) {
     HIP_OK(hipMemcpyAsync(dst->d_chi, src->d_chi, (n - 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
     HIP_OK(hipMemcpyAsync(dst->d_logf, src->d_logf, sizeof(double), hipMemcpyDeviceToDevice, s));
     dst->chi = src->chi;
+    dst->prev_dw = src->prev_dw;
+    dst->prev_tail = src->prev_tail;
     if (dst->opt.k_max == src->opt.k_max) dst->pending = src->pending;
     HIP_OK(hipStreamSynchronize(s));
     return MPS_OK;
@@ -2543,6 +2607,10 @@ mps_status mps_save(mps_handle ctx, const char* path) {
     w.put<uint64_t>(ctx->sketch_seed);
     w.put<uint32_t>(ctx->sketch_stream);
     for (int b = 0; b < ctx->n - 1; ++b) w.put<int32_t>(ctx->chi[b]);
+    for (int b = 0; b < ctx->n - 1; ++b) {
+      w.put<float>(ctx->prev_dw[b]);
+      w.put<float>(ctx->prev_tail[b]);
+    }
     std::vector<char> tmp;
     for (int j = 0; j < ctx->n; ++j) {  // site tensors as stored (complex64 or complex128)
       const size_t bytes = (size_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j) * ctx->esz;
@@ -2641,6 +2709,11 @@ mps_status mps_load(const char* path, mps_handle* out) {
     const int cap = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
     if (!r.ok || chi[b] < 1 || chi[b] > cap) return bad("bond dimension out of range");
   }
+  std::vector<float> pdw(n - 1), ptail(n - 1);
+  for (int b = 0; b < n - 1; ++b) {
+    pdw[b] = r.get<float>();
+    ptail[b] = r.get<float>();
+  }
   const size_t esz = o.precision == MPS_PREC_FP64 ? 16 : 8;
   std::vector<const char*> site_at(n), lam_at(n - 1);
   for (int j = 0; j < n; ++j) {
@@ -2685,6 +2758,8 @@ mps_status mps_load(const char* path, mps_handle* out) {
     HIP_OK(hipMemcpyAsync(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice, s));
     HIP_OK(hipStreamSynchronize(s));  // the host buffers above are released on return
     ctx->stats = st;
+    ctx->prev_dw = pdw;
+    ctx->prev_tail = ptail;
     ctx->sketch_seed = sk_seed;
     ctx->sketch_stream = sk_stream;
     ctx->pending.swap(pending);
@@ -2697,6 +2772,63 @@ mps_status mps_load(const char* path, mps_handle* out) {
   }
   *out = h;
   return MPS_OK;
+}
+
+mps_status mps_sketch_range(mps_handle ctx, int n, int s, const double* G, const double* Omega,
+                            const double* Probe, double* mu, double* V, double* est, int* accepted) {
+  if (!ctx || n < 2 || n > HTD_MAX || s < 1 || s > n || !G || !Omega || !Probe || !mu || !V || !est)
+    return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    hipStream_t st = ctx->stream;
+    HIP_OK(hipStreamSynchronize(st));
+    const size_t ld = (size_t)ceil_div(n, 64) * 64;
+    SkRun k;
+    k.s = s;
+    k.ld_s = ((std::max(s, SK_PROBES) + 7) / 8) * 8;
+    k.ld_y = ((s + 63) / 64) * 64;
+    int nb = std::max(2, ceil_div(s, JB));
+    k.nb = nb + (nb & 1);
+    ctx->arena.reset();
+    HIP_OK(ctx->arena.reserve(ld * ld * sizeof(double2) + sk_bytes(n, k) + 8192));
+    DeviceArena& A = ctx->arena;
+    double2* Gd = (double2*)A.take(ld * ld * sizeof(double2));
+    int* flags = (int*)A.take(12 * sizeof(int));
+    double* scales = (double*)A.take(2 * sizeof(double));
+    double* trace = (double*)A.take(sizeof(double));
+    int* exact = (int*)A.take(4 * sizeof(int));
+    sk_assign(A, k, n, flags, scales);
+    double tr = 0;
+    for (int i = 0; i < n; ++i) tr += G[2 * ((size_t)i * n + i)];
+    HIP_OK(hipMemcpy2DAsync(Gd, ld * sizeof(double2), G, n * sizeof(double2), n * sizeof(double2), n,
+                            hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpy2DAsync(k.Omega, k.ld_s * sizeof(double2), Omega, s * sizeof(double2), s * sizeof(double2), n,
+                            hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpy2DAsync(k.Probe, k.ld_s * sizeof(double2), Probe, SK_PROBES * sizeof(double2),
+                            SK_PROBES * sizeof(double2), n, hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(trace, &tr, sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemsetAsync(exact, 0, 4 * sizeof(int), st));
+    SkLevel S;
+    S.ids.push_back(0);
+    const uint32_t stream_before = ctx->sketch_stream;
+    add_sketch(ctx, S, k, 0, Gd, (int)ld, fixed(n), n, trace, exact);
+    ctx->sketch_stream = stream_before;  // the random streams of the handle's own splits are not consumed
+    DescBlob& B = ctx->blob;
+    B.host.clear();
+    upload_sketch(B, S);
+    HIP_OK(B.prepare());
+    HIP_OK(B.upload(st));
+    std::vector<SkRun> sk{k};
+    launch_sketch(ctx, B, S, sk, flags, 1, false);
+    int use = 0;
+    HIP_OK(hipMemcpyAsync(mu, k.lam, s * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpy2DAsync(V, s * sizeof(double2), k.Vs, k.ld_s * sizeof(double2), s * sizeof(double2), n,
+                            hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(est, k.est, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&use, k.use, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    if (accepted) *accepted = use;
+    return MPS_OK;
+  });
 }
 
 mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im) {
@@ -2867,6 +2999,8 @@ mps_status mps_import(mps_handle ctx, const int* chi, const double* const* sites
       HIP_OK(hipMemcpy(ctx->lam[b], lams[b], chi[b] * sizeof(double), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(ctx->d_chi, ctx->chi.data(), (ctx->n - 1) * sizeof(int), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice));
+    ctx->prev_dw.assign(ctx->n - 1, 0.f);
+    ctx->prev_tail.assign(ctx->n - 1, 1.f);
     return MPS_OK;
   });
 }

@@ -139,6 +139,9 @@ struct mps_ctx {
   // (features, log2 kept rank) of every truncated SVD since the last read
   const float* mlp_params = nullptr;
   std::vector<float> log_x, log_t;
+  // spectrum tail of each bond's last split (features of its next splits):
+  // discarded weight and smallest kept / largest singular value
+  std::vector<float> prev_dw, prev_tail;
   uint64_t sketch_seed = 0x9E3779B97F4A7C15ull;
   uint32_t sketch_stream = 0;
 };

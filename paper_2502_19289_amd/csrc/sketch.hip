@@ -65,7 +65,7 @@ __global__ void gauss_fill_kernel(const SketchDesc* __restrict__ descs, int whic
   }
 }
 
-// Bq[i][j] = U[i][j] / sqrt(lam_j) for lam_j above 1e-24 of the largest, else 0
+// Bq[i][j] = U[i][j] / sqrt(lam_j) for lam_j above 64 n u of the largest, else 0
 // (U: eigenvectors of Y^H Y with eigenvalues on the diagonal of the rotated
 // copy).  One workgroup per problem.
 __global__ __launch_bounds__(256) void orth_scale_kernel(const SketchDesc* __restrict__ descs) {
@@ -79,7 +79,9 @@ __global__ __launch_bounds__(256) void orth_scale_kernel(const SketchDesc* __res
     if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  const double thr = 1e-24 * red[0];
+  // eigenvalues of Y^H Y below its FP64 rounding level (about n u times the
+  // largest) are noise, not directions of Y: their columns are set to zero
+  const double thr = 64.0 * (double)dim_value(d.n) * 1.1102230246251565e-16 * red[0];
   for (int e = threadIdx.x; e < d.s * d.s; e += 256) {
     const int i = e / d.s, j = e % d.s;
     const double l = d.Gy[(int64_t)j * d.ld_y + j].x;
@@ -104,7 +106,8 @@ __global__ __launch_bounds__(256) void newton_schulz_kernel(const SketchDesc* __
 
 // est^2 = mean over probes of ||R[:, p]||^2 (R = G (I - Q Q^H) g); accept when
 // est <= eps_eff^2 trace(G): every eigenvalue outside span(Q) is then below the
-// truncation threshold.  Also copies the H eigenvalues into lam (s entries).
+// truncation threshold (est estimates ||G (I - Q Q^H)||_F, which bounds the
+// largest eigenvalue left out).  Also copies the H eigenvalues into lam (s entries).
 __global__ __launch_bounds__(256) void accept_kernel(const SketchDesc* __restrict__ descs) {
   const SketchDesc& d = descs[blockIdx.x];
   __shared__ double red[256];
@@ -126,11 +129,13 @@ __global__ __launch_bounds__(256) void accept_kernel(const SketchDesc* __restric
   if (threadIdx.x == 0) {
     const double est = sqrt(red[0] / SK_PROBES);
     const double tr = *d.trace;
-    // FP64 rounding of G g - (G Q)(Q^H g) leaves ~u sqrt(n) trace(G) in the
-    // estimate: below that level it cannot tell a missed eigenvalue from zero
-    // (the exact Gram route resolves eigenvalues no better)
-    const double floor_est = 64.0 * 1.1102230246251565e-16 * sqrt((double)n);
-    const int ok = est <= fmax(d.eps_eff * d.eps_eff, floor_est) * tr ? 1 : 0;
+    // the threshold of the exact route: an eigenvalue of G below
+    // eps_eff^2 trace(G) is a singular value below eps_eff of the normalised
+    // spectrum, which the exact split drops too.  FP64 rounding leaves about
+    // u sqrt(n) lambda_1 in the estimate, so at large n an FP64 run (eps_eff^2
+    // about 16 u) seldom accepts; FP32 / BF16X6 runs (eps_eff^2 about 1e-13)
+    // do whenever the sketch holds every kept direction.
+    const int ok = est <= d.eps_eff * d.eps_eff * tr ? 1 : 0;
     *d.use = ok;
     d.est[0] = est;
     d.est[1] = tr;

@@ -54,7 +54,7 @@ EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluste
            "mps_export_site", "mps_import", "mps_amplitudes", "mps_get_stats",
            "mps_set_timing", "mps_set_burst_timing", "mps_kernel_dispatches", "mps_kernel_times", "mps_kernel_bytes", "mps_heev", "mps_heev_noalloc", "mps_last_error", "mps_plan",
            "mlp_num_params", "mlp_create", "mlp_destroy", "mlp_get_params", "mlp_set_params",
-           "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log"]
+           "mlp_forward", "mlp_grad", "mlp_train", "mps_set_sketch_model", "mps_svd_log", "mps_sketch_range"]
 N_FEAT = 12
 
 _lib = None
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mlp_train.argtypes = [P, F, F, I, I, I, C.c_float, C.c_float, C.c_uint64, F]
     lib.mps_set_sketch_model.argtypes = [P, P]
     lib.mps_svd_log.argtypes = [P, F, F, I, C.POINTER(I)]
+    lib.mps_sketch_range.argtypes = [P, I, I, C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(D), C.POINTER(D),
+                                     C.POINTER(D), C.POINTER(I)]
     for name in EXPORTS:
         if name != "mps_last_error":
             getattr(lib, name).restype = C.c_int
@@ -472,6 +474,26 @@ def svd_log(mps: "MPS"):
     t = np.zeros(max(n, 1), dtype=np.float32)
     lib.mps_svd_log(mps.h, _fptr(X), _fptr(t), n, C.byref(cnt))
     return X[:n], t[:n]
+
+
+def sketch_range(mps: "MPS", G: np.ndarray, omega: np.ndarray, probes: np.ndarray):
+    """mps_sketch_range: the device range finder on G with the given test and
+    probe matrices; returns (mu, V, est, trace, accepted)."""
+    lib = load()
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    omega = np.ascontiguousarray(omega, dtype=np.complex128)
+    probes = np.ascontiguousarray(probes, dtype=np.complex128)
+    n, s = omega.shape
+    mu = np.zeros(s)
+    V = np.zeros((n, s), dtype=np.complex128)
+    est = np.zeros(2)
+    acc = C.c_int()
+    st = lib.mps_sketch_range(mps.h, n, s, _dptr(G.view(np.float64)), _dptr(omega.view(np.float64)),
+                              _dptr(probes.view(np.float64)), _dptr(mu), _dptr(V.view(np.float64)), _dptr(est),
+                              C.byref(acc))
+    if st != MPS_OK:
+        raise CtebdError(st, lib.mps_last_error(mps.h).decode())
+    return mu, V, float(est[0]), float(est[1]), bool(acc.value)
 
 
 def plan(n: int, k_max: int, layers, chi: Sequence[int], start: int = 0, q_max: int = 0, l_max: int = 0):

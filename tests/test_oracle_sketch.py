@@ -95,3 +95,46 @@ def test_range_finder_tail_and_estimate():
     assert true >= np.sqrt(np.sum(s_full[s:] ** 2)) - 1e-9
     # the probe estimate tracks the true residual
     assert 0.3 * true < est < 3.0 * true
+
+
+def _gram(n, rank, decay, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((3 * n, rank)) + 1j * rng.standard_normal((3 * n, rank))
+    Qx, _ = np.linalg.qr(X)
+    Z = rng.standard_normal((rank, n)) + 1j * rng.standard_normal((rank, n))
+    Qz, _ = np.linalg.qr(Z.conj().T)
+    s = np.exp(-decay * np.arange(rank))
+    A = (Qx * s) @ Qz.conj().T
+    return A.conj().T @ A
+
+
+def _cgauss(rows, cols, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))) / np.sqrt(2)
+
+
+def test_gram_range_finder_exact_when_sketch_covers_rank():
+    """G of rank 20 and a sketch of 28 columns: the eigenvalues are G's, the
+    vectors span its range and the residual estimate vanishes."""
+    n, r = 96, 20
+    G = _gram(n, r, 0.3, seed=1)
+    mu, V, est, Q = SK.gram_range_finder(G, _cgauss(n, r + 8, 2), _cgauss(n, 8, 3))
+    lam = np.sort(np.linalg.eigvalsh(G))[::-1]
+    assert np.abs(mu[:r] - lam[:r]).max() < 1e-12 * lam[0]
+    assert np.abs(G @ V[:, :r] - V[:, :r] * mu[:r]).max() < 1e-12 * lam[0]
+    assert est < 1e-12 * np.trace(G).real
+
+
+def test_gram_range_finder_residual_estimate_and_tail():
+    """Rank above the sketch: the estimate is an unbiased Frobenius estimate
+    (many probes) and lies between the first missed eigenvalue's scale and the
+    Frobenius norm of the tail; the kept eigenvalues underestimate G's."""
+    n, r, s = 96, 60, 24
+    G = _gram(n, r, 0.15, seed=4)
+    omega = _cgauss(n, s, 5)
+    mu, V, est, Q = SK.gram_range_finder(G, omega, _cgauss(n, 4000, 6))
+    Rf = np.linalg.norm(G - G @ Q @ Q.conj().T)
+    assert abs(est - Rf) < 0.05 * Rf
+    lam = np.sort(np.linalg.eigvalsh(G))[::-1]
+    assert lam[s] * 0.99 <= Rf <= np.sqrt(np.sum(lam[s:] ** 2)) * 100
+    assert np.all(mu <= lam[:s] * (1 + 1e-12))

@@ -210,6 +210,24 @@ mps_status mps_save(mps_handle h, const char* path);
  * holds out-of-range sizes; mps_last_error(NULL) then says why. */
 mps_status mps_load(const char* path, mps_handle* out);
 
+/* Sec. III.B, one step of the adaptive-grouping DMRG on an FP64 handle
+ * (MPS_ESTATE otherwise): the nl layers (layer_len[i] gates each, flattened in
+ * `gates`, disjoint qubits per layer) form the segment.  Buffered layers are
+ * contracted first.  The virtual bond dimensions of Eq. chi_est (E(b) = the
+ * segment's two-qubit gates crossing bond b, capped at chi_max_dmrg) are cut
+ * recursively at their smallest bond (ties: the most balanced cut, then the
+ * leftmost) until every part of N qubits between cuts chi~_L, chi~_R meets
+ * N + log2 chi~_L + log2 chi~_R <= q_max (Eqs. cond_group1/2); a grouped MPS
+ * with one site per part is fitted to the evolved state by `sweeps` sweeps of
+ * one-group updates (right to left, then left to right), starting from the
+ * evolved state compressed at the group cuts by truncated SVDs; it is then
+ * split back into qubit tensors with the handle's chi_max and cutoff.
+ * *f_fit (may be NULL) receives the fit's fidelity |<M|U psi>|^2; the
+ * fidelity sum adds log f_fit and the log of the splits' kept weights.  The
+ * evolved state's bond dimensions must stay <= 1024.  Synchronises. */
+mps_status mps_dmrg_step(mps_handle h, const mps_gate* gates, const int* layer_len, int nl, int chi_max_dmrg,
+                         int q_max, int sweeps, double* f_fit);
+
 /* <a|b> of the current states of two handles with the same n (buffered
  * layers are not applied), by a transfer-matrix sweep in FP64 on the device
  * (E <- sum_s A_s^dagger E B_s).  Synchronises. */

@@ -134,10 +134,13 @@ def dmrg_step(psi: CT.MPS, layers, chi_max_dmrg: int, chi_max_svd: int, eps: flo
     for tau in range(g - 1):
         l, d, r = C.shape
         U, s, Vh = np.linalg.svd(C.reshape(l * d, r), full_matrices=False)
-        k = max(1, min(cut[tau], int(np.count_nonzero(s > 0))))
+        # directions below 1e-10 of the largest singular value carry no weight
+        # (1e-20) and would make the compressed sites rank-deficient
+        k = max(1, min(cut[tau], int(np.count_nonzero(s > 1e-10 * s[0]))))
         M.append(U[:, :k].reshape(l, d, k))
         C = np.tensordot(s[:k, None] * Vh[:k], Tg[tau + 1], axes=(1, 0))
     M.append(C / np.linalg.norm(C))
+    C = M[-1] * np.linalg.norm(C)
     # environments: L[t] = <M_0..M_{t-1} | T_0..T_{t-1}>, R[t] = <M_t..| T_t..>
     def left_env(t):
         Lm = np.ones((1, 1), dtype=np.complex128)
@@ -157,7 +160,9 @@ def dmrg_step(psi: CT.MPS, layers, chi_max_dmrg: int, chi_max_svd: int, eps: flo
         rec.f_updates.append(f)
         return F / math.sqrt(f), f
 
-    f = 1.0
+    # fidelity of the compression itself: the weight its centre kept
+    f = float(np.vdot(C, C).real)
+    rec.f_updates.append(f)
     for _ in range(sweeps):
         for tau in range(g - 1, -1, -1):  # right to left: right-orthonormalise after the update
             Mt, f = update(tau)

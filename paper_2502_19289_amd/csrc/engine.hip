@@ -19,8 +19,10 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <iterator>
 #include <mutex>
+#include <tuple>
 
 #include "engine.hpp"
 
@@ -2225,6 +2227,463 @@ void destroy_ctx(mps_ctx* ctx) {
   delete ctx;
 }
 
+// ------------------------------------------------------------- DMRG --
+// Adaptive-grouping DMRG step (Sec. III.B with the iteration of Sec. II.C) on
+// the library's kernels, FP64: the virtual MPS of Eq. chi_est and the
+// recursive bipartition of Eqs. cond_group1 / cond_group2 on the host; on the
+// device the evolved state U |psi> of the segment (the cluster-TEBD executor
+// on a scratch handle, nothing truncated beyond the Gram route's floor), its
+// grouped tensors (merge GEMM chains), a grouped MPS M fitted to it (initial
+// truncated-SVD compression at the group cuts, then sweeps of one-group
+// updates M = F / ||F||, orthonormalised by polar factors), and M decomposed
+// back into qubit tensors by Gram / eigen splits with chi_max and the cutoff.
+// Every product is one launch of the library's GEMMs with a single problem;
+// the stream is synchronised after each (the descriptor blob is reused), so
+// this path is written for correctness, not speed.
+struct DevOps {
+  mps_ctx* ctx;
+  std::vector<void*> mem;
+  double* d_scalar = nullptr;
+  explicit DevOps(mps_ctx* c) : ctx(c) {}
+  ~DevOps() {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : mem) (void)hipFree(p);
+  }
+  template <typename T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    HIP_OK(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+    mem.push_back(p);
+    return (T*)p;
+  }
+  void release(void* p) {
+    auto it = std::find(mem.begin(), mem.end(), p);
+    if (it == mem.end()) return;
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(p);
+    mem.erase(it);
+  }
+  void run_gemm(const GemmDesc& d, bool cn) {
+    DescBlob& B = ctx->blob;
+    B.host.clear();
+    const size_t o = B.add(&d, sizeof(d));
+    const int tiles = gemm_tiles(d);
+    const std::vector<int> base{0, tiles};
+    const size_t ob = B.add_vec(base);
+    HIP_OK(B.upload(ctx->stream));
+    if (cn)
+      HIP_OK(launch_gemm_cn(B.at<GemmDesc>(o), B.at<int>(ob), 1, tiles, ctx->stream));
+    else
+      HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(o), B.at<int>(ob), 1, tiles, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+  }
+  // C (M x N) = A (M x K) B (K x N)
+  void nn(const double2* A, const double2* B, double2* C, int M, int N, int K, int lda, int ldb, int ldc) {
+    run_gemm(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), false);
+  }
+  // C (M x N) = A^H B, A: K x M, B: K x N
+  void cn(const double2* A, const double2* B, double2* C, int M, int N, int K, int lda, int ldb, int ldc) {
+    run_gemm(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), true);
+  }
+  double norm2(const double2* x, int64_t n) {
+    if (!d_scalar) d_scalar = alloc<double>(1);
+    HIP_OK(launch_dense_norm2(x, n, d_scalar, ctx->stream));
+    double v = 0;
+    HIP_OK(hipMemcpyAsync(&v, d_scalar, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return v;
+  }
+  void scale(double2* x, int64_t n, double a) { HIP_OK(launch_dense_scale(x, n, a, ctx->stream)); }
+  // eigenpairs of the Hermitian n x n matrix G (ld), descending; V columns (ldv)
+  struct Eig {
+    double2* V;
+    int ldv;
+    std::vector<double> w;
+    char* base;  // workspace holding V (release when done)
+  };
+  Eig eigh(const double2* G, int n, int ld) {
+    if (n > HTD_MAX) fail(ctx, MPS_EINVAL, "DMRG: eigenproblem larger than 2048");
+    const size_t lw = (size_t)ceil_div(n, 64) * 64;
+    size_t bytes = 0;
+    HtdDesc h{};
+    auto count = [&](size_t x) -> void* {
+      bytes = ((bytes + 255) & ~size_t(255)) + x;
+      return nullptr;
+    };
+    count(lw * lw * sizeof(double2));
+    count(lw * lw * sizeof(double2));
+    htd_layout(lw, h, count);
+    count(sizeof(HtdDesc));
+    char* base = alloc<char>(bytes);
+    size_t used = 0;
+    auto take = [&](size_t x) -> void* {
+      const size_t off = (used + 255) & ~size_t(255);
+      used = off + x;
+      return base + off;
+    };
+    h.A = (double2*)take(lw * lw * sizeof(double2));
+    h.V = (double2*)take(lw * lw * sizeof(double2));
+    htd_layout(lw, h, take);
+    HtdDesc* dd = (HtdDesc*)take(sizeof(HtdDesc));
+    h.n = Dim{n, nullptr};
+    h.ld = (int)lw;
+    h.rcap = n;
+    h.skip = nullptr;
+    HIP_OK(hipMemcpy2DAsync(h.A, lw * sizeof(double2), G, ld * sizeof(double2), n * sizeof(double2), n,
+                            hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(dd, &h, sizeof(HtdDesc), hipMemcpyHostToDevice, ctx->stream));
+    {
+      // the solver reads no bond dimensions for fixed sizes
+      struct Restore {
+        mps_ctx* c;
+        int n;
+        ~Restore() { c->n = n; }
+      } restore{ctx, ctx->n};
+      ctx->n = 1;
+      solve_htd(ctx, dd, std::vector<HtdDesc>{h});
+    }
+    Eig e;
+    e.V = h.V;
+    e.ldv = (int)lw;
+    e.base = base;
+    e.w.resize(n);
+    HIP_OK(hipMemcpyAsync(e.w.data(), h.lam, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return e;
+  }
+  double* upload(const std::vector<double>& v) {
+    double* d = alloc<double>(v.size());
+    HIP_OK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return d;
+  }
+  // Polar factor of F (rows x cols): left (columns orthonormal, F (F^H F)^-1/2)
+  // or right (rows orthonormal, (F F^H)^-1/2 F); directions below 1e-28 of the
+  // largest eigenvalue are dropped
+  double2* polar(const double2* F, int rows, int cols, bool left) {
+    const int m = left ? cols : rows;
+    double2* G = alloc<double2>((size_t)m * m);
+    double2* Fh = nullptr;
+    if (left) {
+      cn(F, F, G, cols, cols, rows, cols, cols, cols);
+    } else {
+      Fh = alloc<double2>((size_t)rows * cols);
+      HIP_OK(launch_dense_adjoint(F, rows, cols, cols, nullptr, Fh, rows, ctx->stream));
+      cn(Fh, Fh, G, rows, rows, cols, rows, rows, rows);
+    }
+    Eig e = eigh(G, m, m);
+    std::vector<double> d(m, 0.0);
+    const double top = std::max(e.w[0], 1e-300);
+    for (int i = 0; i < m; ++i) d[i] = e.w[i] > 1e-28 * top ? std::pow(e.w[i], -0.25) : 0.0;
+    double* dd = upload(d);
+    double2* Y = alloc<double2>((size_t)m * m);  // Y = diag(w^-1/4) V^H, P = Y^H Y = V w^-1/2 V^H
+    HIP_OK(launch_dense_adjoint(e.V, m, m, e.ldv, dd, Y, m, ctx->stream));
+    double2* P = alloc<double2>((size_t)m * m);
+    cn(Y, Y, P, m, m, m, m, m, m);
+    double2* Q = alloc<double2>((size_t)rows * cols);
+    if (left)
+      nn(F, P, Q, rows, cols, cols, cols, cols, cols);
+    else
+      nn(P, F, Q, rows, cols, rows, rows, cols, cols);
+    release(e.base);
+    release(G);
+    release(Y);
+    release(P);
+    release(dd);
+    if (Fh) release(Fh);
+    return Q;
+  }
+};
+
+struct Tensor3 {
+  double2* p = nullptr;
+  int l = 1, d = 1, r = 1;
+  int64_t size() const { return (int64_t)l * d * r; }
+};
+
+int dmrg_truncation_rank(const std::vector<double>& w, int cap_rows, const mps_ctx* ctx, double* f) {
+  double tot = 0;
+  for (double x : w) tot += std::max(x, 0.0);
+  int kept = 0;
+  for (double x : w)
+    if (tot > 0 && std::sqrt(std::max(x, 0.0) / tot) >= ctx->eps_eff) ++kept;
+  kept = std::max(1, std::min({kept, ctx->chi_max, cap_rows, (int)w.size()}));
+  double k = 0;
+  for (int i = 0; i < kept; ++i) k += std::max(w[i], 0.0);
+  *f = tot > 0 ? k / tot : 1.0;
+  return kept;
+}
+
+// The step itself; `layers`: the segment's gates, layer by layer.  Returns f
+// of the last update (the fit's fidelity) through *f_fit.
+void dmrg_step(mps_ctx* ctx, const std::vector<std::vector<HostGate>>& layers, int chi_max_dmrg, int q_max,
+               int sweeps, double* f_fit) {
+  const int n = ctx->n;
+  hipStream_t s = ctx->stream;
+  // ---- Eq. chi_est and the grouping (host)
+  std::vector<int> E(n - 1, 0);
+  for (const auto& L : layers)
+    for (const auto& g : L)
+      if (g.nq == 2)
+        for (int b = g.lo(); b < g.hi(); ++b) ++E[b];
+  // chit: Eq. chi_est (each gate across a bond counted as doubling it);
+  // chi_exact: a true bound for the evolved state, whose two-qubit gates
+  // multiply a bond by their operator Schmidt rank, up to 4 (SWAP)
+  std::vector<int64_t> chit(n - 1), chi_exact(n - 1);
+  for (int b = 0; b < n - 1; ++b) {
+    const int64_t cap = (int64_t)1 << std::min({b + 1, n - b - 1, 40});
+    chit[b] = std::min({((int64_t)1 << std::min(E[b], 40)) * ctx->chi[b], cap, (int64_t)chi_max_dmrg});
+    chi_exact[b] = std::min(((int64_t)1 << std::min(2 * E[b], 40)) * ctx->chi[b], cap);
+  }
+  std::vector<std::pair<int, int>> groups;
+  std::function<void(int, int, int64_t, int64_t)> rec = [&](int lo, int hi, int64_t cl, int64_t cr) {
+    const int N = hi - lo + 1;
+    const bool fits = N <= 60 && (double)cl * (double)cr * std::ldexp(1.0, N) <= std::ldexp(1.0, q_max);
+    if (lo == hi || fits) {
+      groups.push_back({lo, hi});
+      return;
+    }
+    int best = lo;
+    for (int b = lo + 1; b < hi; ++b) {
+      const auto key = [&](int c) { return std::make_tuple(chit[c], std::abs((c - lo + 1) - (hi - c)), c); };
+      if (key(b) < key(best)) best = b;
+    }
+    rec(lo, best, cl, chit[best]);
+    rec(best + 1, hi, chit[best], cr);
+  };
+  rec(0, n - 1, 1, 1);
+  const int ng = (int)groups.size();
+  // ---- the evolved state U |psi> on a scratch handle
+  int64_t chi_t = 1;
+  for (int b = 0; b < n - 1; ++b) chi_t = std::max(chi_t, chi_exact[b]);
+  if (chi_t > HTD_MAX / 2) fail(ctx, MPS_EINVAL, "DMRG: the evolved state needs a bond dimension above 1024");
+  mps_options to = ctx->opt;
+  to.precision = MPS_PREC_FP64;
+  to.batch = MPS_BATCH_STEP;
+  to.svd_mode = MPS_SVD_EXACT;
+  to.hip_stream = ctx->stream;
+  mps_handle T = nullptr;
+  {
+    const mps_status cs = mps_create(n, (int)chi_t, 0.0, &to, &T);
+    if (cs != MPS_OK) fail(ctx, cs, "DMRG: could not create the scratch handle");
+  }
+  struct Closer {
+    mps_handle h;
+    ~Closer() { destroy_ctx(h); }
+  } closer{T};
+  for (int j = 0; j < n; ++j) {
+    const int64_t cnt = (int64_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j);
+    HIP_OK(hipMemcpyAsync(T->site[j], ctx->site[j], cnt * 16, hipMemcpyDeviceToDevice, s));
+  }
+  for (int b = 0; b < n - 1; ++b)
+    HIP_OK(hipMemcpyAsync(T->lam[b], ctx->lam[b], ctx->chi[b] * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_OK(hipMemcpyAsync(T->d_chi, ctx->d_chi, (n - 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+  T->chi = ctx->chi;
+  for (const auto& L : layers) legalize_layer(L, T->opt.k_max, T->pending);
+  {
+    const mps_status st = guarded(T, [&]() -> mps_status {
+      while (!T->pending.empty()) execute_step(T, 0);
+      return MPS_OK;
+    });
+    if (st != MPS_OK) fail(ctx, st, ("DMRG: evolving the segment: " + T->err).c_str());
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  DevOps D(ctx);
+  // ---- grouped tensors of U |psi>
+  std::vector<Tensor3> Tg(ng);
+  for (int t = 0; t < ng; ++t) {
+    const int a = groups[t].first, b = groups[t].second;
+    Tensor3 cur{(double2*)T->site[a], bond_dim(T, a - 1), 2, bond_dim(T, a)};
+    for (int j = a + 1; j <= b; ++j) {
+      const int rn = bond_dim(T, j);
+      double2* out = D.alloc<double2>((size_t)cur.l * cur.d * 2 * rn);
+      D.nn(cur.p, (const double2*)T->site[j], out, cur.l * cur.d, 2 * rn, cur.r, cur.r, 2 * rn, 2 * rn);
+      cur = Tensor3{out, cur.l, cur.d * 2, rn};
+    }
+    if (a == b) {  // own copy (the scratch handle's site stays valid until the end anyway)
+      double2* out = D.alloc<double2>(cur.size());
+      HIP_OK(hipMemcpyAsync(out, cur.p, cur.size() * 16, hipMemcpyDeviceToDevice, s));
+      cur.p = out;
+    }
+    Tg[t] = cur;
+  }
+  // ---- initial M: truncated-SVD compression at the group cuts, left to right
+  std::vector<Tensor3> M(ng);
+  Tensor3 C = Tg[0];
+  for (int t = 0; t + 1 < ng; ++t) {
+    const int rows = C.l * C.d, r = C.r;
+    double2* G = D.alloc<double2>((size_t)r * r);
+    D.cn(C.p, C.p, G, r, r, rows, r, r, r);
+    DevOps::Eig e = D.eigh(G, r, r);
+    const double top = std::max(e.w[0], 1e-300);
+    int k = 0;
+    for (double w : e.w)
+      if (w > 1e-20 * top) ++k;
+    k = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)k, chit[groups[t].second], (int64_t)rows}));
+    double2* CV = D.alloc<double2>((size_t)rows * k);
+    D.nn(C.p, e.V, CV, rows, k, r, r, e.ldv, k);
+    std::vector<double> inv(k);
+    for (int i = 0; i < k; ++i) inv[i] = 1.0 / std::sqrt(e.w[i]);
+    HIP_OK(launch_dense_scale_cols(CV, rows, k, k, D.upload(inv), s));
+    M[t] = Tensor3{CV, C.l, C.d, k};
+    D.release(e.base);
+    D.release(G);
+    double2* K = D.alloc<double2>((size_t)k * r);  // U^H C = S V^H
+    D.cn(CV, C.p, K, k, r, rows, k, r, r);
+    const Tensor3& Tn = Tg[t + 1];
+    double2* Cn = D.alloc<double2>((size_t)k * Tn.d * Tn.r);
+    D.nn(K, Tn.p, Cn, k, Tn.d * Tn.r, r, r, Tn.d * Tn.r, Tn.d * Tn.r);
+    C = Tensor3{Cn, k, Tn.d, Tn.r};
+  }
+  {
+    double2* last = D.alloc<double2>(C.size());
+    HIP_OK(hipMemcpyAsync(last, C.p, C.size() * 16, hipMemcpyDeviceToDevice, s));
+    D.scale(last, C.size(), 1.0 / std::sqrt(D.norm2(last, C.size())));
+    M[ng - 1] = Tensor3{last, C.l, C.d, C.r};
+  }
+  // ---- sweeps of one-group updates
+  std::vector<double2*> Lenv(ng + 1, nullptr), Renv(ng + 1, nullptr);  // Lenv[t]: chi_M x D (left of group t)
+  std::vector<int> Lm(ng + 1, 1), Ld(ng + 1, 1), Rd(ng + 1, 1), Rm(ng + 1, 1);  // Renv[t]: D x chi_M (right of t-1)
+  const double2 one = make_double2(1.0, 0.0);
+  Lenv[0] = D.alloc<double2>(1);
+  Renv[ng] = D.alloc<double2>(1);
+  HIP_OK(hipMemcpyAsync(Lenv[0], &one, 16, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(Renv[ng], &one, 16, hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  auto left_env = [&](int t) {  // Lenv[t+1] from Lenv[t], M[t], Tg[t]
+    const Tensor3 &m = M[t], &tg = Tg[t];
+    double2* Z = D.alloc<double2>((size_t)m.l * tg.d * tg.r);
+    D.nn(Lenv[t], tg.p, Z, m.l, tg.d * tg.r, tg.l, tg.l, tg.d * tg.r, tg.d * tg.r);
+    double2* L2 = D.alloc<double2>((size_t)m.r * tg.r);
+    D.cn(m.p, Z, L2, m.r, tg.r, m.l * m.d, m.r, tg.r, tg.r);
+    D.release(Z);
+    if (Lenv[t + 1]) D.release(Lenv[t + 1]);
+    Lenv[t + 1] = L2;
+    Lm[t + 1] = m.r;
+    Ld[t + 1] = tg.r;
+  };
+  auto right_env = [&](int t) {  // Renv[t] from Renv[t+1], M[t], Tg[t]
+    const Tensor3 &m = M[t], &tg = Tg[t];
+    double2* W = D.alloc<double2>((size_t)tg.l * tg.d * m.r);
+    D.nn(tg.p, Renv[t + 1], W, tg.l * tg.d, m.r, tg.r, tg.r, m.r, m.r);
+    double2* Mh = D.alloc<double2>((size_t)m.d * m.r * m.l);
+    HIP_OK(launch_dense_adjoint(m.p, m.l, m.d * m.r, m.d * m.r, nullptr, Mh, m.l, s));
+    double2* R2 = D.alloc<double2>((size_t)tg.l * m.l);
+    D.nn(W, Mh, R2, tg.l, m.l, tg.d * m.r, tg.d * m.r, m.l, m.l);
+    D.release(W);
+    D.release(Mh);
+    if (Renv[t]) D.release(Renv[t]);
+    Renv[t] = R2;
+    Rd[t] = tg.l;
+    Rm[t] = m.l;
+  };
+  auto update = [&](int t, double* f) {  // F = Lenv[t] Tg[t] Renv[t+1], normalised
+    const Tensor3& tg = Tg[t];
+    const int ml = Lm[t], mr = Rm[t + 1];
+    double2* Z = D.alloc<double2>((size_t)ml * tg.d * tg.r);
+    D.nn(Lenv[t], tg.p, Z, ml, tg.d * tg.r, tg.l, tg.l, tg.d * tg.r, tg.d * tg.r);
+    double2* F = D.alloc<double2>((size_t)ml * tg.d * mr);
+    D.nn(Z, Renv[t + 1], F, ml * tg.d, mr, tg.r, tg.r, mr, mr);
+    D.release(Z);
+    *f = D.norm2(F, (int64_t)ml * tg.d * mr);
+    D.scale(F, (int64_t)ml * tg.d * mr, 1.0 / std::sqrt(*f));
+    return Tensor3{F, ml, tg.d, mr};
+  };
+  for (int t = 0; t + 1 < ng; ++t) left_env(t);
+  double f = 1.0;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int t = ng - 1; t >= 0; --t) {  // right to left
+      Tensor3 F = update(t, &f);
+      if (t > 0) {
+        double2* Q = D.polar(F.p, F.l, F.d * F.r, false);
+        D.release(F.p);
+        F.p = Q;
+      }
+      D.release(M[t].p);
+      M[t] = F;
+      if (t > 0) right_env(t);
+    }
+    for (int t = 0; t < ng; ++t) {  // left to right
+      Tensor3 F = update(t, &f);
+      if (t + 1 < ng) {
+        double2* Q = D.polar(F.p, F.l * F.d, F.r, true);
+        D.release(F.p);
+        F.p = Q;
+      }
+      D.release(M[t].p);
+      M[t] = F;
+      if (t + 1 < ng) left_env(t);
+    }
+  }
+  if (sweeps == 0) {  // the compression alone: its fidelity is |<M|U psi>|^2
+    for (int t = 0; t + 1 < ng; ++t) left_env(t);
+    Tensor3 F = update(ng - 1, &f);
+    D.release(F.p);
+  }
+  *f_fit = f;
+  // ---- decomposition right to left into the handle's qubit tensors
+  double log_f = std::log(f);
+  std::vector<int> chi_new = ctx->chi;
+  double2* X = Renv[ng];  // the 1 x 1 identity
+  int Xr = 1, Xc = 1;
+  for (int t = ng - 1; t >= 0; --t) {
+    const int a = groups[t].first, b = groups[t].second;
+    const Tensor3& m = M[t];
+    double2* cur = D.alloc<double2>((size_t)m.l * m.d * Xc);
+    D.nn(m.p, X, cur, m.l * m.d, Xc, Xr, Xr, Xc, Xc);
+    int rows = m.l * m.d / 2, right = Xc;
+    for (int q = b; q >= a; --q) {
+      if (q == 0) {
+        const double nrm = std::sqrt(D.norm2(cur, (int64_t)2 * right));
+        D.scale(cur, 2 * right, 1.0 / nrm);
+        HIP_OK(hipMemcpyAsync(ctx->site[0], cur, (size_t)2 * right * 16, hipMemcpyDeviceToDevice, s));
+        break;
+      }
+      const int c2 = 2 * right;
+      double2* G = D.alloc<double2>((size_t)c2 * c2);
+      D.cn(cur, cur, G, c2, c2, rows, c2, c2, c2);
+      DevOps::Eig e = D.eigh(G, c2, c2);
+      double fq = 1.0;
+      const int kk = dmrg_truncation_rank(e.w, rows, ctx, &fq);
+      log_f += std::log(fq);
+      // B_q = V_k^H as (kk, 2, right); Lambda_{q-1} = sqrt(w_k) normalised
+      HIP_OK(launch_dense_adjoint(e.V, c2, kk, e.ldv, nullptr, (double2*)ctx->site[q], c2, s));
+      std::vector<double> lam(kk);
+      double kept = 0;
+      for (int i = 0; i < kk; ++i) kept += std::max(e.w[i], 0.0);
+      for (int i = 0; i < kk; ++i) lam[i] = std::sqrt(std::max(e.w[i], 0.0) / kept);
+      HIP_OK(hipMemcpyAsync(ctx->lam[q - 1], lam.data(), kk * sizeof(double), hipMemcpyHostToDevice, s));
+      chi_new[q - 1] = kk;
+      double2* nxt = D.alloc<double2>((size_t)rows * kk);
+      D.nn(cur, e.V, nxt, rows, kk, c2, c2, e.ldv, kk);
+      D.release(cur);
+      D.release(G);
+      D.release(e.base);
+      cur = nxt;
+      right = kk;
+      if (q > a) {
+        rows /= 2;
+      } else {
+        X = cur;
+        Xr = rows;
+        Xc = kk;
+      }
+    }
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  ctx->chi = chi_new;
+  HIP_OK(hipMemcpyAsync(ctx->d_chi, ctx->chi.data(), (n - 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  double lf0 = 0;
+  HIP_OK(hipMemcpyAsync(&lf0, ctx->d_logf, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  lf0 += log_f;
+  HIP_OK(hipMemcpyAsync(ctx->d_logf, &lf0, sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_OK(hipStreamSynchronize(s));
+  ctx->prev_dw.assign(n - 1, 0.f);
+  ctx->prev_tail.assign(n - 1, 1.f);
+  ctx->stats.steps += 1;
+}
+
 bool options_valid(const mps_options& o) {
   return o.k_max >= 2 && o.k_max <= 12 && o.precision >= 0 && o.precision <= 2 && o.svd_mode >= 0 &&
          o.svd_mode <= 1 && o.batch >= 0 && o.batch <= 2 && o.eig_method >= 0 && o.eig_method <= 2 &&
@@ -2827,6 +3286,32 @@ mps_status mps_sketch_range(mps_handle ctx, int n, int s, const double* G, const
     HIP_OK(hipMemcpyAsync(&use, k.use, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     if (accepted) *accepted = use;
+    return MPS_OK;
+  });
+}
+
+mps_status mps_dmrg_step(mps_handle ctx, const mps_gate* gates, const int* layer_len, int nl, int chi_max_dmrg,
+                         int q_max, int sweeps, double* f_fit) {
+  if (!ctx || nl < 0 || (nl > 0 && (!gates || !layer_len)) || chi_max_dmrg < 1 || q_max < 2 || sweeps < 0)
+    return MPS_EINVAL;
+  return guarded(ctx, [&]() -> mps_status {
+    if (ctx->prec != Prec::FP64) {
+      ctx->err = "mps_dmrg_step: needs an FP64 handle";
+      return MPS_ESTATE;
+    }
+    std::vector<std::vector<HostGate>> layers(nl);
+    int off = 0;
+    for (int l = 0; l < nl; ++l) {
+      if (layer_len[l] < 0) return MPS_EINVAL;
+      const mps_status st = check_gates(ctx, gates + off, layer_len[l], ctx->n);
+      if (st != MPS_OK) return st;
+      for (int i = 0; i < layer_len[l]; ++i) layers[l].push_back(to_host_gate(gates[off + i]));
+      off += layer_len[l];
+    }
+    flush_all(ctx);
+    double f = 1.0;
+    dmrg_step(ctx, layers, chi_max_dmrg, q_max, sweeps, &f);
+    if (f_fit) *f_fit = f;
     return MPS_OK;
   });
 }

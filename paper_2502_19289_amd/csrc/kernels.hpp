@@ -448,6 +448,14 @@ hipError_t launch_convert_f2d(const float2* src, double2* dst, int64_t n, hipStr
 
 // Log-f accumulation in a fixed order (deterministic): total += sum_i v[i]
 hipError_t launch_accumulate(const double* v, int n, double* total, hipStream_t s);
+// Dense FP64 complex helpers of the DMRG fit (row-major): sum |x|^2 into
+// *out; x *= a; out = diag(d) conj(in)^T (d may be null); columns of x
+// scaled by d.
+hipError_t launch_dense_norm2(const double2* x, int64_t n, double* out, hipStream_t s);
+hipError_t launch_dense_scale(double2* x, int64_t n, double a, hipStream_t s);
+hipError_t launch_dense_adjoint(const double2* in, int rows, int cols, int ldi, const double* d, double2* out,
+                                int ldo, hipStream_t s);
+hipError_t launch_dense_scale_cols(double2* x, int rows, int cols, int ld, const double* d, hipStream_t s);
 // total += *v[0] + ... + *v[n-1] (v: device array of n device pointers)
 hipError_t launch_accumulate_ptrs(const double* const* v, int n, double* total, hipStream_t s);
 

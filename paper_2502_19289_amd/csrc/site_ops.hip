@@ -9,6 +9,8 @@
 #include <cfloat>
 
 #include "common.hpp"
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace ctebd {
@@ -298,7 +300,81 @@ __global__ void accumulate_ptrs_kernel(const double* const* __restrict__ v, int 
   }
 }
 
+// ---- small dense helpers of the DMRG fit (FP64 complex, row-major)
+// out[0] = sum |x_i|^2 (one workgroup, fixed order of the partial sums)
+__global__ __launch_bounds__(256) void dense_norm2_kernel(const double2* __restrict__ x, int64_t n,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i].x * x[i].x + x[i].y * x[i].y;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void dense_scale_kernel(double2* __restrict__ x, int64_t n, double a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = make_double2(a * x[i].x, a * x[i].y);
+}
+
+// out (cols x rows, ldo) = conj(in (rows x cols, ldi))^T with row i of out
+// scaled by d[i] when d is non-null
+__global__ void dense_adjoint_kernel(const double2* __restrict__ in, int rows, int cols, int ldi,
+                                     const double* __restrict__ d, double2* __restrict__ out, int ldo) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / rows), j = (int)(e % rows);  // out row i (input column), out column j (input row)
+    const double2 v = in[(int64_t)j * ldi + i];
+    const double sc = d ? d[i] : 1.0;
+    out[(int64_t)i * ldo + j] = make_double2(sc * v.x, -sc * v.y);
+  }
+}
+
+// columns j < cols of x (rows x cols, ld) scaled by d[j]
+__global__ void dense_scale_cols_kernel(double2* __restrict__ x, int rows, int cols, int ld,
+                                        const double* __restrict__ d) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), j = (int)(e % cols);
+    const double2 v = x[(int64_t)i * ld + j];
+    x[(int64_t)i * ld + j] = make_double2(d[j] * v.x, d[j] * v.y);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_dense_norm2(const double2* x, int64_t n, double* out, hipStream_t s) {
+  launch(dense_norm2_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_scale(double2* x, int64_t n, double a, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  launch(dense_scale_kernel, dim3(blocks), dim3(256), 0, s, x, n, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_adjoint(const double2* in, int rows, int cols, int ldi, const double* d, double2* out,
+                                int ldo, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  launch(dense_adjoint_kernel, dim3(blocks), dim3(256), 0, s, in, rows, cols, ldi, d, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_scale_cols(double2* x, int rows, int cols, int ld, const double* d, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  launch(dense_scale_cols_kernel, dim3(blocks), dim3(256), 0, s, x, rows, cols, ld, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_accumulate_ptrs(const double* const* v, int n, double* total, hipStream_t s) {
   if (n <= 0) return hipSuccess;

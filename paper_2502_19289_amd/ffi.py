@@ -47,7 +47,7 @@ class CtebdError(RuntimeError):
         self.status = status
 
 
-EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster", "mps_set_options",
+EXPORTS = ["mps_default_options", "mps_create", "mps_destroy", "mps_apply_cluster", "mps_set_options", "mps_dmrg_step",
            "mps_save", "mps_load",
            "mps_run_layer", "mps_flush", "mps_queue_layer", "mps_step", "mps_run_steps", "mps_clone", "mps_overlap",
            "mps_fidelity", "mps_bond_dims", "mps_schmidt",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.mps_run_steps.argtypes = [P, I, C.POINTER(I), C.POINTER(I)]
     lib.mps_clone.argtypes = [P, C.POINTER(Options), C.POINTER(P)]
     lib.mps_set_options.argtypes = [P, C.POINTER(Options)]
+    lib.mps_dmrg_step.argtypes = [P, C.POINTER(GateC), C.POINTER(I), I, I, I, I, C.POINTER(D)]
     lib.mps_save.argtypes = [P, C.c_char_p]
     lib.mps_load.argtypes = [C.c_char_p, C.POINTER(P)]
     lib.mps_overlap.argtypes = [P, P, C.POINTER(D), C.POINTER(D)]
@@ -276,6 +277,17 @@ class MPS:
         o.hip_stream = hip_stream
         self._check(self.lib.mps_set_options(self.h, C.byref(o)))
         self._opt = o
+
+    def dmrg_step(self, layers, chi_max_dmrg: int, q_max: int, sweeps: int = 2) -> float:
+        """mps_dmrg_step: one adaptive-grouping DMRG step over `layers` (lists of
+        (qubits, matrix)); returns the fit's fidelity."""
+        flat = [g for layer in layers for g in layer]
+        arr, _ = make_gates(flat)
+        ll = np.array([len(layer) for layer in layers], dtype=np.int32)
+        f = C.c_double()
+        self._check(self.lib.mps_dmrg_step(self.h, arr, _iptr(ll), len(layers), int(chi_max_dmrg), int(q_max),
+                                           int(sweeps), C.byref(f)))
+        return f.value
 
     def save(self, path: str):
         """mps_save: the whole handle to a file."""

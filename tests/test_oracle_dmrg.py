@@ -83,3 +83,16 @@ def test_capped_dmrg_fidelities():
     dims = out.bond_dims()
     for (a, b) in rec.groups[:-1]:
         assert dims[b] <= rec.chi_virtual[b]
+
+
+def test_compression_alone_reports_its_fidelity():
+    """With no sweep the fit is the compression at the group cuts; its f is
+    the weight the compressed state keeps, |<M|U psi>|^2 by definition."""
+    c = paper_random_structured(10, 18, 2, d_max=3, seed=4, workload_id=97)
+    out, rec = DM.dmrg_step(CT.product_state(10), c.layers, chi_max_dmrg=2, chi_max_svd=1024, eps=0.0,
+                            q_max=5, sweeps=0)
+    sv = SV.simulate(c)
+    amp = MT.amplitudes(out.B)
+    F = abs(np.vdot(sv, amp)) ** 2 / (np.vdot(amp, amp).real * np.vdot(sv, sv).real)
+    assert rec.f_dmrg < 0.9
+    assert abs(F - rec.f_dmrg) < 1e-12

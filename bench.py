@@ -421,6 +421,13 @@ def main():
         "prep_s": round(prep_s, 1),
         "event_timed_ms_per_step": 1e3 * dt_p / max(1, steps_p),
     }
+    # device time of the kernel classes per step (the replay's event-timed
+    # class totals) against the wall time of the pass without events: the
+    # share of the timed region the GPU spends in kernels, the rest being
+    # launch gaps, host planning and host-device synchronisation
+    dev_ms = sum(class_totals(kt, disp, args.burst_reps).values()) / max(1, steps_p)
+    out["device_ms_per_step"] = dev_ms
+    out["device_busy_frac"] = dev_ms / out["ms_per_step"] if out["ms_per_step"] > 0 else None
     if ref is not None:
         s64, u64, dt64 = timed_steps(ref, steps)
         print(f"# fp64 leg {s64} steps, {dt64:.1f} s", file=sys.stderr, flush=True)

@@ -681,11 +681,12 @@ void solve_htd_chunk(mps_ctx* ctx, const HtdDesc* dd, const HtdSizes& sz, const 
         }
       const int nb_hemv = most([k](int n) { return htd_hemv_blocks(n, k); });
       const bool counted = timed_repeatable(ctx, "trd_hemv", [&] { return launch_trd_hemv(ha, k, nb_hemv, s); });
-      if (counted)  // algorithmic traffic of the HEMV: one triangle of the trailing block read once
+      if (counted)  // algorithmic traffic of the HEMV: one triangle of the trailing block, the rows of
+                    // the j panel columns of V and W and the vector x, each read once
         for (int p = 0; p < np; ++p) {
           const double m = sz.n[p] - k - 1;
           if (m <= 0 || k >= htd_tail_start(sz.n[p])) continue;
-          ctx->timer.bytes[c_hemv] += 16.0 * m * (m + 1) / 2;
+          ctx->timer.bytes[c_hemv] += 16.0 * m * (m + 1) / 2 + 16.0 * m * (2.0 * j + 1.0);
           ctx->timer.flop[c_hemv] += 8.0 * m * m;
         }
     }

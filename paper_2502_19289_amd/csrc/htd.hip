@@ -430,7 +430,8 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   const int m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
   const int wave = tid >> 6, lane = tid & 63, s4 = lane >> 4, cl = lane & 15;
-  const int i0 = I * HV_T, c0 = J * HV_T;  // offsets in the trailing block
+  const int o = htd_hemv_off(k);
+  const int i0 = I * HV_T - o, c0 = J * HV_T - o;  // offsets in the trailing block (>= -o)
   auto rowof = [&](int q) { return i0 + 16 * wave + 4 * q + s4; };
   auto colof = [&](int pp) { return c0 + 16 * pp + cl; };
   // small loads first (memory operations complete in issue order), all
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   const double2 alpha = d.xb[0];
   double2 xr[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) xr[q] = d.xb[min(rowof(q), m - 1)];
+  for (int q = 0; q < 4; ++q) xr[q] = d.xb[min(max(rowof(q), 0), m - 1)];
   auto reflector_norm = [&]() {
     if (tid < 64) {
       const double rm = rq.x, rs = rq.y;
@@ -463,11 +464,12 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   if (!panel) {
     double2 xc[4];
 #pragma unroll
-    for (int pp = 0; pp < 4; ++pp) xc[pp] = d.xb[min(colof(pp), m - 1)];
-    const double2 xcol = d.xb[min(c0 + lane, m - 1)];
+    for (int pp = 0; pp < 4; ++pp) xc[pp] = d.xb[min(max(colof(pp), 0), m - 1)];
+    const double2 xcol = d.xb[min(max(c0 + lane, 0), m - 1)];
     const double2* g0 = d.A + (int64_t)(k + 1) * ld + (k + 1);
     // (the lower triangle and the band of 64 above the diagonal are up to
-    // date, which covers a diagonal tile)
+    // date, which covers a diagonal tile; rows and columns -o..-1 are valid
+    // memory before the block, read whole and masked)
     double2 a[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -510,16 +512,21 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
       acc.y += dpp_take<0x141, 0xf>(acc.y);
       acc.x += dpp_take<0x140, 0xf>(acc.x);
       acc.y += dpp_take<0x140, 0xf>(acc.y);
+      double2 g_r0 = make_double2(0.0, 0.0);  // G[r][0]: column 0 of the block is tile column o
+      if (J == 0) {
+        g_r0.x = __shfl(a[q][0].x, (lane & 48) | o);
+        g_r0.y = __shfl(a[q][0].y, (lane & 48) | o);
+      }
       const int r = rowof(q);
-      if (cl == 0 && r < m) {
-        if (J == 0) acc = cadd(acc, a[q][0]);  // G[r][0] v_0
+      if (cl == 0 && r >= 0 && r < m) {
+        if (J == 0) acc = cadd(acc, g_r0);  // G[r][0] v_0
         const double2 y = ident ? make_double2(0.0, 0.0) : cmul(tau, acc);
         const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
         d.Y[(int64_t)J * ld + r] = y;
         dot = cadd(dot, cmulc(y, vi));
       }
     }
-    if (!diag && tid < 64 && c0 + tid < m) {  // column c = c0 + tid
+    if (!diag && tid < 64 && c0 + tid >= 0 && c0 + tid < m) {  // column c = c0 + tid
       const int c = c0 + tid;
       double2 cs = make_double2(0.0, 0.0);
 #pragma unroll
@@ -597,7 +604,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
       acc.x += dpp_take<0x140, 0xf>(acc.x);
       acc.y += dpp_take<0x140, 0xf>(acc.y);
       const int r = rowof(q);
-      if (cl == 0 && r < m) {
+      if (cl == 0 && r >= 0 && r < m) {
         const double2 y = ident ? make_double2(0.0, 0.0) : cmul(make_double2(-tau.x, -tau.y), acc);
         const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
         d.Y[(int64_t)(T + h) * ld + r] = y;

@@ -164,10 +164,15 @@ __host__ __device__ inline int htd_tail_start(int n) {
 
 // Per-problem workgroup counts of the launches (identical on host and device).
 // HEMV: tile rows T of the trailing block; T (T + 1) / 2 workgroups for the
-// tiles of its lower triangle and 2 T for the panel terms; T + 2 y slots
+// tiles of its lower triangle and 2 T for the panel terms; T + 2 y slots.
+// The tile grid of column k starts o = (k + 1) % 8 rows and columns before
+// the trailing block (at absolute index (k + 1) - o), so that every row
+// segment of a tile is whole 128-byte lines (ld is a multiple of 64); the
+// first o rows and columns are read and masked.  m + o <= n keeps T <= HV_TMAX.
+__host__ __device__ inline int htd_hemv_off(int k) { return (k + 1) & 7; }
 __host__ __device__ inline int htd_hemv_rows(int n, int k) {
   const int m = n - k - 1;
-  return m > 0 && k < htd_tail_start(n) ? (m + HV_T - 1) / HV_T : 0;
+  return m > 0 && k < htd_tail_start(n) ? (m + htd_hemv_off(k) + HV_T - 1) / HV_T : 0;
 }
 __host__ __device__ inline int htd_hemv_blocks(int n, int k) {
   const int t = htd_hemv_rows(n, k);

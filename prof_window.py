@@ -8,6 +8,8 @@ counter read on a device copy of known size.
 
     python prof_window.py trace DIR CLASS BENCH_JSON
     python prof_window.py pmc DIR CLASS D [COPY_BYTES]
+    python prof_window.py counters DIR NAME_PART [D]
+    python prof_window.py sha256 FILE,FILE,...
 """
 from __future__ import annotations
 
@@ -31,6 +33,17 @@ def _one(pattern: str) -> str:
 def _short(name: str) -> str:
     m = re.search(r"(\w+)_kernel", name)
     return m.group(1) if m else name.split("(")[0][-40:]
+
+
+def _workgroups(r: dict) -> int:
+    """Workgroups of one traced dispatch (grid sizes are in threads)."""
+    n = 1
+    for ax in "XYZ":
+        g = int(r.get(f"Grid_Size_{ax}", r.get("Grid_Size", 1)) if ax == "X" else r.get(f"Grid_Size_{ax}", 1))
+        w = int(r.get(f"Workgroup_Size_{ax}", r.get("Workgroup_Size", 1)) if ax == "X" else
+                r.get(f"Workgroup_Size_{ax}", 1))
+        n *= max(1, -(-g // max(1, w)))
+    return n
 
 
 def trace(dirname: str, cls: str, bench_json: str) -> None:
@@ -67,6 +80,15 @@ def trace(dirname: str, cls: str, bench_json: str) -> None:
               f"{collections.Counter(len(r) for r in bursts).most_common(1)[0][0]}; average dispatch "
               f"{sum(bd) / len(bd) / 1e3:.3f} us; gap between dispatches under the tracer: mean "
               f"{sum(gaps) / len(gaps) / 1e3:.2f} us, median {gaps[len(gaps) // 2] / 1e3:.2f} us")
+    shapes = collections.defaultdict(list)
+    for i in win:
+        shapes[_workgroups(rows[i])].append(int(rows[i]["End_Timestamp"]) - int(rows[i]["Start_Timestamp"]))
+    print(f"\nworkgroups launched per dispatch in the window (grid x * y * z / workgroup size):")
+    print("| workgroups | dispatches | avg us |")
+    print("|---:|---:|---:|")
+    for wg in sorted(shapes):
+        v = shapes[wg]
+        print(f"| {wg} | {len(v)} | {sum(v) / len(v) / 1e3:.3f} |")
     r = bench["roofline"]
     print(f"benchmark line of this traced run: avg_launch_ms {r['avg_launch_ms']:.6f}, "
           f"launches_timed {r.get('launches_timed')}, dispatches {r.get('dispatches')}")
@@ -85,6 +107,45 @@ def pmc(dirname: str, cls: str, D: int, copy_bytes: int = 0) -> None:
             print(f"{c} copy of {copy_bytes} bytes: {sum(v):.1f} KiB (scale {copy_bytes / 1024 / sum(v):.4f})")
 
 
+def counters(dirname: str, pattern: str, D: int = 0) -> None:
+    """Per-dispatch means of every collected counter for the kernels whose
+    name contains `pattern`, grouped by instantiation, over the last D
+    dispatches of each (all when D = 0).  The MFMA op counters
+    (SQ_INSTS_VALU_MFMA_MOPS_*) count units of 512 flops; MfmaUtil is the busy
+    share of the matrix cores, SQ_VALU_MFMA_BUSY_CYCLES summed over the SIMDs
+    over the busy cycles of the device times the SIMD count (the CSV holds
+    GRBM_GUI_ACTIVE summed over the XCDs: the device's cycles are that sum
+    over the XCD count)."""
+    f = _one(os.path.join(dirname, "**", "*counter_collection.csv"))
+    simds, xcc = 0, 1
+    agent = glob.glob(os.path.join(dirname, "**", "*agent_info.csv"), recursive=True)
+    for r in (csv.DictReader(open(agent[0])) if agent else []):
+        if r.get("Agent_Type") == "GPU":
+            simds, xcc = int(r["Simd_Count"]), max(1, int(r["Num_Xcc"]))
+    by = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(f)):
+        name = r["Kernel_Name"]
+        if pattern not in name:
+            continue
+        bare = name.replace("(anonymous namespace)::", "")
+        key = bare.split("(")[0] if "<" not in bare else bare[:bare.rfind(">") + 1]
+        by[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for key, cs in sorted(by.items()):
+        print(f"{key}")
+        means = {}
+        for c, v in sorted(cs.items()):
+            w = v[-D:] if D > 0 else v
+            means[c] = sum(w) / len(w)
+            line = f"  {c}: {len(v)} dispatches, window {len(w)}, mean {means[c]:.4g} per dispatch"
+            if "MFMA_MOPS" in c:
+                line += f" ({means[c] * 512 / 1e9:.4g} GFLOP)"
+            print(line)
+        if simds and "SQ_VALU_MFMA_BUSY_CYCLES" in means and means.get("GRBM_GUI_ACTIVE"):
+            cyc = means["GRBM_GUI_ACTIVE"] / xcc
+            print(f"  device busy cycles {cyc:.4g} per dispatch; MfmaUtil over the window: "
+                  f"{100 * means['SQ_VALU_MFMA_BUSY_CYCLES'] / (cyc * simds):.1f} % ({simds} SIMDs, {xcc} XCDs)")
+
+
 def sources_sha256(paths: list[str], root: str) -> str:
     h = hashlib.sha256()
     for p in paths:
@@ -99,6 +160,8 @@ if __name__ == "__main__":
         trace(a[1], a[2], a[3])
     elif a and a[0] == "pmc" and len(a) in (4, 5):
         pmc(a[1], a[2], int(a[3]), int(a[4]) if len(a) == 5 else 0)
+    elif a and a[0] == "counters" and len(a) in (3, 4):
+        counters(a[1], a[2], int(a[3]) if len(a) == 4 else 0)
     elif a and a[0] == "sha256":
         print(sources_sha256(a[1].split(","), os.path.dirname(os.path.abspath(__file__))))
     else:

@@ -88,6 +88,13 @@ def parse():
     ap.add_argument("--compare-tebd", default="",
                     help="instead of the benchmark line: whole-circuit runtime of cluster-TEBD and of gate-by-gate "
                          "TEBD (k_max 2, one sub-layer per step) on the named workload, one JSON line")
+    ap.add_argument("--dmrg", default="",
+                    help="workload: run the adaptive-grouping DMRG variant over it instead (FP64)")
+    ap.add_argument("--dmrg-lmax", default="1,2", help="comma-separated L_max values of the DMRG runs")
+    ap.add_argument("--dmrg-chi", type=int, default=64, help="chi_max^DMRG")
+    ap.add_argument("--dmrg-svd-chi", type=int, default=64, help="chi_max^SVD (the state's chi_max)")
+    ap.add_argument("--dmrg-qmax", type=int, default=20, help="Q_max of the grouping")
+    ap.add_argument("--dmrg-sweeps", type=int, default=3, help="sweeps per DMRG step (n_s)")
     ap.add_argument("--profile-window", action="store_true",
                     help="ask an attached rocprofv3 to collect only during the timed steps")
     ap.add_argument("--burst-reps", type=int, default=BURST_REPS,
@@ -307,10 +314,60 @@ def compare_tebd(args):
     print(json.dumps(out))
 
 
+def dmrg_run(args):
+    """The adaptive-grouping DMRG variant (Sec. III.B) over a whole circuit for
+    each L_max in the list, FP64, against cluster-TEBD at the same chi_max on
+    the same circuit: wall time, steps, the fidelity estimate and the mutual
+    infidelity of the final states.  The paper runs non-Clifford
+    random-structured circuits of 60-100 qubits with n_s = 3 sweeps,
+    Q_max = 20 and chi_max^DMRG = 256; here the evolved segment is formed
+    exactly as an MPS whose bonds (at most 4^E(b) chi_b) must stay within
+    1024, which bounds chi_max^SVD by 1024 / 4^L_max."""
+    import torch
+
+    import paper_2502_19289_amd as P
+    from workloads import make_workload
+
+    circ, p = make_workload(args.dmrg, seed=args.seed)
+    chi_svd = args.dmrg_svd_chi
+    out = {"comparison": "adaptive-grouping DMRG vs cluster-TEBD, whole circuit", "workload": args.dmrg,
+           "n": circ.n, "layers": len(circ.layers), "chi_max_svd": chi_svd, "chi_max_dmrg": args.dmrg_chi,
+           "q_max": args.dmrg_qmax, "sweeps": args.dmrg_sweeps, "eps": p["eps"], "precision": "fp64", "runs": []}
+    ref = P.MPS(circ.n, chi_svd, p["eps"], k_max=p["k_max"], precision="fp64", batch=args.batch)
+    for layer in circ.layers:
+        ref.queue_layer([(g.qubits, P.GATES[g.name]) for g in layer])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref.run_steps(1 << 30)
+    torch.cuda.synchronize()
+    out["ctebd"] = {"seconds": time.perf_counter() - t0, "steps": ref.stats()["steps"], "F_est": ref.fidelity()[0],
+                    "max_chi": max(ref.bond_dims())}
+    print(f"# cluster-TEBD: {out['ctebd']['seconds']:.2f} s", file=sys.stderr, flush=True)
+    for l_max in [int(v) for v in args.dmrg_lmax.split(",")]:
+        m = P.MPS(circ.n, chi_svd, p["eps"], k_max=p["k_max"], precision="fp64")
+        step_s = []
+        for t0_layer in range(0, len(circ.layers), l_max):
+            seg = [[(g.qubits, P.GATES[g.name]) for g in layer] for layer in circ.layers[t0_layer:t0_layer + l_max]]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.dmrg_step(seg, args.dmrg_chi, args.dmrg_qmax, args.dmrg_sweeps)
+            torch.cuda.synchronize()
+            step_s.append(time.perf_counter() - t0)
+        run = {"l_max": l_max, "seconds": sum(step_s), "steps": len(step_s),
+               "median_step_ms": 1e3 * sorted(step_s)[len(step_s) // 2], "F_est": m.fidelity()[0],
+               "max_chi": max(m.bond_dims()), "infidelity_vs_ctebd": m.infidelity(ref)}
+        out["runs"].append(run)
+        print(f"# DMRG L_max {l_max}: {run['seconds']:.2f} s, F_est {run['F_est']:.4f}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.compare_tebd:
         compare_tebd(args)
+        return
+    if args.dmrg:
+        dmrg_run(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))

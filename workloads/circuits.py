@@ -167,6 +167,9 @@ WORKLOADS = {
                                      eps=1e-12),
     "paper_nonclifford_n100_l80": dict(wid=9, n=100, layers=80, version=2, d_max=1, k_max=6, chi_max=1024,
                                        eps=1e-12),
+    # the smallest of the paper's DMRG benchmark sizes (60 qubits, 60 layers, non-Clifford)
+    "paper_nonclifford_n60_l60": dict(wid=10, n=60, layers=60, version=2, d_max=1, k_max=6, chi_max=1024,
+                                      eps=1e-12),
 }
 
 

@@ -23,6 +23,7 @@
 #include <iterator>
 #include <mutex>
 #include <tuple>
+#include <unordered_map>
 
 #include "engine.hpp"
 
@@ -2212,6 +2213,8 @@ mps_status guarded(mps_ctx* ctx, F&& f) {
 void destroy_ctx(mps_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  destroy_ctx(ctx->dmrg_scratch);
+  ctx->dmrg_scratch = nullptr;
   ctx->arena.release();
   ctx->pool.release();
   ctx->blob.release();
@@ -2238,31 +2241,48 @@ void destroy_ctx(mps_ctx* ctx) {
 // truncated-SVD compression at the group cuts, then sweeps of one-group
 // updates M = F / ||F||, orthonormalised by polar factors), and M decomposed
 // back into qubit tensors by Gram / eigen splits with chi_max and the cutoff.
-// Every product is one launch of the library's GEMMs with a single problem;
-// the stream is synchronised after each (the descriptor blob is reused), so
-// this path is written for correctness, not speed.
+// Every product is one launch of the library's GEMMs with a single problem
+// (split along K when it has few output tiles); the stream is synchronised
+// after each (the descriptor blob is reused).
 struct DevOps {
   mps_ctx* ctx;
-  std::vector<void*> mem;
+  std::vector<void*> mem;                       // every block, freed at the end
+  std::unordered_map<void*, size_t> bytes_of;   // their sizes
+  std::vector<std::pair<size_t, void*>> spare;  // released blocks
   double* d_scalar = nullptr;
   explicit DevOps(mps_ctx* c) : ctx(c) {}
   ~DevOps() {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (void* p : mem) (void)hipFree(p);
   }
+  // Blocks are recycled within the step: everything runs on one stream, so a
+  // block released after its last use is only written again by work queued
+  // after that use.  A spare block serves a request of up to twice its size.
   template <typename T>
   T* alloc(size_t n) {
+    const size_t want = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~size_t(255);
+    size_t best = spare.size();
+    for (size_t i = 0; i < spare.size(); ++i)
+      if (spare[i].first >= want && spare[i].first <= 2 * want + (size_t(1) << 20) &&
+          (best == spare.size() || spare[i].first < spare[best].first))
+        best = i;
+    if (best < spare.size()) {
+      void* p = spare[best].second;
+      spare.erase(spare.begin() + best);
+      return (T*)p;
+    }
     void* p = nullptr;
-    HIP_OK(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)));
+    HIP_OK(hipMalloc(&p, want));
     mem.push_back(p);
+    bytes_of[p] = want;
     return (T*)p;
   }
   void release(void* p) {
-    auto it = std::find(mem.begin(), mem.end(), p);
-    if (it == mem.end()) return;
-    HIP_OK(hipStreamSynchronize(ctx->stream));
-    (void)hipFree(p);
-    mem.erase(it);
+    auto it = bytes_of.find(p);
+    if (it == bytes_of.end()) return;
+    for (const auto& e : spare)
+      if (e.second == p) return;
+    spare.push_back({it->second, p});
   }
   void run_gemm(const GemmDesc& d, bool cn) {
     DescBlob& B = ctx->blob;
@@ -2278,13 +2298,42 @@ struct DevOps {
       HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(o), B.at<int>(ob), 1, tiles, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
   }
+  // A product with few 64 x 64 output tiles and a long K (the environment
+  // updates contract a group's whole physical index) is cut into K slices
+  // whose partial products are summed afterwards, so that it fills more than
+  // a handful of compute units.
+  double2* parts = nullptr;
+  size_t parts_cap = 0;
+  void run_split(GemmDesc d, double2* C, int M, int N, int K, int ldc, bool cn) {
+    const int tiles = d.tm * d.tn;
+    int ks = 1;
+    if (tiles < 128 && K >= 1024) ks = std::min({64, std::max(1, 256 / tiles), K / 512});
+    if (ks <= 1) {
+      run_gemm(d, cn);
+      return;
+    }
+    const size_t need = (size_t)ks * M * N;
+    if (need > parts_cap) {
+      if (parts) release(parts);
+      parts = alloc<double2>(need);
+      parts_cap = need;
+    }
+    d.C = parts;
+    d.ldc = fixed(N);
+    d.ksplit = ks;
+    d.part = (int64_t)M * N;
+    run_gemm(d, cn);
+    HIP_OK(launch_dense_sum_parts(parts, ks, (int64_t)M * N, M, N, C, ldc, ctx->stream));
+  }
   // C (M x N) = A (M x K) B (K x N)
   void nn(const double2* A, const double2* B, double2* C, int M, int N, int K, int lda, int ldb, int ldc) {
-    run_gemm(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), false);
+    run_split(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), C, M, N, K,
+              ldc, false);
   }
   // C (M x N) = A^H B, A: K x M, B: K x N
   void cn(const double2* A, const double2* B, double2* C, int M, int N, int K, int lda, int ldb, int ldc) {
-    run_gemm(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), true);
+    run_split(gemm64(A, B, C, fixed(M), fixed(N), fixed(K), fixed(lda), fixed(ldb), fixed(ldc), M, N), C, M, N, K,
+              ldc, true);
   }
   double norm2(const double2* x, int64_t n) {
     if (!d_scalar) d_scalar = alloc<double>(1);
@@ -2463,15 +2512,27 @@ void dmrg_step(mps_ctx* ctx, const std::vector<std::vector<HostGate>>& layers, i
   to.batch = MPS_BATCH_STEP;
   to.svd_mode = MPS_SVD_EXACT;
   to.hip_stream = ctx->stream;
-  mps_handle T = nullptr;
-  {
-    const mps_status cs = mps_create(n, (int)chi_t, 0.0, &to, &T);
-    if (cs != MPS_OK) fail(ctx, cs, "DMRG: could not create the scratch handle");
+  // the scratch handle of the previous step serves again when its cap covers
+  // chi_t and its options match (its cap only bounds, and never binds,
+  // since chi_t bounds the exact state); it is created with chi_t rounded up
+  // to a power of two so that a slowly growing chi_t rarely recreates it
+  mps_handle T = ctx->dmrg_scratch;
+  auto same = [](const mps_options& a, const mps_options& b) {
+    return a.k_max == b.k_max && a.q_max == b.q_max && a.l_max == b.l_max && a.eig_method == b.eig_method &&
+           a.floor_c == b.floor_c && a.hip_stream == b.hip_stream;
+  };
+  if (T && (T->n != n || T->chi_max < chi_t || !same(T->opt, to))) {
+    destroy_ctx(T);
+    T = ctx->dmrg_scratch = nullptr;
   }
-  struct Closer {
-    mps_handle h;
-    ~Closer() { destroy_ctx(h); }
-  } closer{T};
+  if (!T) {
+    int64_t cap = 1;
+    while (cap < chi_t) cap <<= 1;
+    const mps_status cs = mps_create(n, (int)std::min<int64_t>(cap, HTD_MAX / 2), 0.0, &to, &T);
+    if (cs != MPS_OK) fail(ctx, cs, "DMRG: could not create the scratch handle");
+    ctx->dmrg_scratch = T;
+  }
+  T->pending.clear();
   for (int j = 0; j < n; ++j) {
     const int64_t cnt = (int64_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j);
     HIP_OK(hipMemcpyAsync(T->site[j], ctx->site[j], cnt * 16, hipMemcpyDeviceToDevice, s));

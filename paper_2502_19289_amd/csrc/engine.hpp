@@ -142,6 +142,9 @@ struct mps_ctx {
   // spectrum tail of each bond's last split (features of its next splits):
   // discarded weight and smallest kept / largest singular value
   std::vector<float> prev_dw, prev_tail;
+  // DMRG: the handle that holds each step's evolved segment, kept between
+  // steps (same stream; owned, destroyed with this handle; never cloned)
+  mps_ctx* dmrg_scratch = nullptr;
   uint64_t sketch_seed = 0x9E3779B97F4A7C15ull;
   uint32_t sketch_stream = 0;
 };

@@ -461,6 +461,9 @@ hipError_t launch_dense_scale(double2* x, int64_t n, double a, hipStream_t s);
 hipError_t launch_dense_adjoint(const double2* in, int rows, int cols, int ldi, const double* d, double2* out,
                                 int ldo, hipStream_t s);
 hipError_t launch_dense_scale_cols(double2* x, int rows, int cols, int ld, const double* d, hipStream_t s);
+// C (M x N, ldc) = sum of `parts` partial products P + q stride (M x N each)
+hipError_t launch_dense_sum_parts(const double2* P, int parts, int64_t stride, int M, int N, double2* C, int ldc,
+                                  hipStream_t s);
 // total += *v[0] + ... + *v[n-1] (v: device array of n device pointers)
 hipError_t launch_accumulate_ptrs(const double* const* v, int n, double* total, hipStream_t s);
 

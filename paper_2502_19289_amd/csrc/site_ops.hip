@@ -345,7 +345,32 @@ __global__ void dense_scale_cols_kernel(double2* __restrict__ x, int rows, int c
   }
 }
 
+// C (M x N, ldc) = the sum of the `parts` partial products P + q stride
+// (each M x N, row-major), in order q = 0, 1, ...
+__global__ void dense_sum_parts_kernel(const double2* __restrict__ P, int parts, int64_t stride, int M, int N,
+                                       double2* __restrict__ C, int ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int q = 0; q < parts; ++q) {
+      const double2 v = P[(int64_t)q * stride + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    C[(e / N) * ldc + e % N] = acc;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_dense_sum_parts(const double2* P, int parts, int64_t stride, int M, int N, double2* C, int ldc,
+                                  hipStream_t s) {
+  const int64_t n = (int64_t)M * N;
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  launch(dense_sum_parts_kernel, dim3(blocks), dim3(256), 0, s, P, parts, stride, M, N, C, ldc);
+  return hipGetLastError();
+}
 
 hipError_t launch_dense_norm2(const double2* x, int64_t n, double* out, hipStream_t s) {
   launch(dense_norm2_kernel, dim3(1), dim3(256), 0, s, x, n, out);

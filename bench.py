@@ -45,7 +45,7 @@ PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 PEAK_VALU_TF = {"fp64": 78.6, "fp32": 157.3}
 PEAK_HBM = 8000.0
 
-MFMA_CLASSES = ("merge", "apply", "gram", "project", "eig_update", "eig_update32", "eig_rayleigh", "sketch",
+MFMA_CLASSES = ("merge", "apply", "gram", "project", "eig_update", "sketch",
                 "trd_her2k", "bt")
 CONTRACTIONS = ("merge", "apply", "project")
 
@@ -53,7 +53,7 @@ CONTRACTIONS = ("merge", "apply", "project")
 def class_peak(name: str, dtype: str):
     """(bound, precision, peak TFLOP/s) of a kernel class in a run of `dtype`."""
     if name in MFMA_CLASSES:
-        if dtype == "fp64" or name in ("gram", "eig_rayleigh", "eig_update", "sketch", "trd_her2k", "bt"):
+        if dtype == "fp64" or name in ("gram", "eig_update", "sketch", "trd_her2k", "bt"):
             return "mfma", "fp64", PEAK_TF["fp64"]
         if dtype == "bf16x6" and name in CONTRACTIONS:
             # six BF16 products per real product: algorithmic flops against peak/6

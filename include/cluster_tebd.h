@@ -74,8 +74,7 @@ enum {
   MPS_EIG_AUTO = 0,     /* the faster route by size: at present tridiagonal
                            whenever 2c <= 2048 (as MPS_EIG_TRIDIAG), Jacobi
                            above                                                */
-  MPS_EIG_JACOBI = 1,   /* FP64 block Jacobi (an FP32 solve with FP64 Rayleigh
-                           quotients for large cap-limited splits of FP32 runs) */
+  MPS_EIG_JACOBI = 1,   /* FP64 block Jacobi                                    */
   MPS_EIG_TRIDIAG = 2   /* tridiagonal divide and conquer whenever 2c <= 2048   */
 };
 
@@ -224,7 +223,9 @@ mps_status mps_load(const char* path, mps_handle* out);
  * split back into qubit tensors with the handle's chi_max and cutoff.
  * *f_fit (may be NULL) receives the fit's fidelity |<M|U psi>|^2; the
  * fidelity sum adds log f_fit and the log of the splits' kept weights.  The
- * evolved state's bond dimensions must stay <= 1024.  Synchronises. */
+ * evolved state's bond dimensions must stay <= 1024.  chi_max_dmrg >= 1,
+ * q_max >= 1 (1: every group a single qubit), sweeps >= 0 (0: the
+ * compression alone), else MPS_EINVAL.  Synchronises. */
 mps_status mps_dmrg_step(mps_handle h, const mps_gate* gates, const int* layer_len, int nl, int chi_max_dmrg,
                          int q_max, int sweeps, double* f_fit);
 
@@ -267,8 +268,8 @@ mps_status mps_get_stats(mps_handle h, mps_stats* st);
  * measured with HIP events on the handle's stream around every launch of that
  * class (mps_set_timing), the number of launches, and the algorithmic real
  * flops the class performed (8 per complex multiply-add; merges, unitary
- * products, Hermitian half of the Gram matrices, projections, Rayleigh
- * products, and the rotation tiles eig_update applied).  Arrays hold cap
+ * products, Hermitian half of the Gram matrices, projections, and the
+ * rotation tiles eig_update applied).  Arrays hold cap
  * entries; names receives the class names, comma-separated; *count the
  * number of classes. */
 mps_status mps_set_timing(mps_handle h, int on);

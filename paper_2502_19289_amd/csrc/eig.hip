@@ -12,11 +12,8 @@
 // (eig_update).  A sweep in which no subproblem needed a rotation ends the
 // iteration for that matrix.
 //
-// Two instantiations: T = double (the FP64 path) and T = float (the mixed
-// path).  The float solve works on an FP32 copy of the FP64 Gram matrix; its
-// eigenvalues are then taken as FP64 Rayleigh quotients v_i^H G v_i of the
-// FP32 eigenvectors (eig_to64 + an FP64 GEMM W = G V + eig_rayleigh), so the
-// values that decide the truncation and f_i stay FP64.
+// FP64 throughout (the kernels are written over the real type T and built for
+// T = double): the eigenvalues decide the truncation and f_i.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -31,11 +28,6 @@ template <>
 struct JacobiTol<double> {
   static constexpr double inner = 1e-14;     // inner rotation threshold (relative)
   static constexpr double floor = 8.9e-16;   // 2^-50: absolute floor, times trace(G)
-};
-template <>
-struct JacobiTol<float> {
-  static constexpr float inner = 1e-6f;
-  static constexpr float floor = 4.8e-7f;    // 2^-21
 };
 
 __device__ __forceinline__ int nblocks_of(int n) {
@@ -473,82 +465,30 @@ __global__ void eig_sweep_end_kernel(const EigDesc* __restrict__ descs, int npro
   }
 }
 
-// V (FP64) <- Vw (FP32) over the padded square
-__global__ __launch_bounds__(256) void eig_to64_kernel(const EigDesc* __restrict__ descs) {
-  const EigDesc& d = descs[blockIdx.y];
-  const int n = dim_value(d.n);
-  const int npad = nblocks_of(n) * JB;
-  const float2* Vw = (const float2*)d.Vw;
-  for (int row = blockIdx.x; row < npad; row += gridDim.x)
-    for (int c = threadIdx.x; c < npad; c += blockDim.x) {
-      const int64_t e = (int64_t)row * d.ld + c;
-      d.V[e] = make_double2(Vw[e].x, Vw[e].y);
-    }
-}
-
-// lam[i] = Re sum_k conj(V[k][i]) W[k][i], W = G V (FP64 Rayleigh quotients)
-__global__ __launch_bounds__(256) void eig_rayleigh_kernel(const EigDesc* __restrict__ descs) {
-  const EigDesc& d = descs[blockIdx.y];
-  const int n = dim_value(d.n);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double2 v = d.V[(int64_t)k * d.ld + i], w = d.W[(int64_t)k * d.ld + i];
-    s += v.x * w.x + v.y * w.y;
-  }
-  d.lam[i] = s;
-}
-
 }  // namespace
 
-hipError_t launch_eig_init(bool fp32, const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
+hipError_t launch_eig_init(const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   dim3 grid(min(ld_max, 256), nprob);
-  if (fp32)
-    launch(eig_init_kernel<float>, dim3(grid), dim3(256), 0, s, d);
-  else
-    launch(eig_init_kernel<double>, dim3(grid), dim3(256), 0, s, d);
+  launch(eig_init_kernel<double>, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_pairs(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
-                            hipStream_t s) {
+hipError_t launch_eig_pairs(const EigDesc* d, const int* d_base, int nprob, int blocks, int round, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (fp32)
-    launch(eig_pairs_kernel<float>, dim3(blocks), dim3(EP_THREADS), 0, s, d, d_base, nprob, round);
-  else
-    launch(eig_pairs_kernel<double>, dim3(blocks), dim3(EP_THREADS), 0, s, d, d_base, nprob, round);
+  launch(eig_pairs_kernel<double>, dim3(blocks), dim3(EP_THREADS), 0, s, d, d_base, nprob, round);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
-                             hipStream_t s) {
+hipError_t launch_eig_update(const EigDesc* d, const int* d_base, int nprob, int blocks, int round, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (fp32)
-    launch(eig_update_kernel<float>, dim3(blocks), dim3(UP_THREADS), 0, s, d, d_base, nprob, round);
-  else
-    launch(eig_update_kernel<double>, dim3(blocks), dim3(UP_THREADS), 0, s, d, d_base, nprob, round);
+  launch(eig_update_kernel<double>, dim3(blocks), dim3(UP_THREADS), 0, s, d, d_base, nprob, round);
   return hipGetLastError();
 }
 
 hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
   launch(eig_sweep_end_kernel, dim3((nprob + 63) / 64), dim3(64), 0, s, d, nprob);
-  return hipGetLastError();
-}
-
-hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s) {
-  if (nprob <= 0) return hipSuccess;
-  dim3 grid(min(ld_max, 256), nprob);
-  launch(eig_to64_kernel, dim3(grid), dim3(256), 0, s, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s) {
-  if (nprob <= 0) return hipSuccess;
-  dim3 grid((n_max + 255) / 256, nprob);
-  launch(eig_rayleigh_kernel, dim3(grid), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 

@@ -267,9 +267,8 @@ struct JobRun {
   void* Uw = nullptr;
   void* buf[2] = {nullptr, nullptr};
   void* Vr = nullptr;
-  double2 *G = nullptr, *V = nullptr, *part = nullptr, *W = nullptr;
-  void *J = nullptr, *Gw = nullptr, *Vw = nullptr;
-  double* lamR = nullptr;
+  double2 *G = nullptr, *V = nullptr, *part = nullptr;
+  void* J = nullptr;
   int *pair_rot = nullptr, *flags = nullptr, *perm = nullptr;
   double *scale = nullptr, *logf = nullptr, *rec = nullptr;
   int cur = 0;
@@ -351,12 +350,6 @@ size_t job_bytes(const mps_ctx* ctx, const JobRun& j) {
   add(ld * ld * sizeof(double2));  // G
   add(ld * ld * sizeof(double2));  // V
   add(ld * 64 * sizeof(double2));  // J
-  if (ctx->prec != Prec::FP64) {     // FP32 solve: Gw, Vw, W = G V, Rayleigh quotients
-    add(ld * ld * sizeof(float2));
-    add(ld * ld * sizeof(float2));
-    add(ld * ld * sizeof(double2));
-    add(ld * sizeof(double));
-  }
   int ks = 1;
   size_t vr = 0;
   for (const auto& L : j.lv) {
@@ -389,15 +382,6 @@ void assign_job(mps_ctx* ctx, JobRun& j, DeviceArena& A) {
   j.G = (double2*)A.take(ld * ld * sizeof(double2));
   j.V = (double2*)A.take(ld * ld * sizeof(double2));
   j.J = A.take(ld * 64 * sizeof(double2));
-  if (ctx->prec != Prec::FP64) {
-    j.Gw = A.take(ld * ld * sizeof(float2));
-    j.Vw = A.take(ld * ld * sizeof(float2));
-    j.W = (double2*)A.take(ld * ld * sizeof(double2));
-    j.lamR = (double*)A.take(ld * sizeof(double));
-  } else {
-    j.Gw = j.G;
-    j.Vw = j.V;
-  }
   int ks = 1;
   size_t vr = 0;
   for (const auto& L : j.lv) {
@@ -430,22 +414,20 @@ void account_merge(mps_ctx* ctx, const JobRun& r) {
   ctx->timer.flop[ctx->timer.cls_of("apply")] += 8.0 * apply;
 }
 
-void account_level(mps_ctx* ctx, const JobRun& r, int t, bool mixed) {
+void account_level(mps_ctx* ctx, const JobRun& r, int t) {
   const int m = r.lv[t].m;
   const double c = (t == 0) ? r.chi_r : ctx->chi[r.a + m];
   const double rr = ctx->chi[r.a + m - 1];
   const double n2 = 2.0 * c, rows = r.lv[t].rows;
   ctx->timer.flop[ctx->timer.cls_of("gram")] += 8.0 * n2 * (n2 + 1) / 2 * rows;
   ctx->timer.flop[ctx->timer.cls_of("project")] += 8.0 * rows * n2 * rr;
-  if (mixed) ctx->timer.flop[ctx->timer.cls_of("eig_rayleigh")] += 8.0 * n2 * n2 * n2;
 }
 
 // All of a finished step's, plus the rotation tiles eig_update counted on the device.
-void account_flops(mps_ctx* ctx, const std::vector<JobRun>& runs, bool mixed, double eig_cmac,
-                   double pair_flops) {
+void account_flops(mps_ctx* ctx, const std::vector<JobRun>& runs, double eig_cmac, double pair_flops) {
   for (const auto& r : runs) {
     account_merge(ctx, r);
-    for (size_t t = 0; t < r.lv.size(); ++t) account_level(ctx, r, (int)t, mixed);
+    for (size_t t = 0; t < r.lv.size(); ++t) account_level(ctx, r, (int)t);
   }
   ctx->timer.flop[ctx->timer.cls_of("eig_update")] += 8.0 * eig_cmac;
   ctx->timer.flop[ctx->timer.cls_of("eig_pairs")] += pair_flops;
@@ -559,7 +541,7 @@ GemmDesc gemm64(const void* A, const void* B, void* C, Dim M, Dim N, Dim K, Dim 
 // Runs a group of FP64/FP32 block-Jacobi solves to convergence (host checks
 // the convergence flags after every sweep).  flags_dev/h_flags hold `stride`
 // ints per problem at the indices given.
-void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>& host, const int* b_pair,
+void solve_eig(mps_ctx* ctx, EigDesc* de, const std::vector<EigDesc>& host, const int* b_pair,
                const int* b_upd, int n_pair, int n_upd, const int* flags_dev, int nflag_ints,
                const std::vector<int>& flag_at, bool sketch = false) {
   hipStream_t s = ctx->stream;
@@ -586,12 +568,12 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
     ++sweeps;
     for (int round = 0; round < nb_all - 1; ++round) {
       {
-        Timed tm(ctx, sketch ? "sketch_eig" : fp32 ? "eig_pairs32" : "eig_pairs");
-        HIP_OK(launch_eig_pairs(fp32, de, b_pair, np, n_pair, round, s));
+        Timed tm(ctx, sketch ? "sketch_eig" : "eig_pairs");
+        HIP_OK(launch_eig_pairs(de, b_pair, np, n_pair, round, s));
       }
       {
-        Timed tm(ctx, sketch ? "sketch_eig" : fp32 ? "eig_update32" : "eig_update");
-        HIP_OK(launch_eig_update(fp32, de, b_upd, np, n_upd, round, s));
+        Timed tm(ctx, sketch ? "sketch_eig" : "eig_update");
+        HIP_OK(launch_eig_update(de, b_upd, np, n_upd, round, s));
       }
     }
     HIP_OK(launch_eig_sweep_end(de, np, s));
@@ -612,7 +594,7 @@ void solve_eig(mps_ctx* ctx, bool fp32, EigDesc* de, const std::vector<EigDesc>&
     }
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-    std::fprintf(stderr, "eig %s np=%d rounds=%d sweeps=%d ms=%.2f n/bound:%s\n", fp32 ? "fp32" : "fp64", np,
+    std::fprintf(stderr, "eig np=%d rounds=%d sweeps=%d ms=%.2f n/bound:%s\n", np,
                  nb_all - 1, sweeps, ms, sizes.c_str());
   }
 }
@@ -824,20 +806,17 @@ struct LevelDescs {
   std::vector<int> jobs;
   std::vector<GemmDesc> gram, proj;
   std::vector<GramReduceDesc> red;
-  // exact solves: group 0 in FP64, group 1 in FP32 (+ FP64 Rayleigh quotients)
-  std::vector<EigDesc> eig[2];
-  std::vector<int> eig_jobs[2];
+  std::vector<EigDesc> eig;    // block-Jacobi solves (FP64)
+  std::vector<int> eig_jobs;
   std::vector<HtdDesc> htd;   // tridiagonal solves
   std::vector<EigDesc> eig_h;  // their trace / flag initialisation
   size_t o_htd = 0, o_eig_h = 0;
   std::vector<SelectDesc> sel;
-  std::vector<GemmDesc> ray;  // FP32 solve: W = G V in FP64
   std::vector<GatherDesc> gat;
   size_t o_gram, b_gram, o_proj, b_proj, o_red, b_red, o_sel, o_gat, b_gat;
-  size_t o_eig[2] = {0, 0}, b_pair[2] = {0, 0}, b_upd[2] = {0, 0};
-  int n_pair[2] = {0, 0}, n_upd[2] = {0, 0};
-  size_t o_ray = 0, b_ray = 0;
-  int n_gram, n_proj, n_red, n_gat, n_ray = 0;
+  size_t o_eig = 0, b_pair = 0, b_upd = 0;
+  int n_pair = 0, n_upd = 0;
+  int n_gram, n_proj, n_red, n_gat;
   int nb_max_all;
 };
 
@@ -861,25 +840,23 @@ void upload_level(DescBlob& B, LevelDescs& L) {
     L.b_red = B.add_vec(base);
     L.n_red = base.back();
   }
-  for (int g = 0; g < 2; ++g) {
-    if (L.eig[g].empty()) continue;
+  if (!L.eig.empty()) {
     std::vector<int> pb{0}, ub{0};
-    for (const auto& e : L.eig[g]) {
+    for (const auto& e : L.eig) {
       pb.push_back(pb.back() + e.nb_max / 2);
       ub.push_back(ub.back() + 2 * (e.nb_max / 2) * (e.nb_max / 2));
     }
-    L.o_eig[g] = B.add_vec(L.eig[g]);
-    L.b_pair[g] = B.add_vec(pb);
-    L.b_upd[g] = B.add_vec(ub);
-    L.n_pair[g] = pb.back();
-    L.n_upd[g] = ub.back();
+    L.o_eig = B.add_vec(L.eig);
+    L.b_pair = B.add_vec(pb);
+    L.b_upd = B.add_vec(ub);
+    L.n_pair = pb.back();
+    L.n_upd = ub.back();
   }
   if (!L.htd.empty()) {
     L.o_htd = B.add_vec(L.htd);
     L.o_eig_h = B.add_vec(L.eig_h);
   }
   L.o_sel = B.add_vec(L.sel);
-  if (!L.ray.empty()) L.n_ray = upload_gemms(B, L.ray, L.o_ray, L.b_ray);
   std::vector<int> gb{0};
   for (const auto& g : L.gat) gb.push_back(gb.back() + g.tiles);
   L.o_gat = B.add_vec(L.gat);
@@ -906,35 +883,24 @@ void launch_level(mps_ctx* ctx, DescBlob& B, LevelDescs& L, int* flags, int nfla
     HIP_OK(launch_gram_reduce(B.at<GramReduceDesc>(L.o_red), B.at<int>(L.b_red), (int)L.red.size(), L.n_red, s));
   }
   int ldmax = 0;
-  for (int g = 0; g < 2; ++g)
-    for (const auto& e : L.eig[g]) ldmax = std::max(ldmax, e.ld);
+  for (const auto& e : L.eig) ldmax = std::max(ldmax, e.ld);
   for (const auto& e : L.eig_h) ldmax = std::max(ldmax, e.ld);
   if (!L.eig_h.empty()) {
     Timed tm(ctx, "eig_init");
-    HIP_OK(launch_eig_init(false, B.at<EigDesc>(L.o_eig_h), (int)L.eig_h.size(), ldmax, s));
+    HIP_OK(launch_eig_init(B.at<EigDesc>(L.o_eig_h), (int)L.eig_h.size(), ldmax, s));
   }
-  for (int g = 0; g < 2; ++g) {
-    if (L.eig[g].empty()) continue;
+  if (!L.eig.empty()) {
     Timed tm(ctx, "eig_init");
-    HIP_OK(launch_eig_init(g == 1, B.at<EigDesc>(L.o_eig[g]), (int)L.eig[g].size(), ldmax, s));
+    HIP_OK(launch_eig_init(B.at<EigDesc>(L.o_eig), (int)L.eig.size(), ldmax, s));
   }
   between();
-  for (int g = 0; g < 2; ++g) {
-    if (L.eig[g].empty()) continue;
+  if (!L.eig.empty()) {
     std::vector<int> at;
-    for (int q : L.eig_jobs[g]) at.push_back(4 * q);
-    solve_eig(ctx, g == 1, B.at<EigDesc>(L.o_eig[g]), L.eig[g], B.at<int>(L.b_pair[g]), B.at<int>(L.b_upd[g]),
-              L.n_pair[g], L.n_upd[g], flags, nflag_ints, at);
+    for (int q : L.eig_jobs) at.push_back(4 * q);
+    solve_eig(ctx, B.at<EigDesc>(L.o_eig), L.eig, B.at<int>(L.b_pair), B.at<int>(L.b_upd), L.n_pair, L.n_upd,
+              flags, nflag_ints, at);
   }
   if (!L.htd.empty()) solve_htd(ctx, B.at<HtdDesc>(L.o_htd), L.htd);
-  if (!L.eig[1].empty()) {
-    Timed tm(ctx, "eig_rayleigh");
-    EigDesc* de32 = B.at<EigDesc>(L.o_eig[1]);
-    const int n32 = (int)L.eig[1].size();
-    HIP_OK(launch_eig_to64(de32, n32, ldmax, s));
-    HIP_OK(launch_gemm_nn(Prec::FP64, B.at<GemmDesc>(L.o_ray), B.at<int>(L.b_ray), n32, L.n_ray, s));
-    HIP_OK(launch_eig_rayleigh(de32, n32, ldmax, s));
-  }
   {
     Timed tm(ctx, "select");
     HIP_OK(launch_select(B.at<SelectDesc>(L.o_sel), np, s));
@@ -953,7 +919,6 @@ void launch_level(mps_ctx* ctx, DescBlob& B, LevelDescs& L, int* flags, int nfla
 // list, which also indexes its convergence flags) appended to L; skr is the
 // split's learned-sketch run or null.  Advances r's buffer parity.
 void add_level(mps_ctx* ctx, LevelDescs& L, JobRun& r, int i, int t, const SkRun* skr) {
-  const bool mixed = ctx->prec != Prec::FP64;  // FP32 Jacobi + FP64 Rayleigh quotients
   L.jobs.push_back(i);
   const Level& lv = r.lv[t];
   const int m = lv.m;
@@ -993,31 +958,24 @@ void add_level(mps_ctx* ctx, LevelDescs& L, JobRun& r, int i, int t, const SkRun
     }
   }
   {
-    // The FP32 solve resolves eigenvalues of G only to ~1e-7 of its trace;
-    // it serves large splits whose rank bound exceeds chi_max, where the
-    // cut lies far above that level.  Other splits use the FP64 solve.
     const bool uh = level_htd(ctx, lv);
-    const bool e32 =
-        !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
     EigDesc e{};
     e.G = r.G;
     e.V = r.V;
     e.J = r.J;
-    e.Gw = e32 ? r.Gw : (void*)r.G;
-    e.Vw = e32 ? r.Vw : (void*)r.V;
-    e.W = r.W;
-    e.lam = r.lamR;
+    e.Gw = r.G;
+    e.Vw = r.V;
     e.pair_rot = r.pair_rot;
     e.flags = r.flags;
     e.scale = r.scale;
-    e.work = ctx->timing ? ctx->d_work + (e32 ? 2 : 0) : nullptr;
+    e.work = ctx->timing ? ctx->d_work : nullptr;
     e.n = n2c;
     e.ld = r.ld;
     int nb = ceil_div(2 * lv.c_bound, JB);
     nb = std::max(nb, 2);
     nb += nb & 1;
     e.nb_max = nb;
-    e.tol = e32 ? 2e-6 : 1e-13;
+    e.tol = 1e-13;
     if (uh) {
       L.eig_h.push_back(e);
       HtdDesc h = r.hw;
@@ -1030,34 +988,16 @@ void add_level(mps_ctx* ctx, LevelDescs& L, JobRun& r, int i, int t, const SkRun
       L.htd.push_back(h);
     } else {
       L.nb_max_all = std::max(L.nb_max_all, nb);
-      L.eig[e32].push_back(e);
-      L.eig_jobs[e32].push_back(i);
-    }
-    if (e32) {
-      GemmDesc g{};
-      g.A = r.G;
-      g.B = r.V;
-      g.C = r.W;
-      g.M = n2c;
-      g.N = n2c;
-      g.K = n2c;
-      g.lda = g.ldb = g.ldc = fixed(r.ld);
-      g.batch = 1;
-      g.tm = g.tn = ceil_div(2 * lv.c_bound, 64);
-      g.ksplit = 1;
-      g.alpha = 1.0;
-      if (skr) g.skip = skr->use;
-      L.ray.push_back(g);
+      L.eig.push_back(e);
+      L.eig_jobs.push_back(i);
     }
   }
   int* r_out = ctx->d_chi + (r.a + m - 1);
   {
     const bool uh = level_htd(ctx, lv);
-    const bool e32 =
-        !uh && mixed && 2 * lv.c_bound >= 512 && ctx->chi_max < std::min(lv.rows, 2 * lv.c_bound);
     SelectDesc sd{};
     sd.G = r.G;
-    sd.lam_in = uh ? r.hw.lam : e32 ? r.lamR : nullptr;
+    sd.lam_in = uh ? r.hw.lam : nullptr;
     sd.ldg = r.ld;
     sd.n = n2c;
     sd.rows = lv.rows;
@@ -1245,9 +1185,9 @@ void launch_sketch(mps_ctx* ctx, DescBlob& B, SkLevel& S, const std::vector<SkRu
     }
     nn(0);
     HIP_OK(launch_gram(Prec::FP64, B.at<GemmDesc>(S.o[1]), B.at<int>(S.b[1]), ns, S.n[1], s));
-    HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_ea), ns, ldy, s));
+    HIP_OK(launch_eig_init(B.at<EigDesc>(S.o_ea), ns, ldy, s));
   }
-  solve_eig(ctx, false, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+  solve_eig(ctx, B.at<EigDesc>(S.o_ea), S.ea, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
             skflags_all, 12 * nsk, S.flag_a, true);
   {
     Timed tm(ctx, "sketch");
@@ -1261,9 +1201,9 @@ void launch_sketch(mps_ctx* ctx, DescBlob& B, SkLevel& S, const std::vector<SkRu
     }
     nn(3);
     cn(4);
-    HIP_OK(launch_eig_init(false, B.at<EigDesc>(S.o_eb), ns, ldy, s));
+    HIP_OK(launch_eig_init(B.at<EigDesc>(S.o_eb), ns, ldy, s));
   }
-  solve_eig(ctx, false, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
+  solve_eig(ctx, B.at<EigDesc>(S.o_eb), S.eb, B.at<int>(S.bp_a), B.at<int>(S.bu_a), S.np_a, S.nu_a,
             skflags_all, 12 * nsk, S.flag_b, true);
   {
     Timed tm(ctx, "sketch");
@@ -1278,7 +1218,6 @@ void launch_sketch(mps_ctx* ctx, DescBlob& B, SkLevel& S, const std::vector<SkRu
 void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDesc>& sites1q, int nsub) {
   hipStream_t s = ctx->stream;
   const Prec P = ctx->prec;
-  const bool mixed = P != Prec::FP64;  // FP32 Jacobi + FP64 Rayleigh quotients
   std::vector<JobRun> runs(jobs.size());
   size_t bytes = 0;
   for (size_t i = 0; i < jobs.size(); ++i) {
@@ -1570,15 +1509,13 @@ void run_group(mps_ctx* ctx, std::vector<Job>& jobs, const std::vector<Site1QDes
       off += 4 * (r.k - 1);
     }
   }
-  unsigned long long eig_work[4] = {0, 0, 0, 0};
+  unsigned long long eig_work[2] = {0, 0};
   if (ctx->timing)
     HIP_OK(hipMemcpyAsync(eig_work, ctx->d_work, sizeof(eig_work), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (ctx->timing) {
     collect_timing(ctx);
-    account_flops(ctx, runs, mixed, (double)eig_work[0], (double)eig_work[1]);
-    ctx->timer.flop[ctx->timer.cls_of("eig_update32")] += 8.0 * (double)eig_work[2];
-    ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
+    account_flops(ctx, runs, (double)eig_work[0], (double)eig_work[1]);
   }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
   {
@@ -1753,7 +1690,6 @@ void wave_round(mps_ctx* ctx, std::vector<WaveTask>& T, const std::vector<int>& 
                 const std::vector<int>& starting, const std::vector<int>& active) {
   hipStream_t s = ctx->stream;
   const Prec P = ctx->prec;
-  const bool mixed = P != Prec::FP64;
   // workspaces of the starting clusters
   for (int i : starting) {
     WaveTask& w = T[i];
@@ -1971,16 +1907,14 @@ void wave_round(mps_ctx* ctx, std::vector<WaveTask>& T, const std::vector<int>& 
       off += 4 * (r.k - 1);
     }
   }
-  unsigned long long eig_work[4] = {0, 0, 0, 0};
+  unsigned long long eig_work[2] = {0, 0};
   if (ctx->timing) HIP_OK(hipMemcpyAsync(eig_work, ctx->d_work, sizeof(eig_work), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (ctx->timing) {
     collect_timing(ctx);
-    for (int i : active) account_level(ctx, T[i].run, T[i].level, mixed);
+    for (int i : active) account_level(ctx, T[i].run, T[i].level);
     ctx->timer.flop[ctx->timer.cls_of("eig_update")] += 8.0 * (double)eig_work[0];
     ctx->timer.flop[ctx->timer.cls_of("eig_pairs")] += (double)eig_work[1];
-    ctx->timer.flop[ctx->timer.cls_of("eig_update32")] += 8.0 * (double)eig_work[2];
-    ctx->timer.flop[ctx->timer.cls_of("eig_pairs32")] += (double)eig_work[3];
   }
   for (size_t q = 0; q < nrec; q += 4) ctx->stats.discarded_weight += rec[q + 2];
   {
@@ -3354,8 +3288,12 @@ mps_status mps_sketch_range(mps_handle ctx, int n, int s, const double* G, const
 
 mps_status mps_dmrg_step(mps_handle ctx, const mps_gate* gates, const int* layer_len, int nl, int chi_max_dmrg,
                          int q_max, int sweeps, double* f_fit) {
-  if (!ctx || nl < 0 || (nl > 0 && (!gates || !layer_len)) || chi_max_dmrg < 1 || q_max < 2 || sweeps < 0)
+  if (!ctx) return MPS_EINVAL;
+  if (nl < 0 || (nl > 0 && (!gates || !layer_len)) || chi_max_dmrg < 1 || q_max < 1 || sweeps < 0) {
+    ctx->err = "mps_dmrg_step: invalid argument (nl >= 0, gates and layer_len, chi_max_dmrg >= 1, q_max >= 1, "
+               "sweeps >= 0)";
     return MPS_EINVAL;
+  }
   return guarded(ctx, [&]() -> mps_status {
     if (ctx->prec != Prec::FP64) {
       ctx->err = "mps_dmrg_step: needs an FP64 handle";

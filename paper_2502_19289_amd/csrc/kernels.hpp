@@ -69,11 +69,9 @@ constexpr int JP = 2 * JB;    // subproblem / update-tile size
 struct EigDesc {
   double2* G;       // Hermitian Gram matrix (FP64), ld x ld
   double2* V;       // eigenvectors (columns, FP64), ld x ld
-  void* Gw;         // working copy rotated to diagonal form (== G for FP64)
-  void* Vw;         // working eigenvectors (== V for FP64)
+  void* Gw;         // working copy rotated to diagonal form (G itself, or the sketch's)
+  void* Vw;         // working eigenvectors (V itself, or the sketch's)
   void* J;          // workspace: npair_max subproblem rotations of JP x JP
-  double2* W;       // FP32 solve: G V for the Rayleigh quotients
-  double* lam;      // FP32 solve: FP64 Rayleigh quotients (n entries)
   int* pair_rot;    // per pair slot: rotation applied this round
   int* flags;       // [0] converged, [1] rotated during the current sweep
   double* scale;    // trace of G (set by eig_init)
@@ -84,15 +82,10 @@ struct EigDesc {
   double tol;       // relative off-diagonal threshold
 };
 
-// fp32: the solve runs in FP32 on Gw/Vw (then eig_to64 + W = G V + rayleigh)
-hipError_t launch_eig_init(bool fp32, const EigDesc* d, int nprob, int ld_max, hipStream_t s);
-hipError_t launch_eig_pairs(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
-                            hipStream_t s);
-hipError_t launch_eig_update(bool fp32, const EigDesc* d, const int* d_base, int nprob, int blocks, int round,
-                             hipStream_t s);
+hipError_t launch_eig_init(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
+hipError_t launch_eig_pairs(const EigDesc* d, const int* d_base, int nprob, int blocks, int round, hipStream_t s);
+hipError_t launch_eig_update(const EigDesc* d, const int* d_base, int nprob, int blocks, int round, hipStream_t s);
 hipError_t launch_eig_sweep_end(const EigDesc* d, int nprob, hipStream_t s);
-hipError_t launch_eig_to64(const EigDesc* d, int nprob, int ld_max, hipStream_t s);
-hipError_t launch_eig_rayleigh(const EigDesc* d, int nprob, int n_max, hipStream_t s);
 
 // ------------------------------- tridiagonal divide-and-conquer eigen ----
 // Hermitian G = Q T Q^H (Householder, T real tridiagonal), T = Z diag(w) Z^T

@@ -14,7 +14,7 @@ import pytest
 from oracle import dmrg as DM
 from oracle import mps_tools as MT
 from oracle import statevector as SV
-from workloads import paper_random_structured
+from workloads import Circuit, Gate, paper_random_structured
 
 pytestmark = pytest.mark.gpu
 
@@ -66,3 +66,49 @@ def test_dmrg_rejects_mixed_precision_handles():
     with pytest.raises(P.CtebdError) as e:
         m.dmrg_step([[((0, 1), P.GATES["CNOT"])]], 4, 6, 1)
     assert e.value.status == -6
+
+
+def _run_both(c, l_max, chi_dmrg, q_max, sweeps):
+    m, fs = _gpu_dmrg(c, l_max, chi_dmrg, 1024, 1e-7, q_max, sweeps)
+    ref, recs = DM.run(c, l_max=l_max, chi_max_dmrg=chi_dmrg, chi_max_svd=1024, eps=1e-7, q_max=q_max,
+                       sweeps=sweeps)
+    return m, fs, ref, recs
+
+
+def test_dmrg_two_qubits():
+    """n = 2: one bond, the grouping is one group (or two single sites)."""
+    c = Circuit(2, [[Gate("H", (0,)), Gate("X4", (1,))], [Gate("CNOT", (0, 1))], [Gate("T", (0,))],
+                    [Gate("SQRTSWAP", (0, 1))]])
+    for q_max in (1, 2, 4):
+        m, fs, ref, recs = _run_both(c, 2, 4, q_max, 2)
+        assert np.abs(m.amplitudes() - SV.simulate(c)).max() < 1e-12
+        assert all(abs(f - 1) < 1e-12 for f in fs)
+        groups = [(0, 0), (1, 1)] if q_max == 1 else [(0, 1)]
+        assert all(r.groups == groups for r in recs)
+
+
+def test_dmrg_segment_without_entangling_gates():
+    """E(b) = 0 on every bond: chi~ = chi, the fit is exact whatever the
+    grouping, and the entangled input state is carried through unchanged
+    up to the one-qubit gates."""
+    base = paper_random_structured(8, 4, 2, d_max=2, seed=7, workload_id=96)
+    ones = [[Gate(g, (q,)) for q, g in zip(range(8), ["H", "T", "X", "Y", "Z", "P3PI4", "X4", "SQRTW"])]] * 3
+    c = Circuit(8, base.layers + ones)
+    m, fs = _gpu_dmrg(c, 4, 1 << 20, 1024, 1e-7, 6, 1)
+    assert np.abs(m.amplitudes() - SV.simulate(c)).max() < 1e-10
+    assert abs(fs[-1] - 1) < 1e-10
+
+
+@pytest.mark.parametrize("chi_dmrg,q_max", [(1, 6), (2, 3)])
+def test_dmrg_degenerate_caps_vs_oracle(chi_dmrg, q_max):
+    """chi~ = 1 (the fit is a product state across the group cuts) and
+    Q_max = 3 (groups of one to three qubits): each step's fit fidelity and
+    the final state against the oracle; the caps bind in one step each."""
+    c = paper_random_structured(8, 9, 2, d_max=1, seed=0, workload_id=96)
+    m, fs, ref, recs = _run_both(c, 3, chi_dmrg, q_max, 2)
+    for f, r in zip(fs, recs):
+        assert abs(f - r.f_dmrg) < 1e-10, (f, r.f_dmrg)
+    assert min(fs) < 0.99
+    assert abs(m.fidelity()[1] - ref.log_f) < 1e-9
+    assert m.bond_dims() == ref.bond_dims()
+    assert MT.infidelity(m.sites(), ref.B) < 1e-10

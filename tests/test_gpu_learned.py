@@ -200,8 +200,7 @@ def test_learned_sketch_matches_exact(trained_net):
 
 # device time of the exact eigen-solves (the range finders' own solves are
 # timed apart, as "sketch_eig")
-EIG_CLASSES = ("eig_init", "eig_pairs", "eig_update", "eig_pairs32", "eig_update32", "eig_rayleigh",
-               "trd_col", "trd_hemv", "trd_her2k", "trd_tail", "dc", "bt")
+EIG_CLASSES = ("eig_init", "eig_pairs", "eig_update", "trd_col", "trd_hemv", "trd_her2k", "trd_tail", "dc", "bt")
 
 
 def test_learned_sketch_gain_on_learned_workload():

@@ -170,8 +170,8 @@ def test_step_local_cluster_vs_oracle(prec, n, chi, a, k, seed, eig):
     assert infid(m.sites(), ref.B) < INF_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_full_size_cluster_vs_oracle(prec):
+@pytest.mark.parametrize("prec,eig", [("fp64", "auto"), ("fp32", "auto"), ("fp64", "jacobi"), ("fp32", "jacobi")])
+def test_full_size_cluster_vs_oracle(prec, eig):
     """Step-local parity at chi_max = 1024 (the benchmark's cap): a 22-qubit
     state evolved on the GPU (a brickwork of Haar 4-qubit clusters) until its
     middle bonds hold 1024 Schmidt values, so that its Lambda are the state's
@@ -180,7 +180,9 @@ def test_full_size_cluster_vs_oracle(prec):
     whose splits are the 2048 x 2048 Gram matrices of the timed workload's
     largest SVDs, solved by the tridiagonal route.  The oracle (LAPACK SVDs)
     applies the same cluster to the same exported state; the discarded weight,
-    the spectra and the state are compared."""
+    the spectra and the state are compared.  With block Jacobi forced both
+    runs take the FP64 Jacobi solve of the 2048-wide splits (whose cap
+    binds)."""
     n, chi, a, k = 22, 1024, 8, 4
     m0 = P.MPS(n, chi, 1e-10, k_max=4, precision="fp64")
     sd = 0
@@ -193,7 +195,7 @@ def test_full_size_cluster_vs_oracle(prec):
     B = m0.sites()
     lam = [m0.schmidt(b) for b in range(n - 1)]
     U = haar_unitary(2 ** k, seed=11)
-    m = P.MPS(n, chi, 1e-10, k_max=6, precision=prec, eig="auto")
+    m = P.MPS(n, chi, 1e-10, k_max=6, precision=prec, eig=eig)
     m.import_state(B, lam)
     m.apply_cluster(list(range(a, a + k)), U)
     ref = CT.MPS([b.copy() for b in B], [l.copy() for l in lam])

@@ -214,16 +214,12 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramReduceDesc* 
 // >= 2^-16 relative (hh, hm, mh, hl, lh, mm), accumulated in FP32.
 // Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br.  64x64 complex output per workgroup,
 // four wavefronts of 32x32 (2x2 blocks of v_mfma_f32_16x16x32_bf16), K slices
-// of 32 staged in LDS as three planes per real component.
+// of 32 staged in LDS as three planes per real component, k contiguous.
+// Staging: a thread takes 8 consecutive k of one row of A and of one column
+// of B, splits them in registers and writes each plane with one 16-byte LDS
+// store; the next slice's loads are issued (unconditionally, at clamped
+// addresses, masked when staged) before the current slice's products.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)x;
-  const float r1 = x - (float)h;
-  m = (__bf16)r1;
-  const float r2 = r1 - (float)m;
-  l = (__bf16)r2;
-}
 
 constexpr int XK = 32, XPAD = 40;  // K slice and padded LDS row (bf16 elements)
 
@@ -231,15 +227,18 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// acc += X * Y with the six-product split; X planes xa[3], Y planes yb[3]
-__device__ __forceinline__ f32x4 mac6(const bf16x8* xa, const bf16x8* yb, f32x4 acc) {
-  acc = mfma_bf16(xa[0], yb[0], acc);
-  acc = mfma_bf16(xa[0], yb[1], acc);
-  acc = mfma_bf16(xa[1], yb[0], acc);
-  acc = mfma_bf16(xa[0], yb[2], acc);
-  acc = mfma_bf16(xa[2], yb[0], acc);
-  acc = mfma_bf16(xa[1], yb[1], acc);
-  return acc;
+// the three planes of 8 values (v masked to zero where !in)
+__device__ __forceinline__ void split8(const float* v, bf16x8& h, bf16x8& m, bf16x8& l) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 hh = (__bf16)v[i];
+    const float r1 = v[i] - (float)hh;
+    const __bf16 mm = (__bf16)r1;
+    const float r2 = r1 - (float)mm;
+    h[i] = hh;
+    m[i] = mm;
+    l[i] = (__bf16)r2;
+  }
 }
 
 __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __restrict__ descs,
@@ -266,63 +265,109 @@ __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __res
   float2* C = (float2*)d.C + (int64_t)b * d.sC;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  f32x4 arr[2][2], ari[2][2], aim[2][2];  // Ar Br, Ai Bi, Ar Bi + Ai Br
+  // Ar Br, Ai Bi, Ar Bi, Ai Br: four independent accumulator chains per block
+  f32x4 arr[2][2], ari[2][2], aib[2][2], aia[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       arr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
       ari[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      aim[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      aib[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      aia[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 
+  // staging roles: A row ra, k offset ka; B column nb, k offset kb
+  const int ra = tid >> 2, ka = (tid & 3) * 8;
+  const int nb = tid & 63, kb = (tid >> 6) * 8;
+  const bool rowok = m0 + ra < M, colok = n0 + nb < N;
+  const float2* Arow = A + (int64_t)min(m0 + ra, M - 1) * lda;
+  const float2* Bcol = Bm + min(n0 + nb, N - 1);
+  float2 va[8], vb[8];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) va[i] = Arow[min(k0 + ka + i, K - 1)];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) vb[i] = Bcol[(int64_t)min(k0 + kb + i, K - 1) * ldb];
+  };
+  auto stage = [&](int k0) __attribute__((always_inline)) {
+    float re[8], im[8];
+    bf16x8 h, m, l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool in = rowok && k0 + ka + i < K;
+      re[i] = in ? va[i].x : 0.f;
+      im[i] = in ? va[i].y : 0.f;
+    }
+    split8(re, h, m, l);
+    *(bf16x8*)&As[0][0][ra][ka] = h;
+    *(bf16x8*)&As[1][0][ra][ka] = m;
+    *(bf16x8*)&As[2][0][ra][ka] = l;
+    split8(im, h, m, l);
+    *(bf16x8*)&As[0][1][ra][ka] = h;
+    *(bf16x8*)&As[1][1][ra][ka] = m;
+    *(bf16x8*)&As[2][1][ra][ka] = l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool in = colok && k0 + kb + i < K;
+      re[i] = in ? vb[i].x : 0.f;
+      im[i] = in ? vb[i].y : 0.f;
+    }
+    split8(re, h, m, l);
+    *(bf16x8*)&Bs[0][0][nb][kb] = h;
+    *(bf16x8*)&Bs[1][0][nb][kb] = m;
+    *(bf16x8*)&Bs[2][0][nb][kb] = l;
+    split8(im, h, m, l);
+    *(bf16x8*)&Bs[0][1][nb][kb] = h;
+    *(bf16x8*)&Bs[1][1][nb][kb] = m;
+    *(bf16x8*)&Bs[2][1][nb][kb] = l;
+  };
+
+  if (K > 0) {
+    fetch(0);
+    stage(0);
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4), cl = lane & 15;
   for (int k0 = 0; k0 < K; k0 += XK) {
-    {  // A: row r = tid/4, k = (tid%4)*8 .. +7
-      const int r = tid >> 2, k8 = (tid & 3) * 8;
-      const int gm = m0 + r;
+    const bool more = k0 + XK < K;
+    if (more) fetch(k0 + XK);
+    bf16x8 br[2][3], bi[2][3];  // the B planes of both column blocks, read once
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gk = k0 + k8 + i;
-        float2 v = make_float2(0.f, 0.f);
-        if (gm < M && gk < K) v = A[(int64_t)gm * lda + gk];
-        split3(v.x, As[0][0][r][k8 + i], As[1][0][r][k8 + i], As[2][0][r][k8 + i]);
-        split3(v.y, As[0][1][r][k8 + i], As[1][1][r][k8 + i], As[2][1][r][k8 + i]);
-      }
-    }
-    {  // B: row k = tid/8, columns (tid%8)*8 .. +7, stored transposed
-      const int kk = tid >> 3, n8 = (tid & 7) * 8;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gn = n0 + n8 + i;
-        float2 v = make_float2(0.f, 0.f);
-        if (gk < K && gn < N) v = Bm[(int64_t)gk * ldb + gn];
-        split3(v.x, Bs[0][0][n8 + i][kk], Bs[1][0][n8 + i][kk], Bs[2][0][n8 + i][kk]);
-        split3(v.y, Bs[0][1][n8 + i][kk], Bs[1][1][n8 + i][kk], Bs[2][1][n8 + i][kk]);
-      }
-    }
-    __syncthreads();
-    const int kq = 8 * (lane >> 4), cl = lane & 15;
-    bf16x8 ar[2][3], ai[2][3], br[2][3], bi[2][3];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int pl = 0; pl < 3; ++pl) {
-        ar[x][pl] = *(const bf16x8*)&As[pl][0][wm * 32 + x * 16 + cl][kq];
-        ai[x][pl] = *(const bf16x8*)&As[pl][1][wm * 32 + x * 16 + cl][kq];
-        br[x][pl] = *(const bf16x8*)&Bs[pl][0][wn * 32 + x * 16 + cl][kq];
-        bi[x][pl] = *(const bf16x8*)&Bs[pl][1][wn * 32 + x * 16 + cl][kq];
+        br[j][pl] = *(const bf16x8*)&Bs[pl][0][wn * 32 + j * 16 + cl][kq];
+        bi[j][pl] = *(const bf16x8*)&Bs[pl][1][wn * 32 + j * 16 + cl][kq];
       }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
+      bf16x8 ar[3], ai[3];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        arr[i][j] = mac6(ar[i], br[j], arr[i][j]);
-        ari[i][j] = mac6(ai[i], bi[j], ari[i][j]);
-        aim[i][j] = mac6(ar[i], bi[j], aim[i][j]);
-        aim[i][j] = mac6(ai[i], br[j], aim[i][j]);
+      for (int pl = 0; pl < 3; ++pl) {
+        ar[pl] = *(const bf16x8*)&As[pl][0][wm * 32 + i * 16 + cl][kq];
+        ai[pl] = *(const bf16x8*)&As[pl][1][wm * 32 + i * 16 + cl][kq];
       }
+      // the six plane products (hh, hm, mh, hl, lh, mm), each across the
+      // eight chains of this row block before the next
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int pa = q == 2 ? 1 : q == 4 ? 2 : q == 5 ? 1 : 0;
+        const int pb = q == 1 ? 1 : q == 3 ? 2 : q == 5 ? 1 : 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          arr[i][j] = mfma_bf16(ar[pa], br[j][pb], arr[i][j]);
+          ari[i][j] = mfma_bf16(ai[pa], bi[j][pb], ari[i][j]);
+          aib[i][j] = mfma_bf16(ar[pa], bi[j][pb], aib[i][j]);
+          aia[i][j] = mfma_bf16(ai[pa], br[j][pb], aia[i][j]);
+        }
+      }
+    }
     __syncthreads();
+    if (more) {
+      stage(k0 + XK);
+      __syncthreads();
+    }
   }
   const float alpha = (float)d.alpha;
 #pragma unroll
@@ -335,7 +380,7 @@ __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __res
         const int gn = n0 + wn * 32 + bj * 16 + (lane & 15);
         if (gm < M && gn < N)
           C[(int64_t)gm * ldc + gn] =
-              make_float2((arr[bi2][bj][r] - ari[bi2][bj][r]) * alpha, aim[bi2][bj][r] * alpha);
+              make_float2((arr[bi2][bj][r] - ari[bi2][bj][r]) * alpha, (aib[bi2][bj][r] + aia[bi2][bj][r]) * alpha);
       }
 }
 

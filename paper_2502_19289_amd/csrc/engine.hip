@@ -401,7 +401,7 @@ void assign_job(mps_ctx* ctx, JobRun& j, DeviceArena& A) {
 // Algorithmic flops per kernel class, once the sizes are final on the host:
 // merge and unitary products as written (account_merge), and per split level
 // (account_level, after that level's truncation is back) the Hermitian half of
-// the Gram matrix, the projection and the FP64 Rayleigh product.
+// the Gram matrix and the projection.
 void account_merge(mps_ctx* ctx, const JobRun& r) {
   double merge = 0;
   for (int j = 1; j < r.k; ++j) {

@@ -253,3 +253,47 @@ def test_errors_and_edges():
     m.apply_cluster([3, 5], P.GATES["CNOT"])
     sv = SV.apply_gate(exp, 6, P.GATES["CNOT"], [3, 5])
     assert np.abs(m.amplitudes() - sv).max() < 1e-14
+
+
+def test_two_qubit_chain_exact():
+    """n = 2, one bond: clusters of the whole chain and one-qubit gates,
+    nothing truncated, against the statevector."""
+    for prec in ("fp64", "fp32"):
+        m = P.MPS(2, 4, 1e-12, k_max=2, precision=prec)
+        sv = np.zeros(4, complex)
+        sv[0] = 1.0
+        for s in range(4):
+            U = haar_unitary(4, seed=900 + s)
+            m.apply_cluster([0, 1], U)
+            sv = SV.apply_gate(sv, 2, U, [0, 1])
+            V = haar_unitary(2, seed=950 + s)
+            m.run_layer([((1,), V)])
+            m.flush()
+            sv = SV.apply_gate(sv, 2, V, [1])
+        assert np.abs(m.amplitudes() - sv).max() < (1e-13 if prec == "fp64" else 5e-6)
+        assert abs(m.fidelity()[0] - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("chi,eps", [(1, 1e-12), (2, 1e-12), (1024, 0.3)])
+def test_extreme_caps_vs_oracle(prec, chi, eps):
+    """chi_max = 1 (every split keeps one Schmidt value: a product state),
+    chi_max = 2, and a cutoff of 0.3 on the normalised spectrum: a brickwork
+    of Haar 4-qubit clusters from |0...0> (generic spectra, so the kept
+    values are unambiguous) against the oracle with the same caps."""
+    n = 8
+    m = P.MPS(n, chi, eps, k_max=4, precision=prec)
+    ref = CT.product_state(n)
+    sd = 0
+    for layer in range(4):
+        for q in range(0 if layer % 2 == 0 else 2, n - 3, 4):
+            U = haar_unitary(16, seed=500 + sd)
+            m.apply_cluster(list(range(q, q + 4)), U)
+            CT.apply_cluster(ref, q, 4, U, chi, eps)
+            sd += 1
+    assert m.bond_dims() == ref.bond_dims()
+    assert ref.log_f < -1.0  # the caps bind
+    assert abs(m.fidelity()[1] - ref.log_f) < (1e-10 if prec == "fp64" else 1e-6)
+    assert infid(m.sites(), ref.B) < INF_TOL[prec]
+    for b in range(n - 1):
+        assert np.abs(m.schmidt(b) - ref.lam[b]).max() < (1e-9 if prec == "fp64" else 1e-5)

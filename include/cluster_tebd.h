@@ -225,7 +225,10 @@ mps_status mps_load(const char* path, mps_handle* out);
  * fidelity sum adds log f_fit and the log of the splits' kept weights.  The
  * evolved state's bond dimensions must stay <= 1024.  chi_max_dmrg >= 1,
  * q_max >= 1 (1: every group a single qubit), sweeps >= 0 (0: the
- * compression alone), else MPS_EINVAL.  Synchronises. */
+ * compression alone), else MPS_EINVAL.  The device memory that holds the
+ * evolved segment (site tensors at bond cap 2^ceil(log2 chi), chi the
+ * largest bound 4^E(b) chi_b) stays with the handle for the next DMRG step
+ * and is released by mps_destroy.  Synchronises. */
 mps_status mps_dmrg_step(mps_handle h, const mps_gate* gates, const int* layer_len, int nl, int chi_max_dmrg,
                          int q_max, int sweeps, double* f_fit);
 

@@ -764,25 +764,41 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd_all, const std::vector<HtdDesc>& 
   for (size_t q = 0; q < host_all.size(); ++q)
     if (host_all[q].skip) HIP_OK(hipMemcpyAsync(&skip[q], host_all[q].skip, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  std::vector<HtdDesc> host;
-  std::vector<const HtdDesc*> dev;
+  // The problems solved here, in order, with no skip flag: every kernel of
+  // the solver would otherwise read the flag from memory before its data
+  // (one more dependent round trip per launch), and the host has already
+  // decided.  When any problem carries a flag the descriptors are copied to
+  // a device array of the handle (which also makes the chunks consecutive);
+  // flagless descriptors (single solves, DMRG, the no-allocation entry
+  // point) are used where they are.
+  bool flagged = false;
+  for (const auto& h : host_all) flagged = flagged || h.skip != nullptr;
+  std::vector<HtdDesc>& host = ctx->htd_host;
+  host.clear();
   for (size_t q = 0; q < host_all.size(); ++q)
     if (!skip[q]) {
       host.push_back(host_all[q]);
-      dev.push_back(dd_all + q);
+      host.back().skip = nullptr;
     }
   const int np = (int)host.size();
+  if (np == 0) return;
+  const HtdDesc* base = dd_all;
+  if (flagged) {
+    if ((size_t)np > ctx->htd_dev_cap) {  // the stream is idle here (synchronised above)
+      if (ctx->htd_dev) HIP_OK(hipFree(ctx->htd_dev));
+      ctx->htd_dev = nullptr;
+      ctx->htd_dev_cap = 0;
+      HIP_OK(hipMalloc(&ctx->htd_dev, (size_t)np * 2 * sizeof(HtdDesc)));
+      ctx->htd_dev_cap = (size_t)np * 2;
+    }
+    HIP_OK(hipMemcpyAsync(ctx->htd_dev, host.data(), (size_t)np * sizeof(HtdDesc), hipMemcpyHostToDevice, s));
+    base = ctx->htd_dev;
+  }
   for (int c0 = 0; c0 < np; c0 += HTD_GROUP) {
     HtdSizes sz{};
     HtdArgs ha{};
     sz.np = std::min(HTD_GROUP, np - c0);
-    // the chunk's descriptors must be consecutive in device memory
-    const HtdDesc* dd = dev[c0];
-    for (int q = 1; q < sz.np; ++q)
-      if (dev[c0 + q] != dd + q) {
-        sz.np = q;
-        break;
-      }
+    const HtdDesc* dd = base + c0;
     for (int q = 0; q < sz.np; ++q) {
       const Dim& dm = host[c0 + q].n;
       const ptrdiff_t at = dm.ptr ? dm.ptr - ctx->d_chi : -1;
@@ -793,12 +809,11 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd_all, const std::vector<HtdDesc>& 
       sz.nc[q] = std::min(n, host[c0 + q].rcap);
       const HtdDesc& h = host[c0 + q];
       ha.n[q] = n;
-      ha.pr[q] = HtdProb{h.A, (char*)h.d, h.skip, n, h.ld};
+      ha.pr[q] = HtdProb{h.A, (char*)h.d, nullptr, n, h.ld};
       if (!htd_view_matches(ha, q, h)) fail(ctx, MPS_EINVAL, "tridiagonal solve: workspace layout");
     }
     ha.np = sz.np;
     solve_htd_chunk(ctx, dd, sz, ha);
-    c0 -= HTD_GROUP - sz.np;  // a chunk cut short by a skipped problem resumes after it
   }
 }
 
@@ -2149,6 +2164,7 @@ void destroy_ctx(mps_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   destroy_ctx(ctx->dmrg_scratch);
   ctx->dmrg_scratch = nullptr;
+  if (ctx->htd_dev) (void)hipFree(ctx->htd_dev);
   ctx->arena.release();
   ctx->pool.release();
   ctx->blob.release();

@@ -145,6 +145,12 @@ struct mps_ctx {
   // DMRG: the handle that holds each step's evolved segment, kept between
   // steps (same stream; owned, destroyed with this handle; never cloned)
   mps_ctx* dmrg_scratch = nullptr;
+  // the tridiagonal solver's descriptors of the problems it actually solves
+  // (host copy kept until the next solve, which first synchronises; device
+  // copy read by the kernels)
+  std::vector<ctebd::HtdDesc> htd_host;
+  ctebd::HtdDesc* htd_dev = nullptr;
+  size_t htd_dev_cap = 0;
   uint64_t sketch_seed = 0x9E3779B97F4A7C15ull;
   uint32_t sketch_stream = 0;
 };

@@ -808,7 +808,6 @@ void solve_htd(mps_ctx* ctx, const HtdDesc* dd_all, const std::vector<HtdDesc>& 
       sz.n[q] = n;
       sz.nc[q] = std::min(n, host[c0 + q].rcap);
       const HtdDesc& h = host[c0 + q];
-      ha.n[q] = n;
       ha.pr[q] = HtdProb{h.A, (char*)h.d, nullptr, n, h.ld};
       if (!htd_view_matches(ha, q, h)) fail(ctx, MPS_EINVAL, "tridiagonal solve: workspace layout");
     }

@@ -211,7 +211,8 @@ __device__ __forceinline__ void householder(double2 alpha, double smax, double s
 // load reads whole panel rows.  The column entry of row r is the sum of the
 // lanes' terms (through LDS); the dots V^H x, W^H x are per-lane sums over the
 // rows, added over the four wavefronts in LDS.
-__global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
+template <int N>
+__global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int k) {
   constexpr int RPW = KC_ROWS / 4;  // rows per wavefront
   __shared__ double2 dsum[4][2 * HTD_NB];
   __shared__ double2 kv[2 * HTD_NB];  // row k: w_k (V lanes), v_k (W lanes)
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
   const Loc lc{(int)blockIdx.y, (int)blockIdx.x};
   const int n = sz.pr[lc.p].n;
   if (lc.b >= htd_col_blocks(n, k)) return;
-  const HtdDesc d = htd_view(sz, lc.p);
+  const HtdDesc d = htd_view(sz.pr[lc.p]);
   if (skipped(d)) return;
   const int m = n - k - 1, ld = d.ld, tid = threadIdx.x;
   const int j = k & (HTD_NB - 1);
@@ -407,7 +408,8 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdArgs sz, int k) {
 // load instruction reads four row segments of 256 bytes, a row's sum is a
 // 16-lane DPP reduction, a column's sum runs over 4 rows in registers, then
 // through LDS.
-__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) {
+template <int N>
+__global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int k) {
   __shared__ double2 hsum[8][HTD_NB];    // panel: record sums by group
   __shared__ double2 cpart[16][64 + 1];  // tile: column sums of (wavefront, s)
   __shared__ double2 wred[4];
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdArgs sz, int k) 
   const int n = sz.pr[p].n;
   const int T = htd_hemv_rows(n, k), NT = T * (T + 1) / 2;
   if (t >= NT + 2 * T) return;
-  const HtdDesc d = htd_view(sz, p);
+  const HtdDesc d = htd_view(sz.pr[p]);
   if (skipped(d)) return;
   const bool panel = t >= NT;
   int I = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);  // t = I (I + 1) / 2 + J
@@ -1885,10 +1887,29 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
 
 }  // namespace
 
-hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  launch(trd_hemv_kernel, dim3(blocks, a.np), dim3(256), 0, s, a, k);
+// The records of a's problems in the smallest argument block that holds them.
+template <template <int> class K, int N>
+hipError_t launch_probs(const HtdArgs& a, int k, int blocks, hipStream_t s) {
+  if (a.np > N) return launch_probs<K, (N < HTD_GROUP ? 2 * N : N)>(a, k, blocks, s);
+  HtdProbs<N> b;
+  for (int q = 0; q < a.np; ++q) b.pr[q] = a.pr[q];
+  for (int q = a.np; q < N; ++q) b.pr[q] = HtdProb{};
+  launch(K<N>::kernel, dim3(blocks, a.np), dim3(256), 0, s, b, k);
   return hipGetLastError();
+}
+template <int N>
+struct HemvK {
+  static constexpr auto kernel = trd_hemv_kernel<N>;
+};
+template <int N>
+struct ColK {
+  static constexpr auto kernel = trd_col_kernel<N>;
+};
+
+hipError_t launch_trd_hemv(const HtdArgs& a, int k, int blocks, hipStream_t s) {
+  if (blocks <= 0 || a.np <= 0) return hipSuccess;
+  if (a.np > HTD_GROUP) return hipErrorInvalidValue;
+  return launch_probs<HemvK, 1>(a, k, blocks, s);
 }
 hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) {
   if (sz.np <= 0) return hipSuccess;
@@ -1896,9 +1917,9 @@ hipError_t launch_trd_tail(const HtdDesc* d, const HtdSizes& sz, hipStream_t s) 
   return hipGetLastError();
 }
 hipError_t launch_trd_col(const HtdArgs& a, int k, int blocks, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  launch(trd_col_kernel, dim3(blocks, a.np), dim3(256), 0, s, a, k);
-  return hipGetLastError();
+  if (blocks <= 0 || a.np <= 0) return hipSuccess;
+  if (a.np > HTD_GROUP) return hipErrorInvalidValue;
+  return launch_probs<ColK, 1>(a, k, blocks, s);
 }
 hipError_t launch_trd_her2k(const HtdDesc* d, const HtdSizes& sz, int p0, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;

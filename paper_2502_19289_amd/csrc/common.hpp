@@ -6,6 +6,64 @@
 
 namespace ctebd {
 
+// Loads and stores through pointers taken from descriptors in device memory.
+// The compiler cannot tell that such a pointer addresses global memory, so a
+// plain access becomes a flat one, which also counts against the counter of
+// outstanding LDS and scalar operations: every wait for an LDS read then waits
+// for the flat loads in flight too (a prefetch issued before a slice's
+// products would be waited for at its first LDS read).  These helpers access
+// the same address as global memory (every descriptor pointer is a device
+// allocation).
+#define CTEBD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+struct gl_repr {
+  using type = T;
+};
+template <>
+struct gl_repr<float2> {
+  using type = float __attribute__((ext_vector_type(2)));
+};
+template <>
+struct gl_repr<double2> {
+  using type = double __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  using R = typename gl_repr<T>::type;
+  const R v = *(const CTEBD_GLOBAL R*)(const void*)p;
+  if constexpr (sizeof(R) == sizeof(T) && !__is_same(R, T)) {
+    T r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+  } else {
+    return v;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T x) {
+  using R = typename gl_repr<T>::type;
+  if constexpr (!__is_same(R, T)) {
+    R v;
+    v.x = x.x;
+    v.y = x.y;
+    *(CTEBD_GLOBAL R*)(void*)p = v;
+  } else {
+    *(CTEBD_GLOBAL T*)(void*)p = x;
+  }
+}
+
+// The same pointer typed as global memory, for kernels that index plain
+// scalar arrays of a descriptor.
+template <typename T>
+__device__ __forceinline__ const CTEBD_GLOBAL T* gp(const T* p) {
+  return (const CTEBD_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ CTEBD_GLOBAL T* gp(T* p) {
+  return (CTEBD_GLOBAL T*)p;
+}
+
 // A size that is fixed when the work is queued or read from device memory when
 // the kernel runs (ranks chosen by a truncation earlier in the same step):
 // value = mult * (*ptr) if ptr else mult.
@@ -14,7 +72,7 @@ struct Dim {
   const int* ptr;
 };
 
-__device__ __forceinline__ int dim_value(const Dim& d) { return d.ptr ? d.mult * (*d.ptr) : d.mult; }
+__device__ __forceinline__ int dim_value(const Dim& d) { return d.ptr ? d.mult * gld(d.ptr) : d.mult; }
 
 template <typename T>
 struct cpx_of;

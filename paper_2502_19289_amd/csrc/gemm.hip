@@ -51,7 +51,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
   const int b = t / d.ksplit;
   const int m0 = ti * BM, n0 = tj * BN;
   if (b >= d.batch || m0 >= M || n0 >= N) return;
-  if (d.skip && *d.skip) return;
+  if (d.skip && gld(d.skip)) return;
   if (MODE == MODE_GRAM && ti > tj) return;
 
   const CI* A = (const CI*)d.A + (int64_t)b * d.sA;
@@ -88,11 +88,11 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
       const int r = tid >> 2, c4 = (tid & 3) * 4;
       const int gm = min(m0 + r, M - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ra[i] = A[(int64_t)gm * lda + min(k0 + c4 + i, kend - 1)];
+      for (int i = 0; i < 4; ++i) ra[i] = gld(A + (int64_t)gm * lda + min(k0 + c4 + i, kend - 1));
       const int kk = tid >> 4, n1 = tid & 15;
       const int gk = min(k0 + kk, kend - 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) rb[i] = Bm[(int64_t)gk * ldb + min(n0 + n1 + 16 * i, N - 1)];
+      for (int i = 0; i < 4; ++i) rb[i] = gld(Bm + (int64_t)gk * ldb + min(n0 + n1 + 16 * i, N - 1));
     } else {
       // rows gk of A (K x M) and of B (K x N; A itself for a Gram matrix)
       const int kk = tid >> 4, c1 = tid & 15;
@@ -100,10 +100,10 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
       const CI* Bk = MODE == MODE_GRAM ? A + (int64_t)gk * lda : Bm + (int64_t)gk * ldb;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ra[i] = A[(int64_t)gk * lda + min(m0 + c1 + 16 * i, M - 1)];
-        rb[i] = Bk[min(n0 + c1 + 16 * i, N - 1)];
+        ra[i] = gld(A + (int64_t)gk * lda + min(m0 + c1 + 16 * i, M - 1));
+        rb[i] = gld(Bk + min(n0 + c1 + 16 * i, N - 1));
       }
-      if (MODE == MODE_GRAM) wv = (TM)d.w[gk >> d.wshift];
+      if (MODE == MODE_GRAM) wv = (TM)gld(d.w + (gk >> d.wshift));
     }
   };
   // ---- stage A (BM x BK) k-major and B (BK x BN) into buffer q; zero
@@ -176,11 +176,11 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(const GemmDesc* __restrict__ 
           CO v;
           v.x = acc_re(acc[bi][bj], r) * alpha;
           v.y = acc_im(acc[bi][bj], r) * alpha;
-          C[(int64_t)gm * ldc + gn] = v;
+          gst(C + (int64_t)gm * ldc + gn, v);
           // a Gram matrix without split-K is complete here: mirror it
           if (MODE == MODE_GRAM && d.ksplit == 1 && ti < tj) {
             v.y = -v.y;
-            C[(int64_t)gn * ldc + gm] = v;
+            gst(C + (int64_t)gn * ldc + gm, v);
           }
         }
       }
@@ -201,9 +201,9 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const GramReduceDesc* 
     const int i = ti * 64 + (e >> 6), j = tj * 64 + (e & 63);
     if (i >= n || j >= n) continue;
     double2 s = make_double2(0.0, 0.0);
-    for (int q = 0; q < d.ksplit; ++q) s = cadd(s, d.part[(int64_t)q * d.stride + (int64_t)i * ld + j]);
-    d.G[(int64_t)i * ld + j] = s;
-    if (ti < tj) d.G[(int64_t)j * ld + i] = make_double2(s.x, -s.y);
+    for (int q = 0; q < d.ksplit; ++q) s = cadd(s, gld(d.part + (int64_t)q * d.stride + (int64_t)i * ld + j));
+    gst(d.G + (int64_t)i * ld + j, s);
+    if (ti < tj) gst(d.G + (int64_t)j * ld + i, make_double2(s.x, -s.y));
   }
 }
 
@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __res
   const int b = t;
   const int m0 = ti * 64, n0 = tj * 64;
   if (b >= d.batch || m0 >= M || n0 >= N) return;
-  if (d.skip && *d.skip) return;
+  if (d.skip && gld(d.skip)) return;
   const float2* A = (const float2*)d.A + (int64_t)b * d.sA;
   const float2* Bm = (const float2*)d.B + (int64_t)b * d.sB;
   float2* C = (float2*)d.C + (int64_t)b * d.sC;
@@ -286,9 +286,9 @@ __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __res
   float2 va[8], vb[8];
   auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) va[i] = Arow[min(k0 + ka + i, K - 1)];
+    for (int i = 0; i < 8; ++i) va[i] = gld(Arow + min(k0 + ka + i, K - 1));
 #pragma unroll
-    for (int i = 0; i < 8; ++i) vb[i] = Bcol[(int64_t)min(k0 + kb + i, K - 1) * ldb];
+    for (int i = 0; i < 8; ++i) vb[i] = gld(Bcol + (int64_t)min(k0 + kb + i, K - 1) * ldb);
   };
   auto stage = [&](int k0) __attribute__((always_inline)) {
     float re[8], im[8];
@@ -379,8 +379,8 @@ __global__ __launch_bounds__(256) void cgemm_bf16x6_kernel(const GemmDesc* __res
         const int gm = m0 + wm * 32 + bi2 * 16 + 4 * (lane >> 4) + r;
         const int gn = n0 + wn * 32 + bj * 16 + (lane & 15);
         if (gm < M && gn < N)
-          C[(int64_t)gm * ldc + gn] =
-              make_float2((arr[bi2][bj][r] - ari[bi2][bj][r]) * alpha, (aib[bi2][bj][r] + aia[bi2][bj][r]) * alpha);
+          gst(C + (int64_t)gm * ldc + gn,
+              make_float2((arr[bi2][bj][r] - ari[bi2][bj][r]) * alpha, (aib[bi2][bj][r] + aia[bi2][bj][r]) * alpha));
       }
 }
 

@@ -59,7 +59,7 @@ __device__ __forceinline__ Loc locate_d(const HtdSizes& sz, int bid, F count) {
   return Loc{-1, 0};
 }
 
-__device__ __forceinline__ bool skipped(const HtdDesc& d) { return d.skip && *d.skip; }
+__device__ __forceinline__ bool skipped(const HtdDesc& d) { return d.skip && gld(d.skip); }
 
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
@@ -679,23 +679,23 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
       const int q = l & (HTD_NB - 1);
       const int qq = q < nbp ? q : 0;
       const bool av = l < HTD_NB;
-      sa[i] = (av ? d.PV : d.PW)[(int64_t)clampr(r0 + row) * HTD_NB + qq];
-      sb[i] = (av ? d.PW : d.PV)[(int64_t)clampr(c0 + row) * HTD_NB + qq];
+      sa[i] = gld((av ? d.PV : d.PW) + (int64_t)clampr(r0 + row) * HTD_NB + qq);
+      sb[i] = gld((av ? d.PW : d.PV) + (int64_t)clampr(c0 + row) * HTD_NB + qq);
     }
   };
   fetch(0);
   double2 pq[PQ];
 #pragma unroll
-  for (int u = 0; u < PQ; ++u) pq[u] = d.part[tid + 256 * u < nb ? tid + 256 * u : 0];
-  const double2 tl = d.tau[kl];
+  for (int u = 0; u < PQ; ++u) pq[u] = gld(d.part + (tid + 256 * u < nb ? tid + 256 * u : 0));
+  const double2 tl = gld(d.tau + kl);
   // the last column's y at this thread's row (rows r0.., then c0..) from the
   // HEMV's slots (its trailing block starts at row p1): YU slots per thread
   const int wr = clampr((tid & 127) < 64 ? r0 + (tid & 127) : c0 + (tid & 127) - 64);
   const int ty = htd_hemv_rows(n, kl) + 2;
   double2 ys[YU];
 #pragma unroll
-  for (int u = 0; u < YU; ++u) ys[u] = d.Y[(int64_t)min((tid >> 7) + 2 * u, ty - 1) * ld + (wr - p1)];
-  const double2 vl = d.PV[(int64_t)wr * HTD_NB + nbp - 1];
+  for (int u = 0; u < YU; ++u) ys[u] = gld(d.Y + (int64_t)min((tid >> 7) + 2 * u, ty - 1) * ld + (wr - p1));
+  const double2 vl = gld(d.PV + (int64_t)wr * HTD_NB + nbp - 1);
   double sx = 0.0, sy = 0.0;
 #pragma unroll
   for (int u = 0; u < PQ; ++u) {
@@ -746,7 +746,7 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
           for (int q = 0; q < 4; ++q) {
             const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
             const int c = c0 + wn * 32 + y * 16 + (lane & 15);
-            at[x][y][q] = d.A[(int64_t)clampr(r) * ld + clampr(c)];
+            at[x][y][q] = gld(d.A + (int64_t)clampr(r) * ld + clampr(c));
           }
     }
 #pragma unroll
@@ -770,8 +770,8 @@ __global__ __launch_bounds__(256) void trd_her2k_kernel(const HtdDesc* __restric
         const int r = r0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
         if (r < n && c < n)
-          d.A[(int64_t)r * ld + c] =
-              make_double2(at[x][y][q].x - acc_re(acc[x][y], q), at[x][y][q].y - acc_im(acc[x][y], q));
+          gst(d.A + (int64_t)r * ld + c,
+              make_double2(at[x][y][q].x - acc_re(acc[x][y], q), at[x][y][q].y - acc_im(acc[x][y], q)));
       }
 }
 
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
 #pragma unroll
     for (int j = 0; j < TC; ++j) {
       const int cc = c0 + j < mt ? c0 + j : 0;
-      a[i][j] = blk[cc > rr ? (int64_t)cc * ld + rr : (int64_t)rr * ld + cc];
+      a[i][j] = gld(blk + (cc > rr ? (int64_t)cc * ld + rr : (int64_t)rr * ld + cc));
     }
   }
 #pragma unroll
@@ -854,9 +854,9 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
       double beta;
       householder(x[kk + 1], smax, ssq, beta, tau, scale);
       if (tid == 0) {
-        d.d[k] = x[kk].x;
-        d.tau[k] = tau;
-        d.e[k] = beta;
+        gst(d.d + k, x[kk].x);
+        gst(d.tau + k, tau);
+        gst(d.e + k, beta);
       }
     }
     const bool ident = tau.x == 0.0 && tau.y == 0.0;
@@ -865,7 +865,7 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
       return c == kk + 1 ? make_double2(1.0, 0.0)
                          : (c > kk + 1 && !ident ? cmul(x[c], scale) : make_double2(0.0, 0.0));
     };
-    if (tid > kk && tid < mt) d.A[(int64_t)k * ld + k0 + tid] = vat(tid);
+    if (tid > kk && tid < mt) gst(d.A + (int64_t)k * ld + k0 + tid, vat(tid));
     if (ident) continue;  // H = I: the trailing block is unchanged
     // y = tau A v on the rows below kk (each row summed over its 16 lanes)
     double2 vc[TC];
@@ -923,10 +923,10 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
 #pragma unroll
     for (int j = 0; j < TC; ++j)
       if (r0 + i == mt - 1 && c0 + j == mt - 1) {
-        d.d[n - 1] = a[i][j].x;
-        d.A[(int64_t)(n - 1) * ld + (n - 1)] = a[i][j];
+        gst(d.d + (n - 1), a[i][j].x);
+        gst(d.A + (int64_t)(n - 1) * ld + (n - 1), a[i][j]);
       }
-  if (tid == 0) d.e[n - 1] = 0.0;
+  if (tid == 0) gst(d.e + (n - 1), 0.0);
 }
 
 __global__ void trd_finish_kernel(const HtdDesc* __restrict__ ds, const HtdSizes sz) {
@@ -1513,19 +1513,20 @@ __global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict_
   const int T = (s + 63) / 64, per = T * T;
   const int node = lc.b / per, t = lc.b % per, ti = t / T, tj = t % T;
   const int lo = node * s, hi = min(lo + s, n), K = hi - lo;
-  const int* cnt = d.cnt + 4 * lo;
+  const auto cnt = gp(d.cnt + 4 * lo);
   if (!cnt[3]) return;
   const int K2 = cnt[0];
   const int k0 = ti * 64, r0 = tj * 64;  // roots k0.., rows r0..
   if (k0 >= K2 || r0 >= K) return;
-  const double* Qin = d.Q[(L - 1) & 1];
-  double* Qout = d.Q[L & 1];
-  const int* ndc = d.ndcol + lo;
-  const double* dl = d.dl + lo;
-  const double* zh = d.zhat + lo;
-  const int* org = d.origin + lo;
-  const double* st = d.stau + lo;
-  const double* un = d.unrm + lo;
+  const auto Qin = gp((const double*)d.Q[(L - 1) & 1]);
+  const auto Qout = gp(d.Q[L & 1]);
+  const auto pos = gp((const int*)d.pos_nd + lo);
+  const auto ndc = gp((const int*)d.ndcol + lo);
+  const auto dl = gp((const double*)d.dl + lo);
+  const auto zh = gp((const double*)d.zhat + lo);
+  const auto org = gp((const int*)d.origin + lo);
+  const auto st = gp((const double*)d.stau + lo);
+  const auto un = gp((const double*)d.unrm + lo);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
   f64x4 acc[2][2];
 #pragma unroll
@@ -1584,7 +1585,7 @@ __global__ __launch_bounds__(256) void dc_gemm_kernel(const HtdDesc* __restrict_
       for (int q = 0; q < 4; ++q) {
         const int k = k0 + wm * 32 + x * 16 + Mfma<double>::row(lane, q);
         const int r = r0 + wn * 32 + y * 16 + (lane & 15);
-        if (k < K2 && r < K) Qout[(int64_t)(lo + d.pos_nd[lo + k]) * ld + lo + r] = acc[x][y][q];
+        if (k < K2 && r < K) Qout[(int64_t)(lo + pos[k]) * ld + lo + r] = acc[x][y][q];
       }
 }
 
@@ -1623,7 +1624,7 @@ __global__ __launch_bounds__(256) void bt_init_kernel(const HtdDesc* __restrict_
 
 // reflector i of block b (k = BT_NB b + i) at row j: 0 for j <= k, else row k of A
 __device__ __forceinline__ double2 refl(const HtdDesc& d, int k, int j) {
-  return j > k ? d.A[(int64_t)k * d.ld + j] : make_double2(0.0, 0.0);
+  return j > k ? gld(d.A + (int64_t)k * d.ld + j) : make_double2(0.0, 0.0);
 }
 
 // T of each block: H_k0 ... H_k0+nb-1 = I - V_b T V_b^H (upper triangular T,
@@ -1666,7 +1667,7 @@ __global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict
   }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
-    const double2 ti = d.tau[k0 + i];
+    const double2 ti = gld(d.tau + k0 + i);
     if (tid < i) {
       const double2 t = cmul(ti, Ts[tid][i]);
       tv[tid] = make_double2(-t.x, -t.y);
@@ -1681,7 +1682,7 @@ __global__ __launch_bounds__(256) void bt_larft_kernel(const HtdDesc* __restrict
     __syncthreads();
   }
   double2* out = d.T + (int64_t)b * BT_NB * BT_NB;
-  for (int e = tid; e < BT_NB * BT_NB; e += 256) out[e] = Ts[e / BT_NB][e % BT_NB];
+  for (int e = tid; e < BT_NB * BT_NB; e += 256) gst(out + e, Ts[e / BT_NB][e % BT_NB]);
 }
 
 // partial W = V_b^H Z over a chunk of BT_CH rows (rows from k0 + 1) and 64
@@ -1711,12 +1712,12 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       const int e = tid + 256 * u, i = e >> 4, j = j0 + (e & 15);
-      ra[u] = d.A[(int64_t)(k0 + min(i, nb - 1)) * ld + min(j, rend - 1)];
+      ra[u] = gld(d.A + (int64_t)(k0 + min(i, nb - 1)) * ld + min(j, rend - 1));
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = tid + 256 * u, j = j0 + (e >> 6), c = e & 63;
-      rb[u] = d.V[(int64_t)min(j, rend - 1) * ld + min(c0 + c, nc - 1)];
+      rb[u] = gld(d.V + (int64_t)min(j, rend - 1) * ld + min(c0 + c, nc - 1));
     }
   };
   CAcc3<double> acc[BPW];
@@ -1757,7 +1758,7 @@ __global__ __launch_bounds__(256) void bt_wpart_kernel(const HtdDesc* __restrict
     for (int r = 0; r < 4; ++r) {
       const int i = bi * 16 + Mfma<double>::row(lane, r);
       const int c = c0 + bj * 16 + (lane & 15);
-      if (c < nc) d.Wp[((int64_t)ch * BT_NB + i) * ld + c] = make_double2(acc_re(acc[q], r), acc_im(acc[q], r));
+      if (c < nc) gst(d.Wp + ((int64_t)ch * BT_NB + i) * ld + c, make_double2(acc_re(acc[q], r), acc_im(acc[q], r)));
     }
   }
 }
@@ -1783,9 +1784,9 @@ __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict_
   const double2* w = d.Wp + (int64_t)i * ld + min(c0 + c, nc - 1);
   double2 v[NCH];
 #pragma unroll
-  for (int q = 0; q < NCH; ++q) v[q] = w[(int64_t)(q < nch ? q : 0) * BT_NB * ld];
+  for (int q = 0; q < NCH; ++q) v[q] = gld(w + (int64_t)(q < nch ? q : 0) * BT_NB * ld);
 #pragma unroll
-  for (int e = tid; e < BT_NB * BT_NB; e += 256) Ts[e / BT_NB][e % BT_NB] = Tb[e];
+  for (int e = tid; e < BT_NB * BT_NB; e += 256) Ts[e / BT_NB][e % BT_NB] = gld(Tb + e);
   double sx = 0.0, sy = 0.0;
 #pragma unroll
   for (int q = 0; q < NCH; ++q) {
@@ -1796,7 +1797,7 @@ __global__ __launch_bounds__(256) void bt_wred_kernel(const HtdDesc* __restrict_
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
   for (int l = i; l < BT_NB; ++l) s = cadd(s, cmul(Ts[i][l], Ws[l][c]));
-  if (c0 + c < nc) d.W[(int64_t)i * ld + c0 + c] = s;
+  if (c0 + c < nc) gst(d.W + (int64_t)i * ld + c0 + c, s);
 }
 
 // Z[j][c] -= sum_i v_i[j] W[i][c] on 64 x 64 tiles of rows k0 + 1 ...; each
@@ -1823,8 +1824,8 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + 256 * u, i = min(i0 + (e >> 6), nb - 1), x = e & 63;
-      ra[u] = d.A[(int64_t)(k0 + i) * ld + min(j0 + x, n - 1)];
-      rb[u] = d.W[(int64_t)i * ld + min(c0 + x, nc - 1)];
+      ra[u] = gld(d.A + (int64_t)(k0 + i) * ld + min(j0 + x, n - 1));
+      rb[u] = gld(d.W + (int64_t)i * ld + min(c0 + x, nc - 1));
     }
   };
   CAcc3<double> acc[2][2];
@@ -1856,7 +1857,7 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
           for (int r = 0; r < 4; ++r) {
             const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
             const int c = c0 + wn * 32 + y * 16 + (lane & 15);
-            zt[x][y][r] = d.V[(int64_t)min(j, n - 1) * ld + min(c, nc - 1)];
+            zt[x][y][r] = gld(d.V + (int64_t)min(j, n - 1) * ld + min(c, nc - 1));
           }
     }
 #pragma unroll
@@ -1880,8 +1881,8 @@ __global__ __launch_bounds__(256) void bt_update_kernel(const HtdDesc* __restric
         const int j = j0 + wm * 32 + x * 16 + Mfma<double>::row(lane, r);
         const int c = c0 + wn * 32 + y * 16 + (lane & 15);
         if (j < n && c < nc)
-          d.V[(int64_t)j * ld + c] =
-              make_double2(zt[x][y][r].x - acc_re(acc[x][y], r), zt[x][y][r].y - acc_im(acc[x][y], r));
+          gst(d.V + (int64_t)j * ld + c,
+              make_double2(zt[x][y][r].x - acc_re(acc[x][y], r), zt[x][y][r].y - acc_im(acc[x][y], r)));
       }
 }
 

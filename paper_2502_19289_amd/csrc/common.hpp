@@ -31,7 +31,7 @@ template <typename T>
 __device__ __forceinline__ T gld(const T* p) {
   using R = typename gl_repr<T>::type;
   const R v = *(const CTEBD_GLOBAL R*)(const void*)p;
-  if constexpr (sizeof(R) == sizeof(T) && !__is_same(R, T)) {
+  if constexpr (!__is_same(R, T)) {
     T r;
     r.x = v.x;
     r.y = v.y;

@@ -165,6 +165,22 @@ __device__ __forceinline__ double block4_sum(double v, double* sh) {
 // trailing matrix on the matrix cores.  One triangle of the trailing matrix
 // is thus read once per column (HEMV); all of it is read and written once per
 // panel.
+// acc += a b and acc += conj(a) b as four fused multiply-adds each (the
+// product formed with separate multiplies and the sum with a separate add
+// takes half as many instructions again)
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cfmac(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
 // dlassq-style running (scale, sum of squares): sum a^2 = scale^2 * ssq
 __device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
   a = fabs(a);
@@ -323,13 +339,13 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
     al = cmul(make_double2(-0.5 * tpl.x, -0.5 * tpl.y), ps);
   }
   // w_{j-1} = y_{j-1} + alpha v_{j-1}, on row k and on this wavefront's rows
-  if (vfin) rk = cadd(rk, cmul(al, rkv));
+  if (vfin) cfma(rk, al, rkv);
   kv[c] = rk;
   if (fin) {
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
       const int i = lc.b * KC_ROWS + wv + 4 * q;
-      pv[q] = cadd(pv[q], cmul(al, pf[q]));
+      cfma(pv[q], al, pf[q]);
       if (i < m) d.PW[(int64_t)(k + 1 + i) * HTD_NB + u] = pv[q];
     }
   }
@@ -340,8 +356,9 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
   // sum): far fewer instructions than 16 full wavefront reductions.
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
-    const double2 t = live ? cmul(pv[q], make_double2(rk.x, -rk.y)) : make_double2(0.0, 0.0);
-    tx[wv + 4 * q][c] = make_double2(a[q].x - t.x, a[q].y - t.y);
+    double2 xq = a[q];  // a - pv conj(rk) = a + pv (-conj(rk))
+    if (live) cfma(xq, pv[q], make_double2(-rk.x, rk.y));
+    tx[wv + 4 * q][c] = xq;
   }
   __syncthreads();
   {
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
     const int i = i0 + wv + 4 * q;
-    if (live && i > 0 && i < m) acc = cadd(acc, cmulc(pv[q], xr[wv + 4 * q]));
+    if (live && i > 0 && i < m) cfmac(acc, pv[q], xr[wv + 4 * q]);
   }
   dsum[wv][c] = acc;
   __syncthreads();
@@ -488,7 +505,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) {
         const int c = colof(pp);
-        acc = cadd(acc, cmul(a[q][pp], c > 0 && c < m ? xc[pp] : make_double2(0.0, 0.0)));
+        cfma(acc, a[q][pp], c > 0 && c < m ? xc[pp] : make_double2(0.0, 0.0));
       }
       gr[q] = acc;
     }
@@ -497,7 +514,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
       for (int pp = 0; pp < 4; ++pp) {
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc = cadd(acc, cmulc(a[q][pp], rowof(q) < m ? xr[q] : make_double2(0.0, 0.0)));
+        for (int q = 0; q < 4; ++q) cfmac(acc, a[q][pp], rowof(q) < m ? xr[q] : make_double2(0.0, 0.0));
         cpart[wave * 4 + s4][16 * pp + cl] = acc;
       }
     __syncthreads();
@@ -525,7 +542,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         const double2 y = ident ? make_double2(0.0, 0.0) : cmul(tau, acc);
         const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
         d.Y[(int64_t)J * ld + r] = y;
-        dot = cadd(dot, cmulc(y, vi));
+        cfmac(dot, y, vi);
       }
     }
     if (!diag && tid < 64 && c0 + tid >= 0 && c0 + tid < m) {  // column c = c0 + tid
@@ -536,7 +553,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
       const double2 y = ident ? make_double2(0.0, 0.0) : cmul(tau, cmul(scale, cs));
       const double2 vc = c == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xcol, scale));
       d.Y[(int64_t)I * ld + c] = y;
-      dot = cadd(dot, cmulc(y, vc));
+      cfmac(dot, y, vc);
     }
   } else {
     // half h: sum_l P[r][l] c_l over the panel columns l < j, P = V (h = 0) or
@@ -588,15 +605,21 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
 #pragma unroll
         for (int pp = 0; pp < 2; ++pp)
           if (16 * pp + cl >= j) pe[q][pp] = make_double2(0.0, 0.0);
-        h1[q] = cadd(cmul(pe[q][0], c1[0]), cmul(pe[q][1], c1[1]));
-        h2[q] = cadd(cmul(pe[q][0], c2[0]), cmul(pe[q][1], c2[1]));
+        h1[q] = make_double2(0.0, 0.0);
+        h2[q] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int pp = 0; pp < 2; ++pp) {
+          cfma(h1[q], pe[q][pp], c1[pp]);
+          cfma(h2[q], pe[q][pp], c2[pp]);
+        }
       }
     }
     householder(alpha, sh2[0], sh2[1], beta, tau, scale);
     const bool ident = tau.x == 0.0 && tau.y == 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double2 acc = cadd(h1[q], cmul(scale, h2[q]));
+      double2 acc = h1[q];
+      cfma(acc, scale, h2[q]);
       acc.x += dpp_take<0xb1, 0xf>(acc.x);
       acc.y += dpp_take<0xb1, 0xf>(acc.y);
       acc.x += dpp_take<0x4e, 0xf>(acc.x);
@@ -610,7 +633,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         const double2 y = ident ? make_double2(0.0, 0.0) : cmul(make_double2(-tau.x, -tau.y), acc);
         const double2 vi = r == 0 ? make_double2(1.0, 0.0) : (ident ? make_double2(0.0, 0.0) : cmul(xr[q], scale));
         d.Y[(int64_t)(T + h) * ld + r] = y;
-        dot = cadd(dot, cmulc(y, vi));
+        cfmac(dot, y, vi);
         if (h == 0) {  // the reflector: panel column j and row k of A
           d.PV[(int64_t)(k + 1 + r) * HTD_NB + j] = vi;
           d.A[(int64_t)k * ld + (k + 1 + r)] = vi;
@@ -875,7 +898,7 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
     for (int i = 0; i < TR; ++i) {
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int j = 0; j < TC; ++j) acc = cadd(acc, cmul(a[i][j], vc[j]));
+      for (int j = 0; j < TC; ++j) cfma(acc, a[i][j], vc[j]);
       acc.x += dpp_take<0xb1, 0xf>(acc.x);
       acc.y += dpp_take<0xb1, 0xf>(acc.y);
       acc.x += dpp_take<0x4e, 0xf>(acc.x);
@@ -911,9 +934,13 @@ __global__ __launch_bounds__(512) void trd_tail_kernel(const HtdDesc* __restrict
       for (int j = 0; j < TC; ++j) {  // one column at a time keeps the live registers few
         const double2 vj = vc[j];
         const double2 wj = cadd(y[c0 + j], cmul(al, vj));
-        const double2 vcc = make_double2(vj.x, -vj.y), wcc = make_double2(wj.x, -wj.y);
+        // a -= v_r conj(w_j) + w_r conj(v_j): the same conjugate products with
+        // the minus folded in, conj(w_j) (-v_r) + conj(v_j) (-w_r)
 #pragma unroll
-        for (int i = 0; i < TR; ++i) a[i][j] = csub(csub(a[i][j], cmul(vr[i], wcc)), cmul(wr[i], vcc));
+        for (int i = 0; i < TR; ++i) {
+          cfmac(a[i][j], wj, make_double2(-vr[i].x, -vr[i].y));
+          cfmac(a[i][j], vj, make_double2(-wr[i].x, -wr[i].y));
+        }
       }
     }
   }

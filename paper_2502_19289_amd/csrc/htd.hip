@@ -196,6 +196,12 @@ __device__ __forceinline__ void lassq(double a, double& scale, double& ssq) {
 // The reflector H = I - tau v v^H with H^H (alpha, x1)^T = (beta, 0)^T, beta
 // real, v = (1, scale x1), from alpha and the scaled norm of x1
 // (||x1||^2 = smax^2 ssq); tau = 0 (H = I) when x1 = 0 and alpha is real.
+// Worked in units of amax = max(smax, |alpha|): with a = alpha / amax the norm
+// nrm = |(a, x1 / amax)| is at least 1, b = beta / amax = -sign(Re a) nrm,
+// d = a - b has |Re d| = |Re a| + nrm >= 1, so tau = (b - a) / b and
+// scale = 1 / (amax d) = conj(d) / (amax |d|^2) need one reciprocal each
+// (|d|^2 lies in [1, 4 nrm^2]).  Below 2^-1000 (where 1 / amax could
+// overflow) the same quantities are formed by division.
 __device__ __forceinline__ void householder(double2 alpha, double smax, double ssq, double& beta, double2& tau,
                                             double2& scale) {
   const double amax = fmax(smax, fmax(fabs(alpha.x), fabs(alpha.y)));
@@ -203,19 +209,23 @@ __device__ __forceinline__ void householder(double2 alpha, double smax, double s
   scale = make_double2(0.0, 0.0);
   beta = alpha.x;
   if (amax > 0.0) {
-    const double xs2 = ssq * (smax / amax) * (smax / amax);
+    const bool tiny = amax < 0x1p-1000;
+    const double ia = tiny ? 0.0 : 1.0 / amax;
+    const double sr = tiny ? smax / amax : smax * ia;
+    const double xs2 = ssq * sr * sr;
     if (xs2 > 0.0 || alpha.y != 0.0) {
-      const double ar = alpha.x / amax, ai = alpha.y / amax;
-      beta = -copysign(amax * sqrt(ar * ar + ai * ai + xs2), alpha.x);
-      tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-      // scale = 1 / (alpha - beta) by Smith's complex division
-      const double dr = alpha.x - beta, di = alpha.y;
-      if (fabs(dr) >= fabs(di)) {
-        const double rr = di / dr, t = 1.0 / (dr + di * rr);
-        scale = make_double2(t, -rr * t);
+      const double ar = tiny ? alpha.x / amax : alpha.x * ia, ai = tiny ? alpha.y / amax : alpha.y * ia;
+      const double nrm = sqrt(ar * ar + ai * ai + xs2);
+      const double b = -copysign(nrm, alpha.x);
+      beta = amax * b;
+      const double dr = ar - b, den = dr * dr + ai * ai;
+      if (tiny) {
+        tau = make_double2((b - ar) / b, -ai / b);
+        scale = make_double2(dr / den / amax, -ai / den / amax);
       } else {
-        const double rr = dr / di, t = 1.0 / (di + dr * rr);
-        scale = make_double2(rr * t, -t);
+        const double ib = 1.0 / b, q = 1.0 / (den * amax);
+        tau = make_double2((b - ar) * ib, -ai * ib);
+        scale = make_double2(dr * q, -ai * q);
       }
     }
   }

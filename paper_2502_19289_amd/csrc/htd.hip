@@ -113,6 +113,32 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
     v[i] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
   }
 }
+// lane q's value in every lane (q the same in all lanes)
+__device__ __forceinline__ double lane_at(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, q);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), q);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// v + (v of lane c ^ 16) and v + (v of lane c ^ 32) with the lane-swap
+// instructions: swapping a register with itself leaves lanes c and c ^ 16
+// (c ^ 32) holding the pair's two values in its two results, so their sum
+// is the pair sum in both lanes, the same value a shuffle gives, without the
+// LDS crossbar.
+__device__ __forceinline__ double pair_sum16(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]) +
+         __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]) +
+         __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+}
 // Wavefront maximum on the same DPP paths as wave_sum.
 // lane 0's value in every lane
 __device__ __forceinline__ double lane0(double v) {
@@ -329,8 +355,8 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
       ya[x] += dpp_take<0x128, 0xf>(ya[x]);
-      ya[x] += __shfl_xor(ya[x], 16);
-      ya[x] += __shfl_xor(ya[x], 32);
+      ya[x] = pair_sum16(ya[x]);
+      ya[x] = pair_sum32(ya[x]);
     }
     y0[0] = c < ty ? y0l.x : 0.0;
     y0[1] = c < ty ? y0l.y : 0.0;
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
     if (vfin) rk = make_double2(y0[0], y0[1]);
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {  // row q's sum from lane q, in every lane
-      const double2 yq = make_double2(__shfl(ya[0], q), __shfl(ya[1], q));
+      const double2 yq = make_double2(lane_at(ya[0], q), lane_at(ya[1], q));
       if (fin) pv[q] = yq;
     }
   }

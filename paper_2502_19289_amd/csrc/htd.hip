@@ -113,6 +113,15 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
     v[i] = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
   }
 }
+// Orders a wavefront's LDS writes before its later LDS reads of the values
+// other lanes of the same wavefront wrote (the hardware executes a
+// wavefront's LDS operations in order; this keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 // lane q's value in every lane (q the same in all lanes)
 __device__ __forceinline__ double lane_at(double v, int q) {
   const long long b = __double_as_longlong(v);
@@ -387,18 +396,22 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
   }
   // x_r = G[r][k] - sum_u V[r][u] conj(w_k[u]) + W[r][u] conj(v_k[u]):
   // lane c of the row's wavefront contributes pv conj(rk), lane 0 also
-  // G[r][k].  The sums over the 64 lanes go through LDS (the terms of
-  // the 32 rows, then 8 threads per row with 8 terms each and an 8-lane DPP
-  // sum): far fewer instructions than 16 full wavefront reductions.
+  // G[r][k].  The sums over the 64 lanes go through LDS (the terms of the
+  // wavefront's 8 rows, then 8 lanes per row with 8 terms each and an 8-lane
+  // DPP sum): far fewer instructions than 16 full wavefront reductions.  Each
+  // wavefront sums the rows it owns and reads back only what it wrote itself
+  // (a wavefront's LDS operations execute in order), so no workgroup barrier
+  // separates the terms, the sums and the dots.
 #pragma unroll
   for (int q = 0; q < RPW; ++q) {
     double2 xq = a[q];  // a - pv conj(rk) = a + pv (-conj(rk))
     if (live) cfma(xq, pv[q], make_double2(-rk.x, rk.y));
     tx[wv + 4 * q][c] = xq;
   }
-  __syncthreads();
+  wave_lds_order();
+  const int i0 = lc.b * KC_ROWS;  // row r of the workgroup is row i0 + r of the column
   {
-    const int wr = tid >> 3, part = tid & 7;
+    const int wr = wv + 4 * (c >> 3), part = c & 7;
     double2 sxy = make_double2(0.0, 0.0);
 #pragma unroll
     for (int e = 0; e < 8; ++e) sxy = cadd(sxy, tx[wr][part * 8 + e]);
@@ -408,13 +421,23 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
     sxy.y += dpp_take<0x4e, 0xf>(sxy.y);
     sxy.x += dpp_take<0x141, 0xf>(sxy.x);
     sxy.y += dpp_take<0x141, 0xf>(sxy.y);
-    if (part == 0) xr[wr] = sxy;
+    if (part == 0) {
+      xr[wr] = sxy;
+      if (i0 + wr < m) d.xb[i0 + wr] = sxy;
+    }
   }
+  wave_lds_order();
+  // the dots V^H x_1, W^H x_1: lane c sums its column over the wavefront's rows
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < RPW; ++q) {
+    const int i = i0 + wv + 4 * q;
+    if (live && i > 0 && i < m) cfmac(acc, pv[q], xr[wv + 4 * q]);
+  }
+  dsum[wv][c] = acc;
   __syncthreads();
-  const int i0 = lc.b * KC_ROWS;  // row tid of the workgroup is row i0 + tid of the column
-  if (tid < KC_ROWS && i0 + tid < m) d.xb[i0 + tid] = xr[tid];
   double2* rec = d.kpart + (int64_t)lc.b * HTD_KP;
-  if (wv == 0) {  // scaled norm of x_1 (rows i > 0) over the workgroup's rows
+  if (wv == 0) {  // scaled norm of x_1 (rows i > 0) over the workgroup's rows; the dots
     const int i = i0 + c;
     const double2 xv = c < KC_ROWS && i > 0 && i < m ? xr[c] : make_double2(0.0, 0.0);
     const double amax = wave_max(fmax(fabs(xv.x), fabs(xv.y)));
@@ -425,17 +448,8 @@ __global__ __launch_bounds__(256) void trd_col_kernel(const HtdProbs<N> sz, int 
     }
     ss = wave_sum(ss);
     if (c == 0) rec[0] = make_double2(amax, ss);
+    rec[2 + c] = cadd(cadd(dsum[0][c], dsum[1][c]), cadd(dsum[2][c], dsum[3][c]));
   }
-  // the dots V^H x_1, W^H x_1: lane c sums its column over the wavefront's rows
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < RPW; ++q) {
-    const int i = i0 + wv + 4 * q;
-    if (live && i > 0 && i < m) cfmac(acc, pv[q], xr[wv + 4 * q]);
-  }
-  dsum[wv][c] = acc;
-  __syncthreads();
-  if (wv == 0) rec[2 + c] = cadd(cadd(dsum[0][c], dsum[1][c]), cadd(dsum[2][c], dsum[3][c]));
   if (lc.b == 0 && wv == 1) {  // d_k = G[k][k] - 2 sum_q Re(conj(v_k[q]) w_k[q])
     double t = 0.0;
     if (c < j) t = kv[HTD_NB + c].x * kv[c].x + kv[HTD_NB + c].y * kv[c].y;

@@ -480,7 +480,6 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
   __shared__ double2 hsum[8][HTD_NB];    // panel: record sums by group
   __shared__ double2 cpart[16][64 + 1];  // tile: column sums of (wavefront, s)
   __shared__ double2 wred[4];
-  __shared__ double sh2[2];
   // problem blockIdx.y: its record is the only argument line read before the data
   const int p = blockIdx.y, t = blockIdx.x;
   const int n = sz.pr[p].n;
@@ -509,26 +508,23 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
   // later loads are issued)
   const int nka = htd_col_blocks(n, k);
   static_assert(HTD_MAX / KC_ROWS <= 64, "the norm records are reduced by one wavefront");
-  const double2 rq0 = d.kpart[(int64_t)(tid < nka ? tid : 0) * HTD_KP];
-  const double2 rq = tid < nka ? rq0 : make_double2(0.0, 0.0);
+  // every wavefront reads all the records and forms the reflector itself
+  // (same operations, same values), so no workgroup barrier precedes it
+  const double2 rq0 = d.kpart[(int64_t)(lane < nka ? lane : 0) * HTD_KP];
+  const double2 rq = lane < nka ? rq0 : make_double2(0.0, 0.0);
   const double2 alpha = d.xb[0];
   double2 xr[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) xr[q] = d.xb[min(max(rowof(q), 0), m - 1)];
-  auto reflector_norm = [&]() {
-    if (tid < 64) {
-      const double rm = rq.x, rs = rq.y;
-      const double smax = wave_max(rm);
-      const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
-      const double ssq_w = wave_sum(c);
-      if (tid == 0) {
-        sh2[0] = smax;
-        sh2[1] = ssq_w;
-      }
-    }
-  };
   double2 tau, scale;
   double beta;
+  auto reflector = [&]() {
+    const double rm = rq.x, rs = rq.y;
+    const double smax = wave_max(rm);
+    const double c = (rm > 0.0 && smax > 0.0) ? rs * (rm / smax) * (rm / smax) : 0.0;
+    const double ssq = wave_sum(c);
+    householder(alpha, smax, ssq, beta, tau, scale);
+  };
   double2 dot = make_double2(0.0, 0.0);
   if (!panel) {
     double2 xc[4];
@@ -544,7 +540,8 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp) a[q][pp] = g0[(int64_t)min(rowof(q), m - 1) * ld + min(colof(pp), m - 1)];
-    reflector_norm();
+    reflector();
+    const bool ident = tau.x == 0.0 && tau.y == 0.0;
     // row sums over this thread's columns (x_0 = alpha left out: v_0 = 1 is
     // added through G[r][0] itself); column sums over its rows (rows > 0
     // below the diagonal)
@@ -567,9 +564,8 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         for (int q = 0; q < 4; ++q) cfmac(acc, a[q][pp], rowof(q) < m ? xr[q] : make_double2(0.0, 0.0));
         cpart[wave * 4 + s4][16 * pp + cl] = acc;
       }
-    __syncthreads();
-    householder(alpha, sh2[0], sh2[1], beta, tau, scale);
-    const bool ident = tau.x == 0.0 && tau.y == 0.0;
+    // the rows' y: this wavefront's own rows, before the barrier the column
+    // sums need
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double2 acc = cmul(scale, gr[q]);
@@ -595,6 +591,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         cfmac(dot, y, vi);
       }
     }
+    __syncthreads();
     if (!diag && tid < 64 && c0 + tid >= 0 && c0 + tid < m) {  // column c = c0 + tid
       const int c = c0 + tid;
       double2 cs = make_double2(0.0, 0.0);
@@ -635,7 +632,7 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         if (g + 8 * u < nka) tt = cadd(tt, rv[u]);
       hsum[g][e] = tt;
     }
-    reflector_norm();
+    reflector();
     __syncthreads();
     // the two parts of each row's sum: with conj(Q[k+1, l]) and with (Q^H x[1:])_l
     double2 h1[4], h2[4];
@@ -664,7 +661,6 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(const HtdProbs<N> sz, int
         }
       }
     }
-    householder(alpha, sh2[0], sh2[1], beta, tau, scale);
     const bool ident = tau.x == 0.0 && tau.y == 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

@@ -19,7 +19,7 @@ re-launches on the same inputs).  A timed window that starts with no bond at
 chi_max is not the metric's workload: the line then carries
 ``"unmeasured": true``, ``value`` null, and the exit status is 1.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the library runs on one GPU.
 ``--copy-calibration BYTES`` instead runs one device copy of that size (the
 reference kernel for scaling HBM counters).
 """
@@ -370,7 +370,7 @@ def main():
         dmrg_run(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

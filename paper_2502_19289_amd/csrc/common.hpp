@@ -12,8 +12,9 @@ namespace ctebd {
 // outstanding LDS and scalar operations: every wait for an LDS read then waits
 // for the flat loads in flight too (a prefetch issued before a slice's
 // products would be waited for at its first LDS read).  These helpers access
-// the same address as global memory (every descriptor pointer is a device
-// allocation).
+// the same address through the global segment, which is valid because a
+// descriptor pointer never addresses LDS or private memory (the two other
+// apertures a flat access covers).
 #define CTEBD_GLOBAL __attribute__((address_space(1)))
 template <typename T>
 struct gl_repr {

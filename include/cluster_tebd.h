@@ -337,7 +337,7 @@ mps_status mps_kernel_bytes(mps_handle h, double* bytes, int cap, int* count);
 const char* mps_last_error(mps_handle h);
 
 /* ---- learned sketch -------------------------------------------------------
- * The paper does not sketch its SVDs; these calls serve the build's learned
+ * The paper does not sketch its SVDs; these calls serve the library's learned
  * sketch (svd_mode MPS_SVD_LEARNED): a network 12 -> 64 -> 64 -> 1 with GELU
  * (tanh form), FP32 on the device, predicts log2 of the rank a truncated SVD
  * keeps; the prediction sizes a randomized range finder on the split's Gram

@@ -19,7 +19,7 @@ Follows Sec. III.B of the paper (with the DMRG iteration of Sec. II.C):
   * the fitted M is decomposed back into one tensor per qubit by SVDs with
     chi_max^SVD and the cutoff eta (Sec. II.B), their kept weights recorded.
 
-Readings where the paper is silent (also listed in the design notes):
+Readings where the paper is silent:
   * cut choice: the 1-D chain is cut at the bond of smallest virtual
     dimension (the minimum cut of the chain graph), ties going to the most
     balanced cut, then to the leftmost;

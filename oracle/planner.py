@@ -5,7 +5,7 @@ i..i+n-1 marks bonds i..i+n-2; after each layer the entanglement clusters are
 the maximal runs of marked bonds; the circuit is contracted up to the last layer
 for which every cluster obeys log2(size) <= Q_max (size = 2^k chi_left chi_right,
 Eqs. size and cond_cTEBD) and the number of layers obeys L <= L_max (Eq.
-cond2_cTEBD).  Readings (listed in the design notes):
+cond2_cTEBD).  Readings where the paper is silent:
 
   * a gate on non-adjacent qubits (a, b) marks every bond a..b-1, so its cluster
     is the whole span and counts the idle qubits inside it;

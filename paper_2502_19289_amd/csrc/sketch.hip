@@ -1,6 +1,6 @@
 // Learned sketch for the truncated SVD of the split sweep.
 //
-// The paper does not sketch; this is the build's accelerator for splits whose
+// The paper does not sketch; this is the library's accelerator for splits whose
 // kept rank is far below the matrix size.  A small network (12 -> 64 -> 64 -> 1,
 // GELU) predicts log2 of the rank the exact truncated SVD would keep; the
 // prediction sets the size s of a randomized range finder (Halko, Martinsson,

@@ -205,8 +205,11 @@ mps_status mps_save(mps_handle h, const char* path);
 
 /* Creates a new handle from a file written by mps_save (its own stream; use
  * mps_set_options for another).  The file is read and checked on the host
- * first: MPS_EIO when it cannot be read, is truncated, fails its checksum or
- * holds out-of-range sizes; mps_last_error(NULL) then says why. */
+ * first: MPS_EIO when it cannot be read, is truncated, fails its checksum,
+ * holds out-of-range sizes, or holds buffered sub-layers that mps_run_layer
+ * could not have left for the saved k_max (gates of one sub-layer sharing a
+ * qubit, overlapping two-qubit spans, a span wider than k_max);
+ * mps_last_error(NULL) then says why. */
 mps_status mps_load(const char* path, mps_handle* out);
 
 /* Sec. III.B, one step of the adaptive-grouping DMRG on an FP64 handle

@@ -2753,6 +2753,150 @@ struct Reader {
 
 thread_local std::string g_err;  // message of the last failed call without a handle
 
+// mps_load after its argument checks: the whole file is read and checked on
+// the host before a handle exists.  Sub-layers must be as legalize_layer
+// leaves them for the saved k_max (distinct qubits, disjoint two-qubit spans
+// of at most k_max sites), so that the planner sees only clusters it can form.
+mps_status load_checked(const char* path, mps_handle* out) {
+  std::vector<char> buf;
+  {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) {
+      g_err = "mps_load: cannot open the file";
+      return MPS_EIO;
+    }
+    buf.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+  }
+  Reader r{buf.data(), buf.size() >= 8 ? buf.size() - 8 : 0};
+  auto bad = [&](const char* why) {
+    g_err = std::string("mps_load: ") + why;
+    return MPS_EIO;
+  };
+  if (buf.size() < 16 || std::memcmp(buf.data(), kSaveMagic, 8) != 0) return bad("not a saved state");
+  uint64_t sum = 0;
+  std::memcpy(&sum, buf.data() + buf.size() - 8, 8);
+  if (sum != fnv1a(buf.data(), buf.size() - 8)) return bad("checksum mismatch");
+  r.pos = 8;
+  if (r.get<uint32_t>() != kSaveVersion) return bad("unknown version");
+  const int n = r.get<int32_t>(), chi_max = r.get<int32_t>();
+  const double eps = r.get<double>();
+  mps_options o{};
+  o.k_max = r.get<int32_t>();
+  o.q_max = r.get<int32_t>();
+  o.l_max = r.get<int32_t>();
+  o.precision = r.get<int32_t>();
+  o.svd_mode = r.get<int32_t>();
+  o.batch = r.get<int32_t>();
+  o.eig_method = r.get<int32_t>();
+  o.floor_c = r.get<double>();
+  o.hip_stream = nullptr;
+  const double log_f = r.get<double>();
+  mps_stats st{};
+  st.steps = r.get<int64_t>();
+  st.cluster_updates = r.get<int64_t>();
+  st.svds = r.get<int64_t>();
+  st.site_updates = r.get<int64_t>();
+  st.sketch_accepted = r.get<int64_t>();
+  st.sketch_fallback = r.get<int64_t>();
+  st.jacobi_sweeps = r.get<int64_t>();
+  st.discarded_weight = r.get<double>();
+  const uint64_t sk_seed = r.get<uint64_t>();
+  const uint32_t sk_stream = r.get<uint32_t>();
+  if (!r.ok || n < 2 || n > (1 << 24) || chi_max < 1 || chi_max > 2048 || !(eps >= 0.0) || !options_valid(o))
+    return bad("malformed header");
+  std::vector<int> chi(n - 1);
+  for (int b = 0; b < n - 1; ++b) {
+    chi[b] = r.get<int32_t>();
+    const int e = std::min(b + 1, n - b - 1);
+    const int cap = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
+    if (!r.ok || chi[b] < 1 || chi[b] > cap) return bad("bond dimension out of range");
+  }
+  std::vector<float> pdw(n - 1), ptail(n - 1);
+  for (int b = 0; b < n - 1; ++b) {
+    pdw[b] = r.get<float>();
+    ptail[b] = r.get<float>();
+  }
+  const size_t esz = o.precision == MPS_PREC_FP64 ? 16 : 8;
+  std::vector<const char*> site_at(n), lam_at(n - 1);
+  for (int j = 0; j < n; ++j) {
+    const size_t bytes = (size_t)(j > 0 ? chi[j - 1] : 1) * 2 * (j < n - 1 ? chi[j] : 1) * esz;
+    site_at[j] = r.skip(bytes);
+  }
+  for (int b = 0; b < n - 1; ++b) lam_at[b] = r.skip(chi[b] * sizeof(double));
+  // counts are bounded by the bytes left before anything is sized by them
+  const uint32_t nsub = r.get<uint32_t>();
+  if (!r.ok || nsub > (r.end - r.pos) / sizeof(uint32_t)) return bad("malformed sub-layer count");
+  std::vector<SubLayer> pending(nsub);
+  std::vector<char> used(n, 0);
+  std::vector<std::pair<int, int>> spans;
+  constexpr size_t kGateBytes = 3 * sizeof(int32_t) + 32 * sizeof(double);
+  for (auto& sl : pending) {
+    const uint32_t ng = r.get<uint32_t>();
+    if (!r.ok || ng > (uint32_t)n || ng > (r.end - r.pos) / kGateBytes) return bad("malformed sub-layer");
+    sl.resize(ng);
+    spans.clear();
+    for (auto& g : sl) {
+      g.nq = r.get<int32_t>();
+      g.q[0] = r.get<int32_t>();
+      g.q[1] = r.get<int32_t>();
+      for (int e = 0; e < 16; ++e) {
+        const double re = r.get<double>(), im = r.get<double>();
+        g.u[e] = cplx(re, im);
+      }
+      // a one-qubit gate holds its qubit twice; a two-qubit gate two qubits
+      if (g.nq < 1 || g.nq > 2 || g.q[0] < 0 || g.q[0] >= n || g.q[1] < 0 || g.q[1] >= n ||
+          (g.q[0] == g.q[1]) != (g.nq == 1))
+        return bad("malformed gate");
+      if (g.hi() - g.lo() + 1 > o.k_max) return bad("gate span wider than the saved k_max");
+      for (int i = 0; i < g.nq; ++i) {
+        if (used[g.q[i]]) return bad("gates of one sub-layer share a qubit");
+        used[g.q[i]] = 1;
+      }
+      if (g.nq == 2) spans.emplace_back(g.lo(), g.hi());
+    }
+    for (const auto& g : sl)
+      for (int i = 0; i < g.nq; ++i) used[g.q[i]] = 0;
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+      if (spans[i].first <= spans[i - 1].second) return bad("two-qubit spans of one sub-layer overlap");
+  }
+  if (!r.ok || r.pos != buf.size() - 8) return bad("truncated or oversized file");
+  mps_handle h = nullptr;
+  mps_status cs = mps_create(n, chi_max, eps, &o, &h);
+  if (cs != MPS_OK) {
+    g_err = "mps_load: could not create the handle";
+    return cs;
+  }
+  mps_ctx* ctx = h;
+  cs = guarded(ctx, [&]() -> mps_status {
+    hipStream_t s = ctx->stream;
+    ctx->chi = chi;
+    for (int j = 0; j < n; ++j) {
+      const size_t bytes = (size_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j) * esz;
+      HIP_OK(hipMemcpyAsync(ctx->site[j], site_at[j], bytes, hipMemcpyHostToDevice, s));
+    }
+    for (int b = 0; b < n - 1; ++b)
+      HIP_OK(hipMemcpyAsync(ctx->lam[b], lam_at[b], chi[b] * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->d_chi, ctx->chi.data(), (n - 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));  // the host buffers above are released on return
+    ctx->stats = st;
+    ctx->prev_dw = pdw;
+    ctx->prev_tail = ptail;
+    ctx->sketch_seed = sk_seed;
+    ctx->sketch_stream = sk_stream;
+    ctx->pending.swap(pending);
+    return MPS_OK;
+  });
+  if (cs != MPS_OK) {
+    g_err = "mps_load: " + ctx->err;
+    mps_destroy(h);
+    return cs;
+  }
+  *out = h;
+  return MPS_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -3125,123 +3269,15 @@ mps_status mps_load(const char* path, mps_handle* out) {
     return MPS_EINVAL;
   }
   *out = nullptr;
-  std::vector<char> buf;
-  {
-    std::ifstream f(path, std::ios::binary);
-    if (!f) {
-      g_err = "mps_load: cannot open the file";
-      return MPS_EIO;
-    }
-    buf.assign(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
-  }
-  // everything is read and checked on the host before a handle exists
-  Reader r{buf.data(), buf.size() >= 8 ? buf.size() - 8 : 0};
-  auto bad = [&](const char* why) {
-    g_err = std::string("mps_load: ") + why;
+  try {
+    return load_checked(path, out);
+  } catch (const std::bad_alloc&) {
+    g_err = "mps_load: host allocation failed";
+    return MPS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = std::string("mps_load: ") + e.what();
     return MPS_EIO;
-  };
-  if (buf.size() < 16 || std::memcmp(buf.data(), kSaveMagic, 8) != 0) return bad("not a saved state");
-  uint64_t sum = 0;
-  std::memcpy(&sum, buf.data() + buf.size() - 8, 8);
-  if (sum != fnv1a(buf.data(), buf.size() - 8)) return bad("checksum mismatch");
-  r.pos = 8;
-  if (r.get<uint32_t>() != kSaveVersion) return bad("unknown version");
-  const int n = r.get<int32_t>(), chi_max = r.get<int32_t>();
-  const double eps = r.get<double>();
-  mps_options o{};
-  o.k_max = r.get<int32_t>();
-  o.q_max = r.get<int32_t>();
-  o.l_max = r.get<int32_t>();
-  o.precision = r.get<int32_t>();
-  o.svd_mode = r.get<int32_t>();
-  o.batch = r.get<int32_t>();
-  o.eig_method = r.get<int32_t>();
-  o.floor_c = r.get<double>();
-  o.hip_stream = nullptr;
-  const double log_f = r.get<double>();
-  mps_stats st{};
-  st.steps = r.get<int64_t>();
-  st.cluster_updates = r.get<int64_t>();
-  st.svds = r.get<int64_t>();
-  st.site_updates = r.get<int64_t>();
-  st.sketch_accepted = r.get<int64_t>();
-  st.sketch_fallback = r.get<int64_t>();
-  st.jacobi_sweeps = r.get<int64_t>();
-  st.discarded_weight = r.get<double>();
-  const uint64_t sk_seed = r.get<uint64_t>();
-  const uint32_t sk_stream = r.get<uint32_t>();
-  if (!r.ok || n < 2 || n > (1 << 24) || chi_max < 1 || chi_max > 2048 || !options_valid(o))
-    return bad("malformed header");
-  std::vector<int> chi(n - 1);
-  for (int b = 0; b < n - 1; ++b) {
-    chi[b] = r.get<int32_t>();
-    const int e = std::min(b + 1, n - b - 1);
-    const int cap = e >= 30 ? chi_max : std::min(chi_max, 1 << e);
-    if (!r.ok || chi[b] < 1 || chi[b] > cap) return bad("bond dimension out of range");
   }
-  std::vector<float> pdw(n - 1), ptail(n - 1);
-  for (int b = 0; b < n - 1; ++b) {
-    pdw[b] = r.get<float>();
-    ptail[b] = r.get<float>();
-  }
-  const size_t esz = o.precision == MPS_PREC_FP64 ? 16 : 8;
-  std::vector<const char*> site_at(n), lam_at(n - 1);
-  for (int j = 0; j < n; ++j) {
-    const size_t bytes = (size_t)(j > 0 ? chi[j - 1] : 1) * 2 * (j < n - 1 ? chi[j] : 1) * esz;
-    site_at[j] = r.skip(bytes);
-  }
-  for (int b = 0; b < n - 1; ++b) lam_at[b] = r.skip(chi[b] * sizeof(double));
-  std::vector<SubLayer> pending(r.get<uint32_t>());
-  for (auto& sl : pending) {
-    sl.resize(r.ok ? r.get<uint32_t>() : 0);
-    if (sl.size() > (size_t)n) return bad("malformed sub-layer");
-    for (auto& g : sl) {
-      g.nq = r.get<int32_t>();
-      g.q[0] = r.get<int32_t>();
-      g.q[1] = r.get<int32_t>();
-      for (int e = 0; e < 16; ++e) {
-        const double re = r.get<double>(), im = r.get<double>();
-        g.u[e] = cplx(re, im);
-      }
-      if (g.nq < 1 || g.nq > 2 || g.q[0] < 0 || g.q[0] >= n || g.q[1] < 0 || g.q[1] >= n)
-        return bad("malformed gate");
-    }
-  }
-  if (!r.ok || r.pos != buf.size() - 8) return bad("truncated or oversized file");
-  mps_handle h = nullptr;
-  mps_status cs = mps_create(n, chi_max, eps, &o, &h);
-  if (cs != MPS_OK) {
-    g_err = "mps_load: could not create the handle";
-    return cs;
-  }
-  mps_ctx* ctx = h;
-  cs = guarded(ctx, [&]() -> mps_status {
-    hipStream_t s = ctx->stream;
-    ctx->chi = chi;
-    for (int j = 0; j < n; ++j) {
-      const size_t bytes = (size_t)bond_dim(ctx, j - 1) * 2 * bond_dim(ctx, j) * esz;
-      HIP_OK(hipMemcpyAsync(ctx->site[j], site_at[j], bytes, hipMemcpyHostToDevice, s));
-    }
-    for (int b = 0; b < n - 1; ++b)
-      HIP_OK(hipMemcpyAsync(ctx->lam[b], lam_at[b], chi[b] * sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(ctx->d_chi, ctx->chi.data(), (n - 1) * sizeof(int), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(ctx->d_logf, &log_f, sizeof(double), hipMemcpyHostToDevice, s));
-    HIP_OK(hipStreamSynchronize(s));  // the host buffers above are released on return
-    ctx->stats = st;
-    ctx->prev_dw = pdw;
-    ctx->prev_tail = ptail;
-    ctx->sketch_seed = sk_seed;
-    ctx->sketch_stream = sk_stream;
-    ctx->pending.swap(pending);
-    return MPS_OK;
-  });
-  if (cs != MPS_OK) {
-    g_err = "mps_load: " + ctx->err;
-    mps_destroy(h);
-    return cs;
-  }
-  *out = h;
-  return MPS_OK;
 }
 
 mps_status mps_sketch_range(mps_handle ctx, int n, int s, const double* G, const double* Omega,

@@ -1,0 +1,172 @@
+"""mps_load's host-side checks of a saved-state file (no GPU needed).
+
+The files here are written field by field in the layout the header of
+mps_save states (little-endian, a 64-bit FNV-1a checksum of the bytes before
+it), so each malformation carries a valid checksum and reaches the check it
+is aimed at.  A well-formed file passes every check: without a GPU the load
+then stops at creating the handle (MPS_EDEVICE), with one it succeeds.  The
+buffered sub-layers of the well-formed files come from the oracle planner's
+legalisation (Sec. III.A routing), which the library's planner matches."""
+import math
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import planner as PL
+from workloads import random_structured
+
+MAGIC = b"CTEBDMPS"
+VERSION = 2
+
+
+def _lib():
+    from paper_2502_19289_amd import ffi
+    return ffi
+
+
+def _fnv1a(data: bytes) -> int:
+    h = 1469598103934665603
+    for b in data:
+        h ^= b
+        h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _gate_bytes(nq, q0, q1):
+    dim = 1 << min(nq, 2)
+    u = np.zeros(16, complex)
+    u[:dim * dim] = np.eye(dim).ravel()
+    out = struct.pack("<iii", nq, q0, q1)
+    for z in u:
+        out += struct.pack("<dd", z.real, z.imag)
+    return out
+
+
+def _state_file(n=12, chi_max=8, eps=1e-10, k_max=4, precision=1, chi=None, pending=(), n_sub=None,
+                header_eps=None):
+    """A saved product state (or the given bond dimensions, flat Schmidt
+    values) with `pending` sub-layers, each a list of (nq, q0, q1)."""
+    chi = [1] * (n - 1) if chi is None else list(chi)
+    esz = 16 if precision == 0 else 8
+    b = bytearray(MAGIC)
+    b += struct.pack("<I", VERSION)
+    b += struct.pack("<ii", n, chi_max)
+    b += struct.pack("<d", eps if header_eps is None else header_eps)
+    b += struct.pack("<7i", k_max, 0, 0, precision, 0, 1, 0)
+    b += struct.pack("<d", 4.0)            # floor_c
+    b += struct.pack("<d", 0.0)            # sum log f
+    b += struct.pack("<7q", *([0] * 7))    # counters
+    b += struct.pack("<d", 0.0)            # discarded weight
+    b += struct.pack("<QI", 1, 0)          # sketch generator state
+    b += struct.pack(f"<{n - 1}i", *chi)
+    for _ in range(n - 1):
+        b += struct.pack("<ff", 0.0, 1.0)
+    for j in range(n):
+        cl = chi[j - 1] if j > 0 else 1
+        cr = chi[j] if j < n - 1 else 1
+        b += bytes(cl * 2 * cr * esz)
+    for c in chi:
+        b += struct.pack(f"<{c}d", *([1 / math.sqrt(c)] * c))
+    b += struct.pack("<I", len(pending) if n_sub is None else n_sub)
+    for sl in pending:
+        b += struct.pack("<I", len(sl))
+        for g in sl:
+            b += _gate_bytes(*g)
+    b += struct.pack("<Q", _fnv1a(bytes(b)))
+    return bytes(b)
+
+
+def _subs_of(layers, k_max):
+    out = []
+    for sl in PL.legalize(layers, k_max):
+        out.append([(1, g.qubits[0], g.qubits[0]) if len(g.qubits) == 1 else (2, g.qubits[0], g.qubits[1])
+                    for g in sl])
+    return out
+
+
+def _load(tmp_path, data, name="state.ctebd"):
+    ffi = _lib()
+    p = tmp_path / name
+    p.write_bytes(data)
+    return ffi.MPS.load(str(p))
+
+
+def _rejects(tmp_path, data, why):
+    ffi = _lib()
+    with pytest.raises(ffi.CtebdError) as e:
+        _load(tmp_path, data)
+    assert e.value.status == ffi.MPS_EIO, str(e.value)
+    assert why in str(e.value), str(e.value)
+
+
+def _accepts(tmp_path, data, chi):
+    """Every check passed: without a GPU the load stops at creating the
+    handle; with one it returns a handle with the saved bond dimensions."""
+    ffi = _lib()
+    try:
+        m = _load(tmp_path, data)
+    except ffi.CtebdError as e:
+        assert e.status == ffi.MPS_EDEVICE, str(e)
+        return
+    assert m.bond_dims() == list(chi)
+    m.close()
+
+
+@pytest.mark.parametrize("k_max,seed", [(2, 0), (3, 1), (4, 2), (6, 3)])
+def test_legalised_sub_layers_pass(tmp_path, k_max, seed):
+    """Sub-layers as the planner leaves them, SWAP-routed gates included
+    (the circuit has gates on qubits up to 10 apart)."""
+    n = 16
+    c = random_structured(n, 10, 10, ("H", "S", "CNOT"), 0.2, seed=seed, workload_id=31)
+    subs = _subs_of(c.layers, k_max)
+    assert any(g[0] == 2 and abs(g[1] - g[2]) + 1 == k_max for sl in subs for g in sl)
+    _accepts(tmp_path, _state_file(n=n, k_max=k_max, pending=subs), [1] * (n - 1))
+
+
+def test_state_with_bond_dimensions_passes(tmp_path):
+    chi = [2, 4, 8, 8, 8, 4, 2]
+    _accepts(tmp_path, _state_file(n=8, chi_max=8, chi=chi, precision=0), chi)
+
+
+def test_malformed_headers(tmp_path):
+    _rejects(tmp_path, _state_file(header_eps=float("nan")), "malformed header")
+    _rejects(tmp_path, _state_file(k_max=1), "malformed header")
+    _rejects(tmp_path, _state_file(chi_max=4096), "malformed header")
+    # bond 0 of any chain holds at most 2
+    _rejects(tmp_path, _state_file(n=6, chi=[4, 4, 4, 2, 1]), "bond dimension out of range")
+    # a bond above chi_max
+    _rejects(tmp_path, _state_file(n=12, chi_max=4, chi=[2, 4, 8, 4, 2, 1, 1, 1, 1, 1, 1]),
+             "bond dimension out of range")
+
+
+def test_counts_are_bounded_before_allocation(tmp_path):
+    # 2^32 - 1 sub-layers announced, none present
+    _rejects(tmp_path, _state_file(n_sub=0xFFFFFFFF), "sub-layer count")
+    # one sub-layer announcing more gates than the chain has qubits
+    data = bytearray(_state_file(pending=[[(1, 0, 0)]]))
+    body = data[:-8]
+    at = body.rfind(struct.pack("<I", 1) + _gate_bytes(1, 0, 0))
+    body[at:at + 4] = struct.pack("<I", 1000)
+    _rejects(tmp_path, bytes(body) + struct.pack("<Q", _fnv1a(bytes(body))), "malformed sub-layer")
+
+
+@pytest.mark.parametrize("pending,why", [
+    ([[(2, 0, 5)]], "k_max"),                        # span 6 > k_max 4
+    ([[(2, 5, 0)]], "k_max"),                        # the same, qubits in the other order
+    ([[(2, 3, 3)]], "malformed gate"),               # a two-qubit gate on one qubit
+    ([[(1, 2, 7)]], "malformed gate"),               # a one-qubit gate holds its qubit twice
+    ([[(3, 0, 1)]], "malformed gate"),
+    ([[(1, 12, 12)]], "malformed gate"),             # qubit out of range (n = 12)
+    ([[(2, 0, 1), (1, 1, 1)]], "share a qubit"),
+    ([[(2, 0, 2), (2, 1, 3)]], "overlap"),           # distinct qubits, crossing spans
+    ([[(2, 4, 7), (1, 5, 5), (2, 1, 2)], [(2, 2, 3), (2, 3, 4)]], "share a qubit"),
+])
+def test_sub_layers_the_planner_cannot_produce(tmp_path, pending, why):
+    _rejects(tmp_path, _state_file(n=12, k_max=4, pending=pending), why)
+
+
+def test_a_one_qubit_gate_inside_a_span_passes(tmp_path):
+    """legalize_layer keeps the one-qubit gates of a layer in its first
+    sub-layer with the two-qubit gates whose spans they may lie in."""
+    _accepts(tmp_path, _state_file(n=12, k_max=4, pending=[[(2, 2, 5), (1, 3, 3), (1, 4, 4), (2, 6, 7)]]), [1] * 11)

@@ -3353,7 +3353,10 @@ mps_status mps_dmrg_step(mps_handle ctx, const mps_gate* gates, const int* layer
     std::vector<std::vector<HostGate>> layers(nl);
     int off = 0;
     for (int l = 0; l < nl; ++l) {
-      if (layer_len[l] < 0) return MPS_EINVAL;
+      if (layer_len[l] < 0) {
+        ctx->err = "mps_dmrg_step: negative layer length";
+        return MPS_EINVAL;
+      }
       const mps_status st = check_gates(ctx, gates + off, layer_len[l], ctx->n);
       if (st != MPS_OK) return st;
       for (int i = 0; i < layer_len[l]; ++i) layers[l].push_back(to_host_gate(gates[off + i]));

@@ -13,6 +13,11 @@ Contents (each function cites the passage of arXiv:2502.19289 it follows):
   statevector  brute-force 2^n simulation (pins exact contraction)
   stabilizer   CHP tableau + GF(2)-rank entanglement entropies (pins Clifford spectra)
   mps_tools    amplitudes, overlaps, entropies of an MPS (Sec. II.B definitions)
-  sketch       randomized range finder and the kept-rank MLP (the learned sketch);
-               parity unpinned beyond the identities its tests list
+  tebd         gate-by-gate TEBD with an orthogonality centre (Sec. II.C)
+  dmrg         adaptive-grouping DMRG: virtual bond dimensions, bipartition,
+               fitting sweeps, decomposition (Sec. III.B)
+  sketch       randomized range finder and the kept-rank MLP (the learned
+               sketch, not in the paper); the range finder, the network's
+               forward pass, its gradients and the optimiser are pinned, the
+               trained weights are not (parity unpinned: they come from data)
 """

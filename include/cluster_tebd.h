@@ -149,7 +149,11 @@ mps_status mps_destroy(mps_handle h);
  * ascending with qubits[k-1]-qubits[0]+1 <= k_max (else MPS_ESPAN); idle qubits
  * inside the span are padded with the identity.  The block is then split back
  * by k'-1 truncated SVDs (k' = span), adding log f_i of each to the fidelity
- * estimate.  Pending layers are flushed first.  2 <= k <= 12. */
+ * estimate.  Pending layers are flushed first.  2 <= k <= 12.  U must satisfy
+ * ||U^H U - 1||_max <= 1e-10, else MPS_ENOTUNITARY and the state is left as
+ * it was (the product U^H U is formed on the host for 2^k < 512 and on the
+ * device, in FP64, from 512 on; either way the call waits for the handle's
+ * stream). */
 mps_status mps_apply_cluster(mps_handle h, const int* qubits, int k, const double* U);
 
 /* Sec. III.A iteration driver: buffers one circuit layer (gates on disjoint

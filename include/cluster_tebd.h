@@ -340,7 +340,8 @@ mps_status mps_kernel_dispatches(mps_handle h, int64_t* dispatches, int cap, int
 mps_status mps_kernel_bytes(mps_handle h, double* bytes, int cap, int* count);
 
 /* Message of the last failure of h; with h = NULL, of the last failed call
- * of this thread that takes no handle (mps_heev). */
+ * of this thread that takes no handle (mps_heev, mps_heev_noalloc, mps_load,
+ * mps_plan). */
 const char* mps_last_error(mps_handle h);
 
 /* ---- learned sketch -------------------------------------------------------
@@ -402,7 +403,10 @@ mps_status mps_svd_log(mps_handle h, float* X, float* t, int cap, int* count);
  *   layers: nl layers; layer_len[i] gates each; gates flattened in order.
  *   out_end: index (exclusive) of the last sub-layer of the step.
  *   out_clusters: pairs (first site, k) of the step's clusters, at most cap.
- *   n_sub: number of sub-layers after legalisation. */
+ *   n_sub: number of sub-layers after legalisation.
+ * MPS_EINVAL for bad sizes or for gates that mps_run_layer would reject
+ * (nq outside {1, 2}, a qubit out of range, two gates of a layer sharing a
+ * qubit); mps_last_error(NULL) then says why. */
 mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi,
                     const mps_gate* gates, const int* layer_len, int nl, int start,
                     int* out_end, int* out_clusters, int cap, int* out_count,

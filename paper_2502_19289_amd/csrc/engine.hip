@@ -2110,25 +2110,25 @@ HostGate to_host_gate(const mps_gate& g) {
   return h;
 }
 
-mps_status check_gates(mps_ctx* ctx, const mps_gate* gates, int ngates, int n) {
+// Why the gates of one layer are invalid on n qubits, or nullptr.
+const char* gate_error(const mps_gate* gates, int ngates, int n) {
   std::vector<char> used(n, 0);
   for (int i = 0; i < ngates; ++i) {
     const mps_gate& g = gates[i];
-    if (g.nq < 1 || g.nq > 2) {
-      ctx->err = "gate with nq outside {1,2}";
-      return MPS_EINVAL;
-    }
+    if (g.nq < 1 || g.nq > 2) return "gate with nq outside {1,2}";
     for (int j = 0; j < g.nq; ++j) {
-      if (g.q[j] < 0 || g.q[j] >= n) {
-        ctx->err = "gate qubit out of range";
-        return MPS_EINVAL;
-      }
-      if (used[g.q[j]]) {
-        ctx->err = "gates of one layer must act on disjoint qubits";
-        return MPS_EINVAL;
-      }
+      if (g.q[j] < 0 || g.q[j] >= n) return "gate qubit out of range";
+      if (used[g.q[j]]) return "gates of one layer must act on disjoint qubits";
       used[g.q[j]] = 1;
     }
+  }
+  return nullptr;
+}
+
+mps_status check_gates(mps_ctx* ctx, const mps_gate* gates, int ngates, int n) {
+  if (const char* why = gate_error(gates, ngates, n)) {
+    ctx->err = why;
+    return MPS_EINVAL;
   }
   return MPS_OK;
 }
@@ -3843,11 +3843,22 @@ const char* mps_last_error(mps_handle ctx) {
 mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi, const mps_gate* gates,
                     const int* layer_len, int nl, int start, int* out_end, int* out_clusters, int cap,
                     int* out_count, int* n_sub) {
-  if (n < 2 || k_max < 2 || !chi || !layer_len || nl < 0 || !out_end || !out_count) return MPS_EINVAL;
+  if (n < 2 || k_max < 2 || !chi || !layer_len || nl < 0 || !out_end || !out_count || (cap > 0 && !out_clusters)) {
+    g_err = "mps_plan: bad argument (n >= 2, k_max >= 2, non-null arrays)";
+    return MPS_EINVAL;
+  }
   try {
     std::vector<SubLayer> subs;
     int off = 0;
     for (int l = 0; l < nl; ++l) {
+      if (layer_len[l] < 0 || (layer_len[l] > 0 && !gates)) {
+        g_err = "mps_plan: bad layer length or null gates";
+        return MPS_EINVAL;
+      }
+      if (const char* why = gate_error(gates + off, layer_len[l], n)) {
+        g_err = std::string("mps_plan: ") + why;
+        return MPS_EINVAL;
+      }
       std::vector<HostGate> layer;
       for (int i = 0; i < layer_len[l]; ++i) layer.push_back(to_host_gate(gates[off + i]));
       off += layer_len[l];
@@ -3857,7 +3868,9 @@ mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi, cons
     if (start < 0 || start >= (int)subs.size()) {
       *out_end = start;
       *out_count = 0;
-      return subs.empty() ? MPS_OK : MPS_EINVAL;
+      if (subs.empty()) return MPS_OK;
+      g_err = "mps_plan: start outside the sub-layers";
+      return MPS_EINVAL;
     }
     std::vector<int> ch(chi, chi + n - 1);
     std::vector<Cluster> cl;
@@ -3870,7 +3883,11 @@ mps_status mps_plan(int n, int k_max, int q_max, int l_max, const int* chi, cons
       out_clusters[2 * i + 1] = cl[i].k;
     }
     return MPS_OK;
+  } catch (const std::bad_alloc&) {
+    g_err = "mps_plan: host allocation failed";
+    return MPS_ENOMEM;
   } catch (...) {
+    g_err = "mps_plan: unexpected error";
     return MPS_EINVAL;
   }
 }

@@ -520,7 +520,7 @@ def plan(n: int, k_max: int, layers, chi: Sequence[int], start: int = 0, q_max: 
     st = lib.mps_plan(n, k_max, q_max, l_max, _iptr(ch), arr, _iptr(ll), len(layers), start,
                       C.byref(end), _iptr(out), n, C.byref(cnt), C.byref(nsub))
     if st != MPS_OK:
-        raise CtebdError(st, "mps_plan failed")
+        raise CtebdError(st, lib.mps_last_error(None).decode())
     cl = [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(cnt.value)]
     return end.value, cl, nsub.value
 

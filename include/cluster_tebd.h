@@ -340,8 +340,8 @@ mps_status mps_kernel_dispatches(mps_handle h, int64_t* dispatches, int cap, int
 mps_status mps_kernel_bytes(mps_handle h, double* bytes, int cap, int* count);
 
 /* Message of the last failure of h; with h = NULL, of the last failed call
- * of this thread that takes no handle (mps_heev, mps_heev_noalloc, mps_load,
- * mps_plan). */
+ * of this thread that takes no handle or creates one (mps_create, mps_load,
+ * mps_heev, mps_heev_noalloc, mps_plan). */
 const char* mps_last_error(mps_handle h);
 
 /* ---- learned sketch -------------------------------------------------------

@@ -2900,7 +2900,7 @@ mps_status load_checked(const char* path, mps_handle* out) {
   mps_handle h = nullptr;
   mps_status cs = mps_create(n, chi_max, eps, &o, &h);
   if (cs != MPS_OK) {
-    g_err = "mps_load: could not create the handle";
+    g_err = "mps_load: could not create the handle (" + g_err + ")";
     return cs;
   }
   mps_ctx* ctx = h;
@@ -2953,10 +2953,16 @@ mps_status mps_default_options(mps_options* opt) {
 }
 
 mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mps_handle* out) {
-  if (!out || n < 2 || chi_max < 1 || chi_max > 2048 || !(eps >= 0.0)) return MPS_EINVAL;
+  if (!out || n < 2 || chi_max < 1 || chi_max > 2048 || !(eps >= 0.0)) {
+    g_err = "mps_create: need n >= 2, 1 <= chi_max <= 2048, eps >= 0 and an output pointer";
+    return MPS_EINVAL;
+  }
   *out = nullptr;
   mps_ctx* ctx = new (std::nothrow) mps_ctx();
-  if (!ctx) return MPS_ENOMEM;
+  if (!ctx) {
+    g_err = "mps_create: host allocation failed";
+    return MPS_ENOMEM;
+  }
   mps_status st = guarded(ctx, [&]() -> mps_status {
     if (opt)
       ctx->opt = *opt;
@@ -3036,7 +3042,7 @@ mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt, mp
     return MPS_OK;
   });
   if (st != MPS_OK) {
-    std::fprintf(stderr, "mps_create: %s\n", ctx->err.c_str());
+    g_err = "mps_create: " + ctx->err;
     destroy_ctx(ctx);
     return st;
   }

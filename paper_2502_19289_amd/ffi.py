@@ -183,7 +183,7 @@ class MPS:
         h = C.c_void_p()
         st = self.lib.mps_create(n, chi_max, eps, C.byref(o), C.byref(h))
         if st != MPS_OK:
-            raise CtebdError(st, "mps_create failed")
+            raise CtebdError(st, self.lib.mps_last_error(None).decode())
         self._opt = o
         self.h = h
         self.n = n

@@ -37,6 +37,17 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(ffi.CtebdError) as e:
         ffi.MPS(8, 4, 1e-12)
     assert e.value.status == ffi.MPS_EDEVICE
+    assert "no HIP device" in str(e.value)  # through mps_last_error(NULL)
+
+
+@pytest.mark.parametrize("n,chi,eps", [(1, 4, 1e-12), (8, 0, 1e-12), (8, 4096, 1e-12), (8, 4, -1.0),
+                                       (8, 4, float("nan"))])
+def test_create_rejects_bad_sizes_with_a_message(n, chi, eps):
+    ffi = _lib()
+    with pytest.raises(ffi.CtebdError) as e:
+        ffi.MPS(n, chi, eps)
+    assert e.value.status == ffi.MPS_EINVAL
+    assert "chi_max <= 2048" in str(e.value)
 
 
 def _layers_for_abi(c):

@@ -12,6 +12,8 @@ import struct
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 from oracle import planner as PL
 from workloads import random_structured
@@ -170,3 +172,26 @@ def test_a_one_qubit_gate_inside_a_span_passes(tmp_path):
     """legalize_layer keeps the one-qubit gates of a layer in its first
     sub-layer with the two-qubit gates whose spans they may lie in."""
     _accepts(tmp_path, _state_file(n=12, k_max=4, pending=[[(2, 2, 5), (1, 3, 3), (1, 4, 4), (2, 6, 7)]]), [1] * 11)
+
+
+@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(st.data())
+def test_corrupted_files_never_crash_the_reader(tmp_path, data):
+    """One to four bytes of a well-formed file changed, the checksum written
+    again so that the change reaches the field checks: the reader returns
+    MPS_EIO, or accepts the file (a change inside tensor data or Schmidt
+    values) and then stops at the handle (MPS_EDEVICE without a GPU)."""
+    ffi = _lib()
+    good = _state_file(n=8, chi_max=8, chi=[2, 4, 8, 8, 8, 4, 2], precision=0,
+                       pending=[[(2, 0, 1), (1, 3, 3), (2, 4, 6)], [(2, 1, 2)]])
+    body = bytearray(good[:-8])
+    for _ in range(data.draw(st.integers(1, 4))):
+        at = data.draw(st.integers(0, len(body) - 1))
+        body[at] = data.draw(st.integers(0, 255))
+    blob = bytes(body) + struct.pack("<Q", _fnv1a(bytes(body)))
+    try:
+        m = _load(tmp_path, blob, name="fuzz.ctebd")
+    except ffi.CtebdError as e:
+        assert e.status in (ffi.MPS_EIO, ffi.MPS_EDEVICE), str(e)
+        return
+    m.close()

@@ -20,7 +20,9 @@
  *     it needs before returning.  All device memory belongs to the handle and is
  *     released by mps_destroy.
  *   - Errors: every call returns an mps_status; nothing is thrown across the
- *     ABI.  mps_last_error(h) gives a message for the last failed call on h.
+ *     ABI.  mps_last_error(h) gives a message for the last failed call on h;
+ *     mps_last_error(NULL) for the calling thread's last failed call that
+ *     takes no handle or creates one (mps_create, mps_load, ...).
  *   - Concurrency: one handle must not be used from two host threads at once.
  *     Work is queued on the handle's HIP stream; the calls documented as
  *     "synchronises" wait for it.

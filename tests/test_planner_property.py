@@ -49,7 +49,7 @@ def _abi_layers(layers):
     return [[(g.qubits, GATES[g.name]) for g in l] for l in layers]
 
 
-@settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@settings(max_examples=300, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.too_slow])
 @given(planner_cases())
 def test_planner_matches_oracle_on_random_cases(case):
     ffi = _ffi()

@@ -174,7 +174,7 @@ def test_a_one_qubit_gate_inside_a_span_passes(tmp_path):
     _accepts(tmp_path, _state_file(n=12, k_max=4, pending=[[(2, 2, 5), (1, 3, 3), (1, 4, 4), (2, 6, 7)]]), [1] * 11)
 
 
-@settings(max_examples=200, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@settings(max_examples=200, deadline=None, derandomize=True, suppress_health_check=[HealthCheck.function_scoped_fixture])
 @given(st.data())
 def test_corrupted_files_never_crash_the_reader(tmp_path, data):
     """One to four bytes of a well-formed file changed, the checksum written

@@ -74,7 +74,8 @@ def product_state(n: int) -> MPS:
 
 def apply_gate_to_columns(M: np.ndarray, k: int, u: np.ndarray, pos: Sequence[int]) -> np.ndarray:
     """Left-multiply a 2^k x c matrix by gate u acting on local qubits ``pos``
-    (big-endian: local qubit 0 is the most significant bit)."""
+    (big-endian: local qubit 0 is the most significant bit); a gate acts on
+    its qubits' indices of the state tensor (Sec. II.A)."""
     c = M.shape[1]
     g = len(pos)
     T = M.reshape((2,) * k + (c,))
@@ -92,7 +93,9 @@ def apply_gate_to_columns(M: np.ndarray, k: int, u: np.ndarray, pos: Sequence[in
 
 
 def cluster_unitary(a: int, k: int, gates: Sequence) -> np.ndarray:
-    """U_c: the ordered product of the cluster's gates embedded on its k qubits."""
+    """U_c: the ordered product of the cluster's gates embedded on its k qubits
+    (Sec. III.A: the gates of a cluster over the step's layers are contracted
+    into one tensor before it meets the MPS)."""
     U = np.eye(2 ** k, dtype=np.complex128)
     for g in gates:
         U = apply_gate_to_columns(U, k, G.matrix(g.name), [q - a for q in g.qubits])
@@ -110,7 +113,10 @@ def truncation_rank(sigma: np.ndarray, chi_max: int, eps: float) -> int:
 
 def apply_cluster(psi: MPS, a: int, k: int, U: np.ndarray, chi_max: int, eps: float,
                   step: int = 0) -> None:
-    """Steps 2-5 of the module docstring for one cluster, in place."""
+    """Steps 2-5 of the module docstring for one cluster, in place: contract
+    and apply U_c, then split right to left by truncated SVDs with eta and
+    chi_max (Sec. III.A with the truncation of Sec. II.B), recording each
+    f_i (Eq. f_i) and adding log f_i to the fidelity sum (Eq. approxF)."""
     theta = psi.B[a]
     for j in range(1, k):
         theta = np.tensordot(theta, psi.B[a + j], axes=([theta.ndim - 1], [0]))
@@ -141,6 +147,8 @@ def apply_cluster(psi: MPS, a: int, k: int, U: np.ndarray, chi_max: int, eps: fl
 
 
 def apply_one_qubit(psi: MPS, j: int, u: np.ndarray) -> None:
+    """A one-qubit gate on a site outside every cluster of the step (Sec.
+    III.A: no bond grows, no SVD)."""
     psi.B[j] = np.einsum("st,ltr->lsr", u, psi.B[j])
 
 
@@ -152,6 +160,7 @@ class RunResult:
 
     @property
     def fidelity(self) -> float:
+        """F_est = prod f_i (Eq. approxF)."""
         return math.exp(self.psi.log_f)
 
 
@@ -174,7 +183,9 @@ def run_step(psi: MPS, subs, start: int, chi_max: int, eps: float, k_max: int,
 
 def run(circuit, chi_max: int, eps: float, k_max: int, q_max: Optional[int] = None,
         l_max: int = 1 << 30, psi: Optional[MPS] = None, max_steps: Optional[int] = None) -> RunResult:
-    """Simulate ``circuit`` from |0...0> (or ``psi``) with cluster-TEBD."""
+    """Simulate ``circuit`` from |0...0> (or ``psi``) with cluster-TEBD: the
+    iteration of Sec. III.A, one step after another until every layer is
+    contracted."""
     if q_max is None:
         q_max = PL.default_q_max(k_max, chi_max)
     subs = PL.legalize(circuit.layers, k_max)

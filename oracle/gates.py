@@ -38,6 +38,8 @@ SQRTW = _s2 * np.array([[_w, -1j], [1, _w]], dtype=np.complex128)
 
 
 def controlled(u: np.ndarray) -> np.ndarray:
+    """The controlled gates of App. A: u on the second qubit when the first
+    (the more significant index bit) is 1."""
     m = np.eye(4, dtype=np.complex128)
     m[2:, 2:] = u
     return m
@@ -65,4 +67,5 @@ CLIFFORD = {"I", "H", "X", "Y", "Z", "S", "CNOT", "CY", "CZ", "SWAP"}
 
 
 def matrix(name: str) -> np.ndarray:
+    """The matrix of a gate symbol of App. A (plus H, S, T)."""
     return TABLE[name]

@@ -47,6 +47,8 @@ def _disjoint(iv: Tuple[int, int], ivs: Sequence[Tuple[int, int]]) -> bool:
 
 
 def legalize_layer(gates: Sequence[Gate], k_max: int) -> List[List[Gate]]:
+    """One layer (Sec. II.A) as sub-layers of pairwise disjoint spans, gates
+    wider than k_max routed by SWAP chains (Sec. IV.A)."""
     ones = [g for g in gates if len(g.qubits) == 1]
     multi = sorted((g for g in gates if len(g.qubits) > 1), key=lambda g: (_span(g), g.qubits))
     short = [g for g in multi if _span(g)[1] - _span(g)[0] + 1 <= k_max]
@@ -86,6 +88,7 @@ def legalize_layer(gates: Sequence[Gate], k_max: int) -> List[List[Gate]]:
 
 
 def legalize(layers: Sequence[Sequence[Gate]], k_max: int) -> List[List[Gate]]:
+    """Every layer of a circuit through legalize_layer, in order."""
     out: List[List[Gate]] = []
     for layer in layers:
         out.extend(legalize_layer(layer, k_max))
@@ -93,6 +96,8 @@ def legalize(layers: Sequence[Sequence[Gate]], k_max: int) -> List[List[Gate]]:
 
 
 def mark_bonds(bond: List[bool], gates: Sequence[Gate]) -> None:
+    """The bond array of Sec. III.A: a multi-qubit gate marks every bond its
+    span crosses."""
     for g in gates:
         if len(g.qubits) > 1:
             lo, hi = _span(g)
@@ -117,6 +122,8 @@ def clusters_of(bond: Sequence[bool]) -> List[Tuple[int, int]]:
 
 
 def cluster_fits(a: int, k: int, chi: Sequence[int], k_max: int, q_max: int) -> bool:
+    """k <= k_max and size = 2^k chi_l chi_r <= 2^Q_max (Eqs. size and
+    cond_cTEBD), in exact integers."""
     n_bonds = len(chi)
     chi_l = chi[a - 1] if a > 0 else 1
     chi_r = chi[a + k - 1] if a + k - 1 < n_bonds else 1

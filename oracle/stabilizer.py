@@ -78,6 +78,8 @@ def bond_entropies(tab: Tableau):
 
 
 def circuit_entropies(circuit):
+    """Bond entropies of a Clifford circuit's state from |0...0>, by the
+    stabilizer tableau (the integer entropies that pin Clifford spectra)."""
     tab = Tableau(circuit.n)
     for layer in circuit.layers:
         for g in layer:

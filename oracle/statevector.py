@@ -9,6 +9,8 @@ from . import gates as G
 
 
 def apply_gate(psi: np.ndarray, n: int, u: np.ndarray, qubits) -> np.ndarray:
+    """A gate on its qubits of the 2^n state (Sec. II.A), qubit 0 the most
+    significant index bit, by a tensor contraction."""
     g = len(qubits)
     T = psi.reshape((2,) * n)
     T = np.tensordot(u.reshape((2,) * (2 * g)), T, axes=(list(range(g, 2 * g)), list(qubits)))
@@ -17,6 +19,8 @@ def apply_gate(psi: np.ndarray, n: int, u: np.ndarray, qubits) -> np.ndarray:
 
 
 def simulate(circuit) -> np.ndarray:
+    """The circuit's exact state from |0...0> (Secs. II.A, IV.A), layer by
+    layer."""
     n = circuit.n
     psi = np.zeros(2 ** n, dtype=np.complex128)
     psi[0] = 1.0

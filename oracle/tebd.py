@@ -48,6 +48,7 @@ class CentredMPS:
 
 
 def product_state(n: int) -> CentredMPS:
+    """|0...0> with the orthogonality centre on site 0 (Secs. II.C, IV.A)."""
     A = []
     for _ in range(n):
         t = np.zeros((1, 2, 1), dtype=np.complex128)
@@ -78,6 +79,7 @@ def move_centre(psi: CentredMPS, i: int) -> None:
 
 
 def apply_one_qubit(psi: CentredMPS, j: int, u: np.ndarray) -> None:
+    """A one-qubit gate needs no SVD in TEBD (Sec. II.C)."""
     psi.A[j] = np.einsum("st,ltr->lsr", u, psi.A[j])
 
 
@@ -108,6 +110,9 @@ def _permuted(u: np.ndarray, first_is_low: bool) -> np.ndarray:
 
 
 def apply_gate(psi: CentredMPS, gate, chi_max: int, eps: float) -> None:
+    """One gate of the circuit by TEBD (Sec. II.C): one-qubit gates on their
+    site, two-qubit gates on neighbours through steps 1-3, longer ones by
+    SWAP chains (Sec. IV.A)."""
     u = G.matrix(gate.name)
     if len(gate.qubits) == 1:
         apply_one_qubit(psi, gate.qubits[0], u)
@@ -134,6 +139,7 @@ def run(circuit, chi_max: int, eps: float) -> CentredMPS:
 
 
 def amplitudes(psi: CentredMPS) -> np.ndarray:
+    """The 2^n state of the MPS (Sec. II.B), for small n."""
     out = psi.A[0].reshape(2, -1)
     for t in psi.A[1:]:
         out = (out @ t.reshape(t.shape[0], -1)).reshape(-1, t.shape[2])

@@ -20,7 +20,10 @@
  *     it needs before returning.  All device memory belongs to the handle and is
  *     released by mps_destroy.
  *   - Errors: every call returns an mps_status; nothing is thrown across the
- *     ABI.  mps_last_error(h) gives a message for the last failed call on h;
+ *     ABI.  Common to all calls: MPS_EINVAL for a NULL handle or a NULL
+ *     pointer that the call writes through, MPS_EDEVICE / MPS_ENOMEM when a
+ *     HIP call or an allocation fails (the handle stays valid and can be
+ *     destroyed).  mps_last_error(h) gives a message for the last failed call on h;
  *     mps_last_error(NULL) for the calling thread's last failed call that
  *     takes no handle or creates one (mps_create, mps_load, ...).
  *   - Concurrency: one handle must not be used from two host threads at once.
@@ -143,6 +146,7 @@ mps_status mps_default_options(mps_options* opt);
  * possible size min(chi_max, 2^min(b+1, n-b-1)) per bond. */
 mps_status mps_create(int n, int chi_max, double eps, const mps_options* opt,
                       mps_handle* out);
+/* Releases the handle and all its device memory (NULL: nothing to do). */
 mps_status mps_destroy(mps_handle h);
 
 /* Sec. III.A steps "contract" and "decompose" for one cluster: applies the
@@ -161,7 +165,9 @@ mps_status mps_apply_cluster(mps_handle h, const int* qubits, int k, const doubl
 /* Sec. III.A iteration driver: buffers one circuit layer (gates on disjoint
  * qubits, Sec. II.A).  Gates wider than k_max are routed by adjacent SWAPs.
  * When the buffered layers no longer fit the caps (k_max, Eq. cond_cTEBD,
- * Eq. cond2_cTEBD) the step made of the layers that do fit is contracted. */
+ * Eq. cond2_cTEBD) the step made of the layers that do fit is contracted.
+ * MPS_EINVAL (nothing buffered) for nq outside {1, 2}, a qubit out of range
+ * or two gates sharing a qubit.  Gate matrices are taken as given. */
 mps_status mps_run_layer(mps_handle h, const mps_gate* gates, int ngates);
 
 /* Contracts every buffered layer (as many steps as the caps need). */
@@ -243,7 +249,7 @@ mps_status mps_dmrg_step(mps_handle h, const mps_gate* gates, const int* layer_l
 
 /* <a|b> of the current states of two handles with the same n (buffered
  * layers are not applied), by a transfer-matrix sweep in FP64 on the device
- * (E <- sum_s A_s^dagger E B_s).  Synchronises. */
+ * (E <- sum_s A_s^dagger E B_s).  Synchronises.  MPS_EINVAL when n differs. */
 mps_status mps_overlap(mps_handle a, mps_handle b, double* re, double* im);
 
 /* Eq. approxF: synchronises and returns F_est = exp(sum log f_i) and
@@ -255,23 +261,29 @@ mps_status mps_fidelity(mps_handle h, double* F_est, double* log_f);
 mps_status mps_bond_dims(mps_handle h, int* chi);
 
 /* Synchronises; copies the normalised Schmidt values of bond b (descending,
- * FP64) into sigma[0..cap-1] and their count into *len. */
+ * FP64) into sigma[0..cap-1] and their count into *len (sigma may be NULL to
+ * ask for the count).  MPS_EINVAL for a bond outside 0..n-2. */
 mps_status mps_schmidt(mps_handle h, int bond, double* sigma, int cap, int* len);
 
 /* Synchronises; copies site tensor B_j, shape (chi_{j-1}, 2, chi_j) row-major,
  * as interleaved complex128 into B[0..2*cap-1] (cap counts complex entries)
- * and its shape into dims[0..2].  Sites 1..n-1 are right-canonical; the
- * state is the contraction B_0 B_1 ... B_{n-1}. */
+ * and its shape into dims[0..2] (B may be NULL to ask for the shape).  Sites
+ * 1..n-1 are right-canonical up to the weight a truncation discarded while
+ * the site was the leftmost of its cluster; the state is the contraction
+ * B_0 B_1 ... B_{n-1}.  MPS_EINVAL for a site outside 0..n-1 or a cap below
+ * the tensor's size. */
 mps_status mps_export_site(mps_handle h, int site, double* B, int64_t cap, int* dims);
 
 /* Replaces the whole state: sites[j] points at chi_{j-1}*2*chi_j interleaved
  * complex128 values (right-canonical for j >= 1), lams[b] at chi[b] Schmidt
- * values.  Bond dimensions must not exceed the handle's capacities. */
+ * values.  Bond dimensions must not exceed the handle's capacities
+ * (MPS_EINVAL, state unchanged).  Buffered layers are contracted first. */
 mps_status mps_import(mps_handle h, const int* chi, const double* const* sites,
                       const double* const* lams, double log_f);
 
 /* Synchronises; writes the 2^n amplitudes (interleaved complex128) of the
- * state; n <= 24 and cap >= 2^n. */
+ * state, buffered layers contracted first; n <= 24 and cap >= 2^n, else
+ * MPS_EINVAL. */
 mps_status mps_amplitudes(mps_handle h, double* psi, int64_t cap);
 
 mps_status mps_get_stats(mps_handle h, mps_stats* st);
